@@ -1,0 +1,95 @@
+"""Seeded synthetic initial fields for the benchmark and test workloads.
+
+This module only builds input arrays (numpy float64, [ny][nx], x fastest); it holds none of the
+method's arithmetic.  Lattice constants it needs (the sound speed) are passed in by the caller.
+The fields follow the initial-value problems of Sec. 4 of the paper (pulses, vortex) at the sizes
+of the workloads named below.
+"""
+import numpy as np
+
+# tau giving kinematic viscosity nu = (tau - 1/2) cs^2 = 0.1 on D2Q37 (Sec. 4 uses nu = 0.1)
+NU_D2Q37 = 0.1
+
+
+def grid(nx, ny):
+    x = np.arange(nx, dtype=np.float64)
+    y = np.arange(ny, dtype=np.float64)
+    return np.meshgrid(x, y)
+
+
+def gaussian_density_pulse(nx, ny, amp=1e-3, width=8.0, center=None):
+    """rho = 1 + amp exp(-r^2 / (2 width^2)), u = 0, T = 1 (D2Q9 pulse, 256 x 128)."""
+    X, Y = grid(nx, ny)
+    cx, cy = center if center is not None else ((nx - 1) / 2.0, (ny - 1) / 2.0)
+    r2 = (X - cx) ** 2 + (Y - cy) ** 2
+    rho = 1.0 + amp * np.exp(-r2 / (2.0 * width ** 2))
+    z = np.zeros_like(rho)
+    return rho, z.copy(), z.copy(), np.ones_like(rho)
+
+
+def temperature_pulse(nx, ny, amp=1e-3, width=12.0, center=None):
+    """rho = 1, u = 0, T = 1 + amp exp(-r^2 / (2 width^2)): pressure and temperature pulse."""
+    X, Y = grid(nx, ny)
+    cx, cy = center if center is not None else ((nx - 1) / 2.0, (ny - 1) / 2.0)
+    r2 = (X - cx) ** 2 + (Y - cy) ** 2
+    T = 1.0 + amp * np.exp(-r2 / (2.0 * width ** 2))
+    z = np.zeros_like(T)
+    return np.ones_like(T), z.copy(), z.copy(), T
+
+
+def planar_temperature_pulse(nx, ny, amp=1e-3, width=10.0, x0=None):
+    """Pulse that depends on x only (a 1D problem on a y-periodic strip)."""
+    X, _ = grid(nx, ny)
+    x0 = (nx - 1) / 2.0 if x0 is None else x0
+    T = 1.0 + amp * np.exp(-((X - x0) ** 2) / (2.0 * width ** 2))
+    z = np.zeros_like(T)
+    return np.ones_like(T), z.copy(), z.copy(), T
+
+
+def isentropic_vortex(nx, ny, cs, mach=0.2, radius=20.0, strength=0.05, center=(256.0, None)):
+    """Vortex convected by a uniform flow u0 = (mach cs, 0).
+
+    du = U_v exp((1 - r^2/R^2)/2) (-(y - y0), x - x0) / R,
+    T = 1 - U_v^2 / (4 cs^2) exp(1 - r^2/R^2), rho = T (isentropic for cp/cv = 2).
+    """
+    X, Y = grid(nx, ny)
+    x0 = center[0]
+    y0 = (ny - 1) / 2.0 if center[1] is None else center[1]
+    dx, dy = X - x0, Y - y0
+    g = np.exp(1.0 - (dx ** 2 + dy ** 2) / radius ** 2)
+    amp = strength * np.sqrt(g) / radius
+    ux = mach * cs - amp * dy
+    uy = amp * dx
+    T = 1.0 - strength ** 2 / (4.0 * cs * cs) * g
+    return T.copy(), ux, uy, T
+
+
+def random_temperature(nx, ny, std=1e-4, seed=2307):
+    """rho = 1, u = 0, T = 1 + std N(0, 1) per node (numpy default_rng, PCG64)."""
+    rng = np.random.default_rng(seed)
+    T = 1.0 + std * rng.standard_normal((ny, nx))
+    z = np.zeros_like(T)
+    return np.ones_like(T), z.copy(), z.copy(), T
+
+
+def shear_layer(nx, ny, u0=0.1, thickness=10.0, noise=1e-3, seed=16766):
+    """u_x = u0 tanh((y - ny/2) / thickness) + noise U(-1, 1), u_y = noise U(-1, 1), rho = T = 1.
+
+    Returns the fields and the unperturbed inlet profile [ny][4] = (rho, u_x, u_y, T) at x = 0.
+    """
+    rng = np.random.default_rng(seed)
+    X, Y = grid(nx, ny)
+    base = u0 * np.tanh((Y - ny / 2.0) / thickness)
+    ux = base + noise * rng.uniform(-1.0, 1.0, (ny, nx))
+    uy = noise * rng.uniform(-1.0, 1.0, (ny, nx))
+    one = np.ones((ny, nx))
+    prof = np.zeros((ny, 4))
+    prof[:, 0] = 1.0
+    prof[:, 1] = base[:, 0]
+    prof[:, 3] = 1.0
+    return (one.copy(), ux, uy, one.copy()), prof
+
+
+def uniform_flow(nx, ny, ux=0.0, uy=0.0, rho=1.0, T=1.0):
+    one = np.ones((ny, nx))
+    return rho * one, ux * one, uy * one, T * one

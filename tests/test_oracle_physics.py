@@ -1,0 +1,286 @@
+"""Pins of the oracle's full solver against closed forms, invariants and the paper's claims."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2307_16766_amd import workloads as W
+
+CS2_37 = O.lattice(37)[0]
+TAU_37 = 0.5 + W.NU_D2Q37 / CS2_37   # nu = (tau - 1/2) cs^2 = 0.1 (Sec. 2, Sec. 4)
+
+BC_TYPES = ["lodi", "lodi_relax", "cbc", "cbc_relax", "zg"]
+
+
+def _smooth_random(nx, ny, seed, amp):
+    rng = np.random.default_rng(seed)
+    X, Y = W.grid(nx, ny)
+    out = np.zeros((ny, nx))
+    for _ in range(4):
+        kx, ky = rng.integers(1, 3, 2)
+        out += amp * rng.uniform(-1, 1) * np.sin(2 * np.pi * (kx * X / nx + ky * Y / ny) + rng.uniform(0, 6))
+    return out
+
+
+@pytest.mark.parametrize("stencil", [9, 37])
+def test_periodic_conservation(stencil):
+    # BGK + periodic streaming conserve mass, momentum (and energy for D2Q37) globally
+    nx, ny = 24, 20
+    tau = TAU_37 if stencil == 37 else 0.6
+    o = O.Oracle(stencil, nx, ny, tau, ["periodic"] * 4)
+    rho = 1 + _smooth_random(nx, ny, 1, 0.02)
+    ux, uy = _smooth_random(nx, ny, 2, 0.05), _smooth_random(nx, ny, 3, 0.05)
+    T = 1 + (_smooth_random(nx, ny, 4, 0.02) if stencil == 37 else np.zeros((ny, nx)))
+    o.init(rho, ux, uy, T)
+    d0 = o.diag()
+    o.step(200)
+    d1 = o.diag()
+    assert abs(d1[0] - d0[0]) < 1e-13 * d0[0]
+    assert abs(d1[1] - d0[1]) < 1e-13 * d0[0]
+    assert abs(d1[2] - d0[2]) < 1e-13 * d0[0]
+    if stencil == 37:
+        assert abs(d1[3] - d0[3]) < 1e-13 * d0[3]
+
+
+@pytest.mark.parametrize("bcs", [
+    ["lodi", "lodi_relax", "periodic", "periodic"],
+    ["cbc", "cbc_relax", "periodic", "periodic"],
+    ["lodi_relax"] * 4, ["cbc_relax"] * 4, ["lodi"] * 4, ["cbc"] * 4, ["zg"] * 4,
+    ["dirichlet", "lodi_relax", "periodic", "periodic"],
+])
+def test_uniform_flow_stays_uniform(bcs):
+    nx, ny = 30, 24
+    u0 = 0.1 * math.sqrt(CS2_37)
+    o = O.Oracle(37, nx, ny, TAU_37, bcs)
+    o.set_relax(-1, sigma=0.25, alpha=0.1, mach=0.1)
+    o.init(*W.uniform_flow(nx, ny, ux=u0))
+    o.step(100)
+    r, ux, uy, T = o.macro()
+    assert np.abs(r - 1).max() < 1e-13
+    assert np.abs(ux - u0).max() < 1e-13
+    assert np.abs(uy).max() < 1e-13
+    assert np.abs(T - 1).max() < 1e-13
+
+
+def test_d2q9_uniform_flow_lodi():
+    cs = math.sqrt(1 / 3)
+    o = O.Oracle(9, 24, 16, 0.6, ["lodi_relax", "lodi_relax", "lodi", "lodi"])
+    o.set_relax(-1, sigma=0.25, alpha=0.1, mach=0.1)
+    o.init(*W.uniform_flow(24, 16, ux=0.1 * cs, uy=0.02))
+    o.step(100)
+    r, ux, uy, T = o.macro()
+    assert np.abs(r - 1).max() < 1e-13 and np.abs(ux - 0.1 * cs).max() < 1e-13 and np.abs(uy - 0.02).max() < 1e-13
+
+
+def _peak(profile, lo, hi):
+    i = lo + int(np.argmax(profile[lo:hi]))
+    a, b, c = profile[i - 1], profile[i], profile[i + 1]
+    return i + 0.5 * (a - c) / (a - 2 * b + c)
+
+
+@pytest.mark.parametrize("stencil", [9, 37])
+def test_sound_speed(stencil):
+    # isothermal cs (D2Q9) and adiabatic sqrt(gamma cs^2 T), gamma = c_p / c_v = 2 (D2Q37,
+    # Sec. 2 and the eigenvalues of Sec. 3.1): a planar pulse splits into halves at that speed
+    nx, ny, t = 320, 4, 80
+    tau = TAU_37 if stencil == 37 else 0.6
+    cs2 = O.lattice(stencil)[0]
+    c = math.sqrt(2 * cs2) if stencil == 37 else math.sqrt(cs2)
+    X, _ = W.grid(nx, ny)
+    x0 = 100.0
+    # right-moving simple wave: d rho = rho0 d u / c, plus the matching temperature for D2Q37
+    amp = 1e-4
+    g = amp * np.exp(-((X - x0) ** 2) / (2 * 6.0 ** 2))
+    rho = 1 + g
+    ux = c * g
+    T = 1 + (g if stencil == 37 else 0)   # adiabatic: dT/T = (gamma - 1) d rho / rho
+    o = O.Oracle(stencil, nx, ny, tau, ["periodic"] * 4)
+    o.init(rho, ux, np.zeros_like(g), T)
+    o.step(t)
+    r = o.macro()[0][1]
+    xp = _peak(r - 1, int(x0 + 0.5 * c * t), int(x0 + 1.5 * c * t))
+    assert abs((xp - x0) / t - c) < 0.005 * c
+
+
+@pytest.mark.parametrize("stencil,mode", [(9, "shear"), (37, "shear"), (37, "entropy")])
+def test_mode_decay(stencil, mode):
+    # shear mode decays as exp(-nu k^2 t), entropy mode as exp(-alpha k^2 t), nu = alpha =
+    # (tau - 1/2) cs^2 (Sec. 2, Pr = 1)
+    nx, ny = 96, 4
+    tau = TAU_37 if stencil == 37 else 0.6
+    cs2 = O.lattice(stencil)[0]
+    nu = (tau - 0.5) * cs2
+    k = 2 * math.pi / nx
+    X, _ = W.grid(nx, ny)
+    A = 1e-4
+    o = O.Oracle(stencil, nx, ny, tau, ["periodic"] * 4)
+    if mode == "shear":
+        o.init(np.ones_like(X), np.zeros_like(X), A * np.sin(k * X), np.ones_like(X))
+    else:
+        Tw = 1 + A * np.sin(k * X)
+        o.init(1 / Tw, np.zeros_like(X), np.zeros_like(X), Tw)
+
+    def amp():
+        r, ux, uy, T = o.macro()
+        z = uy[1] if mode == "shear" else T[1] - T[1].mean()
+        return abs(np.sum(z * np.sin(k * X[1])) * 2 / nx)
+
+    # least-squares rate over several acoustic periods (the start-up transient of an equilibrium
+    # initialisation leaves a small acoustic beat on the entropy mode)
+    ts, logs = [], []
+    o.step(50)
+    for n in range(201):
+        ts.append(50 + 5 * n)
+        logs.append(math.log(amp()))
+        o.step(5)
+    rate = -np.polyfit(ts, logs, 1)[0]
+    assert abs(rate / (nu * k * k) - 1) < 0.01
+
+
+@pytest.mark.parametrize("bc", BC_TYPES)
+def test_d4_symmetry(bc):
+    # a centred pulse with the same boundary on all four sides keeps the square's symmetry,
+    # which exercises every side frame and all four corners
+    n = 36
+    o = O.Oracle(37, n, n, TAU_37, [bc] * 4)
+    o.set_relax(-1, sigma=0.25, alpha=0.1, mach=0.05)
+    o.init(*W.temperature_pulse(n, n, amp=1e-3, width=4.0))
+    o.step(50)
+    r, ux, uy, T = o.macro()
+    assert np.abs(r - r.T).max() < 1e-13
+    assert np.abs(r - r[::-1, :]).max() < 1e-13
+    assert np.abs(r - r[:, ::-1]).max() < 1e-13
+    assert np.abs(ux - uy.T).max() < 1e-13
+    assert np.abs(ux + ux[:, ::-1]).max() < 1e-13
+    assert np.abs(T - T.T).max() < 1e-13
+
+
+def test_reflection_lodi_vs_zero_gradient():
+    # Sec. 4.3: zero-gradient reflects about 4 % of an impinging wave at normal incidence, the
+    # characteristic boundary about an order of magnitude less
+    nx, ny = 240, 6
+    def reflected(bc):
+        o = O.Oracle(37, nx, ny, TAU_37, [bc, bc, "periodic", "periodic"])
+        o.init(*W.planar_temperature_pulse(nx, ny, amp=1e-3, width=10.0))
+        o.step(40)
+        inc = np.abs(o.macro()[1][:, 60:180]).max()   # both halves still inside the window
+        o.step(90)
+        ref = 0.0
+        for _ in range(5):   # the reflected fronts cross the window x in [60, 180) at t = 130..170
+            ref = max(ref, np.abs(o.macro()[1][:, 60:180]).max())
+            o.step(10)
+        return ref / inc
+    zg = reflected("zg")
+    lodi = reflected("lodi")
+    cbc = reflected("cbc")
+    assert 0.03 < zg < 0.07
+    assert lodi < zg / 4 and cbc < zg / 4
+
+
+@pytest.mark.parametrize("mode", ["shear", "entropy"])
+def test_viscous_terms_match_laplacian(mode):
+    # eq. LaplaceU / LaplaceT: the mesoscopic viscous terms equal nu lap(u_t) and
+    # (nu c_p / (Pr cs^2)) lap(T~) = 2 nu lap(T) of a resolved wave (FD error O(k^2))
+    nx, ny = 64, 8
+    k = 2 * math.pi / nx
+    nu = W.NU_D2Q37
+    X, _ = W.grid(nx, ny)
+    A = 1e-3
+    o = O.Oracle(37, nx, ny, TAU_37, ["periodic"] * 4)
+    if mode == "shear":
+        o.init(np.ones_like(X), np.zeros_like(X), A * np.sin(k * X), np.ones_like(X))
+    else:
+        Tw = 1 + A * np.sin(k * X)
+        o.init(1 / Tw, np.zeros_like(X), np.zeros_like(X), Tw)
+    o.step(20)
+    r, ux, uy, T = o.macro()
+    x = 20
+    for sn in (1, -1):
+        V = o.visc_probe(0, sn, x, 3)
+        if mode == "shear":
+            ref = -nu * k * k * uy[3, x]
+            assert abs(V[2] / ref - 1) < 0.01
+        else:
+            ref = -2 * nu * k * k * (T[3, x] - T[3].mean())
+            assert abs(V[3] / ref - 1) < 0.015
+
+
+@pytest.mark.parametrize("flow", ["rest", "diagonal"])
+def test_tangent_mode_matches_finite_differences(flow):
+    # the dual-number instantiation reproduces central differences of the plain solver.  At rest
+    # the wave directions of the entropy/shear waves flip with the sign of u_n, which leaves kinks
+    # (not jumps) in the loss; with a diagonal background flow no direction changes.
+    nx, ny, steps = 22, 20, 30
+    bc = ["lodi_relax"] * 4
+    rho, ux, uy, T = W.random_temperature(nx, ny, std=1e-3, seed=9)
+    if flow == "diagonal":
+        ux, uy = ux + 0.02, uy + 0.015
+    base = np.array([0.25, 0.1, 1.0, 1.0, 0.05, 0.0])
+    relax = np.tile(base, (4, 1))
+    rng = np.random.default_rng(4)
+    dT = np.zeros((3, ny, nx))
+    dT[2] = rng.standard_normal((ny, nx))
+    loss, dl = O.tangent_run(37, nx, ny, TAU_37, bc, relax, [1, 0, 0], [0, 1, 0], (rho, ux, uy, T), dT, steps)
+
+    def run(sig, al, TT):
+        o = O.Oracle(37, nx, ny, TAU_37, bc)
+        o.set_relax(-1, sigma=sig, alpha=al, mach=0.05)
+        o.init(rho, ux, uy, TT)
+        o.step(steps)
+        return o.loss()
+
+    assert abs(run(0.25, 0.1, T) - loss) < 1e-15 * max(1.0, loss) + 1e-20
+    h = 1e-5
+    fd = [(run(0.25 + h, 0.1, T) - run(0.25 - h, 0.1, T)) / (2 * h),
+          (run(0.25, 0.1 + h, T) - run(0.25, 0.1 - h, T)) / (2 * h),
+          (run(0.25, 0.1, T + h * dT[2]) - run(0.25, 0.1, T - h * dT[2])) / (2 * h)]
+    tol = [1e-6, 1e-6, 1e-3 if flow == "rest" else 1e-6]
+    for a, b, t in zip(dl, fd, tol):
+        assert abs(a - b) <= t * abs(b), (dl, fd)
+
+
+def test_d2q9_reflection_and_mirror_symmetry():
+    # isothermal characteristic system (D2Q9, Sec. 4.4): a planar density pulse leaves through
+    # LODI-RELAX sides with far less reflection than zero-gradient; the C1-type pulse setup is
+    # mirror symmetric in x and y
+    nx, ny = 200, 4
+    def run(bc):
+        o = O.Oracle(9, nx, ny, 0.6, [bc, bc, "periodic", "periodic"])
+        o.set_relax(-1, sigma=0.25, alpha=0.0, mach=0.0)
+        X, _ = W.grid(nx, ny)
+        o.init(1 + 1e-3 * np.exp(-((X - 99.5) ** 2) / (2 * 8.0 ** 2)), 0, 0, 1)
+        o.step(40)
+        inc = np.abs(o.macro()[1][:, 50:150]).max()
+        o.step(170)   # fronts reflected at t ~ 175 re-enter the window around t ~ 200..260
+        ref = 0.0
+        for _ in range(6):
+            ref = max(ref, np.abs(o.macro()[1][:, 50:150]).max())
+            o.step(10)
+        return ref / inc
+    zg, lodi = run("zg"), run("lodi_relax")
+    assert zg > 0.01 and lodi < zg / 4
+    o = O.Oracle(9, 64, 32, 0.6, ["lodi_relax", "lodi_relax", "periodic", "periodic"])
+    o.set_relax(-1, sigma=0.25)
+    o.init(*W.gaussian_density_pulse(64, 32, amp=1e-3, width=4.0))
+    o.step(80)
+    r, ux, uy, _ = o.macro()
+    assert np.abs(r - r[:, ::-1]).max() < 1e-14 and np.abs(r - r[::-1, :]).max() < 1e-14
+    assert np.abs(ux + ux[:, ::-1]).max() < 1e-14
+
+
+@pytest.mark.parametrize("stencil", [9, 37])
+def test_pressure_relaxation_direction(stencil):
+    # eq. LODI-Relax with Z = P: a uniform state at pressure P != P_inf drifts toward P_inf;
+    # without relaxation (LODI) the uniform state is kept
+    nx, ny = 24, 8
+    tau = TAU_37 if stencil == 37 else 0.6
+    res = {}
+    for bc in ("lodi", "lodi_relax"):
+        o = O.Oracle(stencil, nx, ny, tau, [bc, bc, "periodic", "periodic"])
+        o.set_relax(-1, sigma=0.5, rho_inf=1.0, T_inf=1.0)
+        o.init(1.001, 0, 0, 1)
+        o.step(300)
+        res[bc] = o.macro()[0].mean() - 1.0
+    assert abs(res["lodi"] - 1e-3) < 1e-12
+    assert 0 < res["lodi_relax"] < 0.8e-3
