@@ -1,0 +1,154 @@
+/*
+ * lbm.h -- C ABI of liblbm_hip.so: thermal lattice Boltzmann method with characteristic
+ * (LODI / CBC) non-reflecting boundary conditions on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Klass, Gabbana & Bartel, "Characteristic Boundary Condition for Thermal Lattice
+ * Boltzmann Methods" (arXiv 2307.16766).
+ *   - bulk: BGK lattice Boltzmann equation (Sec. 2, eq. lbe and eq. bgk) on the single-speed
+ *     D2Q9 stencil (isothermal, 2nd-order equilibrium) or the multi-speed D2Q37 stencil
+ *     (Appendix B, Tab. d2q37; 4th-order Hermite equilibrium, eq. feq-4);
+ *   - boundary: layerwise characteristic analysis on the M outer layers (Sec. 3.3), wave
+ *     amplitudes of eq. thermal_WAV, incoming amplitudes by one of the four schemes of
+ *     Tab. CBCs (eq. PNR, LODI-Relax, CBC-PNR, CBC-Relax), RK4 in time, equilibrium Dirichlet
+ *     reconstruction of all populations on the layers (Sec. 3.3 "Mesoscopic BC").
+ *
+ * Conventions
+ *   - Grid: nx * ny nodes, row-major, x fastest.  Side order: x = 0, x = nx-1, y = 0, y = ny-1.
+ *   - Units: lattice units (dx = dt = 1).  T is dimensionless with reference T = 1; the lattice
+ *     temperature is cs^2 T and the pressure P = rho cs^2 T.  D2Q9 is isothermal (T = 1).
+ *   - Memory: every pointer argument named d_* is device memory on the current HIP device.
+ *     The caller owns all device memory (workspace, fields, checkpoint buffers) and the HIP
+ *     stream; the library borrows them until lbm_destroy.  The library owns only its host-side
+ *     context and one auxiliary HIP stream (default priority) plus two events.
+ *   - Asynchrony: every call that takes a context enqueues work on the caller's stream and
+ *     returns without synchronising, except lbm_diagnostics, which synchronises.
+ *   - Errors: functions return LBM_OK (0) or a negative code; nothing throws across the ABI.
+ *     lbm_last_error(ctx) gives a message for the last failure on that context
+ *     (lbm_last_error(NULL) for failures before a context exists).
+ *   - Macroscopic input and output are FP64 [ny][nx] arrays whatever the storage precision.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum lbm_status {
+    LBM_OK = 0,
+    LBM_E_ARG = -1,          /* invalid argument or configuration */
+    LBM_E_HIP = -2,          /* a HIP runtime call failed */
+    LBM_E_NONFINITE = -3,    /* diagnostics found a non-finite population */
+    LBM_E_STATE = -4,        /* call not valid in the context's current state */
+    LBM_E_UNSUPPORTED = -5   /* valid but not supported combination */
+};
+
+enum lbm_stencil { LBM_D2Q9 = 9, LBM_D2Q37 = 37 };
+
+/* Storage precision of the populations.  FP64 stores f - w_i in double.  FP32DEV stores the
+ * deviation f - w_i from the lattice weight in float and runs the bulk update in float; the
+ * boundary solve, the macroscopic output and the diagnostics are FP64 in both modes. */
+enum lbm_precision { LBM_FP64 = 0, LBM_FP32DEV = 1 };
+
+/* Boundary types (Tab. CBCs, eq. zg-bc).  Periodic sides must come in pairs (x0 with x1,
+ * y0 with y1).  Corners (both axes non-periodic) are supported between characteristic sides
+ * (LODI..CBC_RELAX) and between zero-gradient sides. */
+enum lbm_bc {
+    LBM_BC_PERIODIC = 0,
+    LBM_BC_LODI = 1,        /* eq. thermal_LODI_macro_evo with eq. PNR */
+    LBM_BC_LODI_RELAX = 2,  /* eq. thermal_LODI_macro_evo with eq. LODI-Relax */
+    LBM_BC_CBC = 3,         /* eq. thermal_CBC_macro_evo with eq. CBC-PNR (D2Q37 only) */
+    LBM_BC_CBC_RELAX = 4,   /* eq. thermal_CBC_macro_evo with eq. CBC-Relax (D2Q37 only) */
+    LBM_BC_ZG = 5,          /* zero-gradient copy of the adjacent bulk node, eq. zg-bc */
+    LBM_BC_DIRICHLET = 6    /* equilibrium populations of a fixed profile (inlet) */
+};
+
+typedef struct lbm_config {
+    int stencil;     /* LBM_D2Q9 or LBM_D2Q37 */
+    int precision;   /* lbm_precision */
+    int nx, ny;      /* nodes; non-periodic axes need >= 2M+3 nodes, periodic ones >= M+1 */
+    double tau;      /* BGK relaxation time, > 1/2; nu = (tau - 1/2) cs^2 (Sec. 2) */
+    int bc[4];       /* lbm_bc for sides x0, x1, y0, y1 */
+} lbm_config;
+
+/* Relaxation parameters of one characteristic side (eq. LODI-Relax / eq. CBC-Relax).  The
+ * incoming acoustic amplitude receives  -alpha * T_x,i + K (P - P_inf) / (4 rho cs^2)
+ * (D2Q37) or  -alpha * T_x,i + K (P - P_inf)  (D2Q9), with
+ * K = sigma (1 - mach^2) c_inf / length, c_inf = sqrt(2 cs^2 T_inf) (D2Q37) or cs (D2Q9),
+ * P_inf = rho_inf cs^2 T_inf.  length <= 0 selects the domain extent normal to the side.
+ * Sides without relaxation (LODI, CBC) ignore these values.  Defaults: all zero except
+ * rho_inf = T_inf = 1. */
+typedef struct lbm_relax {
+    double sigma;
+    double alpha;
+    double rho_inf;
+    double T_inf;
+    double mach;
+    double length;
+} lbm_relax;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Device workspace the caller must provide to lbm_init for this configuration (bytes).
+ * Returns 0 for an invalid configuration. */
+size_t lbm_workspace_bytes(const lbm_config* cfg);
+
+/* Create a context and set the initial state f = f^eq(rho0, u0, T0) at every node (Sec. 2,
+ * "Initialize"); boundary states start from the same fields.  d_workspace: device buffer of
+ * at least lbm_workspace_bytes(cfg) bytes, 256-byte aligned.  hip_stream: hipStream_t (NULL
+ * for the null stream).  d_rho0, d_ux0, d_uy0, d_T0: device FP64 [ny][nx]; d_T0 may be NULL
+ * for D2Q9.  On success *out receives the context. */
+int lbm_init(const lbm_config* cfg, void* d_workspace, size_t workspace_bytes, void* hip_stream,
+             const double* d_rho0, const double* d_ux0, const double* d_uy0, const double* d_T0,
+             lbm_ctx** out);
+
+/* Set the relaxation parameters of side 0..3, or of every side with side = -1.  Takes effect
+ * from the next lbm_step. */
+int lbm_cbc_params(lbm_ctx* ctx, int side, const lbm_relax* p);
+
+/* Fixed profile of a Dirichlet side: d_U is device FP64 [len][4] = (rho, u_x, u_y, T) per row
+ * along the side (len = ny for x-sides, nx for y-sides).  Default: the initial fields on the
+ * first boundary layer.  Writes the equilibrium populations of every layer immediately. */
+int lbm_dirichlet_profile(lbm_ctx* ctx, int side, const double* d_U);
+
+/* Advance nsteps time steps: fused stream + collide on the bulk, characteristic boundary solve
+ * and reconstruction on the boundary layers (Sec. 3.3, Fig. flowchart-cbc-lbm). */
+int lbm_step(lbm_ctx* ctx, int nsteps);
+
+/* Macroscopic fields (eq. macro) of the current state at every node, FP64 [ny][nx] device
+ * arrays; d_T may be NULL. */
+int lbm_macroscopic(lbm_ctx* ctx, double* d_rho, double* d_ux, double* d_uy, double* d_T);
+
+/* Boundary solver state of a characteristic side: device FP64 [M][len][4], layer j = 1..M
+ * (x_{b,j}, j = M outermost) then row, (rho, u_x, u_y, T). */
+int lbm_boundary_state(lbm_ctx* ctx, int side, double* d_out);
+
+/* Diagnostics of the current state (synchronises the stream).  h_out (host) receives
+ * [0] total mass, [1] x momentum, [2] y momentum, [3] energy 1/2 sum f |c|^2,
+ * [4] loss = sum over bulk nodes of (P - cs^2)^2, [5] max |u|, [6] number of non-finite
+ * populations, [7] steps done.  Returns LBM_E_NONFINITE when [6] > 0. */
+int lbm_diagnostics(lbm_ctx* ctx, double* h_out);
+
+/* Checkpoint of the complete state (populations and boundary solver state): device buffer of
+ * lbm_state_bytes(ctx) bytes.  Save then restore reproduces the run bit for bit. */
+size_t lbm_state_bytes(const lbm_ctx* ctx);
+int lbm_save(lbm_ctx* ctx, void* d_buf);
+int lbm_restore(lbm_ctx* ctx, const void* d_buf);
+
+/* Number of steps taken since lbm_init (or the restored checkpoint's count). */
+long lbm_steps_done(const lbm_ctx* ctx);
+
+/* Lattice constants used by the library (host pointers, arrays of q entries, library order).
+ * Returns q, or a negative code for an unknown stencil. */
+int lbm_lattice_info(int stencil, int* M, double* cs2, double* w, int* cx, int* cy);
+
+const char* lbm_last_error(const lbm_ctx* ctx);
+void lbm_destroy(lbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,728 @@
+// kernels.h -- HIP kernels of the thermal LBM with characteristic boundaries (gfx950).
+//
+// Data layout in HBM (one context):
+//   f[2]   : two population buffers, structure of arrays f[i][y][x] (plane stride P elements,
+//            a multiple of 64), storing deviations f_i - w_i in T = double or float.
+//   region : two parity copies of the boundary solver state (FP64): per characteristic side
+//            U_b[M][len][4], the bulk strip U[MS][len][4] at x_f (and x_f - 1 for M = 1), the
+//            viscous moments [3][len][6] at x_f, x_f-1, x_f-2; per corner U_c[4] and the two
+//            inward diagonal bulk nodes [2][4].  Parity p holds time level n with n % 2 = p.
+// One time step n -> n+1 is two kernels that run concurrently on two streams:
+//   k_bulk      : pull-stream + moments + equilibrium + BGK for every bulk node, A -> B;
+//   k_boundary  : one work-group per chunk of rows of a side; re-pulls the strip from A,
+//                 integrates the characteristic system with RK4 in LDS and writes the
+//                 equilibrium populations of the M boundary layers of B.
+// Both only read A and write disjoint nodes of B.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lattice.h"
+
+namespace lbm {
+
+enum { BC_PERIODIC = 0, BC_LODI = 1, BC_LODI_RELAX = 2, BC_CBC = 3, BC_CBC_RELAX = 4, BC_ZG = 5, BC_DIRICHLET = 6 };
+enum { KIND_NONE = 0, KIND_CHAR = 1, KIND_ZG = 2, KIND_DIRICHLET = 3 };
+
+struct SideDev {
+    int kind, scheme;
+    int nax, sn, Nn, Nt, r0, len, xf, tper;
+    int blk0, nblk, rows;        // work-groups of this side in k_boundary, rows per work-group
+    int corner_lo, corner_hi;    // corners at row -1 / row len (non-periodic tangent), else -1
+    int owns_corners;            // x-sides write the corner blocks
+    double K, alpha, Pinf;       // relaxation (eq. LODI-Relax / CBC-Relax)
+    unsigned long long off_ub, off_strip, off_vis;   // byte offsets inside one parity region
+};
+
+struct CornerDev {
+    int active, zg, relax;
+    int xc, yc, vx, vy;          // innermost corner node and inward diagonal step
+    int x0, y0, sxn, syn;        // corner block: x0 + sxn*j, y0 + syn*j, j = 0..M-1
+    double K, Pinf, ndx, ndy;    // relaxation of the x-side, outward diagonal normal
+    unsigned long long off_cu, off_cd;
+};
+
+struct BndArgs {
+    int nx, ny, nbulk_x0, nbulk_x1, nbulk_y0, nbulk_y1, xper, yper;
+    unsigned long long P;
+    double omega, tau;
+    char* reg_cur;    // parity region of time level n
+    char* reg_next;   // parity region of time level n+1
+    SideDev s[4];
+    CornerDev c[4];
+};
+
+__device__ __forceinline__ int wrapi(int v, int n) {
+    v = v < 0 ? v + n : v;
+    return v >= n ? v - n : v;
+}
+
+// node of side s at outward index k (k = 0: x_f, k = j: layer x_{b,j}) and physical row r
+__device__ __forceinline__ void side_node(const SideDev& s, int k, int r, int& x, int& y) {
+    const int nc = s.xf + s.sn * k;
+    const int tc = s.r0 + r;
+    if (s.nax == 0) { x = nc; y = tc; } else { x = tc; y = nc; }
+}
+
+// ------------------------------------------------------------------ pull of one node (FP64)
+template <int Q, typename T>
+__device__ __forceinline__ void pull_node(const T* __restrict__ A, const BndArgs& a, int x, int y, double* d) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        int xs = x - cx<Q>(i), ys = y - cy<Q>(i);
+        if (a.xper) xs = wrapi(xs, a.nx);
+        if (a.yper) ys = wrapi(ys, a.ny);
+        d[i] = (double)A[(unsigned long long)i * a.P + (unsigned long long)ys * a.nx + xs];
+    }
+}
+
+// ================================================================== bulk: fused stream + collide
+struct BulkArgs {
+    int nx, ny, x0, x1, y0, y1;   // bulk node range (inclusive)
+    unsigned long long P;
+    float omega_f;
+    double omega_d;
+};
+
+template <int Q, typename T, bool PX, bool PY>
+__global__ __launch_bounds__(256) void k_bulk(const T* __restrict__ A, T* __restrict__ B, BulkArgs g) {
+    const int x = g.x0 + (int)(blockIdx.x * 256 + threadIdx.x);
+    const int y = g.y0 + (int)blockIdx.y;
+    if (x > g.x1) return;
+    T d[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        int xs = x - cx<Q>(i);
+        int ys = y - cy<Q>(i);
+        if (PX) xs = wrapi(xs, g.nx);
+        if (PY) ys = wrapi(ys, g.ny);
+        const T* Ai = A + (unsigned long long)i * g.P + (unsigned long long)ys * g.nx;
+        d[i] = __builtin_nontemporal_load(Ai + xs);
+    }
+    const T omega = sizeof(T) == 4 ? (T)g.omega_f : (T)g.omega_d;
+    collide_dev<Q, T>(d, omega);
+    T* Bo = B + (unsigned long long)y * g.nx + x;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(d[i], Bo + (unsigned long long)i * g.P);
+}
+
+// ================================================================== initialisation
+template <int Q, typename T>
+__global__ __launch_bounds__(256) void k_init_fields(const double* __restrict__ rho, const double* __restrict__ ux,
+                                                     const double* __restrict__ uy, const double* __restrict__ Tf,
+                                                     T* __restrict__ A, T* __restrict__ B, int n, unsigned long long P) {
+    const int id = blockIdx.x * 256 + threadIdx.x;
+    if (id >= n) return;
+    double fe[Q];
+    const double th = (Lat<Q>::thermal && Tf) ? Tf[id] - 1.0 : 0.0;
+    feq_dev<Q, double>(rho[id] - 1.0, ux[id], uy[id], th, fe);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        A[(unsigned long long)i * P + id] = (T)fe[i];
+        B[(unsigned long long)i * P + id] = (T)fe[i];
+    }
+}
+
+// macroscopic field value (rho, ux, uy, T) of node (x, y) from the initial arrays
+__device__ __forceinline__ void field_at(const double* rho, const double* ux, const double* uy, const double* Tf,
+                                         int nx, int x, int y, double* u4) {
+    const int id = y * nx + x;
+    u4[0] = rho[id]; u4[1] = ux[id]; u4[2] = uy[id]; u4[3] = Tf ? Tf[id] : 1.0;
+}
+
+// boundary solver state at time 0 from the initial fields; both parities' viscous moments 0
+template <int Q>
+__global__ __launch_bounds__(256) void k_init_boundary(BndArgs a, const double* __restrict__ rho, const double* __restrict__ ux,
+                                                       const double* __restrict__ uy, const double* __restrict__ Tf,
+                                                       double* __restrict__ inlet0, double* __restrict__ inlet1,
+                                                       double* __restrict__ inlet2, double* __restrict__ inlet3) {
+    constexpr int M = Lat<Q>::M, MS = (M == 1) ? 2 : 1;
+    const int s = blockIdx.y;
+    const SideDev& sd = a.s[s];
+    const bool thermal = Lat<Q>::thermal;
+    const double* Tuse = thermal ? Tf : nullptr;
+    for (int r = blockIdx.x * 256 + threadIdx.x; r < sd.len; r += gridDim.x * 256) {
+        if (sd.kind == KIND_CHAR) {
+            double* ub = (double*)(a.reg_cur + sd.off_ub);
+            double* st = (double*)(a.reg_cur + sd.off_strip);
+            for (int j = 1; j <= M; ++j) {
+                int x, y; side_node(sd, j, r, x, y);
+                field_at(rho, ux, uy, Tuse, a.nx, x, y, &ub[((size_t)(j - 1) * sd.len + r) * 4]);
+            }
+            for (int k = 0; k < MS; ++k) {
+                int x, y; side_node(sd, -k, r, x, y);
+                field_at(rho, ux, uy, Tuse, a.nx, x, y, &st[((size_t)k * sd.len + r) * 4]);
+            }
+            if (sd.scheme == BC_CBC || sd.scheme == BC_CBC_RELAX) {
+                // equilibrium initial state: no stress, no heat flux; density of the fields
+                double* v0 = (double*)(a.reg_cur + sd.off_vis);
+                double* v1 = (double*)(a.reg_next + sd.off_vis);
+                for (int k = 0; k < 3; ++k) {
+                    int x, y; side_node(sd, -k, r, x, y);
+                    const double rk = rho[y * a.nx + x];
+                    for (int c = 0; c < 6; ++c) {
+                        v0[((size_t)k * sd.len + r) * 6 + c] = c == 0 ? rk : 0.0;
+                        v1[((size_t)k * sd.len + r) * 6 + c] = c == 0 ? rk : 0.0;
+                    }
+                }
+            }
+        } else if (sd.kind == KIND_DIRICHLET) {
+            double* inl = s == 0 ? inlet0 : s == 1 ? inlet1 : s == 2 ? inlet2 : inlet3;
+            int x, y; side_node(sd, 1, r, x, y);
+            field_at(rho, ux, uy, Tuse, a.nx, x, y, &inl[(size_t)r * 4]);
+        }
+    }
+    if (s == 0 && blockIdx.x == 0 && threadIdx.x < 4) {
+        const CornerDev& c = a.c[threadIdx.x];
+        if (c.active && !c.zg) {
+            double* cu = (double*)(a.reg_cur + c.off_cu);
+            double* cd = (double*)(a.reg_cur + c.off_cd);
+            field_at(rho, ux, uy, Tuse, a.nx, c.xc, c.yc, cu);
+            field_at(rho, ux, uy, Tuse, a.nx, c.xc + c.vx, c.yc + c.vy, cd);
+            field_at(rho, ux, uy, Tuse, a.nx, c.xc + 2 * c.vx, c.yc + 2 * c.vy, cd + 4);
+        }
+    }
+}
+
+// equilibrium populations of a fixed profile on every layer of a Dirichlet side, both buffers
+template <int Q, typename T>
+__global__ __launch_bounds__(256) void k_dirichlet(BndArgs a, int s, const double* __restrict__ prof, T* __restrict__ A,
+                                                   T* __restrict__ B) {
+    constexpr int M = Lat<Q>::M;
+    const SideDev& sd = a.s[s];
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= sd.len * M) return;
+    const int r = t / M, j = 1 + t % M;
+    int x, y; side_node(sd, j, r, x, y);
+    const double* u = prof + (size_t)r * 4;
+    double fe[Q];
+    feq_dev<Q, double>(u[0] - 1.0, u[1], u[2], Lat<Q>::thermal ? u[3] - 1.0 : 0.0, fe);
+    const unsigned long long id = (unsigned long long)y * a.nx + x;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) { A[i * a.P + id] = (T)fe[i]; B[i * a.P + id] = (T)fe[i]; }
+}
+
+// ================================================================== macroscopic output
+template <int Q, typename T>
+__global__ __launch_bounds__(256) void k_macro(const T* __restrict__ A, int n, unsigned long long P, double* __restrict__ rho,
+                                               double* __restrict__ ux, double* __restrict__ uy, double* __restrict__ Tf) {
+    const int id = blockIdx.x * 256 + threadIdx.x;
+    if (id >= n) return;
+    double d[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) d[i] = (double)A[(unsigned long long)i * P + id];
+    double rm1, u, v, th;
+    moments_dev<Q, double>(d, rm1, u, v, th);
+    rho[id] = 1.0 + rm1; ux[id] = u; uy[id] = v;
+    if (Tf) Tf[id] = 1.0 + th;
+}
+
+// ================================================================== diagnostics (two passes)
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// partial[blk][8]: mass, jx, jy, energy, loss, max|u|, non-finite count, 0
+template <int Q, typename T>
+__global__ __launch_bounds__(256) void k_diag_partial(const T* __restrict__ A, int nx, int ny, unsigned long long P,
+                                                      int bx0, int bx1, int by0, int by1, double* __restrict__ partial) {
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    const int n = nx * ny;
+    for (int id = blockIdx.x * 256 + threadIdx.x; id < n; id += gridDim.x * 256) {
+        double d[Q];
+        double bad = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            d[i] = (double)A[(unsigned long long)i * P + id];
+            bad += (isfinite(d[i]) ? 0.0 : 1.0);
+        }
+        double rm1, u, v, th;
+        moments_dev<Q, double>(d, rm1, u, v, th);
+        const double r = 1.0 + rm1;
+        double e = Lat<Q>::cs2;   // 1/2 sum w |c|^2
+#pragma unroll
+        for (int i = 0; i < Q; ++i) e += 0.5 * (double)c2<Q>(i) * d[i];
+        acc[0] += r; acc[1] += r * u; acc[2] += r * v; acc[3] += e;
+        const int x = id % nx, y = id / nx;
+        if (x >= bx0 && x <= bx1 && y >= by0 && y <= by1) {
+            const double p = Lat<Q>::cs2 * (rm1 + th + rm1 * th);   // P - cs^2
+            acc[4] += p * p;
+        }
+        const double um = sqrt(u * u + v * v);
+        acc[5] = (um == um) ? fmax(acc[5], um) : acc[5];
+        acc[6] += bad;
+    }
+    __shared__ double red[4][8];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int k = 0; k < 7; ++k) {
+        const double v = k == 5 ? wave_max(acc[k]) : wave_sum(acc[k]);
+        if (lane == 0) red[wid][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 7) {
+        const int k = threadIdx.x;
+        double v = red[0][k];
+        for (int w = 1; w < 4; ++w) v = (k == 5) ? fmax(v, red[w][k]) : v + red[w][k];
+        partial[blockIdx.x * 8 + k] = v;
+    }
+    if (threadIdx.x == 7) partial[blockIdx.x * 8 + 7] = 0.0;
+}
+
+__global__ __launch_bounds__(64) void k_diag_final(const double* __restrict__ partial, int nblk, double* __restrict__ out) {
+    const int k = threadIdx.x;
+    if (k >= 8) return;
+    double v = 0.0;
+    for (int b = 0; b < nblk; ++b) v = (k == 5) ? fmax(v, partial[b * 8 + k]) : v + partial[b * 8 + k];
+    out[k] = v;
+}
+
+// ================================================================== characteristic boundary
+// Rate dU/dt (side-local (rho, u_n, u_t, T)) of one boundary node: wave amplitudes of
+// eq. thermal_WAV written out with T~ = cs^2 T, incoming amplitudes by scheme (Tab. CBCs), the
+// relaxation acting on the incoming acoustic wave, then -S^-1 Lbar (+ T + V for CBC variants).
+// up / dw: node values at the neighbouring rows (transverse central differences); U0: the
+// node's value at time t, which fixes the wave directions.
+template <bool THERMAL>
+__device__ __forceinline__ void char_rate(const double* U, const double* dn, const double* up, const double* dw,
+                                          const double* V, const double* U0, int scheme, double K, double alpha,
+                                          double Pinf, double* rate) {
+    constexpr double cs2 = THERMAL ? Lat<37>::cs2 : Lat<9>::cs2;
+    constexpr double cs = THERMAL ? Lat<37>::cs : Lat<9>::cs;
+    const bool full = scheme == BC_CBC || scheme == BC_CBC_RELAX;
+    const bool relax = scheme == BC_LODI_RELAX || scheme == BC_CBC_RELAX;
+    const double rho = U[0], u = U[1], v = U[2], T = U[3];
+    const double ir = 1.0 / rho;
+    // transverse terms (eq. NSF-CHAR), central in the row direction
+    const double T1 = -0.5 * (up[0] * up[2] - dw[0] * dw[2]);
+    const double T2 = -v * 0.5 * (up[1] - dw[1]);
+    double T3, T4;
+    if (THERMAL) {
+        T3 = -cs2 * ir * 0.5 * (up[0] * up[3] - dw[0] * dw[3]) - v * 0.5 * (up[2] - dw[2]);
+        T4 = -0.5 * (up[3] * up[2] - dw[3] * dw[2]);
+    } else {
+        T3 = -cs2 * ir * 0.5 * (up[0] - dw[0]) - v * 0.5 * (up[2] - dw[2]);
+        T4 = 0.0;
+    }
+    const double u0 = U0[1];
+    if (THERMAL) {
+        const double s = sqrt(2.0 * cs2 * T);
+        const double s0 = sqrt(2.0 * cs2 * U0[3]);
+        const double a = 0.25 * T * ir, b = s * (0.25 / cs2);
+        const double L1 = u * (-2.0 * a * dn[0] + 0.5 * dn[3]);
+        const double L2 = u * dn[2];
+        const double L3 = (u - s) * (a * dn[0] - b * dn[1] + 0.25 * dn[3]);
+        const double L4 = (u + s) * (a * dn[0] + b * dn[1] + 0.25 * dn[3]);
+        // S T and S V
+        const double ST1 = -2.0 * a * T1 + 0.5 * T4, ST2 = T3;
+        const double ST3 = a * T1 - b * T2 + 0.25 * T4, ST4 = a * T1 + b * T2 + 0.25 * T4;
+        double in1 = 0.0, in2 = 0.0, in3 = 0.0, in4 = 0.0;
+        if (full) {
+            in1 = ST1 + 0.5 * V[3];
+            in2 = ST2 + V[2];
+            in3 = ST3 - b * V[1] + 0.25 * V[3];
+            in4 = ST4 + b * V[1] + 0.25 * V[3];
+        }
+        if (relax) {
+            const double pr = K * (rho * cs2 * T - Pinf) * ir * (0.25 / cs2);
+            in3 += pr - alpha * ST3;
+            in4 += pr - alpha * ST4;
+        }
+        const double B1 = u0 >= 0.0 ? L1 : in1;
+        const double B2 = u0 >= 0.0 ? L2 : in2;
+        const double B3 = u0 - s0 >= 0.0 ? L3 : in3;
+        const double B4 = u0 + s0 >= 0.0 ? L4 : in4;
+        rate[0] = rho / T * (B1 - B3 - B4);
+        rate[1] = 2.0 * cs2 / s * (B3 - B4);
+        rate[2] = -B2;
+        rate[3] = -(B1 + B3 + B4);
+        if (full) {
+            rate[0] += T1;
+            rate[1] += T2 + V[1];
+            rate[2] += T3 + V[2];
+            rate[3] += T4 + V[3];
+        }
+    } else {
+        const double c = cs;
+        const double L0 = u * dn[2];
+        const double Lm = (u - c) * (cs2 * dn[0] - rho * c * dn[1]);
+        const double Lp = (u + c) * (cs2 * dn[0] + rho * c * dn[1]);
+        double inm = 0.0, inp = 0.0;
+        if (relax) {
+            const double pr = K * (cs2 * rho - Pinf);
+            inm = pr - alpha * (cs2 * T1 - rho * c * T2);
+            inp = pr - alpha * (cs2 * T1 + rho * c * T2);
+        }
+        const double B0 = u0 >= 0.0 ? L0 : 0.0;
+        const double Bm = u0 - c >= 0.0 ? Lm : inm;
+        const double Bp = u0 + c >= 0.0 ? Lp : inp;
+        rate[0] = -(Bm + Bp) * (0.5 / cs2);
+        rate[1] = (Bm - Bp) * (0.5 / c) * ir;
+        rate[2] = -B0;
+        rate[3] = 0.0;
+    }
+}
+
+__device__ __forceinline__ void to_local(const SideDev& s, const double* g, double* l) {
+    l[0] = g[0];
+    l[1] = s.sn * g[1 + s.nax];
+    l[2] = g[2 - s.nax];
+    l[3] = g[3];
+}
+__device__ __forceinline__ void rate_to_global(const SideDev& s, const double* l, double* g) {
+    g[0] = l[0];
+    g[1 + s.nax] = s.sn * l[1];
+    g[2 - s.nax] = l[2];
+    g[3] = l[3];
+}
+
+template <int Q>
+__device__ __forceinline__ void moments_u4(const double* d, double* u4) {
+    double rm1, th;
+    moments_dev<Q, double>(d, rm1, u4[1], u4[2], th);
+    u4[0] = 1.0 + rm1;
+    u4[3] = 1.0 + th;
+}
+
+// viscous moments at a node in side-local components (rho, Pi'_nn, Pi'_nt, Pi'_tt, q_n, q_t),
+// Pi' = -(1 - 1/(2 tau)) sum c c (f - f^eq), q = (1 - 1/(2 tau)) 1/2 sum f |c - u|^2 (c - u)
+template <int Q>
+__device__ __forceinline__ void visc_moments(const SideDev& s, const double* d, double tau, double* o6) {
+    double rm1, u, v, th;
+    moments_dev<Q, double>(d, rm1, u, v, th);
+    double fe[Q];
+    feq_dev<Q, double>(rm1, u, v, th, fe);
+    const double fac = 1.0 - 0.5 / tau;
+    double pxx = 0, pxy = 0, pyy = 0, qx = 0, qy = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double c0 = cx<Q>(i), c1 = cy<Q>(i);
+        const double fn = d[i] - fe[i];
+        pxx -= c0 * c0 * fn; pxy -= c0 * c1 * fn; pyy -= c1 * c1 * fn;
+        const double dx = c0 - u, dy = c1 - v;
+        const double e = (wt<Q>(i) + d[i]) * (dx * dx + dy * dy);
+        qx += e * dx; qy += e * dy;
+    }
+    pxx *= fac; pxy *= fac; pyy *= fac;
+    qx *= 0.5 * fac; qy *= 0.5 * fac;
+    o6[0] = 1.0 + rm1;
+    o6[1] = s.nax == 0 ? pxx : pyy;
+    o6[2] = s.sn * pxy;
+    o6[3] = s.nax == 0 ? pyy : pxx;
+    o6[4] = s.sn * (s.nax == 0 ? qx : qy);
+    o6[5] = s.nax == 0 ? qy : qx;
+}
+
+// corner LODI along the outward diagonal, rate in global components
+template <int Q>
+__device__ __forceinline__ void corner_rate(const CornerDev& c, const double* Uc, const double* U1, const double* U2,
+                                            const double* Un, double* rate) {
+    const double tdx = -c.ndy, tdy = c.ndx;
+    double l0[4], l1[4], l2[4], ln[4];
+    auto loc = [&](const double* g, double* l) {
+        l[0] = g[0]; l[1] = g[1] * c.ndx + g[2] * c.ndy; l[2] = g[1] * tdx + g[2] * tdy; l[3] = g[3];
+    };
+    loc(Uc, l0); loc(U1, l1); loc(U2, l2); loc(Un, ln);
+    constexpr double inv = 0.35355339059327376220;   // 1 / (2 sqrt 2): diagonal spacing sqrt 2
+    double dn[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) dn[k] = (3.0 * l0[k] - 4.0 * l1[k] + l2[k]) * inv;
+    const double zero[4] = {0, 0, 0, 0};
+    double rl[4];
+    char_rate<Lat<Q>::thermal>(l0, dn, l0, l0, zero, ln, c.relax ? BC_LODI_RELAX : BC_LODI, c.K, 0.0, c.Pinf, rl);
+    rate[0] = rl[0];
+    rate[1] = rl[1] * c.ndx + rl[2] * tdx;
+    rate[2] = rl[1] * c.ndy + rl[2] * tdy;
+    rate[3] = rl[3];
+}
+
+template <int Q, typename T>
+__device__ __forceinline__ void write_feq(T* __restrict__ B, unsigned long long P, int nx, int x, int y, const double* u4) {
+    double fe[Q];
+    feq_dev<Q, double>(u4[0] - 1.0, u4[1], u4[2], Lat<Q>::thermal ? u4[3] - 1.0 : 0.0, fe);
+    const unsigned long long id = (unsigned long long)y * nx + x;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) B[i * P + id] = (T)fe[i];
+}
+
+// one corner: RK4 of the diagonal LODI system; returns U_c^{n+1}; the x-side's work-group also
+// stores the new corner state and writes the M x M corner block
+template <int Q, typename T>
+__device__ void corner_step(const T* __restrict__ A, T* __restrict__ B, const BndArgs& a, int ci, bool owner,
+                            double* cn_out, double* cp_out) {
+    constexpr int M = Lat<Q>::M;
+    const CornerDev& c = a.c[ci];
+    const double* cu = (const double*)(a.reg_cur + c.off_cu);
+    const double* cd = (const double*)(a.reg_cur + c.off_cd);
+    double Un[4], D1n[4], D2n[4], D1p[4], D2p[4];
+    for (int k = 0; k < 4; ++k) { Un[k] = cu[k]; D1n[k] = cd[k]; D2n[k] = cd[4 + k]; }
+    double d[Q];
+    pull_node<Q, T>(A, a, c.xc + c.vx, c.yc + c.vy, d);
+    moments_u4<Q>(d, D1p);
+    pull_node<Q, T>(A, a, c.xc + 2 * c.vx, c.yc + 2 * c.vy, d);
+    moments_u4<Q>(d, D2p);
+    const double ast[4] = {0.0, 0.5, 0.5, 1.0}, bst[4] = {1.0, 2.0, 2.0, 1.0};
+    double k4[4] = {0, 0, 0, 0}, acc[4];
+    for (int m = 0; m < 4; ++m) acc[m] = Un[m];
+    for (int st = 0; st < 4; ++st) {
+        const double th = ast[st];
+        double Y[4], B1[4], B2[4];
+        for (int m = 0; m < 4; ++m) {
+            Y[m] = Un[m] + ast[st] * k4[m];
+            B1[m] = (1.0 - th) * D1n[m] + th * D1p[m];
+            B2[m] = (1.0 - th) * D2n[m] + th * D2p[m];
+        }
+        corner_rate<Q>(c, Y, B1, B2, Un, k4);
+        for (int m = 0; m < 4; ++m) acc[m] += bst[st] * (1.0 / 6.0) * k4[m];
+    }
+    for (int m = 0; m < 4; ++m) { cn_out[m] = Un[m]; cp_out[m] = acc[m]; }
+    if (owner) {
+        double* cun = (double*)(a.reg_next + c.off_cu);
+        double* cdn = (double*)(a.reg_next + c.off_cd);
+        for (int m = 0; m < 4; ++m) { cun[m] = acc[m]; cdn[m] = D1p[m]; cdn[4 + m] = D2p[m]; }
+        for (int jx = 0; jx < M; ++jx)
+            for (int jy = 0; jy < M; ++jy) write_feq<Q, T>(B, a.P, a.nx, c.x0 + c.sxn * jx, c.y0 + c.syn * jy, acc);
+    }
+}
+
+// ---------------------------------------------------------------- chunk of a characteristic side
+// LDS row lr <-> side row r = r0 - 4 + lr (4 halo rows: one per RK stage).  Thread t handles
+// node (lr = t / M, layer j = t % M + 1) in the RK stages.
+template <int Q, typename T>
+__device__ void char_chunk(const T* __restrict__ A, T* __restrict__ B, const BndArgs& a, const SideDev& sd, int chunk) {
+    constexpr int M = Lat<Q>::M, NR = 256 / M, MS = (M == 1) ? 2 : 1;
+    constexpr bool TH = Lat<Q>::thermal;
+    __shared__ double sY0[NR * M * 4], sYs[NR * M * 4], sK[NR * M * 4], sAcc[NR * M * 4];
+    __shared__ double sBn[NR * MS * 4], sBp[NR * MS * 4], sV[NR * 4];
+    __shared__ double sC[2][2][4];
+    const int tid = threadIdx.x;
+    const int len = sd.len, tper = sd.tper;
+    const int r0 = chunk * sd.rows;
+    const int r1 = min(r0 + sd.rows, len);
+    const bool full = sd.scheme == BC_CBC || sd.scheme == BC_CBC_RELAX;
+    const double* ub = (const double*)(a.reg_cur + sd.off_ub);
+    double* ubn = (double*)(a.reg_next + sd.off_ub);
+    const double* st = (const double*)(a.reg_cur + sd.off_strip);
+    double* stn = (double*)(a.reg_next + sd.off_strip);
+    const double* vis = (const double*)(a.reg_cur + sd.off_vis);
+    double* visn = (double*)(a.reg_next + sd.off_vis);
+    auto valid = [&](int r) { return tper || (r >= 0 && r < len); };
+    auto phys = [&](int r) { return tper ? ((r % len) + len) % len : r; };
+
+    // ---- phase A: load time level n, re-pull time level n+1 ------------------------------
+    for (int t = tid; t < NR * M; t += blockDim.x) {
+        const int lr = t / M, j = t % M, r = r0 - 4 + lr;
+        if (!valid(r)) continue;
+        const double* src = &ub[((size_t)j * len + phys(r)) * 4];
+        for (int m = 0; m < 4; ++m) sY0[(lr * M + j) * 4 + m] = src[m];
+    }
+    for (int t = tid; t < NR * MS; t += blockDim.x) {
+        const int lr = t / MS, k = t % MS, r = r0 - 4 + lr;
+        if (!valid(r)) continue;
+        const double* src = &st[((size_t)k * len + phys(r)) * 4];
+        for (int m = 0; m < 4; ++m) sBn[(lr * MS + k) * 4 + m] = src[m];
+    }
+    constexpr int KPmax = 3;
+    const int KP = full ? KPmax : MS;
+    for (int t = tid; t < NR * KP; t += blockDim.x) {
+        const int lr = t / KP, k = t % KP, r = r0 - 4 + lr;
+        if (!valid(r)) continue;
+        const int rp = phys(r);
+        const bool owned = r >= r0 && r < r1;
+        const bool need_strip = k < MS;
+        const bool need_vis = full && owned;
+        if (!need_strip && !need_vis) continue;
+        int x, y; side_node(sd, -k, rp, x, y);
+        double d[Q];
+        pull_node<Q, T>(A, a, x, y, d);
+        if (need_strip) {
+            double u4[4];
+            moments_u4<Q>(d, u4);
+            for (int m = 0; m < 4; ++m) sBp[(lr * MS + k) * 4 + m] = u4[m];
+            if (owned) for (int m = 0; m < 4; ++m) stn[((size_t)k * len + rp) * 4 + m] = u4[m];
+        }
+        if (need_vis) {
+            double o6[6];
+            visc_moments<Q>(sd, d, a.tau, o6);
+            for (int m = 0; m < 6; ++m) visn[((size_t)k * len + rp) * 6 + m] = o6[m];
+        }
+    }
+    // viscous terms of time level n (frozen during the RK stages)
+    if (full) {
+        const double nu = (a.tau - 0.5) * Lat<Q>::cs2;
+        for (int lr = tid; lr < NR; lr += blockDim.x) {
+            const int r = r0 - 4 + lr;
+            if (!valid(r)) continue;
+            const int rp = phys(r);
+            const double* v0 = &vis[((size_t)0 * len + rp) * 6];
+            const double* v1 = &vis[((size_t)1 * len + rp) * 6];
+            const double* v2 = &vis[((size_t)2 * len + rp) * 6];
+            double upv[6] = {0, 0, 0, 0, 0, 0}, dwv[6] = {0, 0, 0, 0, 0, 0};
+            if (valid(r + 1)) for (int m = 0; m < 6; ++m) upv[m] = vis[((size_t)0 * len + phys(r + 1)) * 6 + m];
+            if (valid(r - 1)) for (int m = 0; m < 6; ++m) dwv[m] = vis[((size_t)0 * len + phys(r - 1)) * 6 + m];
+            auto dn_ = [&](int m) { return 0.5 * (3.0 * v0[m] - 4.0 * v1[m] + v2[m]); };
+            auto dt_ = [&](int m) { return 0.5 * (upv[m] - dwv[m]); };
+            const double rho = v0[0];
+            sV[lr * 4 + 0] = 0.0;
+            sV[lr * 4 + 1] = (dn_(1) + dt_(2)) / rho;
+            sV[lr * 4 + 2] = (dn_(2) + dt_(3)) / rho;
+            double vt = 0.0;
+            if (TH) {
+                const double heat = (0.5 * (v0[1] * v0[1] + v0[3] * v0[3]) + v0[2] * v0[2]) / (rho * rho * nu * Lat<Q>::cs2);
+                vt = -(dn_(4) + dt_(5)) / (rho * Lat<Q>::cs2) + heat;
+            }
+            sV[lr * 4 + 3] = vt;
+        }
+    }
+    // corners at the ends of a side with non-periodic rows
+    if (!tper) {
+        if (r0 == 0 && tid == 0) corner_step<Q, T>(A, B, a, sd.corner_lo, sd.owns_corners, sC[0][0], sC[0][1]);
+        if (r1 == len && tid == 64) corner_step<Q, T>(A, B, a, sd.corner_hi, sd.owns_corners, sC[1][0], sC[1][1]);
+    }
+    for (int t = tid; t < NR * M; t += blockDim.x) {
+        const int lr = t / M, r = r0 - 4 + lr;
+        if (r >= r0 && r < r1)
+            for (int m = 0; m < 4; ++m) sAcc[t * 4 + m] = sY0[t * 4 + m];
+    }
+    __syncthreads();
+
+    // ---- phase B: RK4, stage st valid on rows within 3 - st of the owned range -------------
+    const double ast[4] = {0.0, 0.5, 0.5, 1.0}, bst[4] = {1.0, 2.0, 2.0, 1.0};
+    for (int stg = 0; stg < 4; ++stg) {
+        const int hy = 4 - stg, he = 3 - stg;
+        for (int t = tid; t < NR * M; t += blockDim.x) {
+            const int lr = t / M, r = r0 - 4 + lr;
+            if (r < r0 - hy || r >= r1 + hy || !valid(r)) continue;
+            for (int m = 0; m < 4; ++m) sYs[t * 4 + m] = stg == 0 ? sY0[t * 4 + m] : sY0[t * 4 + m] + ast[stg] * sK[t * 4 + m];
+        }
+        __syncthreads();
+        const double th = ast[stg];
+        for (int t = tid; t < NR * M; t += blockDim.x) {
+            const int lr = t / M, jj = t % M, j = jj + 1, r = r0 - 4 + lr;
+            if (r < r0 - he || r >= r1 + he || !valid(r)) continue;
+            // side-local values along the normal (k) at this row
+            auto val_n = [&](int k, double* l) {
+                double g[4];
+                if (k >= 1) {
+                    for (int m = 0; m < 4; ++m) g[m] = sYs[(lr * M + k - 1) * 4 + m];
+                } else {
+                    const double* bn = &sBn[(lr * MS - k) * 4];
+                    const double* bp = &sBp[(lr * MS - k) * 4];
+                    for (int m = 0; m < 4; ++m) g[m] = (1.0 - th) * bn[m] + th * bp[m];
+                }
+                to_local(sd, g, l);
+            };
+            auto val_t = [&](int rr, double* l) {   // same layer, row rr (LDS row lr + rr - r)
+                double g[4];
+                if (!tper && rr < 0) {
+                    for (int m = 0; m < 4; ++m) g[m] = (1.0 - th) * sC[0][0][m] + th * sC[0][1][m];
+                } else if (!tper && rr >= len) {
+                    for (int m = 0; m < 4; ++m) g[m] = (1.0 - th) * sC[1][0][m] + th * sC[1][1][m];
+                } else {
+                    const int l2 = lr + (rr - r);
+                    for (int m = 0; m < 4; ++m) g[m] = sYs[(l2 * M + jj) * 4 + m];
+                }
+                to_local(sd, g, l);
+            };
+            double U[4], dn[4], up[4], dw[4], U0[4], Vl[4] = {0, 0, 0, 0};
+            val_n(j, U);
+            if (j == M) {   // eq. FD-dx-bw
+                double b1[4], b2[4];
+                val_n(M - 1, b1); val_n(M - 2, b2);
+                for (int m = 0; m < 4; ++m) dn[m] = 0.5 * (3.0 * U[m] - 4.0 * b1[m] + b2[m]);
+            } else {        // eq. FD-dx-center
+                double p1[4], m1[4];
+                val_n(j + 1, p1); val_n(j - 1, m1);
+                for (int m = 0; m < 4; ++m) dn[m] = 0.5 * (p1[m] - m1[m]);
+            }
+            val_t(r + 1, up);
+            val_t(r - 1, dw);
+            to_local(sd, &sY0[t * 4], U0);
+            if (full) for (int m = 0; m < 4; ++m) Vl[m] = sV[lr * 4 + m];
+            double rl[4], rg[4];
+            char_rate<TH>(U, dn, up, dw, Vl, U0, sd.scheme, sd.K, sd.alpha, sd.Pinf, rl);
+            rate_to_global(sd, rl, rg);
+            for (int m = 0; m < 4; ++m) sK[t * 4 + m] = rg[m];
+            if (r >= r0 && r < r1)
+                for (int m = 0; m < 4; ++m) sAcc[t * 4 + m] += bst[stg] * (1.0 / 6.0) * rg[m];
+        }
+        __syncthreads();
+    }
+
+    // ---- phase C: new boundary state and equilibrium reconstruction of the layers ----------
+    for (int t = tid; t < (r1 - r0) * M; t += blockDim.x) {
+        const int lr = 4 + t / M, j = t % M, r = r0 + t / M;
+        const double* u4 = &sAcc[(lr * M + j) * 4];
+        for (int m = 0; m < 4; ++m) ubn[((size_t)j * len + r) * 4 + m] = u4[m];
+        int x, y; side_node(sd, j + 1, r, x, y);
+        write_feq<Q, T>(B, a.P, a.nx, x, y, u4);
+    }
+}
+
+// ---------------------------------------------------------------- zero-gradient side (eq. zg-bc)
+template <int Q, typename T>
+__device__ void zg_chunk(const T* __restrict__ A, T* __restrict__ B, const BndArgs& a, const SideDev& sd, int chunk) {
+    constexpr int M = Lat<Q>::M;
+    const T omega = sizeof(T) == 4 ? (T)(float)a.omega : (T)a.omega;
+    const int r = chunk * sd.rows + threadIdx.x;
+    if (threadIdx.x < sd.rows && r < sd.len) {
+        int x, y; side_node(sd, 0, r, x, y);
+        T d[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            int xs = x - cx<Q>(i), ys = y - cy<Q>(i);
+            if (a.xper) xs = wrapi(xs, a.nx);
+            if (a.yper) ys = wrapi(ys, a.ny);
+            d[i] = A[(unsigned long long)i * a.P + (unsigned long long)ys * a.nx + xs];
+        }
+        collide_dev<Q, T>(d, omega);
+        for (int j = 1; j <= M; ++j) {
+            int xb, yb; side_node(sd, j, r, xb, yb);
+            const unsigned long long id = (unsigned long long)yb * a.nx + xb;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) B[i * a.P + id] = d[i];
+        }
+    }
+    // corner blocks copy the post-collision state of the inward diagonal node
+    if (!sd.tper && sd.owns_corners && threadIdx.x == 0) {
+        for (int e = 0; e < 2; ++e) {
+            const int ci = e == 0 ? sd.corner_lo : sd.corner_hi;
+            const bool mine = e == 0 ? (chunk == 0) : ((chunk + 1) * sd.rows >= sd.len);
+            if (ci < 0 || !mine) continue;
+            const CornerDev& c = a.c[ci];
+            const int x = c.xc + c.vx, y = c.yc + c.vy;
+            T d[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                int xs = x - cx<Q>(i), ys = y - cy<Q>(i);
+                d[i] = A[(unsigned long long)i * a.P + (unsigned long long)ys * a.nx + xs];
+            }
+            collide_dev<Q, T>(d, omega);
+            for (int jx = 0; jx < M; ++jx)
+                for (int jy = 0; jy < M; ++jy) {
+                    const unsigned long long id = (unsigned long long)(c.y0 + c.syn * jy) * a.nx + (c.x0 + c.sxn * jx);
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) B[i * a.P + id] = d[i];
+                }
+        }
+    }
+}
+
+template <int Q, typename T>
+__global__ __launch_bounds__(256) void k_boundary(const T* __restrict__ A, T* __restrict__ B, BndArgs a) {
+    const int b = blockIdx.x;
+    int s = 0;
+    while (s < 4 && !(a.s[s].nblk > 0 && b >= a.s[s].blk0 && b < a.s[s].blk0 + a.s[s].nblk)) ++s;
+    if (s == 4) return;
+    const SideDev& sd = a.s[s];
+    if (sd.kind == KIND_CHAR) char_chunk<Q, T>(A, B, a, sd, b - sd.blk0);
+    else if (sd.kind == KIND_ZG) zg_chunk<Q, T>(A, B, a, sd, b - sd.blk0);
+}
+
+}  // namespace lbm

@@ -1,0 +1,490 @@
+// lbm.hip -- host side of the C ABI declared in include/lbm.h (liblbm_hip.so, gfx950).
+//
+// The library owns no device memory: the caller's workspace is carved into two population
+// buffers, two parity copies of the boundary solver state, the Dirichlet profiles and the
+// diagnostics scratch.  One step launches the bulk kernel on the caller's stream and the
+// boundary kernel on an auxiliary stream; two events order step n+1 after step n.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "kernels.h"
+#include "lbm.h"
+
+using namespace lbm;
+
+namespace {
+
+std::string g_err;
+
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+bool is_char(int b) { return b >= BC_LODI && b <= BC_CBC_RELAX; }
+bool is_relax(int b) { return b == BC_LODI_RELAX || b == BC_CBC_RELAX; }
+bool is_full(int b) { return b == BC_CBC || b == BC_CBC_RELAX; }
+
+int stencil_M(int st) { return st == 9 ? 1 : 3; }
+int chunk_rows(int M) { return 256 / M - 8; }   // must match NR - 8 in char_chunk
+
+struct Layout {
+    int Q = 0, M = 0, MS = 0;
+    size_t esz = 0;
+    unsigned long long P = 0;
+    size_t f_bytes = 0, region_bytes = 0, off_region = 0, off_inlet[4] = {0, 0, 0, 0}, off_diag = 0, total = 0;
+    int diag_blocks = 0;
+    SideDev s[4];
+    CornerDev c[4];
+};
+
+int validate(const lbm_config* c, std::string& err) {
+    if (!c) { err = "null config"; return LBM_E_ARG; }
+    if (c->stencil != 9 && c->stencil != 37) { err = "stencil must be LBM_D2Q9 or LBM_D2Q37"; return LBM_E_ARG; }
+    if (c->precision != LBM_FP64 && c->precision != LBM_FP32DEV) { err = "unknown precision"; return LBM_E_ARG; }
+    if (!(c->tau > 0.5) || !std::isfinite(c->tau)) { err = "tau must be a finite value above 1/2"; return LBM_E_ARG; }
+    for (int s = 0; s < 4; ++s)
+        if (c->bc[s] < 0 || c->bc[s] > 6) { err = "unknown boundary type"; return LBM_E_ARG; }
+    if ((c->bc[0] == BC_PERIODIC) != (c->bc[1] == BC_PERIODIC) || (c->bc[2] == BC_PERIODIC) != (c->bc[3] == BC_PERIODIC)) {
+        err = "periodic sides must come in pairs"; return LBM_E_ARG;
+    }
+    const int M = stencil_M(c->stencil);
+    const bool xp = c->bc[0] == BC_PERIODIC, yp = c->bc[2] == BC_PERIODIC;
+    if (c->nx < (xp ? M + 1 : 2 * M + 3) || c->ny < (yp ? M + 1 : 2 * M + 3)) { err = "grid too small"; return LBM_E_ARG; }
+    if ((double)c->nx * (double)c->ny > 2.0e9) { err = "grid too large"; return LBM_E_ARG; }
+    if (!xp && !yp)
+        for (int sx = 0; sx < 2; ++sx)
+            for (int sy = 2; sy < 4; ++sy) {
+                const bool ok = (is_char(c->bc[sx]) && is_char(c->bc[sy])) || (c->bc[sx] == BC_ZG && c->bc[sy] == BC_ZG);
+                if (!ok) { err = "corner between these boundary types is not supported"; return LBM_E_UNSUPPORTED; }
+            }
+    if (c->stencil == 9)
+        for (int s = 0; s < 4; ++s)
+            if (is_full(c->bc[s])) { err = "CBC with viscous terms needs the heat-flux moment (D2Q37 only)"; return LBM_E_UNSUPPORTED; }
+    return LBM_OK;
+}
+
+void make_layout(const lbm_config* c, Layout& L) {
+    L.Q = c->stencil;
+    L.M = stencil_M(c->stencil);
+    L.MS = L.M == 1 ? 2 : 1;
+    L.esz = c->precision == LBM_FP64 ? 8 : 4;
+    const unsigned long long n = (unsigned long long)c->nx * c->ny;
+    L.P = (n + 63) / 64 * 64;
+    L.f_bytes = align_up((size_t)L.Q * L.P * L.esz);
+    const bool xp = c->bc[0] == BC_PERIODIC, yp = c->bc[2] == BC_PERIODIC;
+    size_t reg = 0;
+    int blk = 0;
+    for (int s = 0; s < 4; ++s) {
+        SideDev& d = L.s[s];
+        std::memset(&d, 0, sizeof(d));
+        const int b = c->bc[s];
+        d.scheme = b;
+        d.kind = b == BC_PERIODIC ? KIND_NONE : is_char(b) ? KIND_CHAR : b == BC_ZG ? KIND_ZG : KIND_DIRICHLET;
+        d.nax = s < 2 ? 0 : 1;
+        d.sn = (s % 2 == 0) ? -1 : 1;
+        d.Nn = d.nax == 0 ? c->nx : c->ny;
+        d.Nt = d.nax == 0 ? c->ny : c->nx;
+        d.tper = d.nax == 0 ? yp : xp;
+        d.r0 = d.tper ? 0 : L.M;
+        d.len = d.tper ? d.Nt : d.Nt - 2 * L.M;
+        d.xf = d.sn > 0 ? d.Nn - 1 - L.M : L.M;
+        d.corner_lo = d.corner_hi = -1;
+        if (!d.tper) {
+            if (d.nax == 0) { d.corner_lo = (s & 1); d.corner_hi = (s & 1) | 2; }
+            else { d.corner_lo = ((s - 2) << 1); d.corner_hi = 1 | ((s - 2) << 1); }
+        }
+        d.owns_corners = d.nax == 0;
+        d.Pinf = 0;
+        if (d.kind == KIND_CHAR) {
+            d.rows = chunk_rows(L.M);
+            d.nblk = (d.len + d.rows - 1) / d.rows;
+            d.off_ub = reg; reg += align_up((size_t)L.M * d.len * 4 * 8);
+            d.off_strip = reg; reg += align_up((size_t)L.MS * d.len * 4 * 8);
+            if (is_full(b)) { d.off_vis = reg; reg += align_up((size_t)3 * d.len * 6 * 8); }
+        } else if (d.kind == KIND_ZG) {
+            d.rows = 256;
+            d.nblk = (d.len + 255) / 256;
+        }
+        d.blk0 = blk;
+        blk += d.nblk;
+    }
+    for (int ci = 0; ci < 4; ++ci) {
+        CornerDev& k = L.c[ci];
+        std::memset(&k, 0, sizeof(k));
+        const int sx = ci & 1, sy = 2 + (ci >> 1);
+        k.active = !xp && !yp;
+        if (!k.active) continue;
+        k.zg = c->bc[sx] == BC_ZG;
+        const SideDev &X = L.s[sx], &Y = L.s[sy];
+        k.xc = X.xf + X.sn;
+        k.yc = Y.xf + Y.sn;
+        k.vx = -X.sn;
+        k.vy = -Y.sn;
+        k.x0 = X.xf + X.sn; k.sxn = X.sn;
+        k.y0 = Y.xf + Y.sn; k.syn = Y.sn;
+        k.ndx = X.sn / std::sqrt(2.0);
+        k.ndy = Y.sn / std::sqrt(2.0);
+        if (!k.zg) {
+            k.off_cu = reg; reg += ALIGN;
+            k.off_cd = reg; reg += ALIGN;
+        }
+    }
+    L.region_bytes = align_up(reg > 0 ? reg : ALIGN);
+    size_t off = 2 * L.f_bytes;
+    L.off_region = off;
+    off += 2 * L.region_bytes;
+    for (int s = 0; s < 4; ++s) {
+        L.off_inlet[s] = off;
+        if (L.s[s].kind == KIND_DIRICHLET) off += align_up((size_t)L.s[s].len * 4 * 8);
+    }
+    L.diag_blocks = (int)std::min<unsigned long long>(1024, (n + 255) / 256);
+    L.off_diag = off;
+    off += align_up((size_t)(L.diag_blocks + 1) * 8 * 8);
+    L.total = off;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+    lbm_config cfg;
+    Layout L;
+    char* ws = nullptr;
+    void* f[2] = {nullptr, nullptr};
+    char* region[2] = {nullptr, nullptr};
+    double* inlet[4] = {nullptr, nullptr, nullptr, nullptr};
+    double* diag = nullptr;
+    int cur = 0;
+    long steps = 0;
+    long save_steps = 0;
+    hipStream_t stream = nullptr, aux = nullptr;
+    hipEvent_t ev_main = nullptr, ev_aux = nullptr;
+    int nbnd = 0;
+    lbm_relax relax[4];
+    BulkArgs bulk;
+    std::string err;
+};
+
+namespace {
+
+int fail(lbm_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg; else g_err = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                  \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess) return fail(ctx, LBM_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+BndArgs make_bnd(const lbm_ctx* c) {
+    BndArgs a;
+    std::memset(&a, 0, sizeof(a));
+    const lbm_config& g = c->cfg;
+    a.nx = g.nx; a.ny = g.ny;
+    a.xper = g.bc[0] == BC_PERIODIC;
+    a.yper = g.bc[2] == BC_PERIODIC;
+    a.P = c->L.P;
+    a.omega = 1.0 / g.tau;
+    a.tau = g.tau;
+    a.reg_cur = c->region[c->cur];
+    a.reg_next = c->region[c->cur ^ 1];
+    const double cs2 = g.stencil == 9 ? Lat<9>::cs2 : Lat<37>::cs2;
+    const bool thermal = g.stencil == 37;
+    for (int s = 0; s < 4; ++s) {
+        a.s[s] = c->L.s[s];
+        const lbm_relax& p = c->relax[s];
+        const double cinf = thermal ? std::sqrt(2.0 * cs2 * p.T_inf) : std::sqrt(cs2);
+        const double len = p.length > 0 ? p.length : (double)a.s[s].Nn;
+        a.s[s].K = p.sigma * (1.0 - p.mach * p.mach) * cinf / len;
+        a.s[s].alpha = p.alpha;
+        a.s[s].Pinf = p.rho_inf * cs2 * (thermal ? p.T_inf : 1.0);
+    }
+    for (int ci = 0; ci < 4; ++ci) {
+        a.c[ci] = c->L.c[ci];
+        const int sx = ci & 1;
+        a.c[ci].relax = is_relax(g.bc[sx]);
+        a.c[ci].K = a.s[sx].K;
+        a.c[ci].Pinf = a.s[sx].Pinf;
+    }
+    return a;
+}
+
+template <int Q, typename T>
+int launch_step(lbm_ctx* c) {
+    const BndArgs a = make_bnd(c);
+    const T* A = (const T*)c->f[c->cur];
+    T* B = (T*)c->f[c->cur ^ 1];
+    const BulkArgs& g = c->bulk;
+    const dim3 grid((g.x1 - g.x0 + 1 + 255) / 256, g.y1 - g.y0 + 1);
+    const bool px = c->cfg.bc[0] == BC_PERIODIC, py = c->cfg.bc[2] == BC_PERIODIC;
+    auto bulk = [&](hipStream_t s) {
+        if (px && py) hipLaunchKernelGGL((k_bulk<Q, T, true, true>), grid, dim3(256), 0, s, A, B, g);
+        else if (px) hipLaunchKernelGGL((k_bulk<Q, T, true, false>), grid, dim3(256), 0, s, A, B, g);
+        else if (py) hipLaunchKernelGGL((k_bulk<Q, T, false, true>), grid, dim3(256), 0, s, A, B, g);
+        else hipLaunchKernelGGL((k_bulk<Q, T, false, false>), grid, dim3(256), 0, s, A, B, g);
+    };
+    if (c->nbnd > 0) {
+        HIPCHK(c, hipEventRecord(c->ev_main, c->stream));
+        HIPCHK(c, hipStreamWaitEvent(c->aux, c->ev_main, 0));
+        hipLaunchKernelGGL((k_boundary<Q, T>), dim3(c->nbnd), dim3(256), 0, c->aux, A, B, a);
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipEventRecord(c->ev_aux, c->aux));
+        bulk(c->stream);
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_aux, 0));
+    } else {
+        bulk(c->stream);
+        HIPCHK(c, hipGetLastError());
+    }
+    c->cur ^= 1;
+    c->steps += 1;
+    return LBM_OK;
+}
+
+template <int Q, typename T>
+int launch_init(lbm_ctx* c, const double* rho, const double* ux, const double* uy, const double* Tf) {
+    const int n = c->cfg.nx * c->cfg.ny;
+    hipLaunchKernelGGL((k_init_fields<Q, T>), dim3((n + 255) / 256), dim3(256), 0, c->stream, rho, ux, uy,
+                       Q == 37 ? Tf : nullptr, (T*)c->f[0], (T*)c->f[1], n, c->L.P);
+    HIPCHK(c, hipGetLastError());
+    const BndArgs a = make_bnd(c);
+    int maxlen = 1;
+    for (int s = 0; s < 4; ++s) maxlen = std::max(maxlen, c->L.s[s].len);
+    hipLaunchKernelGGL((k_init_boundary<Q>), dim3((maxlen + 255) / 256, 4), dim3(256), 0, c->stream, a, rho, ux, uy,
+                       Q == 37 ? Tf : nullptr, c->inlet[0], c->inlet[1], c->inlet[2], c->inlet[3]);
+    HIPCHK(c, hipGetLastError());
+    for (int s = 0; s < 4; ++s) {
+        if (c->L.s[s].kind != KIND_DIRICHLET) continue;
+        const int tot = c->L.s[s].len * c->L.M;
+        hipLaunchKernelGGL((k_dirichlet<Q, T>), dim3((tot + 255) / 256), dim3(256), 0, c->stream, a, s, c->inlet[s],
+                           (T*)c->f[0], (T*)c->f[1]);
+        HIPCHK(c, hipGetLastError());
+    }
+    return LBM_OK;
+}
+
+template <typename F>
+int dispatch(const lbm_ctx* c, F&& f) {
+    if (c->cfg.stencil == 9) return c->cfg.precision == LBM_FP64 ? f.template operator()<9, double>() : f.template operator()<9, float>();
+    return c->cfg.precision == LBM_FP64 ? f.template operator()<37, double>() : f.template operator()<37, float>();
+}
+
+}  // namespace
+
+// =========================================================================== C ABI
+extern "C" {
+
+size_t lbm_workspace_bytes(const lbm_config* cfg) {
+    std::string err;
+    if (validate(cfg, err) != LBM_OK) { g_err = err; return 0; }
+    Layout L;
+    make_layout(cfg, L);
+    return L.total;
+}
+
+int lbm_init(const lbm_config* cfg, void* d_workspace, size_t workspace_bytes, void* hip_stream, const double* d_rho0,
+             const double* d_ux0, const double* d_uy0, const double* d_T0, lbm_ctx** out) {
+    if (!out) return fail(nullptr, LBM_E_ARG, "out is NULL");
+    *out = nullptr;
+    std::string err;
+    const int v = validate(cfg, err);
+    if (v != LBM_OK) return fail(nullptr, v, err);
+    if (!d_workspace || ((uintptr_t)d_workspace % ALIGN) != 0) return fail(nullptr, LBM_E_ARG, "workspace must be non-NULL and 256-byte aligned");
+    if (!d_rho0 || !d_ux0 || !d_uy0 || (cfg->stencil == 37 && !d_T0)) return fail(nullptr, LBM_E_ARG, "initial field pointer is NULL");
+    lbm_ctx* c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail(nullptr, LBM_E_ARG, "out of host memory");
+    c->cfg = *cfg;
+    make_layout(cfg, c->L);
+    if (workspace_bytes < c->L.total) {
+        delete c;
+        return fail(nullptr, LBM_E_ARG, "workspace smaller than lbm_workspace_bytes(cfg)");
+    }
+    c->ws = (char*)d_workspace;
+    c->f[0] = c->ws;
+    c->f[1] = c->ws + c->L.f_bytes;
+    c->region[0] = c->ws + c->L.off_region;
+    c->region[1] = c->region[0] + c->L.region_bytes;
+    for (int s = 0; s < 4; ++s) c->inlet[s] = (double*)(c->ws + c->L.off_inlet[s]);
+    c->diag = (double*)(c->ws + c->L.off_diag);
+    c->stream = (hipStream_t)hip_stream;
+    for (int s = 0; s < 4; ++s) c->relax[s] = lbm_relax{0.0, 0.0, 1.0, 1.0, 0.0, 0.0};
+    c->nbnd = 0;
+    for (int s = 0; s < 4; ++s) c->nbnd += c->L.s[s].nblk;
+    const int M = c->L.M;
+    const bool xp = cfg->bc[0] == BC_PERIODIC, yp = cfg->bc[2] == BC_PERIODIC;
+    c->bulk.nx = cfg->nx; c->bulk.ny = cfg->ny;
+    c->bulk.x0 = xp ? 0 : M; c->bulk.x1 = xp ? cfg->nx - 1 : cfg->nx - 1 - M;
+    c->bulk.y0 = yp ? 0 : M; c->bulk.y1 = yp ? cfg->ny - 1 : cfg->ny - 1 - M;
+    c->bulk.P = c->L.P;
+    c->bulk.omega_d = 1.0 / cfg->tau;
+    c->bulk.omega_f = (float)(1.0 / cfg->tau);
+    if (c->nbnd > 0) {
+        hipError_t e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_main, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_aux, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            std::string m = std::string("stream/event creation: ") + hipGetErrorString(e);
+            lbm_destroy(c);
+            return fail(nullptr, LBM_E_HIP, m);
+        }
+    }
+    const int rc = dispatch(c, [&]<int Q, typename T>() -> int { return launch_init<Q, T>(c, d_rho0, d_ux0, d_uy0, d_T0); });
+    if (rc != LBM_OK) {
+        g_err = c->err;
+        lbm_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+int lbm_cbc_params(lbm_ctx* c, int side, const lbm_relax* p) {
+    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+    if (!p || side < -1 || side > 3) return fail(c, LBM_E_ARG, "bad side or params");
+    const double vals[6] = {p->sigma, p->alpha, p->rho_inf, p->T_inf, p->mach, p->length};
+    for (double v : vals)
+        if (!std::isfinite(v)) return fail(c, LBM_E_ARG, "non-finite relaxation parameter");
+    if (!(p->rho_inf > 0) || !(p->T_inf > 0)) return fail(c, LBM_E_ARG, "rho_inf and T_inf must be positive");
+    for (int s = 0; s < 4; ++s)
+        if (side < 0 || s == side) c->relax[s] = *p;
+    return LBM_OK;
+}
+
+int lbm_dirichlet_profile(lbm_ctx* c, int side, const double* d_U) {
+    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+    if (side < 0 || side > 3 || !d_U) return fail(c, LBM_E_ARG, "bad side or profile pointer");
+    if (c->L.s[side].kind != KIND_DIRICHLET) return fail(c, LBM_E_STATE, "side is not a Dirichlet side");
+    const size_t bytes = (size_t)c->L.s[side].len * 4 * 8;
+    HIPCHK(c, hipMemcpyAsync(c->inlet[side], d_U, bytes, hipMemcpyDeviceToDevice, c->stream));
+    return dispatch(c, [&]<int Q, typename T>() -> int {
+        const BndArgs a = make_bnd(c);
+        const int tot = c->L.s[side].len * c->L.M;
+        hipLaunchKernelGGL((k_dirichlet<Q, T>), dim3((tot + 255) / 256), dim3(256), 0, c->stream, a, side,
+                           c->inlet[side], (T*)c->f[0], (T*)c->f[1]);
+        HIPCHK(c, hipGetLastError());
+        return LBM_OK;
+    });
+}
+
+int lbm_step(lbm_ctx* c, int nsteps) {
+    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+    if (nsteps < 0) return fail(c, LBM_E_ARG, "nsteps < 0");
+    for (int k = 0; k < nsteps; ++k) {
+        const int rc = dispatch(c, [&]<int Q, typename T>() -> int { return launch_step<Q, T>(c); });
+        if (rc != LBM_OK) return rc;
+    }
+    return LBM_OK;
+}
+
+int lbm_macroscopic(lbm_ctx* c, double* rho, double* ux, double* uy, double* Tf) {
+    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+    if (!rho || !ux || !uy) return fail(c, LBM_E_ARG, "output pointer is NULL");
+    const int n = c->cfg.nx * c->cfg.ny;
+    return dispatch(c, [&]<int Q, typename T>() -> int {
+        hipLaunchKernelGGL((k_macro<Q, T>), dim3((n + 255) / 256), dim3(256), 0, c->stream, (const T*)c->f[c->cur], n,
+                           c->L.P, rho, ux, uy, Tf);
+        HIPCHK(c, hipGetLastError());
+        return LBM_OK;
+    });
+}
+
+int lbm_boundary_state(lbm_ctx* c, int side, double* d_out) {
+    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+    if (side < 0 || side > 3 || !d_out) return fail(c, LBM_E_ARG, "bad side or output pointer");
+    const SideDev& s = c->L.s[side];
+    if (s.kind != KIND_CHAR) return fail(c, LBM_E_STATE, "side is not a characteristic side");
+    HIPCHK(c, hipMemcpyAsync(d_out, c->region[c->cur] + s.off_ub, (size_t)c->L.M * s.len * 4 * 8, hipMemcpyDeviceToDevice, c->stream));
+    return LBM_OK;
+}
+
+int lbm_diagnostics(lbm_ctx* c, double* h_out) {
+    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+    if (!h_out) return fail(c, LBM_E_ARG, "output pointer is NULL");
+    const BulkArgs& g = c->bulk;
+    const int nb = c->L.diag_blocks;
+    const int rc = dispatch(c, [&]<int Q, typename T>() -> int {
+        hipLaunchKernelGGL((k_diag_partial<Q, T>), dim3(nb), dim3(256), 0, c->stream, (const T*)c->f[c->cur], c->cfg.nx,
+                           c->cfg.ny, c->L.P, g.x0, g.x1, g.y0, g.y1, c->diag);
+        HIPCHK(c, hipGetLastError());
+        hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, c->stream, c->diag, nb, c->diag + (size_t)nb * 8);
+        HIPCHK(c, hipGetLastError());
+        return LBM_OK;
+    });
+    if (rc != LBM_OK) return rc;
+    double out[8];
+    HIPCHK(c, hipMemcpyAsync(out, c->diag + (size_t)nb * 8, sizeof(out), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    out[7] = (double)c->steps;
+    std::memcpy(h_out, out, sizeof(out));
+    if (out[6] > 0) return fail(c, LBM_E_NONFINITE, "non-finite populations");
+    return LBM_OK;
+}
+
+size_t lbm_state_bytes(const lbm_ctx* c) {
+    if (!c) return 0;
+    return ALIGN + c->L.f_bytes + c->L.region_bytes;
+}
+
+int lbm_save(lbm_ctx* c, void* d_buf) {
+    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+    if (!d_buf) return fail(c, LBM_E_ARG, "buffer is NULL");
+    char* b = (char*)d_buf;
+    c->save_steps = c->steps;
+    HIPCHK(c, hipMemcpyAsync(b, &c->save_steps, sizeof(long), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(b + ALIGN, c->f[c->cur], c->L.f_bytes, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(b + ALIGN + c->L.f_bytes, c->region[c->cur], c->L.region_bytes, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+int lbm_restore(lbm_ctx* c, const void* d_buf) {
+    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+    if (!d_buf) return fail(c, LBM_E_ARG, "buffer is NULL");
+    const char* b = (const char*)d_buf;
+    long steps = 0;
+    HIPCHK(c, hipMemcpyAsync(&steps, b, sizeof(long), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->f[0], b + ALIGN, c->L.f_bytes, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->region[0], b + ALIGN + c->L.f_bytes, c->L.region_bytes, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->cur = 0;
+    c->steps = steps;
+    return LBM_OK;
+}
+
+long lbm_steps_done(const lbm_ctx* c) { return c ? c->steps : -1; }
+
+int lbm_lattice_info(int stencil, int* M, double* cs2, double* w, int* cxo, int* cyo) {
+    if (stencil == 9) {
+        if (M) *M = 1;
+        if (cs2) *cs2 = Lat<9>::cs2;
+        for (int i = 0; i < 9; ++i) { if (w) w[i] = wt<9>(i); if (cxo) cxo[i] = cx<9>(i); if (cyo) cyo[i] = cy<9>(i); }
+        return 9;
+    }
+    if (stencil == 37) {
+        if (M) *M = 3;
+        if (cs2) *cs2 = Lat<37>::cs2;
+        for (int i = 0; i < 37; ++i) { if (w) w[i] = wt<37>(i); if (cxo) cxo[i] = cx<37>(i); if (cyo) cyo[i] = cy<37>(i); }
+        return 37;
+    }
+    g_err = "unknown stencil";
+    return LBM_E_ARG;
+}
+
+const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }
+
+void lbm_destroy(lbm_ctx* c) {
+    if (!c) return;
+    if (c->aux) { (void)hipStreamSynchronize(c->aux); (void)hipStreamDestroy(c->aux); }
+    if (c->ev_main) (void)hipEventDestroy(c->ev_main);
+    if (c->ev_aux) (void)hipEventDestroy(c->ev_aux);
+    delete c;
+}
+
+}  // extern "C"

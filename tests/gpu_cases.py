@@ -1,0 +1,90 @@
+"""Shared helpers of the GPU parity tests: run the HIP library and the oracle on the same seeded
+inputs and compare macroscopic fields node by node."""
+import math
+import sys
+
+import numpy as np
+
+from oracle import oracle as O
+from paper_2307_16766_amd import workloads as W
+
+CS2_37 = O.lattice(37)[0]
+CS_37 = math.sqrt(CS2_37)
+TAU_37 = 0.5 + W.NU_D2Q37 / CS2_37
+
+# Tolerances: relative L2 error bound on rho and T, and on u the same relative bound plus an
+# absolute rounding floor per step.  The floor is needed because u is compared where it is small
+# (1e-6..1e-4 in the pulse cases) while it is a moment of O(w_i) populations: the oracle stores
+# f itself, whose rounding is about one ulp of an O(1) number per step (2.2e-16 in FP64); FP32
+# deviation storage rounds deviations of size ~1e-3 w_i at 6e-8 relative (~1e-10 per step).
+TOL = {"fp64": (1e-12, 2.2e-16), "fp32dev": (2e-5, 1e-10)}
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel_errors(gpu, ref):
+    """Relative L2 errors of (rho, u, T) over all nodes (u as a vector field)."""
+    r, ux, uy, T = gpu
+    R, UX, UY, TT = ref
+    e_rho = np.linalg.norm(r - R) / np.linalg.norm(R)
+    nu = math.sqrt(np.sum(UX ** 2 + UY ** 2))
+    e_u = math.sqrt(np.sum((ux - UX) ** 2 + (uy - UY) ** 2)) / max(nu, 1e-300)
+    e_T = np.linalg.norm(T - TT) / np.linalg.norm(TT)
+    return e_rho, e_u, e_T
+
+
+def make_pair(stencil, nx, ny, tau, bc, fields, precision, relax=None, inlet=None):
+    from paper_2307_16766_amd import lbm
+    g = lbm.LBM(stencil, nx, ny, tau, bc, fields, precision=precision)
+    o = O.Oracle(stencil, nx, ny, tau, bc)
+    o.init(*fields)
+    if relax is not None:
+        g.set_relax(-1, **relax)
+        o.set_relax(-1, **relax)
+    if inlet is not None:
+        side, U = inlet
+        g.set_inlet(side, U)
+        o.set_inlet(side, U)
+    return g, o
+
+
+def check_fields(name, precision, n, gpu, ref, tol=None):
+    """Assert parity of (rho, u, T) after n steps; returns the relative errors."""
+    rel, floor = TOL[precision] if tol is None else tol
+    errs = rel_errors(gpu, ref)
+    assert all(np.isfinite(errs)), (name, n, errs)
+    assert errs[0] <= rel and errs[2] <= rel, f"{name} {precision} step {n}: rel errors rho/u/T = {errs}"
+    du = math.sqrt(np.mean((gpu[1] - ref[1]) ** 2 + (gpu[2] - ref[2]) ** 2))
+    uref = math.sqrt(np.mean(ref[1] ** 2 + ref[2] ** 2))
+    assert du <= rel * uref + floor * (n + 1), f"{name} {precision} step {n}: rms du {du:.3e}, rms u {uref:.3e}"
+    return errs
+
+
+def compare_run(name, stencil, nx, ny, tau, bc, fields, precision, steps, relax=None, inlet=None, tol=None):
+    """Step both implementations, comparing after every listed step count.  Returns worst errors."""
+    log(f"[gpu-case] {name} {precision} {nx}x{ny} D2Q{stencil} bc={bc} steps={steps}")
+    g, o = make_pair(stencil, nx, ny, tau, bc, fields, precision, relax, inlet)
+    worst = [0.0, 0.0, 0.0]
+    done = 0
+    for n in steps:
+        g.step(n - done)
+        o.step(n - done)
+        done = n
+        errs = check_fields(name, precision, n, g.macro_numpy(), o.macro(), tol)
+        worst = [max(a, b) for a, b in zip(worst, errs)]
+    g.close()
+    log(f"[gpu-case] {name} {precision} ok worst rel errors rho/u/T = {worst}")
+    return worst
+
+
+def smooth_random(nx, ny, seed, amp):
+    rng = np.random.default_rng(seed)
+    X, Y = W.grid(nx, ny)
+    out = np.zeros((ny, nx))
+    for _ in range(4):
+        kx, ky = rng.integers(1, 3, 2)
+        out += amp * rng.uniform(-1, 1) * np.sin(2 * np.pi * (kx * X / nx + ky * Y / ny) + rng.uniform(0, 6))
+    return out

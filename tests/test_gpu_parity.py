@@ -1,0 +1,87 @@
+"""GPU parity: the HIP library against the FP64 oracle, node by node, on seeded inputs.
+
+Small grids are compared after every early step; multi-tile grids span several bulk work-groups,
+several boundary chunks per side and a ragged last chunk."""
+import numpy as np
+import pytest
+
+from gpu_cases import CS_37, TAU_37, compare_run, smooth_random
+from paper_2307_16766_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+PRECISIONS = ["fp64", "fp32dev"]
+EARLY = [1, 2, 3, 5, 10, 30, 60]
+RELAX = dict(sigma=0.25, alpha=0.1, mach=0.05)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_d2q9_pulse_lodi_relax_x(precision):
+    nx, ny = 40, 24
+    f = W.gaussian_density_pulse(nx, ny, amp=1e-3, width=4.0)
+    compare_run("d2q9-pulse", 9, nx, ny, 0.6, ["lodi_relax", "lodi_relax", "periodic", "periodic"], f, precision,
+                EARLY, relax=dict(sigma=0.25))
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_d2q9_corners(precision):
+    nx, ny = 36, 30
+    f = W.gaussian_density_pulse(nx, ny, amp=1e-3, width=4.0)
+    compare_run("d2q9-corners", 9, nx, ny, 0.6, ["lodi_relax", "lodi", "lodi_relax", "lodi"], f, precision, EARLY,
+                relax=RELAX)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_d2q37_pulse_four_sides(precision):
+    nx, ny = 40, 44
+    f = W.temperature_pulse(nx, ny, amp=1e-3, width=4.0)
+    compare_run("d2q37-pulse-4sides", 37, nx, ny, TAU_37, ["lodi_relax"] * 4, f, precision, EARLY, relax=RELAX)
+
+
+@pytest.mark.parametrize("bc", ["lodi", "cbc", "cbc_relax", "zg"])
+def test_d2q37_schemes_four_sides(bc):
+    nx, ny = 38, 34
+    f = W.temperature_pulse(nx, ny, amp=1e-3, width=4.0, center=(15.0, 20.0))
+    rho, ux, uy, T = f
+    ux = ux + 0.01
+    uy = uy - 0.004
+    compare_run(f"d2q37-{bc}", 37, nx, ny, TAU_37, [bc] * 4, (rho, ux, uy, T), "fp64", EARLY, relax=RELAX)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_d2q37_vortex_cbc_relax_outflow(precision):
+    nx, ny = 64, 40
+    f = W.isentropic_vortex(nx, ny, CS_37, mach=0.2, radius=6.0, strength=0.05, center=(40.0, None))
+    compare_run("d2q37-vortex", 37, nx, ny, TAU_37, ["lodi_relax", "cbc_relax", "periodic", "periodic"], f, precision,
+                EARLY, relax=dict(sigma=0.25, alpha=0.2, mach=0.2))
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_d2q37_dirichlet_inlet(precision):
+    nx, ny = 48, 32
+    (f, prof) = W.shear_layer(nx, ny, u0=0.05, thickness=4.0, noise=1e-3, seed=16766)
+    compare_run("d2q37-inlet", 37, nx, ny, TAU_37, ["dirichlet", "lodi_relax", "periodic", "periodic"], f, precision,
+                EARLY, relax=dict(sigma=0.25, mach=0.05), inlet=(0, prof))
+
+
+def test_d2q37_periodic():
+    nx, ny = 40, 30
+    f = (1 + smooth_random(nx, ny, 1, 0.01), smooth_random(nx, ny, 2, 0.03), smooth_random(nx, ny, 3, 0.03),
+         1 + smooth_random(nx, ny, 4, 0.01))
+    compare_run("d2q37-periodic", 37, nx, ny, TAU_37, ["periodic"] * 4, f, "fp64", EARLY)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_d2q37_multi_tile(precision):
+    # 300 x 200: two bulk work-groups per row with a ragged tail, 3 and 4 boundary chunks per side
+    nx, ny = 300, 200
+    f = W.temperature_pulse(nx, ny, amp=1e-3, width=10.0, center=(60.0, 150.0))
+    rho, ux, uy, T = f
+    compare_run("d2q37-multitile", 37, nx, ny, TAU_37, ["lodi_relax", "cbc_relax", "lodi_relax", "lodi_relax"],
+                (rho, ux + 0.02, uy, T), precision, [1, 5, 20], relax=RELAX)
+
+
+def test_d2q9_multi_tile():
+    nx, ny = 600, 300
+    f = W.gaussian_density_pulse(nx, ny, amp=1e-3, width=12.0, center=(40.0, 280.0))
+    compare_run("d2q9-multitile", 9, nx, ny, 0.6, ["lodi_relax"] * 4, f, "fp64", [1, 5, 20], relax=RELAX)
