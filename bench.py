@@ -1,0 +1,241 @@
+#!/usr/bin/env python
+"""Throughput benchmark of the thermal LBM with characteristic boundaries on one MI355X.
+
+Workload (the throughput configuration): D2Q37, 4096 x 2048 nodes, FP32 deviation storage,
+shear layer u_x = 0.1 tanh((y - ny/2)/10) plus seeded noise (amplitude 1e-3, seed 16766),
+equilibrium Dirichlet inlet at x = 0 with the unperturbed profile, LODI-RELAX outflow at
+x = nx-1 (sigma = 0.25), periodic in y, nu = 0.1.  One step = bulk stream + collide over every
+bulk node plus the characteristic boundary solve and reconstruction (lbm_step).
+
+Prints one JSON line: MLUPS of the FP32 deviation path over all nx*ny nodes, the roofline of the
+bulk kernel (algorithmic bytes 2 * 37 * 4 per bulk node per launch over its HIP-event-timed
+duration, against 8 TB/s), the FP64 path on the same workload, and the FP64 CPU oracle timed on
+a bounded slab of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+NX, NY = 4096, 2048
+Q = 37
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bulk_d2q37_fp32_4096x2048_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2307_16766_amd", "csrc", n) for n in ("kernels.h", "lattice.h")]
+
+
+def eprint(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(nx, ny):
+    from paper_2307_16766_amd import workloads as W
+    fields, prof = W.shear_layer(nx, ny, u0=0.1, thickness=10.0, noise=1e-3, seed=16766)
+    return fields, prof
+
+
+def relax_params(cs2):
+    # reference Mach number of the outflow: peak shear-layer speed over the adiabatic sound speed
+    return dict(sigma=0.25, alpha=0.0, mach=0.1 / math.sqrt(2.0 * cs2))
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def run_gpu(precision, steps, warmup):
+    import torch
+    from paper_2307_16766_amd import lbm
+    cs2 = lbm.lattice_info(Q)[0]
+    tau = 0.5 + 0.1 / cs2
+    fields, prof = workload(NX, NY)
+    g = lbm.LBM(Q, NX, NY, tau, ["dirichlet", "lodi_relax", "periodic", "periodic"], fields, precision=precision)
+    g.set_relax(1, **relax_params(cs2))
+    g.set_inlet(0, prof)
+    del fields
+    g.step(warmup)
+    torch.cuda.synchronize()
+    g.set_kernel_timing(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(g.stream)
+    g.step(steps)
+    e1.record(g.stream)
+    torch.cuda.synchronize()
+    step_ms = e0.elapsed_time(e1) / steps
+    kms, launches = g.bulk_kernel_time()
+    g.set_kernel_timing(False)
+    diag = g.diagnostics()
+    g.close()
+    del g
+    torch.cuda.empty_cache()
+    M = 3
+    bulk_nodes = (NX - 2 * M) * NY
+    esz = 4 if precision == "fp32dev" else 8
+    bytes_per_launch = bulk_nodes * 2 * Q * esz
+    kernel_ms = kms / max(launches, 1)
+    gbps = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
+    return {
+        "ms_per_step": step_ms,
+        "mlups": NX * NY / (step_ms * 1e-3) / 1e6,
+        "bulk_kernel_ms": kernel_ms,
+        "bulk_launches": launches,
+        "bulk_bytes_per_launch": bytes_per_launch,
+        "bulk_GBps": gbps,
+        "bulk_frac": gbps / HBM_PEAK_GBPS,
+        "mass": diag[0],
+        "finite": bool(diag[6] == 0),
+    }
+
+
+def cpu_baseline(steps=None):
+    """FP64 oracle on a 512 x 256 slab of the same workload (same BCs, same fields recipe)."""
+    from oracle import oracle as O
+    nx, ny = 512, 256
+    cs2 = O.lattice(Q)[0]
+    tau = 0.5 + 0.1 / cs2
+    fields, prof = workload(nx, ny)
+    o = O.Oracle(Q, nx, ny, tau, ["dirichlet", "lodi_relax", "periodic", "periodic"])
+    o.init(*fields)
+    o.set_relax(1, **relax_params(cs2))
+    o.set_inlet(0, prof)
+    o.step(1)
+    if steps is None:   # size the sample to about 15 s of CPU work
+        t = time.perf_counter()
+        o.step(2)
+        per = (time.perf_counter() - t) / 2
+        steps = max(3, min(400, int(15.0 / max(per, 1e-6))))
+    t = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t
+    return {
+        "value": nx * ny * steps / dt / 1e6,
+        "unit": "MLUPS",
+        "cores": O.num_threads(),
+        "kind": "oracle",
+        "sample": f"{nx}x{ny} slab of the same workload (D2Q37, Dirichlet inlet + LODI-RELAX outflow, periodic y), "
+                  f"{steps} steps, {dt:.1f} s",
+    }
+
+
+def traffic_from_profile():
+    """HBM bytes per bulk launch from the committed rocprofv3 counter summary, if it was taken on
+    the current kernel sources (else None)."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_sources_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_probe(gib):
+    """Plain device copy of known size (calibration of the FETCH_SIZE / WRITE_SIZE counters)."""
+    import torch
+    n = int(gib * (1 << 30)) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    eprint(f"copy probe: 5 copies of {n * 4} bytes")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=None)
+    ap.add_argument("--copy-probe", type=float, default=None, metavar="GIB",
+                    help="only run a plain copy of GIB gibibytes (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.copy_probe is not None:
+        copy_probe(args.copy_probe)
+        return
+    import torch
+    if not torch.cuda.is_available():
+        eprint("bench.py needs a GPU")
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    eprint(f"[bench] fp32dev {NX}x{NY}: warmup {args.warmup}, steps {args.steps}")
+    r32 = run_gpu("fp32dev", args.steps, args.warmup)
+    eprint(f"[bench] fp32dev: {r32['ms_per_step']:.3f} ms/step, bulk {r32['bulk_kernel_ms']:.3f} ms, "
+           f"{r32['bulk_GBps']:.0f} GB/s")
+    r64 = None
+    if not args.no_fp64:
+        s64 = max(10, args.steps // 2)
+        eprint(f"[bench] fp64 {NX}x{NY}: steps {s64}")
+        r64 = run_gpu("fp64", s64, max(5, args.warmup // 2))
+        eprint(f"[bench] fp64: {r64['ms_per_step']:.3f} ms/step, bulk {r64['bulk_GBps']:.0f} GB/s")
+    cpu = None
+    if not args.no_cpu_baseline:
+        eprint("[bench] cpu baseline (oracle)")
+        cpu = cpu_baseline(args.cpu_steps)
+        eprint(f"[bench] cpu baseline: {cpu['value']:.3f} MLUPS on {cpu['cores']} threads")
+    traffic = traffic_from_profile()
+    out = {
+        "metric": "MLUPS, D2Q37 FP32 deviation storage (HBM roofline fraction; FP64 path alongside)",
+        "value": r32["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "D2Q37 shear-layer throughput run 4096x2048, FP32 deviation storage, "
+                        "Dirichlet inlet + LODI-RELAX outflow, periodic y, 1 GPU",
+            "nx": NX, "ny": NY, "stencil": "D2Q37", "precision": "fp32dev", "nu": 0.1,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": r32["bulk_GBps"],
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": r32["bulk_frac"],
+            "traffic": traffic,
+            "kernel": "k_bulk<37,float>",
+            "kernel_ms": r32["bulk_kernel_ms"],
+            "bytes_per_launch": r32["bulk_bytes_per_launch"],
+        },
+        "fp64": None if r64 is None else {
+            "mlups": r64["mlups"], "ms_per_step": r64["ms_per_step"], "bulk_GBps": r64["bulk_GBps"],
+            "bulk_frac": r64["bulk_frac"], "fp32dev_over_fp64": r32["mlups"] / r64["mlups"],
+        },
+        "cpu_baseline": cpu,
+        "finite": r32["finite"] and (r64 is None or r64["finite"]),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

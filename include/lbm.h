@@ -140,6 +140,13 @@ int lbm_restore(lbm_ctx* ctx, const void* d_buf);
 /* Number of steps taken since lbm_init (or the restored checkpoint's count). */
 long lbm_steps_done(const lbm_ctx* ctx);
 
+/* Kernel timing for measurement.  With enable != 0, lbm_step records a pair of HIP events
+ * around every bulk stream-collide launch on the caller's stream (resetting earlier records);
+ * lbm_bulk_kernel_time synchronises on them and returns the summed elapsed milliseconds and the
+ * number of timed launches.  Disabled by default; at most 65536 launches are recorded. */
+int lbm_set_kernel_timing(lbm_ctx* ctx, int enable);
+int lbm_bulk_kernel_time(lbm_ctx* ctx, double* total_ms, long* launches);
+
 /* Lattice constants used by the library (host pointers, arrays of q entries, library order).
  * Returns q, or a negative code for an unknown stencil. */
 int lbm_lattice_info(int stencil, int* M, double* cs2, double* w, int* cx, int* cy);

@@ -50,6 +50,9 @@
 #include <cstring>
 #include <string>
 #include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 namespace {
 
@@ -918,6 +921,14 @@ extern "C" {
 
 const char* oracle_error(void) { return g_err.c_str(); }
 
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 int oracle_lattice(int stencil, int* q, int* M, double* cs2, double* w, int* cx, int* cy) {
     if (stencil != 9 && stencil != 37) return -1;
     const Lattice& L = lattice(stencil);
@@ -965,10 +976,21 @@ int oracle_set_relax(void* h, int side, const double* p) {
     return 0;
 }
 
+// Fixed profile of a Dirichlet side [len][4]; it takes effect at once: the boundary layers get
+// the equilibrium populations of the profile.
 int oracle_set_inlet(void* h, int side, const double* Uin) {
     auto* s = static_cast<Sim<double>*>(h);
     if (side < 0 || side > 3 || s->bc[side] != BC_DIRICHLET) return -1;
     for (size_t k = 0; k < s->inlet[side].size(); ++k) s->inlet[side][k] = Uin[k];
+    const SideGeo& g = s->geo[side];
+    for (int r = 0; r < g.len; ++r)
+        for (int j = 1; j <= s->M; ++j) {
+            int x, y; s->node(g, j, r, x, y);
+            const double* u4 = &s->inlet[side][(size_t)r * 4];
+            s->setU(s->U, x, y, u4);
+            s->node_feq(s->f, x, y, u4);
+            s->node_feq(s->fpre, x, y, u4);
+        }
     return 0;
 }
 

@@ -31,6 +31,7 @@ def lib():
             _build.build()
         L = ctypes.CDLL(path)
         L.oracle_error.restype = ctypes.c_char_p
+        L.oracle_num_threads.restype = ctypes.c_int
         L.oracle_lattice.argtypes = [ctypes.c_int, _ip, _ip, _dp, _dp, _ip, _ip]
         L.oracle_feq.argtypes = [ctypes.c_int] + [ctypes.c_double] * 4 + [_dp]
         L.oracle_moments.argtypes = [ctypes.c_int, _dp, _dp]
@@ -53,6 +54,11 @@ def lib():
                                          _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int, _dp]
         _LIB = L
     return _LIB
+
+
+def num_threads():
+    """Threads the oracle's OpenMP loops use."""
+    return lib().oracle_num_threads()
 
 
 def lattice(stencil):

@@ -13,6 +13,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "kernels.h"
 #include "lbm.h"
@@ -168,6 +169,10 @@ struct lbm_ctx {
     lbm_relax relax[4];
     BulkArgs bulk;
     std::string err;
+    // bulk kernel timing (measurement only)
+    bool timing = false;
+    std::vector<hipEvent_t> tev;   // pairs: start, end
+    size_t tcount = 0;             // recorded pairs
 };
 
 namespace {
@@ -216,6 +221,33 @@ BndArgs make_bnd(const lbm_ctx* c) {
     return a;
 }
 
+constexpr size_t MAX_TIMED = 65536;
+
+// launch the bulk kernel, bracketed by timing events when kernel timing is on
+template <typename F>
+hipError_t timed_bulk(lbm_ctx* c, F&& bulk) {
+    const bool rec = c->timing && c->tcount < MAX_TIMED;
+    if (rec) {
+        while (c->tev.size() < 2 * (c->tcount + 1)) {
+            hipEvent_t e;
+            const hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+            c->tev.push_back(e);
+        }
+        const hipError_t r = hipEventRecord(c->tev[2 * c->tcount], c->stream);
+        if (r != hipSuccess) return r;
+    }
+    bulk(c->stream);
+    hipError_t r = hipGetLastError();
+    if (r != hipSuccess) return r;
+    if (rec) {
+        r = hipEventRecord(c->tev[2 * c->tcount + 1], c->stream);
+        if (r != hipSuccess) return r;
+        c->tcount += 1;
+    }
+    return hipSuccess;
+}
+
 template <int Q, typename T>
 int launch_step(lbm_ctx* c) {
     const BndArgs a = make_bnd(c);
@@ -236,12 +268,10 @@ int launch_step(lbm_ctx* c) {
         hipLaunchKernelGGL((k_boundary<Q, T>), dim3(c->nbnd), dim3(256), 0, c->aux, A, B, a);
         HIPCHK(c, hipGetLastError());
         HIPCHK(c, hipEventRecord(c->ev_aux, c->aux));
-        bulk(c->stream);
-        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, timed_bulk(c, bulk));
         HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_aux, 0));
     } else {
-        bulk(c->stream);
-        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, timed_bulk(c, bulk));
     }
     c->cur ^= 1;
     c->steps += 1;
@@ -460,6 +490,28 @@ int lbm_restore(lbm_ctx* c, const void* d_buf) {
 
 long lbm_steps_done(const lbm_ctx* c) { return c ? c->steps : -1; }
 
+int lbm_set_kernel_timing(lbm_ctx* c, int enable) {
+    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+    c->timing = enable != 0;
+    c->tcount = 0;
+    return LBM_OK;
+}
+
+int lbm_bulk_kernel_time(lbm_ctx* c, double* total_ms, long* launches) {
+    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+    if (!total_ms || !launches) return fail(c, LBM_E_ARG, "output pointer is NULL");
+    double sum = 0.0;
+    for (size_t k = 0; k < c->tcount; ++k) {
+        HIPCHK(c, hipEventSynchronize(c->tev[2 * k + 1]));
+        float ms = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->tev[2 * k], c->tev[2 * k + 1]));
+        sum += ms;
+    }
+    *total_ms = sum;
+    *launches = (long)c->tcount;
+    return LBM_OK;
+}
+
 int lbm_lattice_info(int stencil, int* M, double* cs2, double* w, int* cxo, int* cyo) {
     if (stencil == 9) {
         if (M) *M = 1;
@@ -484,6 +536,7 @@ void lbm_destroy(lbm_ctx* c) {
     if (c->aux) { (void)hipStreamSynchronize(c->aux); (void)hipStreamDestroy(c->aux); }
     if (c->ev_main) (void)hipEventDestroy(c->ev_main);
     if (c->ev_aux) (void)hipEventDestroy(c->ev_aux);
+    for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
     delete c;
 }
 

@@ -22,7 +22,8 @@ PRECISION = {"fp64": FP64, "fp32dev": FP32DEV}
 # exported symbols, as declared in include/lbm.h
 SYMBOLS = ["lbm_workspace_bytes", "lbm_init", "lbm_cbc_params", "lbm_dirichlet_profile", "lbm_step",
            "lbm_macroscopic", "lbm_boundary_state", "lbm_diagnostics", "lbm_state_bytes", "lbm_save",
-           "lbm_restore", "lbm_steps_done", "lbm_lattice_info", "lbm_last_error", "lbm_destroy"]
+           "lbm_restore", "lbm_steps_done", "lbm_set_kernel_timing", "lbm_bulk_kernel_time",
+           "lbm_lattice_info", "lbm_last_error", "lbm_destroy"]
 
 
 class LBMError(RuntimeError):
@@ -70,6 +71,8 @@ def load():
     L.lbm_restore.argtypes = [_vp, _vp]
     L.lbm_steps_done.restype = ctypes.c_long
     L.lbm_steps_done.argtypes = [_vp]
+    L.lbm_set_kernel_timing.argtypes = [_vp, ctypes.c_int]
+    L.lbm_bulk_kernel_time.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_long)]
     L.lbm_lattice_info.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
                                    ctypes.POINTER(ctypes.c_int)]
@@ -204,3 +207,13 @@ class LBM:
 
     def steps_done(self):
         return load().lbm_steps_done(self.ctx)
+
+    def set_kernel_timing(self, enable=True):
+        self._check(load().lbm_set_kernel_timing(self.ctx, 1 if enable else 0))
+
+    def bulk_kernel_time(self):
+        """(summed milliseconds, launches) of the timed bulk kernel launches."""
+        ms = ctypes.c_double()
+        n = ctypes.c_long()
+        self._check(load().lbm_bulk_kernel_time(self.ctx, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
