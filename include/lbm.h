@@ -19,7 +19,7 @@
  *   - Memory: every pointer argument named d_* is device memory on the current HIP device.
  *     The caller owns all device memory (workspace, fields, checkpoint buffers) and the HIP
  *     stream; the library borrows them until lbm_destroy.  The library owns only its host-side
- *     context and one auxiliary HIP stream (default priority) plus two events.
+ *     context (and, while kernel timing is enabled, the timing events).
  *   - Asynchrony: every call that takes a context enqueues work on the caller's stream and
  *     returns without synchronising, except lbm_diagnostics, which synchronises.
  *   - Errors: functions return LBM_OK (0) or a negative code; nothing throws across the ABI.
@@ -141,9 +141,10 @@ int lbm_restore(lbm_ctx* ctx, const void* d_buf);
 long lbm_steps_done(const lbm_ctx* ctx);
 
 /* Kernel timing for measurement.  With enable != 0, lbm_step records a pair of HIP events
- * around every bulk stream-collide launch on the caller's stream (resetting earlier records);
- * lbm_bulk_kernel_time synchronises on them and returns the summed elapsed milliseconds and the
- * number of timed launches.  Disabled by default; at most 65536 launches are recorded. */
+ * around every step kernel launch (fused bulk stream-collide and boundary solve) on the
+ * caller's stream (resetting earlier records); lbm_bulk_kernel_time synchronises on them and
+ * returns the summed elapsed milliseconds and the number of timed launches.  Disabled by
+ * default; at most 65536 launches are recorded. */
 int lbm_set_kernel_timing(lbm_ctx* ctx, int enable);
 int lbm_bulk_kernel_time(lbm_ctx* ctx, double* total_ms, long* launches);
 

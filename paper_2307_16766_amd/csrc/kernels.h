@@ -1,18 +1,22 @@
 // kernels.h -- HIP kernels of the thermal LBM with characteristic boundaries (gfx950).
 //
 // Data layout in HBM (one context):
-//   f[2]   : two population buffers, structure of arrays f[i][y][x] (plane stride P elements,
-//            a multiple of 64), storing deviations f_i - w_i in T = double or float.
+//   f[2]   : two population buffers in row-interleaved structure-of-arrays order f[y][i][x]
+//            (the q planes of one row are contiguous; row pitch padded to a multiple of 64
+//            elements so every plane segment starts on a 256-byte boundary), storing the
+//            deviations f_i - w_i in T = double or float.  Interleaving the planes per row keeps
+//            the write stream of a row of work-groups in one contiguous region.
 //   region : two parity copies of the boundary solver state (FP64): per characteristic side
 //            U_b[M][len][4], the bulk strip U[MS][len][4] at x_f (and x_f - 1 for M = 1), the
 //            viscous moments [3][len][6] at x_f, x_f-1, x_f-2; per corner U_c[4] and the two
 //            inward diagonal bulk nodes [2][4].  Parity p holds time level n with n % 2 = p.
-// One time step n -> n+1 is two kernels that run concurrently on two streams:
-//   k_bulk      : pull-stream + moments + equilibrium + BGK for every bulk node, A -> B;
-//   k_boundary  : one work-group per chunk of rows of a side; re-pulls the strip from A,
-//                 integrates the characteristic system with RK4 in LDS and writes the
-//                 equilibrium populations of the M boundary layers of B.
-// Both only read A and write disjoint nodes of B.
+// One time step n -> n+1 is one launch of k_step: its first work-groups each take a chunk of
+// rows of a boundary side (re-pull of the strip from A, RK4 of the characteristic system in
+// LDS, equilibrium populations of the M boundary layers of B); the remaining work-groups each
+// take 256 bulk nodes of one row (pull-stream + moments + equilibrium + BGK, A -> B).  Both
+// kinds only read A and write disjoint nodes of B, so they need no ordering among themselves.
+// The boundary path's LDS (and registers) cap the launch at 2-3 work-groups per CU, which is
+// also the occupancy at which this many-stream access pattern streams fastest from HBM.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -27,7 +31,7 @@ enum { KIND_NONE = 0, KIND_CHAR = 1, KIND_ZG = 2, KIND_DIRICHLET = 3 };
 struct SideDev {
     int kind, scheme;
     int nax, sn, Nn, Nt, r0, len, xf, tper;
-    int blk0, nblk, rows;        // work-groups of this side in k_boundary, rows per work-group
+    int blk0, nblk, rows;        // boundary work-groups of this side in k_step, rows per work-group
     int corner_lo, corner_hi;    // corners at row -1 / row len (non-periodic tangent), else -1
     int owns_corners;            // x-sides write the corner blocks
     double K, alpha, Pinf;       // relaxation (eq. LODI-Relax / CBC-Relax)
@@ -44,7 +48,7 @@ struct CornerDev {
 
 struct BndArgs {
     int nx, ny, nbulk_x0, nbulk_x1, nbulk_y0, nbulk_y1, xper, yper;
-    unsigned long long P;
+    unsigned long long pitch;   // padded row length (elements) of one population plane row
     double omega, tau;
     char* reg_cur;    // parity region of time level n
     char* reg_next;   // parity region of time level n+1
@@ -55,6 +59,12 @@ struct BndArgs {
 __device__ __forceinline__ int wrapi(int v, int n) {
     v = v < 0 ? v + n : v;
     return v >= n ? v - n : v;
+}
+
+// element of population i at node (x, y)
+template <int Q>
+__device__ __forceinline__ unsigned long long pix(unsigned long long pitch, int i, int x, int y) {
+    return ((unsigned long long)y * Q + i) * pitch + x;
 }
 
 // node of side s at outward index k (k = 0: x_f, k = j: layer x_{b,j}) and physical row r
@@ -72,54 +82,63 @@ __device__ __forceinline__ void pull_node(const T* __restrict__ A, const BndArgs
         int xs = x - cx<Q>(i), ys = y - cy<Q>(i);
         if (a.xper) xs = wrapi(xs, a.nx);
         if (a.yper) ys = wrapi(ys, a.ny);
-        d[i] = (double)A[(unsigned long long)i * a.P + (unsigned long long)ys * a.nx + xs];
+        d[i] = (double)A[pix<Q>(a.pitch, i, xs, ys)];
     }
 }
 
 // ================================================================== bulk: fused stream + collide
 struct BulkArgs {
     int nx, ny, x0, x1, y0, y1;   // bulk node range (inclusive)
-    unsigned long long P;
+    unsigned long long pitch;
     float omega_f;
     double omega_d;
 };
 
+// One thread per node.  Work-group x-ranges start at x = 0 (multiples of 256), so every
+// wavefront's store of a plane is one aligned 256 B (float) / 512 B (double) segment; lanes
+// outside the bulk range do nothing.  Loads are ordinary (cached) loads, issued source row by
+// source row: the shifted pulls of neighbouring wavefronts share cache lines at their edges,
+// which L2 serves once.  Stores are non-temporal: the output is not re-read in this step.
 template <int Q, typename T, bool PX, bool PY>
-__global__ __launch_bounds__(256) void k_bulk(const T* __restrict__ A, T* __restrict__ B, BulkArgs g) {
-    const int x = g.x0 + (int)(blockIdx.x * 256 + threadIdx.x);
-    const int y = g.y0 + (int)blockIdx.y;
-    if (x > g.x1) return;
+__device__ __forceinline__ void bulk_node(const T* __restrict__ A, T* __restrict__ B, const BulkArgs& g, int x, int y) {
+    if (x < g.x0 || x > g.x1) return;
     T d[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        int xs = x - cx<Q>(i);
-        int ys = y - cy<Q>(i);
-        if (PX) xs = wrapi(xs, g.nx);
+    for (int dy = -Lat<Q>::M; dy <= Lat<Q>::M; ++dy) {
+        int ys = y - dy;
         if (PY) ys = wrapi(ys, g.ny);
-        const T* Ai = A + (unsigned long long)i * g.P + (unsigned long long)ys * g.nx;
-        d[i] = __builtin_nontemporal_load(Ai + xs);
+        const T* Ar = A + pix<Q>(g.pitch, 0, 0, ys);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            if (cy<Q>(i) != dy) continue;
+            int xs = x - cx<Q>(i);
+            if (PX) xs = wrapi(xs, g.nx);
+            d[i] = Ar[(unsigned long long)i * g.pitch + xs];
+        }
     }
     const T omega = sizeof(T) == 4 ? (T)g.omega_f : (T)g.omega_d;
     collide_dev<Q, T>(d, omega);
-    T* Bo = B + (unsigned long long)y * g.nx + x;
+    T* Bo = B + pix<Q>(g.pitch, 0, x, y);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(d[i], Bo + (unsigned long long)i * g.P);
+    for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(d[i], Bo + (unsigned long long)i * g.pitch);
 }
 
 // ================================================================== initialisation
 template <int Q, typename T>
 __global__ __launch_bounds__(256) void k_init_fields(const double* __restrict__ rho, const double* __restrict__ ux,
                                                      const double* __restrict__ uy, const double* __restrict__ Tf,
-                                                     T* __restrict__ A, T* __restrict__ B, int n, unsigned long long P) {
+                                                     T* __restrict__ A, T* __restrict__ B, int nx, int n,
+                                                     unsigned long long pitch) {
     const int id = blockIdx.x * 256 + threadIdx.x;
     if (id >= n) return;
+    const int x = id % nx, y = id / nx;
     double fe[Q];
     const double th = (Lat<Q>::thermal && Tf) ? Tf[id] - 1.0 : 0.0;
     feq_dev<Q, double>(rho[id] - 1.0, ux[id], uy[id], th, fe);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        A[(unsigned long long)i * P + id] = (T)fe[i];
-        B[(unsigned long long)i * P + id] = (T)fe[i];
+        A[pix<Q>(pitch, i, x, y)] = (T)fe[i];
+        B[pix<Q>(pitch, i, x, y)] = (T)fe[i];
     }
 }
 
@@ -197,20 +216,21 @@ __global__ __launch_bounds__(256) void k_dirichlet(BndArgs a, int s, const doubl
     const double* u = prof + (size_t)r * 4;
     double fe[Q];
     feq_dev<Q, double>(u[0] - 1.0, u[1], u[2], Lat<Q>::thermal ? u[3] - 1.0 : 0.0, fe);
-    const unsigned long long id = (unsigned long long)y * a.nx + x;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) { A[i * a.P + id] = (T)fe[i]; B[i * a.P + id] = (T)fe[i]; }
+    for (int i = 0; i < Q; ++i) { A[pix<Q>(a.pitch, i, x, y)] = (T)fe[i]; B[pix<Q>(a.pitch, i, x, y)] = (T)fe[i]; }
 }
 
 // ================================================================== macroscopic output
 template <int Q, typename T>
-__global__ __launch_bounds__(256) void k_macro(const T* __restrict__ A, int n, unsigned long long P, double* __restrict__ rho,
-                                               double* __restrict__ ux, double* __restrict__ uy, double* __restrict__ Tf) {
+__global__ __launch_bounds__(256) void k_macro(const T* __restrict__ A, int nx, int n, unsigned long long pitch,
+                                               double* __restrict__ rho, double* __restrict__ ux, double* __restrict__ uy,
+                                               double* __restrict__ Tf) {
     const int id = blockIdx.x * 256 + threadIdx.x;
     if (id >= n) return;
+    const int x = id % nx, y = id / nx;
     double d[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) d[i] = (double)A[(unsigned long long)i * P + id];
+    for (int i = 0; i < Q; ++i) d[i] = (double)A[pix<Q>(pitch, i, x, y)];
     double rm1, u, v, th;
     moments_dev<Q, double>(d, rm1, u, v, th);
     rho[id] = 1.0 + rm1; ux[id] = u; uy[id] = v;
@@ -231,16 +251,17 @@ __device__ __forceinline__ double wave_max(double v) {
 
 // partial[blk][8]: mass, jx, jy, energy, loss, max|u|, non-finite count, 0
 template <int Q, typename T>
-__global__ __launch_bounds__(256) void k_diag_partial(const T* __restrict__ A, int nx, int ny, unsigned long long P,
+__global__ __launch_bounds__(256) void k_diag_partial(const T* __restrict__ A, int nx, int ny, unsigned long long pitch,
                                                       int bx0, int bx1, int by0, int by1, double* __restrict__ partial) {
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};
     const int n = nx * ny;
     for (int id = blockIdx.x * 256 + threadIdx.x; id < n; id += gridDim.x * 256) {
         double d[Q];
         double bad = 0.0;
+        const int x = id % nx, y = id / nx;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            d[i] = (double)A[(unsigned long long)i * P + id];
+            d[i] = (double)A[pix<Q>(pitch, i, x, y)];
             bad += (isfinite(d[i]) ? 0.0 : 1.0);
         }
         double rm1, u, v, th;
@@ -250,7 +271,6 @@ __global__ __launch_bounds__(256) void k_diag_partial(const T* __restrict__ A, i
 #pragma unroll
         for (int i = 0; i < Q; ++i) e += 0.5 * (double)c2<Q>(i) * d[i];
         acc[0] += r; acc[1] += r * u; acc[2] += r * v; acc[3] += e;
-        const int x = id % nx, y = id / nx;
         if (x >= bx0 && x <= bx1 && y >= by0 && y <= by1) {
             const double p = Lat<Q>::cs2 * (rm1 + th + rm1 * th);   // P - cs^2
             acc[4] += p * p;
@@ -443,12 +463,11 @@ __device__ __forceinline__ void corner_rate(const CornerDev& c, const double* Uc
 }
 
 template <int Q, typename T>
-__device__ __forceinline__ void write_feq(T* __restrict__ B, unsigned long long P, int nx, int x, int y, const double* u4) {
+__device__ __forceinline__ void write_feq(T* __restrict__ B, unsigned long long pitch, int x, int y, const double* u4) {
     double fe[Q];
     feq_dev<Q, double>(u4[0] - 1.0, u4[1], u4[2], Lat<Q>::thermal ? u4[3] - 1.0 : 0.0, fe);
-    const unsigned long long id = (unsigned long long)y * nx + x;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) B[i * P + id] = (T)fe[i];
+    for (int i = 0; i < Q; ++i) B[pix<Q>(pitch, i, x, y)] = (T)fe[i];
 }
 
 // one corner: RK4 of the diagonal LODI system; returns U_c^{n+1}; the x-side's work-group also
@@ -487,7 +506,7 @@ __device__ void corner_step(const T* __restrict__ A, T* __restrict__ B, const Bn
         double* cdn = (double*)(a.reg_next + c.off_cd);
         for (int m = 0; m < 4; ++m) { cun[m] = acc[m]; cdn[m] = D1p[m]; cdn[4 + m] = D2p[m]; }
         for (int jx = 0; jx < M; ++jx)
-            for (int jy = 0; jy < M; ++jy) write_feq<Q, T>(B, a.P, a.nx, c.x0 + c.sxn * jx, c.y0 + c.syn * jy, acc);
+            for (int jy = 0; jy < M; ++jy) write_feq<Q, T>(B, a.pitch, c.x0 + c.sxn * jx, c.y0 + c.syn * jy, acc);
     }
 }
 
@@ -661,7 +680,7 @@ __device__ void char_chunk(const T* __restrict__ A, T* __restrict__ B, const Bnd
         const double* u4 = &sAcc[(lr * M + j) * 4];
         for (int m = 0; m < 4; ++m) ubn[((size_t)j * len + r) * 4 + m] = u4[m];
         int x, y; side_node(sd, j + 1, r, x, y);
-        write_feq<Q, T>(B, a.P, a.nx, x, y, u4);
+        write_feq<Q, T>(B, a.pitch, x, y, u4);
     }
 }
 
@@ -679,14 +698,13 @@ __device__ void zg_chunk(const T* __restrict__ A, T* __restrict__ B, const BndAr
             int xs = x - cx<Q>(i), ys = y - cy<Q>(i);
             if (a.xper) xs = wrapi(xs, a.nx);
             if (a.yper) ys = wrapi(ys, a.ny);
-            d[i] = A[(unsigned long long)i * a.P + (unsigned long long)ys * a.nx + xs];
+            d[i] = A[pix<Q>(a.pitch, i, xs, ys)];
         }
         collide_dev<Q, T>(d, omega);
         for (int j = 1; j <= M; ++j) {
             int xb, yb; side_node(sd, j, r, xb, yb);
-            const unsigned long long id = (unsigned long long)yb * a.nx + xb;
 #pragma unroll
-            for (int i = 0; i < Q; ++i) B[i * a.P + id] = d[i];
+            for (int i = 0; i < Q; ++i) B[pix<Q>(a.pitch, i, xb, yb)] = d[i];
         }
     }
     // corner blocks copy the post-collision state of the inward diagonal node
@@ -701,28 +719,45 @@ __device__ void zg_chunk(const T* __restrict__ A, T* __restrict__ B, const BndAr
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 int xs = x - cx<Q>(i), ys = y - cy<Q>(i);
-                d[i] = A[(unsigned long long)i * a.P + (unsigned long long)ys * a.nx + xs];
+                d[i] = A[pix<Q>(a.pitch, i, xs, ys)];
             }
             collide_dev<Q, T>(d, omega);
             for (int jx = 0; jx < M; ++jx)
                 for (int jy = 0; jy < M; ++jy) {
-                    const unsigned long long id = (unsigned long long)(c.y0 + c.syn * jy) * a.nx + (c.x0 + c.sxn * jx);
 #pragma unroll
-                    for (int i = 0; i < Q; ++i) B[i * a.P + id] = d[i];
+                    for (int i = 0; i < Q; ++i) B[pix<Q>(a.pitch, i, c.x0 + c.sxn * jx, c.y0 + c.syn * jy)] = d[i];
                 }
         }
     }
 }
 
+// one boundary work-group: find its side and chunk
 template <int Q, typename T>
-__global__ __launch_bounds__(256) void k_boundary(const T* __restrict__ A, T* __restrict__ B, BndArgs a) {
-    const int b = blockIdx.x;
+__device__ __forceinline__ void boundary_job(const T* __restrict__ A, T* __restrict__ B, const BndArgs& a, int b) {
     int s = 0;
     while (s < 4 && !(a.s[s].nblk > 0 && b >= a.s[s].blk0 && b < a.s[s].blk0 + a.s[s].nblk)) ++s;
     if (s == 4) return;
     const SideDev& sd = a.s[s];
     if (sd.kind == KIND_CHAR) char_chunk<Q, T>(A, B, a, sd, b - sd.blk0);
     else if (sd.kind == KIND_ZG) zg_chunk<Q, T>(A, B, a, sd, b - sd.blk0);
+}
+
+// Waves per SIMD the step kernel is compiled for: 3 for D2Q37 in float (caps registers at 168
+// and matches the 3 work-groups per CU that the boundary LDS allows), 2 otherwise.
+template <int Q, typename T> struct StepOcc { static constexpr int waves = (Q == 37 && sizeof(T) == 4) ? 3 : 2; };
+
+// one full time step: work-groups [0, nbnd) are boundary chunks, the rest bulk tiles of 256
+// nodes (bpr tiles per row, rows from g.y0)
+template <int Q, typename T, bool PX, bool PY>
+__global__ __launch_bounds__(256, (StepOcc<Q, T>::waves)) void k_step(const T* __restrict__ A, T* __restrict__ B, BndArgs a,
+                                                                     BulkArgs g, int nbnd, int bpr) {
+    const int b = (int)blockIdx.x;
+    if (b < nbnd) {
+        boundary_job<Q, T>(A, B, a, b);
+        return;
+    }
+    const int t = b - nbnd;
+    bulk_node<Q, T, PX, PY>(A, B, g, (t % bpr) * 256 + (int)threadIdx.x, g.y0 + t / bpr);
 }
 
 }  // namespace lbm

@@ -2,8 +2,7 @@
 //
 // The library owns no device memory: the caller's workspace is carved into two population
 // buffers, two parity copies of the boundary solver state, the Dirichlet profiles and the
-// diagnostics scratch.  One step launches the bulk kernel on the caller's stream and the
-// boundary kernel on an auxiliary stream; two events order step n+1 after step n.
+// diagnostics scratch.  One step is one kernel launch (k_step) on the caller's stream.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -37,7 +36,7 @@ int chunk_rows(int M) { return 256 / M - 8; }   // must match NR - 8 in char_chu
 struct Layout {
     int Q = 0, M = 0, MS = 0;
     size_t esz = 0;
-    unsigned long long P = 0;
+    unsigned long long pitch = 0;   // padded row length of a population plane (elements)
     size_t f_bytes = 0, region_bytes = 0, off_region = 0, off_inlet[4] = {0, 0, 0, 0}, off_diag = 0, total = 0;
     int diag_blocks = 0;
     SideDev s[4];
@@ -76,8 +75,8 @@ void make_layout(const lbm_config* c, Layout& L) {
     L.MS = L.M == 1 ? 2 : 1;
     L.esz = c->precision == LBM_FP64 ? 8 : 4;
     const unsigned long long n = (unsigned long long)c->nx * c->ny;
-    L.P = (n + 63) / 64 * 64;
-    L.f_bytes = align_up((size_t)L.Q * L.P * L.esz);
+    L.pitch = ((unsigned long long)c->nx + 63) / 64 * 64;
+    L.f_bytes = align_up((size_t)L.Q * L.pitch * c->ny * L.esz);
     const bool xp = c->bc[0] == BC_PERIODIC, yp = c->bc[2] == BC_PERIODIC;
     size_t reg = 0;
     int blk = 0;
@@ -163,8 +162,7 @@ struct lbm_ctx {
     int cur = 0;
     long steps = 0;
     long save_steps = 0;
-    hipStream_t stream = nullptr, aux = nullptr;
-    hipEvent_t ev_main = nullptr, ev_aux = nullptr;
+    hipStream_t stream = nullptr;
     int nbnd = 0;
     lbm_relax relax[4];
     BulkArgs bulk;
@@ -195,7 +193,7 @@ BndArgs make_bnd(const lbm_ctx* c) {
     a.nx = g.nx; a.ny = g.ny;
     a.xper = g.bc[0] == BC_PERIODIC;
     a.yper = g.bc[2] == BC_PERIODIC;
-    a.P = c->L.P;
+    a.pitch = c->L.pitch;
     a.omega = 1.0 / g.tau;
     a.tau = g.tau;
     a.reg_cur = c->region[c->cur];
@@ -223,9 +221,9 @@ BndArgs make_bnd(const lbm_ctx* c) {
 
 constexpr size_t MAX_TIMED = 65536;
 
-// launch the bulk kernel, bracketed by timing events when kernel timing is on
+// launch the step kernel, bracketed by timing events when kernel timing is on
 template <typename F>
-hipError_t timed_bulk(lbm_ctx* c, F&& bulk) {
+hipError_t timed_launch(lbm_ctx* c, F&& launch) {
     const bool rec = c->timing && c->tcount < MAX_TIMED;
     if (rec) {
         while (c->tev.size() < 2 * (c->tcount + 1)) {
@@ -237,7 +235,7 @@ hipError_t timed_bulk(lbm_ctx* c, F&& bulk) {
         const hipError_t r = hipEventRecord(c->tev[2 * c->tcount], c->stream);
         if (r != hipSuccess) return r;
     }
-    bulk(c->stream);
+    launch(c->stream);
     hipError_t r = hipGetLastError();
     if (r != hipSuccess) return r;
     if (rec) {
@@ -254,25 +252,16 @@ int launch_step(lbm_ctx* c) {
     const T* A = (const T*)c->f[c->cur];
     T* B = (T*)c->f[c->cur ^ 1];
     const BulkArgs& g = c->bulk;
-    const dim3 grid((g.x1 - g.x0 + 1 + 255) / 256, g.y1 - g.y0 + 1);
+    const int bpr = (g.x1 + 1 + 255) / 256;   // bulk tiles per row, aligned to x = 0
+    const int nblk = c->nbnd + bpr * (g.y1 - g.y0 + 1);
     const bool px = c->cfg.bc[0] == BC_PERIODIC, py = c->cfg.bc[2] == BC_PERIODIC;
-    auto bulk = [&](hipStream_t s) {
-        if (px && py) hipLaunchKernelGGL((k_bulk<Q, T, true, true>), grid, dim3(256), 0, s, A, B, g);
-        else if (px) hipLaunchKernelGGL((k_bulk<Q, T, true, false>), grid, dim3(256), 0, s, A, B, g);
-        else if (py) hipLaunchKernelGGL((k_bulk<Q, T, false, true>), grid, dim3(256), 0, s, A, B, g);
-        else hipLaunchKernelGGL((k_bulk<Q, T, false, false>), grid, dim3(256), 0, s, A, B, g);
+    auto step = [&](hipStream_t s) {
+        if (px && py) hipLaunchKernelGGL((k_step<Q, T, true, true>), dim3(nblk), dim3(256), 0, s, A, B, a, g, c->nbnd, bpr);
+        else if (px) hipLaunchKernelGGL((k_step<Q, T, true, false>), dim3(nblk), dim3(256), 0, s, A, B, a, g, c->nbnd, bpr);
+        else if (py) hipLaunchKernelGGL((k_step<Q, T, false, true>), dim3(nblk), dim3(256), 0, s, A, B, a, g, c->nbnd, bpr);
+        else hipLaunchKernelGGL((k_step<Q, T, false, false>), dim3(nblk), dim3(256), 0, s, A, B, a, g, c->nbnd, bpr);
     };
-    if (c->nbnd > 0) {
-        HIPCHK(c, hipEventRecord(c->ev_main, c->stream));
-        HIPCHK(c, hipStreamWaitEvent(c->aux, c->ev_main, 0));
-        hipLaunchKernelGGL((k_boundary<Q, T>), dim3(c->nbnd), dim3(256), 0, c->aux, A, B, a);
-        HIPCHK(c, hipGetLastError());
-        HIPCHK(c, hipEventRecord(c->ev_aux, c->aux));
-        HIPCHK(c, timed_bulk(c, bulk));
-        HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_aux, 0));
-    } else {
-        HIPCHK(c, timed_bulk(c, bulk));
-    }
+    HIPCHK(c, timed_launch(c, step));
     c->cur ^= 1;
     c->steps += 1;
     return LBM_OK;
@@ -282,7 +271,7 @@ template <int Q, typename T>
 int launch_init(lbm_ctx* c, const double* rho, const double* ux, const double* uy, const double* Tf) {
     const int n = c->cfg.nx * c->cfg.ny;
     hipLaunchKernelGGL((k_init_fields<Q, T>), dim3((n + 255) / 256), dim3(256), 0, c->stream, rho, ux, uy,
-                       Q == 37 ? Tf : nullptr, (T*)c->f[0], (T*)c->f[1], n, c->L.P);
+                       Q == 37 ? Tf : nullptr, (T*)c->f[0], (T*)c->f[1], c->cfg.nx, n, c->L.pitch);
     HIPCHK(c, hipGetLastError());
     const BndArgs a = make_bnd(c);
     int maxlen = 1;
@@ -352,19 +341,9 @@ int lbm_init(const lbm_config* cfg, void* d_workspace, size_t workspace_bytes, v
     c->bulk.nx = cfg->nx; c->bulk.ny = cfg->ny;
     c->bulk.x0 = xp ? 0 : M; c->bulk.x1 = xp ? cfg->nx - 1 : cfg->nx - 1 - M;
     c->bulk.y0 = yp ? 0 : M; c->bulk.y1 = yp ? cfg->ny - 1 : cfg->ny - 1 - M;
-    c->bulk.P = c->L.P;
+    c->bulk.pitch = c->L.pitch;
     c->bulk.omega_d = 1.0 / cfg->tau;
     c->bulk.omega_f = (float)(1.0 / cfg->tau);
-    if (c->nbnd > 0) {
-        hipError_t e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_main, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_aux, hipEventDisableTiming);
-        if (e != hipSuccess) {
-            std::string m = std::string("stream/event creation: ") + hipGetErrorString(e);
-            lbm_destroy(c);
-            return fail(nullptr, LBM_E_HIP, m);
-        }
-    }
     const int rc = dispatch(c, [&]<int Q, typename T>() -> int { return launch_init<Q, T>(c, d_rho0, d_ux0, d_uy0, d_T0); });
     if (rc != LBM_OK) {
         g_err = c->err;
@@ -418,8 +397,8 @@ int lbm_macroscopic(lbm_ctx* c, double* rho, double* ux, double* uy, double* Tf)
     if (!rho || !ux || !uy) return fail(c, LBM_E_ARG, "output pointer is NULL");
     const int n = c->cfg.nx * c->cfg.ny;
     return dispatch(c, [&]<int Q, typename T>() -> int {
-        hipLaunchKernelGGL((k_macro<Q, T>), dim3((n + 255) / 256), dim3(256), 0, c->stream, (const T*)c->f[c->cur], n,
-                           c->L.P, rho, ux, uy, Tf);
+        hipLaunchKernelGGL((k_macro<Q, T>), dim3((n + 255) / 256), dim3(256), 0, c->stream, (const T*)c->f[c->cur],
+                           c->cfg.nx, n, c->L.pitch, rho, ux, uy, Tf);
         HIPCHK(c, hipGetLastError());
         return LBM_OK;
     });
@@ -441,7 +420,7 @@ int lbm_diagnostics(lbm_ctx* c, double* h_out) {
     const int nb = c->L.diag_blocks;
     const int rc = dispatch(c, [&]<int Q, typename T>() -> int {
         hipLaunchKernelGGL((k_diag_partial<Q, T>), dim3(nb), dim3(256), 0, c->stream, (const T*)c->f[c->cur], c->cfg.nx,
-                           c->cfg.ny, c->L.P, g.x0, g.x1, g.y0, g.y1, c->diag);
+                           c->cfg.ny, c->L.pitch, g.x0, g.x1, g.y0, g.y1, c->diag);
         HIPCHK(c, hipGetLastError());
         hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, c->stream, c->diag, nb, c->diag + (size_t)nb * 8);
         HIPCHK(c, hipGetLastError());
@@ -533,9 +512,6 @@ const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : g_err
 
 void lbm_destroy(lbm_ctx* c) {
     if (!c) return;
-    if (c->aux) { (void)hipStreamSynchronize(c->aux); (void)hipStreamDestroy(c->aux); }
-    if (c->ev_main) (void)hipEventDestroy(c->ev_main);
-    if (c->ev_aux) (void)hipEventDestroy(c->ev_aux);
     for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
     delete c;
 }
