@@ -8,9 +8,11 @@ x = nx-1 (sigma = 0.25), periodic in y, nu = 0.1.  One step = bulk stream + coll
 bulk node plus the characteristic boundary solve and reconstruction (lbm_step).
 
 Prints one JSON line: MLUPS of the FP32 deviation path over all nx*ny nodes, the roofline of the
-bulk kernel (algorithmic bytes 2 * 37 * 4 per bulk node per launch over its HIP-event-timed
-duration, against 8 TB/s), the FP64 path on the same workload, and the FP64 CPU oracle timed on
-a bounded slab of the same workload.
+step kernel k_step (one launch per step: bulk stream + collide and the boundary chunks), with
+algorithmic bytes per launch = 2 q s per bulk node (read q populations, write q) + q s per
+written boundary-layer node + q s per re-pulled strip node (s = 4 or 8 bytes), over its
+HIP-event-timed duration, against 8 TB/s; the FP64 path on the same workload; and the FP64 CPU
+oracle timed on a bounded slab of the same workload.
 """
 import argparse
 import hashlib
@@ -26,7 +28,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0
 NX, NY = 4096, 2048
 Q = 37
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bulk_d2q37_fp32_4096x2048_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_d2q37_fp32_4096x2048_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2307_16766_amd", "csrc", n) for n in ("kernels.h", "lattice.h")]
 
 
@@ -80,10 +82,7 @@ def run_gpu(precision, steps, warmup):
     g.close()
     del g
     torch.cuda.empty_cache()
-    M = 3
-    bulk_nodes = (NX - 2 * M) * NY
-    esz = 4 if precision == "fp32dev" else 8
-    bytes_per_launch = bulk_nodes * 2 * Q * esz
+    bytes_per_launch = algorithmic_bytes(4 if precision == "fp32dev" else 8)
     kernel_ms = kms / max(launches, 1)
     gbps = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
     return {
@@ -97,6 +96,17 @@ def run_gpu(precision, steps, warmup):
         "mass": diag[0],
         "finite": bool(diag[6] == 0),
     }
+
+
+def algorithmic_bytes(esz):
+    """Bytes one step kernel must move: bulk nodes read and write q populations; the outflow
+    side's M layers are written (equilibrium reconstruction) and its x_f column re-pulled (q
+    reads); the Dirichlet inlet layers are static and cost nothing per step."""
+    M = 3
+    bulk_nodes = (NX - 2 * M) * NY
+    layer_nodes = M * NY
+    strip_nodes = NY
+    return (2 * bulk_nodes + layer_nodes + strip_nodes) * Q * esz
 
 
 def cpu_baseline(steps=None):
@@ -223,7 +233,7 @@ def main():
             "unit": "GB/s",
             "frac": r32["bulk_frac"],
             "traffic": traffic,
-            "kernel": "k_bulk<37,float>",
+            "kernel": "k_step<37,float> (bulk tiles + boundary chunks, one launch per step)",
             "kernel_ms": r32["bulk_kernel_ms"],
             "bytes_per_launch": r32["bulk_bytes_per_launch"],
         },

@@ -295,12 +295,20 @@ __global__ __launch_bounds__(256) void k_diag_partial(const T* __restrict__ A, i
     if (threadIdx.x == 7) partial[blockIdx.x * 8 + 7] = 0.0;
 }
 
-__global__ __launch_bounds__(64) void k_diag_final(const double* __restrict__ partial, int nblk, double* __restrict__ out) {
-    const int k = threadIdx.x;
-    if (k >= 8) return;
+// second pass: one work-group per quantity, fixed-order tree over the partials (deterministic)
+__global__ __launch_bounds__(256) void k_diag_final(const double* __restrict__ partial, int nblk, double* __restrict__ out) {
+    const int k = blockIdx.x;   // 0..7
+    __shared__ double red[256];
     double v = 0.0;
-    for (int b = 0; b < nblk; ++b) v = (k == 5) ? fmax(v, partial[b * 8 + k]) : v + partial[b * 8 + k];
-    out[k] = v;
+    for (int b = threadIdx.x; b < nblk; b += 256) v = (k == 5) ? fmax(v, partial[b * 8 + k]) : v + partial[b * 8 + k];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            red[threadIdx.x] = (k == 5) ? fmax(red[threadIdx.x], red[threadIdx.x + w]) : red[threadIdx.x] + red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[k] = red[0];
 }
 
 // ================================================================== characteristic boundary
@@ -746,8 +754,10 @@ __device__ __forceinline__ void boundary_job(const T* __restrict__ A, T* __restr
 // and matches the 3 work-groups per CU that the boundary LDS allows), 2 otherwise.
 template <int Q, typename T> struct StepOcc { static constexpr int waves = (Q == 37 && sizeof(T) == 4) ? 3 : 2; };
 
-// one full time step: work-groups [0, nbnd) are boundary chunks, the rest bulk tiles of 256
-// nodes (bpr tiles per row, rows from g.y0)
+// One full time step: work-groups [0, nbnd) are boundary chunks, the rest bulk tiles of 256
+// nodes, bpr tiles per row, rows from g.y0, in row-major order (the whole chip sweeps the rows
+// in order, which streams best from HBM; an XCD-aware order that keeps a row's tiles on one L2
+// removes the ~10 % duplicate edge-line fetches but streams slower).
 template <int Q, typename T, bool PX, bool PY>
 __global__ __launch_bounds__(256, (StepOcc<Q, T>::waves)) void k_step(const T* __restrict__ A, T* __restrict__ B, BndArgs a,
                                                                      BulkArgs g, int nbnd, int bpr) {

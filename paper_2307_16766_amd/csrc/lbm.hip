@@ -253,13 +253,14 @@ int launch_step(lbm_ctx* c) {
     T* B = (T*)c->f[c->cur ^ 1];
     const BulkArgs& g = c->bulk;
     const int bpr = (g.x1 + 1 + 255) / 256;   // bulk tiles per row, aligned to x = 0
-    const int nblk = c->nbnd + bpr * (g.y1 - g.y0 + 1);
+    const int nbnd = c->nbnd;
+    const int nblk = nbnd + bpr * (g.y1 - g.y0 + 1);
     const bool px = c->cfg.bc[0] == BC_PERIODIC, py = c->cfg.bc[2] == BC_PERIODIC;
     auto step = [&](hipStream_t s) {
-        if (px && py) hipLaunchKernelGGL((k_step<Q, T, true, true>), dim3(nblk), dim3(256), 0, s, A, B, a, g, c->nbnd, bpr);
-        else if (px) hipLaunchKernelGGL((k_step<Q, T, true, false>), dim3(nblk), dim3(256), 0, s, A, B, a, g, c->nbnd, bpr);
-        else if (py) hipLaunchKernelGGL((k_step<Q, T, false, true>), dim3(nblk), dim3(256), 0, s, A, B, a, g, c->nbnd, bpr);
-        else hipLaunchKernelGGL((k_step<Q, T, false, false>), dim3(nblk), dim3(256), 0, s, A, B, a, g, c->nbnd, bpr);
+        if (px && py) hipLaunchKernelGGL((k_step<Q, T, true, true>), dim3(nblk), dim3(256), 0, s, A, B, a, g, nbnd, bpr);
+        else if (px) hipLaunchKernelGGL((k_step<Q, T, true, false>), dim3(nblk), dim3(256), 0, s, A, B, a, g, nbnd, bpr);
+        else if (py) hipLaunchKernelGGL((k_step<Q, T, false, true>), dim3(nblk), dim3(256), 0, s, A, B, a, g, nbnd, bpr);
+        else hipLaunchKernelGGL((k_step<Q, T, false, false>), dim3(nblk), dim3(256), 0, s, A, B, a, g, nbnd, bpr);
     };
     HIPCHK(c, timed_launch(c, step));
     c->cur ^= 1;
@@ -422,7 +423,7 @@ int lbm_diagnostics(lbm_ctx* c, double* h_out) {
         hipLaunchKernelGGL((k_diag_partial<Q, T>), dim3(nb), dim3(256), 0, c->stream, (const T*)c->f[c->cur], c->cfg.nx,
                            c->cfg.ny, c->L.pitch, g.x0, g.x1, g.y0, g.y1, c->diag);
         HIPCHK(c, hipGetLastError());
-        hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, c->stream, c->diag, nb, c->diag + (size_t)nb * 8);
+        hipLaunchKernelGGL(k_diag_final, dim3(8), dim3(256), 0, c->stream, c->diag, nb, c->diag + (size_t)nb * 8);
         HIPCHK(c, hipGetLastError());
         return LBM_OK;
     });
