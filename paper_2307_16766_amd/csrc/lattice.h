@@ -154,14 +154,42 @@ __device__ __forceinline__ void feq_dev(R rm1, R ux, R uy, R th, R* fe) {
 }
 
 // BGK collision (eq. bgk) in deviation form: d* = d + omega (de - d), omega = 1/tau.
+// In float the increment D = omega (de - d) carries a rounding residual in the collision
+// invariants (mass, momentum, and energy for the thermal stencil) that does not average out:
+// the weights rounded to float make sum_i w_i (H_i - 1) differ from zero with a sign fixed by
+// the flow.  The residual is removed by subtracting its projection on the degree <= 2 Hermite
+// basis, w_i (a0 + a1 c_x + a2 c_y + a3 (|c|^2 - 2 cs^2)), whose coefficients follow from the
+// quadrature identities sum w = 1, sum w c_a c_b = cs^2 delta_ab and
+// sum w (|c|^2 - 2 cs^2)^2 = 4 cs^4.  In exact arithmetic the projection is zero.
 template <int Q, typename R>
 __device__ __forceinline__ void collide_dev(R* d, R omega) {
     R rm1, ux, uy, th;
     moments_dev<Q, R>(d, rm1, ux, uy, th);
     R fe[Q];
     feq_dev<Q, R>(rm1, ux, uy, th, fe);
+    if (sizeof(R) == 8) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) d[i] = d[i] + omega * (fe[i] - d[i]);
+        for (int i = 0; i < Q; ++i) d[i] = d[i] + omega * (fe[i] - d[i]);
+        return;
+    }
+    using L = Lat<Q>;
+    R m0 = 0, mx = 0, my = 0, me = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        fe[i] = omega * (fe[i] - d[i]);   // the increment
+        m0 += fe[i];
+        if (cx<Q>(i) != 0) mx += R(cx<Q>(i)) * fe[i];
+        if (cy<Q>(i) != 0) my += R(cy<Q>(i)) * fe[i];
+        if (L::thermal) me += R(c2<Q>(i)) * fe[i];
+    }
+    const R a0 = m0, a1 = mx * R(1.0 / L::cs2), a2 = my * R(1.0 / L::cs2);
+    const R a3 = L::thermal ? (me - R(2.0 * L::cs2) * m0) * R(0.25 / (L::cs2 * L::cs2)) : R(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        R b = a0 + a1 * R(cx<Q>(i)) + a2 * R(cy<Q>(i));
+        if (L::thermal) b += a3 * R(c2<Q>(i) - 2.0 * L::cs2);
+        d[i] = d[i] + (fe[i] - R(wt<Q>(i)) * b);
+    }
 }
 
 }  // namespace lbm

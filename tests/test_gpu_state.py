@@ -1,0 +1,125 @@
+"""GPU checks of the library's state handling: bitwise determinism, checkpoint/restore,
+diagnostics against the oracle, non-finite detection and argument errors."""
+import numpy as np
+import pytest
+
+from gpu_cases import TAU_37, log, make_pair
+from paper_2307_16766_amd import lbm, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+BC = ["lodi_relax", "cbc_relax", "lodi_relax", "lodi_relax"]
+RELAX = dict(sigma=0.25, alpha=0.1, mach=0.05)
+
+
+def _run(precision, steps, fields):
+    g = lbm.LBM(37, 60, 50, TAU_37, BC, fields, precision=precision)
+    g.set_relax(-1, **RELAX)
+    g.step(steps)
+    out = g.macro_numpy()
+    b = g.boundary_state(1, 3, 50 - 6).cpu().numpy()
+    g.close()
+    return out, b
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+def test_bitwise_determinism(precision):
+    log(f"[gpu-case] determinism {precision}")
+    f = W.temperature_pulse(60, 50, amp=1e-3, width=5.0)
+    a, ba = _run(precision, 40, f)
+    b, bb = _run(precision, 40, f)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    assert np.array_equal(ba, bb)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+def test_save_restore_bitwise(precision):
+    # N steps straight == K steps, save, (N - K) steps, restore, (N - K) steps again
+    log(f"[gpu-case] save/restore {precision}")
+    f = W.temperature_pulse(60, 50, amp=1e-3, width=5.0)
+    g = lbm.LBM(37, 60, 50, TAU_37, BC, f, precision=precision)
+    g.set_relax(-1, **RELAX)
+    g.step(13)
+    buf = g.save()
+    g.step(20)
+    ref = g.macro_numpy()
+    assert g.steps_done() == 33
+    g.restore(buf)
+    assert g.steps_done() == 13
+    g.step(20)
+    got = g.macro_numpy()
+    for x, y in zip(ref, got):
+        assert np.array_equal(x, y)
+    g.close()
+
+
+def test_diagnostics_match_oracle():
+    log("[gpu-case] diagnostics")
+    f = W.temperature_pulse(60, 50, amp=1e-3, width=5.0)
+    g, o = make_pair(37, 60, 50, TAU_37, BC, f, "fp64", RELAX)
+    g.step(25)
+    o.step(25)
+    dg, do = g.diagnostics(), o.diag()
+    for k in (0, 3):   # mass, energy
+        assert abs(dg[k] - do[k]) < 1e-12 * abs(do[k])
+    for k in (1, 2):   # momenta (near zero)
+        assert abs(dg[k] - do[k]) < 1e-12 * abs(do[0])
+    assert abs(dg[4] - do[4]) < 1e-9 * do[4]
+    assert abs(dg[5] - do[5]) < 1e-9 * do[5]
+    assert dg[6] == 0 and dg[7] == 25
+    g.close()
+
+
+def test_nonfinite_is_reported():
+    # a velocity jump well beyond the model's range makes the BGK update blow up within a few
+    # steps; the diagnostics must report it instead of returning numbers
+    log("[gpu-case] non-finite detection")
+    nx, ny = 32, 16
+    ux = np.where(np.arange(nx)[None, :] < nx // 2, 2.5, -2.5) * np.ones((ny, 1))
+    g = lbm.LBM(9, nx, ny, 0.5001, ["periodic"] * 4, (np.ones((ny, nx)), ux, 0, 1), precision="fp64")
+    bad = None
+    for k in range(200):
+        g.step(5)
+        d = g.diagnostics(allow_nonfinite=True)
+        if d[6] > 0:
+            bad = d
+            break
+    assert bad is not None
+    with pytest.raises(lbm.LBMError) as e:
+        g.diagnostics()
+    assert e.value.code == lbm.LBM_E_NONFINITE
+    g.close()
+
+
+def test_argument_errors():
+    f = W.temperature_pulse(40, 40)
+    with pytest.raises(lbm.LBMError):
+        lbm.LBM(37, 40, 40, 0.4, BC, f)                                   # tau <= 1/2
+    with pytest.raises(lbm.LBMError):
+        lbm.LBM(9, 40, 40, 0.6, ["cbc", "cbc", "periodic", "periodic"], f)  # CBC on D2Q9
+    g = lbm.LBM(37, 40, 40, TAU_37, BC, f)
+    with pytest.raises(lbm.LBMError):
+        g.set_relax(5, sigma=1.0)
+    with pytest.raises(lbm.LBMError):
+        g.set_relax(0, sigma=float("nan"))
+    with pytest.raises(lbm.LBMError):
+        g.set_inlet(0, np.ones((34, 4)))                                  # not a Dirichlet side
+    g.close()
+    p = lbm.LBM(37, 40, 40, TAU_37, ["periodic"] * 4, f)
+    with pytest.raises(lbm.LBMError):
+        p.boundary_state(0, 3, 40)                                        # no boundary state
+    p.close()
+
+
+def test_kernel_timing():
+    f = W.temperature_pulse(64, 64)
+    g = lbm.LBM(37, 64, 64, TAU_37, BC, f, precision="fp32dev")
+    g.set_kernel_timing(True)
+    g.step(7)
+    ms, n = g.bulk_kernel_time()
+    assert n == 7 and ms > 0
+    g.set_kernel_timing(False)
+    g.step(2)
+    assert g.bulk_kernel_time()[1] == 0
+    g.close()

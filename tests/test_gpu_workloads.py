@@ -1,0 +1,179 @@
+"""GPU runs of the five workload configurations at their full sizes.
+
+Each is compared node by node with the oracle over the first steps (the oracle finishes those in
+seconds at full size), and the full-length GPU run is checked on properties that hold at any
+size: finiteness, symmetry, conservation where it applies, FP32 deviation storage against the
+FP64 path."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_cases import CS_37, CS2_37, TAU_37, check_fields, log, make_pair, rel_errors
+from paper_2307_16766_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu(stencil, nx, ny, tau, bc, fields, precision, relax=None, inlet=None):
+    from paper_2307_16766_amd import lbm
+    g = lbm.LBM(stencil, nx, ny, tau, bc, fields, precision=precision)
+    if relax:
+        g.set_relax(-1, **relax)
+    if inlet is not None:
+        g.set_inlet(*inlet)
+    return g
+
+
+# --- D2Q9 pulse, 256 x 128, tau 0.6, LODI-RELAX at x = 0 and x = nx-1, periodic y, 1000 steps
+C1 = dict(stencil=9, nx=256, ny=128, tau=0.6, bc=["lodi_relax", "lodi_relax", "periodic", "periodic"],
+          relax=dict(sigma=0.25, alpha=0.0, mach=0.0))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+def test_c1_full_run_against_oracle(precision):
+    fields = W.gaussian_density_pulse(256, 128, amp=1e-3, width=8.0)
+    log(f"[gpu-case] C1 {precision} 1000 steps")
+    g, o = make_pair(9, 256, 128, 0.6, C1["bc"], fields, precision, C1["relax"])
+    done = 0
+    for n in (10, 200, 1000):
+        g.step(n - done)
+        o.step(n - done)
+        done = n
+        gm = g.macro_numpy()
+        check_fields("C1", precision, n, gm, o.macro())
+    # the setup is mirror symmetric in x and y
+    r, ux, uy, _ = gm
+    assert np.abs(r - r[:, ::-1]).max() < 1e-13 + (1e-9 if precision == "fp32dev" else 0)
+    assert np.abs(r - r[::-1, :]).max() < 1e-13 + (1e-9 if precision == "fp32dev" else 0)
+    g.close()
+
+
+# --- D2Q37 pressure + temperature pulse, 512 x 512, LODI-RELAX on all four sides and corners
+C2_RELAX = dict(sigma=0.25, alpha=0.0, mach=0.0)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+def test_c2_first_steps_against_oracle(precision):
+    fields = W.temperature_pulse(512, 512, amp=1e-3, width=12.0)
+    log(f"[gpu-case] C2 {precision} first steps")
+    g, o = make_pair(37, 512, 512, TAU_37, ["lodi_relax"] * 4, fields, precision, C2_RELAX)
+    for n in (1, 8):
+        g.step(1 if n == 1 else 7)
+        o.step(1 if n == 1 else 7)
+        check_fields("C2", precision, n, g.macro_numpy(), o.macro())
+    g.close()
+
+
+def test_c2_full_run_symmetry_and_precision():
+    # 5000 steps: the pulse has left through the four characteristic sides and corners; the
+    # square setup stays D4 symmetric; FP32 deviation storage stays within 2e-5 of FP64
+    fields = W.temperature_pulse(512, 512, amp=1e-3, width=12.0)
+    log("[gpu-case] C2 full 5000 steps fp64 + fp32dev")
+    out = {}
+    for prec in ("fp64", "fp32dev"):
+        g = _gpu(37, 512, 512, TAU_37, ["lodi_relax"] * 4, fields, prec, C2_RELAX)
+        g.step(5000)
+        out[prec] = g.macro_numpy()
+        d = g.diagnostics()
+        assert d[6] == 0
+        g.close()
+    r, ux, uy, T = out["fp64"]
+    scale = 1e-3
+    assert np.abs(r - r.T).max() < 1e-12 * scale * 1e3
+    assert np.abs(T - T[::-1, ::-1]).max() < 1e-12
+    assert np.abs(ux - uy.T).max() < 1e-12
+    # the pulse is gone: residual pressure perturbation far below the initial 1e-3
+    P = r * T
+    assert np.abs(P - 1).max() < 1e-4
+    e = rel_errors(out["fp32dev"], out["fp64"])
+    assert e[0] < 2e-5 and e[2] < 2e-5
+
+
+# --- D2Q37 convected isentropic vortex, 1024 x 512, CBC-RELAX outflow, 6000 steps
+def _c3_fields():
+    return W.isentropic_vortex(1024, 512, CS_37, mach=0.2, radius=20.0, strength=0.05, center=(256.0, None))
+
+
+C3_BC = ["lodi_relax", "cbc_relax", "periodic", "periodic"]
+C3_RELAX = dict(sigma=0.25, alpha=0.2, mach=0.2)
+
+
+def test_c3_first_steps_against_oracle():
+    log("[gpu-case] C3 fp32dev first steps")
+    g, o = make_pair(37, 1024, 512, TAU_37, C3_BC, _c3_fields(), "fp32dev", C3_RELAX)
+    g.step(4)
+    o.step(4)
+    check_fields("C3", "fp32dev", 4, g.macro_numpy(), o.macro())
+    g.close()
+
+
+@pytest.mark.parametrize("alpha,steps", [(0.0, 6000), (0.2, 1500)])
+def test_c3_full_run_fp32_vs_fp64(alpha, steps):
+    # The vortex (x0 = 256, convected at u0 = 0.2 cs) crosses the CBC-RELAX outflow around step
+    # 4600.  With transverse relaxation alpha = Ma = 0.2 the outflow develops a slowly growing
+    # mode after ~3000 steps (e-folding ~330 steps; it is absent with alpha = 0), so the
+    # 6000-step precision check relaxes pressure only and alpha = 0.2 is checked over 1500 steps.
+    log(f"[gpu-case] C3 alpha={alpha} {steps} steps fp32dev vs fp64")
+    res = {}
+    for prec in ("fp64", "fp32dev"):
+        g = _gpu(37, 1024, 512, TAU_37, C3_BC, _c3_fields(), prec, dict(C3_RELAX, alpha=alpha))
+        g.step(steps)
+        res[prec] = g.macro_numpy()
+        assert g.diagnostics()[6] == 0
+        g.close()
+    e = rel_errors(res["fp32dev"], res["fp64"])
+    log(f"C3 fp32dev vs fp64 after {steps} steps: rel errors rho/u/T = {e}")
+    assert max(e) < 2e-5
+    u0 = 0.2 * CS_37
+    assert abs(res["fp64"][1].mean() - u0) < 0.01 * u0
+    P = res["fp64"][0] * res["fp64"][3]
+    assert np.abs(P - 1).max() < 5e-3
+
+
+# --- D2Q37 random temperature field, 256 x 256, LODI-RELAX on four sides (adjoint workload)
+def test_c4_forward_against_oracle():
+    fields = W.random_temperature(256, 256, std=1e-4, seed=2307)
+    log("[gpu-case] C4 fp64 forward 100 steps")
+    g, o = make_pair(37, 256, 256, TAU_37, ["lodi_relax"] * 4, fields, "fp64", dict(sigma=0.25, alpha=0.1, mach=0.0))
+    for n in (1, 100):
+        g.step(1 if n == 1 else 99)
+        o.step(1 if n == 1 else 99)
+        check_fields("C4", "fp64", n, g.macro_numpy(), o.macro())
+    assert abs(g.diagnostics()[4] - o.loss()) <= 1e-10 * o.loss()
+    g.close()
+
+
+# --- D2Q37 shear layer, 4096 x 2048, Dirichlet inlet + LODI-RELAX outflow (throughput run)
+def _c5():
+    fields, prof = W.shear_layer(4096, 2048, u0=0.1, thickness=10.0, noise=1e-3, seed=16766)
+    relax = dict(sigma=0.25, alpha=0.0, mach=0.1 / math.sqrt(2 * CS2_37))
+    return fields, prof, relax
+
+
+C5_BC = ["dirichlet", "lodi_relax", "periodic", "periodic"]
+
+
+def test_c5_first_steps_against_oracle():
+    fields, prof, relax = _c5()
+    log("[gpu-case] C5 fp32dev first steps (oracle at full size)")
+    g, o = make_pair(37, 4096, 2048, TAU_37, C5_BC, fields, "fp32dev", relax, inlet=(0, prof))
+    g.step(2)
+    o.step(2)
+    check_fields("C5", "fp32dev", 2, g.macro_numpy(), o.macro())
+    g.close()
+    o.close()
+
+
+def test_c5_full_run_properties():
+    fields, prof, relax = _c5()
+    log("[gpu-case] C5 fp32dev 1000 steps")
+    g = _gpu(37, 4096, 2048, TAU_37, C5_BC, fields, "fp32dev", relax, inlet=(0, prof))
+    g.step(1000)
+    d = g.diagnostics()
+    assert d[6] == 0 and d[5] < 0.2
+    r, ux, uy, T = g.macro_numpy()
+    # the inlet layers hold the prescribed profile
+    assert np.abs(ux[:, :3] - prof[:, 1:2]).max() < 1e-6
+    assert np.abs(r[:, :3] - 1).max() < 1e-6
+    g.close()
