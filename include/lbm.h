@@ -148,6 +148,38 @@ long lbm_steps_done(const lbm_ctx* ctx);
 int lbm_set_kernel_timing(lbm_ctx* ctx, int enable);
 int lbm_bulk_kernel_time(lbm_ctx* ctx, double* total_ms, long* launches);
 
+/* Discrete adjoint with checkpointing.  The paper has no adjoint: these calls differentiate
+ * the discrete map that lbm_step computes (bulk stream + BGK collide, the RK4 characteristic
+ * solve of every side and corner with wave directions frozen at the start of the step, and the
+ * equilibrium reconstruction), in FP64 whatever the storage precision.  Supported boundaries:
+ * periodic, LODI and LODI_RELAX (D2Q9 additionally needs one periodic axis); other
+ * configurations return LBM_E_UNSUPPORTED.
+ *
+ * lbm_tape_bytes: device bytes of the tape for nsteps steps with a checkpoint every `every`
+ * steps (0 for invalid arguments).  The tape holds ceil(nsteps / every) checkpoints of the
+ * state plus the reverse sweep's scratch: two adjoint population buffers, two recomputation
+ * buffers and (every + 1) slots of per-node moments and boundary state.
+ *
+ * lbm_record: from the initial state (no step taken since lbm_init; else LBM_E_STATE), advance
+ * nsteps steps exactly as lbm_step does while storing the checkpoints in d_tape (caller-owned,
+ * 256-byte aligned, at least lbm_tape_bytes bytes, borrowed until the next lbm_record, the
+ * context's destruction, or lbm_restore, which discards the recording).
+ *
+ * lbm_adjoint: gradient of a scalar loss L of the final macroscopic fields with respect to the
+ * initial fields and the relaxation parameters.  d_seed: device FP64 [4][ny][nx] =
+ * dL/d(rho, u_x, u_y, T) at the final step and every node (the T plane is ignored for D2Q9),
+ * or NULL for the pressure loss of lbm_diagnostics ([4]: sum over bulk nodes of
+ * (P - cs^2)^2).  d_grad_fields (device FP64 [4][ny][nx]) receives
+ * dL/d(rho0, u_x0, u_y0, T0) of the fields given to lbm_init; h_grad_relax (host [4][2])
+ * receives dL/dsigma and dL/dalpha of each side (0 for sides without relaxation).  Runs the
+ * reverse sweep segment by segment from the last checkpoint: each segment is recomputed from
+ * its checkpoint, then reversed step by step.  The context must not have stepped since
+ * lbm_record (LBM_E_STATE); its state is left unchanged, and the call may be repeated with
+ * other seeds.  Synchronises the stream before returning. */
+size_t lbm_tape_bytes(const lbm_ctx* ctx, int nsteps, int every);
+int lbm_record(lbm_ctx* ctx, int nsteps, int every, void* d_tape, size_t tape_bytes);
+int lbm_adjoint(lbm_ctx* ctx, const double* d_seed, double* d_grad_fields, double* h_grad_relax);
+
 /* Lattice constants used by the library (host pointers, arrays of q entries, library order).
  * Returns q, or a negative code for an unknown stencil. */
 int lbm_lattice_info(int stencil, int* M, double* cs2, double* w, int* cx, int* cy);

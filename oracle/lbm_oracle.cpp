@@ -440,11 +440,15 @@ struct Sim {
     }
 
     // initial state: f = f^eq(fields) at every node (Sec. 2, "Initialize")
-    void init(const double* rho, const double* ux, const double* uy, const double* T, const std::vector<S>* dT) {
+    // dT: seeded temperature [ny][nx]; dF: seeded (rho, ux, uy, T) [4][ny][nx] (either or none)
+    void init(const double* rho, const double* ux, const double* uy, const double* T, const std::vector<S>* dT,
+              const std::vector<S>* dF = nullptr) {
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 S u4[4] = {rho[id(x, y)], ux[id(x, y)], uy[id(x, y)], L.thermal ? S(T[id(x, y)]) : S(1.0)};
                 if (dT && L.thermal) u4[3] = (*dT)[id(x, y)];
+                if (dF)
+                    for (int c = 0; c < (L.thermal ? 4 : 3); ++c) u4[c] = (*dF)[c * plane() + id(x, y)];
                 setU(U, x, y, u4);
                 node_feq(f, x, y, u4);
             }
@@ -1047,6 +1051,45 @@ int oracle_tangent_run(int stencil, int nx, int ny, double tau, const int* bc, c
     s.init(rho, ux, uy, T, &Td);
     for (int k = 0; k < nsteps; ++k) s.step();
     Dual l = s.loss();
+    out[0] = l.v;
+    for (int k = 0; k < NTAN; ++k) out[1 + k] = l.d[k];
+    return 0;
+}
+
+// Forward-mode run with tangents on all four initial fields: direction k perturbs sigma and
+// alpha as above and (rho0, ux0, uy0, T0) by dF[k][4][ny][nx].  The loss is the pressure loss
+// above, or with wlin != NULL the linear functional sum over all nodes of
+// wlin[c][y][x] * (rho, ux, uy, T)_c at the final step.  out: loss, then NTAN derivatives.
+int oracle_tangent_run_fields(int stencil, int nx, int ny, double tau, const int* bc, const double* relax,
+                              const double* dsigma, const double* dalpha, const double* rho, const double* ux,
+                              const double* uy, const double* T, const double* dF, const double* wlin, int nsteps,
+                              double* out) {
+    if (validate(stencil, nx, ny, tau, bc) != 0) return -1;
+    Sim<Dual> s(lattice(stencil), nx, ny, tau, bc);
+    for (int side = 0; side < 4; ++side) {
+        const double* p = relax + 6 * side;
+        Dual sg(p[0]), al(p[1]);
+        for (int k = 0; k < NTAN; ++k) { sg.d[k] = dsigma[k]; al.d[k] = dalpha[k]; }
+        s.rp[side].sigma = sg; s.rp[side].alpha = al;
+        s.rp[side].rho_inf = p[2]; s.rp[side].T_inf = p[3]; s.rp[side].mach = p[4]; s.rp[side].length = p[5];
+    }
+    const size_t n = (size_t)nx * ny;
+    const double* base[4] = {rho, ux, uy, T};
+    std::vector<Dual> F(4 * n);
+    for (int c = 0; c < 4; ++c)
+        for (size_t e = 0; e < n; ++e) {
+            F[c * n + e] = Dual(base[c] ? base[c][e] : 1.0);
+            for (int k = 0; k < NTAN; ++k) F[c * n + e].d[k] = dF[((size_t)k * 4 + c) * n + e];
+        }
+    s.init(rho, ux, uy, T, nullptr, &F);
+    for (int k = 0; k < nsteps; ++k) s.step();
+    Dual l = 0.0;
+    if (wlin) {
+        for (int c = 0; c < 4; ++c)
+            for (size_t e = 0; e < n; ++e) l = l + Dual(wlin[c * n + e]) * s.U[c * n + e];
+    } else {
+        l = s.loss();
+    }
     out[0] = l.v;
     for (int k = 0; k < NTAN; ++k) out[1 + k] = l.d[k];
     return 0;

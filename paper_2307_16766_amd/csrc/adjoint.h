@@ -1,0 +1,835 @@
+// adjoint.h -- discrete adjoint of the time step of kernels.h (gfx950, FP64 adjoint state).
+//
+// The paper has no adjoint; this differentiates the discrete map that the GPU path computes.
+// State of step n: post-collision populations f^n (all nodes), the boundary layer states U_b^n
+// of every characteristic side and the corner states U_c^n.  With g^{n+1}(x) = pull of f^n at x,
+//   bulk x          : f^{n+1}(x) = C(g^{n+1}(x))                     (eq. lbe, eq. bgk)
+//   strip, diagonal : X^{n+1} = m(g^{n+1}(x_f)), D^{n+1} = m(g^{n+1}(c + v), g^{n+1}(c + 2v))
+//   corners         : U_c^{n+1} = RK4_c(U_c^n; D^n, D^{n+1})
+//   sides           : U_b^{n+1} = RK4_s(U_b^n; X^n, X^{n+1}, U_c^n, U_c^{n+1})
+//   layers, blocks  : f^{n+1} = f^eq(U_b^{n+1}), f^eq(U_c^{n+1})
+// with m = (rho, u_x, u_y, T) the moments (eq. macro).  Because the collision conserves the
+// moments, m(C(g)) = m(g) identically, so X^n = m(g^n(x_f)) as a function.
+//
+// Adjoint variables (all FP64):
+//   V(x) : nu = dL/dg at bulk nodes (adjoint of the pulled, pre-collision populations);
+//          lambda = dL/df at boundary-layer and corner-block nodes;
+//   adjoint region (same offsets as the forward region): direct adjoints of U_b^n, of the
+//          strip X^n and corner diagonal D^n as time-n inputs, and of U_c^n.
+// One reverse step n+1 -> n is three launches:
+//   k_adj_side   : per chunk of side rows, fold lambda^{n+1} of the layers into the adjoint of
+//                  U_b^{n+1} (J_feq^T), recompute the RK4 stages, reverse them (hand-written
+//                  VJP of the characteristic rate), emit the adjoints of U_b^n, X^n, X^{n+1},
+//                  of the corner values, and of the relaxation parameters;
+//   k_adj_corner : corners (fold of the M x M block, reverse corner RK4), then the strip and
+//                  diagonal adjoints are added to nu^{n+1} through J_m^T;
+//   k_adj_bulk   : lambda^n(y, i) = nu^{n+1}(y + c_i, i) (reverse pull, bulk sources only),
+//                  nu^n = J_C^T lambda^n at bulk nodes:
+//                  nu_i = (1 - omega) lambda_i + omega (G_0 + c_ix G_1 + c_iy G_2 + |c_i|^2 G_3),
+//                  G = (dm/dM)^T (df^eq/dm)^T lambda, M the linear moments (sum f, sum f c,
+//                  sum f |c|^2); at n = 0 it gives dL/d(rho0, ux0, uy0, T0) = (df^eq/dm)^T lambda^0.
+// Supported boundaries: periodic, LODI and LODI-RELAX (the CBC variants' viscous terms and the
+// zero-gradient / Dirichlet sides have no adjoint here).
+#pragma once
+
+#include "kernels.h"
+
+namespace lbm {
+
+// ------------------------------------------------------------------ per-node adjoint pieces
+// G = (d f^eq / d(rho, ux, uy, T))^T lam, from the pair form of feq_dev: per opposite pair
+// H - 1 = E(a) +- O(a), so sum_pm lam w H = w (S (1 + E) + D O) with S, D the sum and
+// difference of the pair's lam.
+template <int Q>
+__device__ __forceinline__ void feq_vjp(const double* m, const double* lam, double* G) {
+    using L = Lat<Q>;
+    const double rho = m[0];
+    const double th = L::thermal ? m[3] - 1.0 : 0.0;
+    const double ics = 1.0 / L::cs;
+    const double vx = m[1] * ics, vy = m[2] * ics;
+    const double u2 = vx * vx + vy * vy;
+    double C0[L::NG], C1[L::NG], D0[L::NG], C0t[L::NG], C0u[L::NG], C1t[L::NG], D0t[L::NG];
+#pragma unroll
+    for (int g = 0; g < L::NG; ++g) {
+        if (L::thermal) {
+            const double xi2 = L::c2g(g) / L::cs2;
+            const double x4 = xi2 * xi2 - 8.0 * xi2 + 8.0;
+            C0[g] = 0.5 * (th * (xi2 - 2.0) - u2) + 0.125 * u2 * u2 + 0.25 * th * u2 * (4.0 - xi2) + 0.125 * th * th * x4;
+            C1[g] = 0.5 + 0.25 * (th * (xi2 - 6.0) - u2);
+            D0[g] = 1.0 + 0.5 * (th * (xi2 - 4.0) - u2);
+            C0t[g] = 0.5 * (xi2 - 2.0) + 0.25 * u2 * (4.0 - xi2) + 0.25 * th * x4;
+            C0u[g] = -0.5 + 0.25 * u2 + 0.25 * th * (4.0 - xi2);
+            C1t[g] = 0.25 * (xi2 - 6.0);
+            D0t[g] = 0.5 * (xi2 - 4.0);
+        } else {
+            C0[g] = -0.5 * u2; C1[g] = 0.5; D0[g] = 1.0;
+            C0t[g] = 0.0; C0u[g] = -0.5; C1t[g] = 0.0; D0t[g] = 0.0;
+        }
+    }
+    double gr = L::wg(0) * lam[0] * (1.0 + C0[0]);
+    double gth = L::wg(0) * lam[0] * C0t[0];
+    double gu2 = L::wg(0) * lam[0] * C0u[0];
+    double gvx = 0.0, gvy = 0.0;
+#pragma unroll
+    for (int p = 1; p <= L::NP; ++p) {
+        const int g = L::grp(p);
+        const double w = L::wg(g);
+        const double a = (L::pcx(p) * vx + L::pcy(p) * vy) * ics;
+        const double a2 = a * a;
+        const double S = lam[p] + lam[p + L::NP], D = lam[p] - lam[p + L::NP];
+        double E, O, Et, Ot, Eu, Ou, Ea, Oa;
+        if (L::thermal) {
+            E = C0[g] + a2 * (C1[g] + a2 * (1.0 / 24.0));
+            O = a * (D0[g] + a2 * (1.0 / 6.0));
+            Et = C0t[g] + a2 * C1t[g];
+            Ot = a * D0t[g];
+            Eu = C0u[g] - 0.25 * a2;
+            Ou = -0.5 * a;
+            Ea = 2.0 * a * C1[g] + a2 * a * (1.0 / 6.0);
+            Oa = D0[g] + 0.5 * a2;
+        } else {
+            E = C0[g] + C1[g] * a2;
+            O = a;
+            Et = 0.0; Ot = 0.0;
+            Eu = -0.5; Ou = 0.0;
+            Ea = a; Oa = 1.0;
+        }
+        gr += w * (S * (1.0 + E) + D * O);
+        gth += w * (S * Et + D * Ot);
+        gu2 += w * (S * Eu + D * Ou);
+        const double ga = w * (S * Ea + D * Oa);
+        if (L::pcx(p) != 0) gvx += L::pcx(p) * ga;
+        if (L::pcy(p) != 0) gvy += L::pcy(p) * ga;
+    }
+    // f^eq = w rho (1 + E +- O): every term but the first carries the factor rho
+    G[0] = gr;
+    G[1] = rho * (gvx * ics + 2.0 * vx * gu2) * ics;
+    G[2] = rho * (gvy * ics + 2.0 * vy * gu2) * ics;
+    G[3] = L::thermal ? rho * gth : 0.0;
+}
+
+// GM = (dm/dM)^T G for m = (rho, ux, uy, T) as functions of M = (sum f, sum f c_x, sum f c_y,
+// sum f |c|^2): rho = M0, u = (M1, M2)/rho, T = (M3 - |j|^2/rho) / (2 rho cs^2).
+template <int Q>
+__device__ __forceinline__ void mom_vjp(const double* m, const double* G, double* GM) {
+    const double ir = 1.0 / m[0];
+    const double ux = m[1], uy = m[2];
+    if (Lat<Q>::thermal) {
+        const double k = 0.5 * ir / Lat<Q>::cs2;
+        GM[0] = G[0] - (ux * G[1] + uy * G[2]) * ir + (ux * ux + uy * uy - 2.0 * Lat<Q>::cs2 * m[3]) * k * G[3];
+        GM[1] = G[1] * ir - 2.0 * k * ux * G[3];
+        GM[2] = G[2] * ir - 2.0 * k * uy * G[3];
+        GM[3] = k * G[3];
+    } else {
+        GM[0] = G[0] - (ux * G[1] + uy * G[2]) * ir;
+        GM[1] = G[1] * ir;
+        GM[2] = G[2] * ir;
+        GM[3] = 0.0;
+    }
+}
+
+template <int Q>
+__device__ __forceinline__ double phi_dot(int i, const double* GM) {
+    double v = GM[0];
+    if (cx<Q>(i) != 0) v += cx<Q>(i) * GM[1];
+    if (cy<Q>(i) != 0) v += cy<Q>(i) * GM[2];
+    if (Lat<Q>::thermal) v += c2<Q>(i) * GM[3];
+    return v;
+}
+
+// VJP of char_rate (LODI and LODI-RELAX; the CBC variants are not differentiated).  Inputs as
+// char_rate, rb = adjoint of the rate; outputs the adjoints of U, dn, up, dw (side-local
+// components) and of K and alpha.  The wave directions are frozen at time t (no derivative).
+template <bool THERMAL>
+__device__ __forceinline__ void char_rate_vjp(const double* U, const double* dn, const double* up, const double* dw,
+                                              const double* U0, int scheme, double K, double alpha, double Pinf,
+                                              const double* rb, double* Ub, double* dnb, double* upb, double* dwb,
+                                              double& Kb, double& alb) {
+    constexpr double cs2 = THERMAL ? Lat<37>::cs2 : Lat<9>::cs2;
+    constexpr double cs = THERMAL ? Lat<37>::cs : Lat<9>::cs;
+    const bool relax = scheme == BC_LODI_RELAX;
+    const double rho = U[0], u = U[1], v = U[2], T = U[3];
+    const double ir = 1.0 / rho;
+    const double T1 = -0.5 * (up[0] * up[2] - dw[0] * dw[2]);
+    const double T2 = -v * 0.5 * (up[1] - dw[1]);
+    const double T4 = THERMAL ? -0.5 * (up[3] * up[2] - dw[3] * dw[2]) : 0.0;
+    const double u0 = U0[1];
+    double rhob = 0.0, ub = 0.0, vb = 0.0, Tb = 0.0, T1b = 0.0, T2b = 0.0, T4b = 0.0;
+    for (int m = 0; m < 4; ++m) dnb[m] = 0.0;
+    Kb = 0.0;
+    alb = 0.0;
+    if (THERMAL) {
+        const double s = sqrt(2.0 * cs2 * T);
+        const double s0 = sqrt(2.0 * cs2 * U0[3]);
+        const double a = 0.25 * T * ir, b = s * (0.25 / cs2);
+        const double W3 = a * dn[0] - b * dn[1] + 0.25 * dn[3];
+        const double W4 = a * dn[0] + b * dn[1] + 0.25 * dn[3];
+        const double L1 = u * (-2.0 * a * dn[0] + 0.5 * dn[3]);
+        const double L3 = (u - s) * W3, L4 = (u + s) * W4;
+        const double ST3 = a * T1 - b * T2 + 0.25 * T4, ST4 = a * T1 + b * T2 + 0.25 * T4;
+        const double pr = relax ? K * (rho * cs2 * T - Pinf) * ir * (0.25 / cs2) : 0.0;
+        const double in3 = relax ? pr - alpha * ST3 : 0.0, in4 = relax ? pr - alpha * ST4 : 0.0;
+        const bool o1 = u0 >= 0.0, o3 = u0 - s0 >= 0.0, o4 = u0 + s0 >= 0.0;
+        const double B1 = o1 ? L1 : 0.0, B3 = o3 ? L3 : in3, B4 = o4 ? L4 : in4;
+        const double rhoT = rho / T, q = 2.0 * cs2 / s;
+        const double Bb1 = rb[0] * rhoT - rb[3];
+        const double Bb2 = -rb[2];
+        const double Bb3 = -rb[0] * rhoT + rb[1] * q - rb[3];
+        const double Bb4 = -rb[0] * rhoT - rb[1] * q - rb[3];
+        const double Bs = B1 - B3 - B4;
+        rhob += rb[0] * Bs / T;
+        Tb += -rb[0] * rho * Bs / (T * T);
+        double sb = -rb[1] * q * (B3 - B4) / s;
+        const double L1b = o1 ? Bb1 : 0.0, L2b = o1 ? Bb2 : 0.0, L3b = o3 ? Bb3 : 0.0, L4b = o4 ? Bb4 : 0.0;
+        const double in3b = o3 ? 0.0 : Bb3, in4b = o4 ? 0.0 : Bb4;
+        double ab = 0.0, bb = 0.0, ST3b = 0.0, ST4b = 0.0;
+        if (relax) {
+            const double prb = in3b + in4b;
+            alb = -(in3b * ST3 + in4b * ST4);
+            ST3b = -alpha * in3b;
+            ST4b = -alpha * in4b;
+            Kb = prb * (rho * cs2 * T - Pinf) * ir * (0.25 / cs2);
+            // pr = K (T / 4 - Pinf / (4 cs^2 rho))
+            Tb += prb * K * 0.25;
+            rhob += prb * K * 0.25 * Pinf * ir * ir / cs2;
+        }
+        ab += T1 * (ST3b + ST4b);
+        T1b += a * (ST3b + ST4b);
+        bb += T2 * (ST4b - ST3b);
+        T2b += b * (ST4b - ST3b);
+        T4b += 0.25 * (ST3b + ST4b);
+        // amplitudes
+        ub += (-2.0 * a * dn[0] + 0.5 * dn[3]) * L1b;
+        ab += -2.0 * u * dn[0] * L1b;
+        dnb[0] += -2.0 * a * u * L1b;
+        dnb[3] += 0.5 * u * L1b;
+        ub += dn[2] * L2b;
+        dnb[2] += u * L2b;
+        ub += W3 * L3b + W4 * L4b;
+        sb += -W3 * L3b + W4 * L4b;
+        const double W3b = (u - s) * L3b, W4b = (u + s) * L4b;
+        ab += dn[0] * (W3b + W4b);
+        dnb[0] += a * (W3b + W4b);
+        bb += dn[1] * (W4b - W3b);
+        dnb[1] += b * (W4b - W3b);
+        dnb[3] += 0.25 * (W3b + W4b);
+        // b = s / (4 cs^2), a = T / (4 rho), s = sqrt(2 cs^2 T)
+        sb += bb * (0.25 / cs2);
+        Tb += ab * 0.25 * ir;
+        rhob += -ab * 0.25 * T * ir * ir;
+        Tb += sb * cs2 / s;
+    } else {
+        const double c = cs;
+        const double Wm = cs2 * dn[0] - rho * c * dn[1], Wp = cs2 * dn[0] + rho * c * dn[1];
+        const double Lm = (u - c) * Wm, Lp = (u + c) * Wp;
+        const double pr = relax ? K * (cs2 * rho - Pinf) : 0.0;
+        const double inm = relax ? pr - alpha * (cs2 * T1 - rho * c * T2) : 0.0;
+        const double inp = relax ? pr - alpha * (cs2 * T1 + rho * c * T2) : 0.0;
+        const bool o0 = u0 >= 0.0, om = u0 - c >= 0.0, op = u0 + c >= 0.0;
+        const double Bm = om ? Lm : inm, Bp = op ? Lp : inp;
+        const double Bmb = -rb[0] * (0.5 / cs2) + rb[1] * (0.5 / c) * ir;
+        const double Bpb = -rb[0] * (0.5 / cs2) - rb[1] * (0.5 / c) * ir;
+        const double B0b = -rb[2];
+        rhob += -rb[1] * (Bm - Bp) * (0.5 / c) * ir * ir;
+        const double L0b = o0 ? B0b : 0.0, Lmb = om ? Bmb : 0.0, Lpb = op ? Bpb : 0.0;
+        const double inmb = om ? 0.0 : Bmb, inpb = op ? 0.0 : Bpb;
+        ub += dn[2] * L0b;
+        dnb[2] += u * L0b;
+        ub += Wm * Lmb + Wp * Lpb;
+        const double Wmb = (u - c) * Lmb, Wpb = (u + c) * Lpb;
+        dnb[0] += cs2 * (Wmb + Wpb);
+        dnb[1] += rho * c * (Wpb - Wmb);
+        rhob += c * dn[1] * (Wpb - Wmb);
+        if (relax) {
+            const double prb = inmb + inpb;
+            Kb = prb * (cs2 * rho - Pinf);
+            rhob += prb * K * cs2;
+            alb = -(inmb * (cs2 * T1 - rho * c * T2) + inpb * (cs2 * T1 + rho * c * T2));
+            T1b += -alpha * cs2 * (inmb + inpb);
+            T2b += alpha * rho * c * (inmb - inpb);
+            rhob += alpha * c * T2 * (inmb - inpb);
+        }
+    }
+    // transverse terms T1, T2, T4 (eq. NSF-CHAR, central differences)
+    upb[0] = -0.5 * up[2] * T1b;
+    upb[2] = -0.5 * up[0] * T1b;
+    dwb[0] = 0.5 * dw[2] * T1b;
+    dwb[2] = 0.5 * dw[0] * T1b;
+    vb += -0.5 * (up[1] - dw[1]) * T2b;
+    upb[1] = -0.5 * v * T2b;
+    dwb[1] = 0.5 * v * T2b;
+    if (THERMAL) {
+        upb[3] = -0.5 * up[2] * T4b;
+        upb[2] += -0.5 * up[3] * T4b;
+        dwb[3] = 0.5 * dw[2] * T4b;
+        dwb[2] += 0.5 * dw[3] * T4b;
+    } else {
+        upb[3] = 0.0;
+        dwb[3] = 0.0;
+    }
+    Ub[0] = rhob; Ub[1] = ub; Ub[2] = vb; Ub[3] = THERMAL ? Tb : 0.0;
+}
+
+// VJP of corner_rate: adjoints of Uc, U1, U2 (global components) and of K
+template <int Q>
+__device__ __forceinline__ void corner_rate_vjp(const CornerDev& c, const double* Uc, const double* U1, const double* U2,
+                                                const double* Un, const double* rb, double* Ucb, double* U1b,
+                                                double* U2b, double& Kb) {
+    const double tdx = -c.ndy, tdy = c.ndx;
+    double l0[4], l1[4], l2[4], ln[4];
+    auto loc = [&](const double* g, double* l) {
+        l[0] = g[0]; l[1] = g[1] * c.ndx + g[2] * c.ndy; l[2] = g[1] * tdx + g[2] * tdy; l[3] = g[3];
+    };
+    auto loc_t = [&](const double* l, double* g) {   // transpose of loc
+        g[0] = l[0]; g[1] = l[1] * c.ndx + l[2] * tdx; g[2] = l[1] * c.ndy + l[2] * tdy; g[3] = l[3];
+    };
+    loc(Uc, l0); loc(U1, l1); loc(U2, l2); loc(Un, ln);
+    constexpr double inv = 0.35355339059327376220;
+    double dn[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) dn[k] = (3.0 * l0[k] - 4.0 * l1[k] + l2[k]) * inv;
+    double rl[4];
+    rl[0] = rb[0];
+    rl[1] = rb[1] * c.ndx + rb[2] * c.ndy;
+    rl[2] = rb[1] * tdx + rb[2] * tdy;
+    rl[3] = rb[3];
+    double Ub[4], dnb[4], upb[4], dwb[4], alb;
+    char_rate_vjp<Lat<Q>::thermal>(l0, dn, l0, l0, ln, c.relax ? BC_LODI_RELAX : BC_LODI, c.K, 0.0, c.Pinf, rl, Ub,
+                                   dnb, upb, dwb, Kb, alb);
+    double a0[4], a1[4], a2[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        a0[k] = Ub[k] + upb[k] + dwb[k] + 3.0 * inv * dnb[k];
+        a1[k] = -4.0 * inv * dnb[k];
+        a2[k] = inv * dnb[k];
+    }
+    loc_t(a0, Ucb); loc_t(a1, U1b); loc_t(a2, U2b);
+}
+
+// ------------------------------------------------------------------ kernel arguments
+struct AdjArgs {
+    BndArgs b;               // geometry and relaxation; reg_cur = forward region of time n, reg_next = n+1
+    char* adj_cur;           // adjoint region of time n (written)
+    const char* adj_next;    // adjoint region of time n+1 (read)
+    char* xnew;              // region-shaped: strip adjoints at time n+1 from this step's side RK4
+    double* ccon;            // [corner][side axis][n, n+1][4]: side contributions to the corner adjoints
+    double* acc;             // [side blocks][2] (dK, dalpha), then [corner] (dK)
+    double* V1;              // nu / lambda of time n+1
+    double* V0;              // nu / lambda of time n (written by k_adj_bulk)
+    const double* mom;       // moments of time n, planes [4][ny][pitch]
+    double* grad;            // n = 0: dL/d(rho0, ux0, uy0, T0), [4][ny][nx]
+    int ablk0[4], anblk[4];  // side blocks of k_adj_side
+    int arows;               // owned rows per side block
+    int nadj;                // total side blocks
+    int cside[4][2];         // per corner: adjacent side of each axis (-1 if none)
+    int crow[4][2];          // per corner: that side's row next to the corner
+};
+
+// ------------------------------------------------------------------ reverse of a side chunk
+// LDS row lr <-> side row r = r0 - 8 + lr.  Owned rows [r0, r1).  Reverse dependencies: the
+// adjoint of U_b^n on owned rows needs stage s's VJP within s + 1 rows of them, which needs the
+// forward stage inputs within s + 2 rows, hence 8 rows of recomputation halo.
+template <int Q>
+__device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int blk, int chunk) {
+    constexpr int M = Lat<Q>::M, NR = 256 / M, MS = (M == 1) ? 2 : 1, H = 8, NN = NR * M;
+    constexpr bool TH = Lat<Q>::thermal;
+    __shared__ double sY[4][NN * 4];            // stage inputs Y_0 = U_b^n, Y_1, Y_2, Y_3 (global components)
+    __shared__ double sYb1[NN * 4];             // adjoint of U_b^{n+1}
+    __shared__ double sG[NN * 4];               // adjoint of the stage input of the later stage
+    __shared__ double sGn[NN * 4], sGu[NN * 4], sGd[NN * 4];   // per node: adjoints of dn, up, dw
+    __shared__ double sXn[NR * MS * 4], sXp[NR * MS * 4];       // strip values at n, n+1
+    __shared__ double sXbn[NR * MS * 4], sXbp[NR * MS * 4];     // strip adjoints (owned rows)
+    __shared__ double sC[2][2][4];
+    __shared__ double sCb[2][2][M][4];
+    __shared__ double sRed[2][4];
+    const BndArgs& a = g.b;
+    const int tid = threadIdx.x;
+    const int len = sd.len, tper = sd.tper;
+    const int r0 = chunk * g.arows;
+    const int r1 = min(r0 + g.arows, len);
+    const double* ubn = (const double*)(a.reg_cur + sd.off_ub);
+    const double* ubp = (const double*)(a.reg_next + sd.off_ub);
+    const double* stn = (const double*)(a.reg_cur + sd.off_strip);
+    const double* stp = (const double*)(a.reg_next + sd.off_strip);
+    const double* mub1 = (const double*)(g.adj_next + sd.off_ub);
+    double* mub0 = (double*)(g.adj_cur + sd.off_ub);
+    double* xbo = (double*)(g.adj_cur + sd.off_strip);
+    double* xbw = (double*)(g.xnew + sd.off_strip);
+    auto valid = [&](int r) { return tper || (r >= 0 && r < len); };
+    auto phys = [&](int r) { return tper ? ((r % len) + len) % len : r; };
+    auto within = [&](int r, int h) { return r >= r0 - h && r < r1 + h; };
+
+    // ---- phase A: time-n and time-(n+1) values, fold of lambda^{n+1} on the layers ----------
+    const int t = tid;
+    const int lr = t / M, jj = t % M, j = jj + 1, r = r0 - H + lr;
+    const bool node = t < NN && valid(r);
+    if (t < NN) {
+        for (int m = 0; m < 4; ++m) { sYb1[t * 4 + m] = 0.0; sG[t * 4 + m] = 0.0; }
+        if (node) {
+            const int rp = phys(r);
+            for (int m = 0; m < 4; ++m) sY[0][t * 4 + m] = ubn[((size_t)jj * len + rp) * 4 + m];
+            if (within(r, 4)) {
+                double u4[4], lam[Q], G[4];
+                for (int m = 0; m < 4; ++m) u4[m] = ubp[((size_t)jj * len + rp) * 4 + m];
+                int x, y; side_node(sd, j, rp, x, y);
+#pragma unroll
+                for (int i = 0; i < Q; ++i) lam[i] = g.V1[pix<Q>(a.pitch, i, x, y)];
+                feq_vjp<Q>(u4, lam, G);
+                for (int m = 0; m < 4; ++m) sYb1[t * 4 + m] = mub1[((size_t)jj * len + rp) * 4 + m] + G[m];
+            }
+        }
+    }
+    for (int e = tid; e < NR * MS; e += blockDim.x) {
+        const int l2 = e / MS, k = e % MS, rr = r0 - H + l2;
+        for (int m = 0; m < 4; ++m) { sXbn[e * 4 + m] = 0.0; sXbp[e * 4 + m] = 0.0; }
+        if (!valid(rr)) continue;
+        for (int m = 0; m < 4; ++m) {
+            sXn[e * 4 + m] = stn[((size_t)k * len + phys(rr)) * 4 + m];
+            sXp[e * 4 + m] = stp[((size_t)k * len + phys(rr)) * 4 + m];
+        }
+    }
+    if (!tper && tid < 16) {
+        const int e = tid / 8, w = (tid / 4) % 2, m = tid % 4;
+        const int ci = e == 0 ? sd.corner_lo : sd.corner_hi;
+        const char* reg = w == 0 ? a.reg_cur : a.reg_next;
+        sC[e][w][m] = ((const double*)(reg + a.c[ci].off_cu))[m];
+    }
+    if (tid < 2 * 2 * M * 4) (&sCb[0][0][0][0])[tid] = 0.0;
+    __syncthreads();
+
+    const double ast[4] = {0.0, 0.5, 0.5, 1.0}, bst[4] = {1.0, 2.0, 2.0, 1.0};
+    // side-local stage-st inputs of this thread's node
+    auto inputs = [&](int st, double* U, double* dn, double* up, double* dw, double* U0) {
+        const double th = ast[st];
+        const double* Ys = sY[st];
+        auto val_n = [&](int k, double* l) {
+            double gv[4];
+            if (k >= 1) {
+                for (int m = 0; m < 4; ++m) gv[m] = Ys[(lr * M + k - 1) * 4 + m];
+            } else {
+                const double* bn = &sXn[(lr * MS - k) * 4];
+                const double* bp = &sXp[(lr * MS - k) * 4];
+                for (int m = 0; m < 4; ++m) gv[m] = (1.0 - th) * bn[m] + th * bp[m];
+            }
+            to_local(sd, gv, l);
+        };
+        auto val_t = [&](int rr, double* l) {
+            double gv[4];
+            if (!tper && rr < 0) {
+                for (int m = 0; m < 4; ++m) gv[m] = (1.0 - th) * sC[0][0][m] + th * sC[0][1][m];
+            } else if (!tper && rr >= len) {
+                for (int m = 0; m < 4; ++m) gv[m] = (1.0 - th) * sC[1][0][m] + th * sC[1][1][m];
+            } else {
+                const int l2 = lr + (rr - r);
+                for (int m = 0; m < 4; ++m) gv[m] = Ys[(l2 * M + jj) * 4 + m];
+            }
+            to_local(sd, gv, l);
+        };
+        val_n(j, U);
+        if (j == M) {
+            double b1[4], b2[4];
+            val_n(M - 1, b1); val_n(M - 2, b2);
+            for (int m = 0; m < 4; ++m) dn[m] = 0.5 * (3.0 * U[m] - 4.0 * b1[m] + b2[m]);
+        } else {
+            double p1[4], m1[4];
+            val_n(j + 1, p1); val_n(j - 1, m1);
+            for (int m = 0; m < 4; ++m) dn[m] = 0.5 * (p1[m] - m1[m]);
+        }
+        val_t(r + 1, up);
+        val_t(r - 1, dw);
+        to_local(sd, &sY[0][t * 4], U0);
+    };
+
+    // ---- phase B: recompute the stage inputs Y_1..Y_3 (rates k_0..k_2 within 7, 6, 5 rows) ---
+    for (int st = 0; st < 3; ++st) {
+        if (node && within(r, H - 1 - st)) {
+            double U[4], dn[4], up[4], dw[4], U0[4], rl[4], rg[4];
+            const double zero[4] = {0, 0, 0, 0};
+            inputs(st, U, dn, up, dw, U0);
+            char_rate<TH>(U, dn, up, dw, zero, U0, sd.scheme, sd.K, sd.alpha, sd.Pinf, rl);
+            rate_to_global(sd, rl, rg);
+            for (int m = 0; m < 4; ++m) sY[st + 1][t * 4 + m] = sY[0][t * 4 + m] + ast[st + 1] * rg[m];
+        }
+        __syncthreads();
+    }
+
+    // ---- phase C: reverse stages 3..0 ---------------------------------------------------------
+    const bool owned = node && r >= r0 && r < r1;
+    double ybn[4];   // adjoint of U_b^n (owned rows)
+    for (int m = 0; m < 4; ++m) ybn[m] = owned ? sYb1[t * 4 + m] : 0.0;
+    double aK = 0.0, aA = 0.0;
+    for (int st = 3; st >= 0; --st) {
+        const double th = ast[st];
+        double gself[4] = {0, 0, 0, 0};
+        if (node && within(r, st + 1)) {
+            double kb[4], rb[4];
+            for (int m = 0; m < 4; ++m)
+                kb[m] = bst[st] * (1.0 / 6.0) * sYb1[t * 4 + m] + (st < 3 ? ast[st + 1] * sG[t * 4 + m] : 0.0);
+            to_local(sd, kb, rb);
+            double U[4], dn[4], up[4], dw[4], U0[4];
+            inputs(st, U, dn, up, dw, U0);
+            double Ubl[4], dnbl[4], upbl[4], dwbl[4], Kb, alb;
+            char_rate_vjp<TH>(U, dn, up, dw, U0, sd.scheme, sd.K, sd.alpha, sd.Pinf, rb, Ubl, dnbl, upbl, dwbl, Kb, alb);
+            double Ubg[4], dnbg[4], upbg[4], dwbg[4];
+            rate_to_global(sd, Ubl, Ubg);
+            rate_to_global(sd, dnbl, dnbg);
+            rate_to_global(sd, upbl, upbg);
+            rate_to_global(sd, dwbl, dwbg);
+            for (int m = 0; m < 4; ++m) {
+                gself[m] = Ubg[m] + (j == M ? 1.5 * dnbg[m] : 0.0);
+                sGn[t * 4 + m] = dnbg[m];
+                sGu[t * 4 + m] = upbg[m];
+                sGd[t * 4 + m] = dwbg[m];
+            }
+            if (owned) {
+                aK += Kb;
+                aA += alb;
+                if (jj == 0) {   // the strip enters the normal difference of layer 1
+                    double xb[MS][4];
+                    for (int m = 0; m < 4; ++m) {
+                        if (M == 1) { xb[0][m] = -2.0 * dnbg[m]; xb[MS - 1][m] = 0.5 * dnbg[m]; }
+                        else xb[0][m] = -0.5 * dnbg[m];
+                    }
+                    for (int k = 0; k < MS; ++k)
+                        for (int m = 0; m < 4; ++m) {
+                            sXbn[(lr * MS + k) * 4 + m] += (1.0 - th) * xb[k][m];
+                            sXbp[(lr * MS + k) * 4 + m] += th * xb[k][m];
+                        }
+                }
+                if (!tper && r == 0)
+                    for (int m = 0; m < 4; ++m) { sCb[0][0][jj][m] += (1.0 - th) * dwbg[m]; sCb[0][1][jj][m] += th * dwbg[m]; }
+                if (!tper && r == len - 1)
+                    for (int m = 0; m < 4; ++m) { sCb[1][0][jj][m] += (1.0 - th) * upbg[m]; sCb[1][1][jj][m] += th * upbg[m]; }
+            }
+        }
+        __syncthreads();
+        // gather the adjoint of this stage's input on rows within st of the owned range
+        if (node && within(r, st)) {
+            double yb[4];
+            for (int m = 0; m < 4; ++m) yb[m] = gself[m];
+            for (int q = 1; q <= M; ++q) {   // normal differences of the other layers of this row
+                double cf = 0.0;
+                if (q == j) continue;
+                if (q == M) cf = (j == M - 1) ? -2.0 : (j == M - 2 ? 0.5 : 0.0);
+                else cf = (j == q + 1) ? 0.5 : (j == q - 1 ? -0.5 : 0.0);
+                if (cf != 0.0)
+                    for (int m = 0; m < 4; ++m) yb[m] += cf * sGn[((lr * M) + q - 1) * 4 + m];
+            }
+            if (valid(r - 1)) for (int m = 0; m < 4; ++m) yb[m] += sGu[((lr - 1) * M + jj) * 4 + m];
+            if (valid(r + 1)) for (int m = 0; m < 4; ++m) yb[m] += sGd[((lr + 1) * M + jj) * 4 + m];
+            for (int m = 0; m < 4; ++m) sG[t * 4 + m] = yb[m];
+            if (owned) for (int m = 0; m < 4; ++m) ybn[m] += yb[m];
+        }
+        __syncthreads();
+    }
+
+    // ---- phase D: outputs ----------------------------------------------------------------------
+    if (owned) {
+        const int rp = phys(r);
+        for (int m = 0; m < 4; ++m) mub0[((size_t)jj * len + rp) * 4 + m] = ybn[m];
+    }
+    for (int e = tid; e < NR * MS; e += blockDim.x) {
+        const int l2 = e / MS, k = e % MS, rr = r0 - H + l2;
+        if (rr < r0 || rr >= r1 || !valid(rr)) continue;
+        const int rp = phys(rr);
+        for (int m = 0; m < 4; ++m) {
+            xbo[((size_t)k * len + rp) * 4 + m] = sXbn[e * 4 + m];
+            xbw[((size_t)k * len + rp) * 4 + m] = sXbp[e * 4 + m];
+        }
+    }
+    if (!tper && tid < 16) {
+        const int e = tid / 8, w = (tid / 4) % 2, m = tid % 4;
+        const bool mine = e == 0 ? (r0 == 0) : (r1 == len);
+        if (mine) {
+            double v = 0.0;
+            for (int q = 0; q < M; ++q) v += sCb[e][w][q][m];
+            const int ci = e == 0 ? sd.corner_lo : sd.corner_hi;
+            g.ccon[((ci * 2 + sd.nax) * 2 + w) * 4 + m] = v;
+        }
+    }
+    // parameter adjoints: fixed-order block reduction
+    const double wk = wave_sum(aK), wa = wave_sum(aA);
+    if ((tid & 63) == 0) { sRed[0][tid >> 6] = wk; sRed[1][tid >> 6] = wa; }
+    __syncthreads();
+    if (tid < 2) {
+        const double v = sRed[tid][0] + sRed[tid][1] + sRed[tid][2] + sRed[tid][3];
+        g.acc[blk * 2 + tid] += v;
+    }
+}
+
+template <int Q>
+__global__ __launch_bounds__(256) void k_adj_side(AdjArgs g) {
+    const int b = blockIdx.x;
+    int s = 0;
+    while (s < 4 && !(g.anblk[s] > 0 && b >= g.ablk0[s] && b < g.ablk0[s] + g.anblk[s])) ++s;
+    if (s == 4) return;
+    adj_chunk<Q>(g, g.b.s[s], b, b - g.ablk0[s]);
+}
+
+// ------------------------------------------------------------------ corners and strip corrections
+// Blocks 0..3: corner ci (fold of its M x M block, reverse of the corner RK4, corrections of nu
+// at the two diagonal nodes, which also carry the end rows of both adjacent sides' strips).
+// Blocks 4..: rows of the sides' strips away from corners: nu(x_f) += phi . (dm/dM)^T Xbar.
+template <int Q>
+__global__ __launch_bounds__(256) void k_adj_corner(AdjArgs g) {
+    constexpr int M = Lat<Q>::M, MS = (M == 1) ? 2 : 1;
+    const BndArgs& a = g.b;
+    const int tid = threadIdx.x;
+    if (blockIdx.x < 4) {
+        const int ci = blockIdx.x;
+        const CornerDev& c = a.c[ci];
+        if (!c.active || c.zg) return;
+        __shared__ double sF[M * M][4];
+        __shared__ double sGM[2][4];
+        const double* cun = (const double*)(a.reg_cur + c.off_cu);
+        const double* cup = (const double*)(a.reg_next + c.off_cu);
+        const double* cdn = (const double*)(a.reg_cur + c.off_cd);
+        const double* cdp = (const double*)(a.reg_next + c.off_cd);
+        if (tid < M * M) {
+            const int jx = tid / M, jy = tid % M;
+            const int x = c.x0 + c.sxn * jx, y = c.y0 + c.syn * jy;
+            double lam[Q], u4[4], G[4];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) lam[i] = g.V1[pix<Q>(a.pitch, i, x, y)];
+            for (int m = 0; m < 4; ++m) u4[m] = cup[m];
+            feq_vjp<Q>(u4, lam, G);
+            for (int m = 0; m < 4; ++m) sF[tid][m] = G[m];
+        }
+        __syncthreads();
+        if (tid == 0) {
+            const double* mucp = (const double*)(g.adj_next + c.off_cu);
+            const double* dbo = (const double*)(g.adj_next + c.off_cd);
+            double ub[4];
+            for (int m = 0; m < 4; ++m) {
+                ub[m] = mucp[m];
+                for (int q = 0; q < M * M; ++q) ub[m] += sF[q][m];
+                for (int ax = 0; ax < 2; ++ax) ub[m] += g.ccon[((ci * 2 + ax) * 2 + 1) * 4 + m];
+            }
+            // recompute the stage inputs
+            const double ast[4] = {0.0, 0.5, 0.5, 1.0}, bst[4] = {1.0, 2.0, 2.0, 1.0};
+            double Un[4], Y[4][4], k4[4] = {0, 0, 0, 0};
+            for (int m = 0; m < 4; ++m) Un[m] = cun[m];
+            for (int st = 0; st < 4; ++st) {
+                double B1[4], B2[4];
+                for (int m = 0; m < 4; ++m) {
+                    Y[st][m] = Un[m] + ast[st] * k4[m];
+                    B1[m] = (1.0 - ast[st]) * cdn[m] + ast[st] * cdp[m];
+                    B2[m] = (1.0 - ast[st]) * cdn[4 + m] + ast[st] * cdp[4 + m];
+                }
+                if (st < 3) corner_rate<Q>(c, Y[st], B1, B2, Un, k4);
+            }
+            // reverse
+            double ybn[4], yb[4] = {0, 0, 0, 0}, Dbn[8] = {0, 0, 0, 0, 0, 0, 0, 0}, Dbp[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            double Kacc = 0.0;
+            for (int m = 0; m < 4; ++m) ybn[m] = ub[m];
+            for (int st = 3; st >= 0; --st) {
+                const double th = ast[st];
+                double kb[4], B1[4], B2[4], Ycb[4], B1b[4], B2b[4], Kb;
+                for (int m = 0; m < 4; ++m) {
+                    kb[m] = bst[st] * (1.0 / 6.0) * ub[m] + (st < 3 ? ast[st + 1] * yb[m] : 0.0);
+                    B1[m] = (1.0 - th) * cdn[m] + th * cdp[m];
+                    B2[m] = (1.0 - th) * cdn[4 + m] + th * cdp[4 + m];
+                }
+                corner_rate_vjp<Q>(c, Y[st], B1, B2, Un, kb, Ycb, B1b, B2b, Kb);
+                Kacc += Kb;
+                for (int m = 0; m < 4; ++m) {
+                    yb[m] = Ycb[m];
+                    ybn[m] += Ycb[m];
+                    Dbn[m] += (1.0 - th) * B1b[m]; Dbn[4 + m] += (1.0 - th) * B2b[m];
+                    Dbp[m] += th * B1b[m]; Dbp[4 + m] += th * B2b[m];
+                }
+            }
+            double* mucn = (double*)(g.adj_cur + c.off_cu);
+            double* dbn = (double*)(g.adj_cur + c.off_cd);
+            for (int m = 0; m < 4; ++m) {
+                mucn[m] = ybn[m] + g.ccon[((ci * 2 + 0) * 2 + 0) * 4 + m] + g.ccon[((ci * 2 + 1) * 2 + 0) * 4 + m];
+                dbn[m] = Dbn[m];
+                dbn[4 + m] = Dbn[4 + m];
+            }
+            g.acc[2 * g.nadj + ci] += Kacc;
+            // corrections at c + v (with the adjacent strips' end rows) and c + 2v, time n+1
+            double Z1[4], Z2[4];
+            for (int m = 0; m < 4; ++m) {
+                Z1[m] = Dbp[m] + dbo[m];
+                Z2[m] = Dbp[4 + m] + dbo[4 + m];
+            }
+            for (int ax = 0; ax < 2; ++ax) {
+                const int s = g.cside[ci][ax];
+                if (s < 0) continue;
+                const SideDev& sd = a.s[s];
+                const size_t o = (size_t)g.crow[ci][ax] * 4;
+                const double* xo = (const double*)(g.adj_next + sd.off_strip);
+                const double* xw = (const double*)(g.xnew + sd.off_strip);
+                for (int m = 0; m < 4; ++m) Z1[m] += xo[o + m] + xw[o + m];
+            }
+            mom_vjp<Q>(cdp, Z1, sGM[0]);
+            mom_vjp<Q>(cdp + 4, Z2, sGM[1]);
+        }
+        __syncthreads();
+        if (tid < Q) {
+            const int i = tid;
+            for (int e = 0; e < 2; ++e) {
+                const int x = c.xc + (e + 1) * c.vx, y = c.yc + (e + 1) * c.vy;
+                g.V1[pix<Q>(a.pitch, i, x, y)] += phi_dot<Q>(i, sGM[e]);
+            }
+        }
+        return;
+    }
+    // strip rows
+    int b = blockIdx.x - 4;
+    for (int s = 0; s < 4; ++s) {
+        const SideDev& sd = a.s[s];
+        if (sd.kind != KIND_CHAR) continue;
+        const int nb = (sd.len * MS + 255) / 256;
+        if (b >= nb) { b -= nb; continue; }
+        const int e = b * 256 + tid;
+        if (e >= sd.len * MS) return;
+        const int k = e / sd.len, r = e % sd.len;
+        if (!sd.tper && k == 0 && (r == 0 || r == sd.len - 1)) return;   // corner diagonal nodes
+        const double* xo = (const double*)(g.adj_next + sd.off_strip);
+        const double* xw = (const double*)(g.xnew + sd.off_strip);
+        const double* mv = (const double*)(a.reg_next + sd.off_strip);
+        const size_t o = ((size_t)k * sd.len + r) * 4;
+        double Z[4], GM[4];
+        for (int m = 0; m < 4; ++m) Z[m] = xo[o + m] + xw[o + m];
+        mom_vjp<Q>(mv + o, Z, GM);
+        int x, y; side_node(sd, -k, r, x, y);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) g.V1[pix<Q>(a.pitch, i, x, y)] += phi_dot<Q>(i, GM);
+        return;
+    }
+}
+
+// ------------------------------------------------------------------ bulk reverse
+// One thread per node (all nodes; 256-node tiles of one row).  INIT: the reverse of the
+// initialisation f^0 = f^eq(fields) at every node; the fields are read back as the moments of
+// f^0 (mom of time 0), which the equilibrium reproduces exactly.
+template <int Q, bool PX, bool PY, bool INIT>
+__global__ __launch_bounds__(256) void k_adj_bulk(AdjArgs g, BulkArgs k, int bpr) {
+    const int x = (blockIdx.x % bpr) * 256 + threadIdx.x, y = blockIdx.x / bpr;
+    if (x >= k.nx) return;
+    const unsigned long long pitch = k.pitch;
+    double lam[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        int xs = x + cx<Q>(i), ys = y + cy<Q>(i);
+        if (PX) xs = wrapi(xs, k.nx);
+        if (PY) ys = wrapi(ys, k.ny);
+        const bool src = xs >= k.x0 && xs <= k.x1 && ys >= k.y0 && ys <= k.y1;
+        const double v = g.V1[src ? pix<Q>(pitch, i, xs, ys) : 0ull];   // in bounds either way
+        lam[i] = src ? v : 0.0;
+    }
+    if (INIT) {
+        const int id = y * k.nx + x;
+        const unsigned long long plane = (unsigned long long)k.ny * pitch, o = (unsigned long long)y * pitch + x;
+        const double m[4] = {g.mom[o], g.mom[plane + o], g.mom[2 * plane + o], Lat<Q>::thermal ? g.mom[3 * plane + o] : 1.0};
+        double G[4];
+        feq_vjp<Q>(m, lam, G);
+        const size_t n = (size_t)k.nx * k.ny;
+        for (int a = 0; a < 4; ++a) g.grad[a * n + id] = G[a];
+        return;
+    }
+    const bool bulk = x >= k.x0 && x <= k.x1 && y >= k.y0 && y <= k.y1;
+    double* out = g.V0 + pix<Q>(pitch, 0, x, y);
+    if (!bulk) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) out[(unsigned long long)i * pitch] = lam[i];
+        return;
+    }
+    const unsigned long long plane = (unsigned long long)k.ny * pitch, o = (unsigned long long)y * pitch + x;
+    const double m[4] = {g.mom[o], g.mom[plane + o], g.mom[2 * plane + o], g.mom[3 * plane + o]};
+    double G[4], GM[4];
+    feq_vjp<Q>(m, lam, G);
+    mom_vjp<Q>(m, G, GM);
+    const double om = k.omega_d;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) out[(unsigned long long)i * pitch] = (1.0 - om) * lam[i] + om * phi_dot<Q>(i, GM);
+}
+
+// ------------------------------------------------------------------ seed at the final step
+// V^N = J_m^T dL/dm at every node (nu at bulk nodes, lambda at layer and block nodes).  seed:
+// dL/d(rho, ux, uy, T) [4][ny][nx], or NULL for the pressure loss sum over the bulk nodes of
+// (P - cs^2)^2, P = cs^2 rho T.
+template <int Q, typename T>
+__global__ __launch_bounds__(256) void k_adj_seed(const T* __restrict__ F, const double* __restrict__ seed, double* V,
+                                                  BulkArgs k, int bpr) {
+    const int x = (blockIdx.x % bpr) * 256 + threadIdx.x, y = blockIdx.x / bpr;
+    if (x >= k.nx) return;
+    double d[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) d[i] = (double)F[pix<Q>(k.pitch, i, x, y)];
+    double rm1, u, v, th;
+    moments_dev<Q, double>(d, rm1, u, v, th);
+    const double m[4] = {1.0 + rm1, u, v, 1.0 + th};
+    double s[4] = {0, 0, 0, 0};
+    if (seed) {
+        const size_t n = (size_t)k.nx * k.ny, id = (size_t)y * k.nx + x;
+        for (int a = 0; a < 4; ++a) s[a] = seed[a * n + id];
+    } else if (x >= k.x0 && x <= k.x1 && y >= k.y0 && y <= k.y1) {
+        const double cs2 = Lat<Q>::cs2;
+        const double p = cs2 * (rm1 + th + rm1 * th);   // P - cs^2
+        s[0] = 2.0 * p * cs2 * m[3];
+        s[3] = Lat<Q>::thermal ? 2.0 * p * cs2 * m[0] : 0.0;
+    }
+    double GM[4];
+    mom_vjp<Q>(m, s, GM);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) V[pix<Q>(k.pitch, i, x, y)] = phi_dot<Q>(i, GM);
+}
+
+// moments of a population buffer into (rho, ux, uy, T) planes (start of a recomputed segment)
+template <int Q, typename T>
+__global__ __launch_bounds__(256) void k_adj_moments(const T* __restrict__ F, double* __restrict__ mom, BulkArgs k, int bpr) {
+    const int x = (blockIdx.x % bpr) * 256 + threadIdx.x, y = blockIdx.x / bpr;
+    if (x >= k.nx) return;
+    double d[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) d[i] = (double)F[pix<Q>(k.pitch, i, x, y)];
+    double rm1, u, v, th;
+    moments_dev<Q, double>(d, rm1, u, v, th);
+    const unsigned long long plane = (unsigned long long)k.ny * k.pitch, o = (unsigned long long)y * k.pitch + x;
+    mom[o] = 1.0 + rm1; mom[plane + o] = u; mom[2 * plane + o] = v; mom[3 * plane + o] = 1.0 + th;
+}
+
+// ------------------------------------------------------------------ boundary terms of the initial fields
+// U_b^0, the strip X^0, U_c^0 and D^0 are the initial fields at their nodes.  One work-group,
+// one source at a time (sides in order, then corners), so nodes shared by two sources are
+// updated in a fixed order.
+template <int Q>
+__global__ __launch_bounds__(256) void k_adj_final(AdjArgs g) {
+    constexpr int M = Lat<Q>::M, MS = (M == 1) ? 2 : 1;
+    const BndArgs& a = g.b;
+    const size_t n = (size_t)a.nx * a.ny;
+    const char* adj = g.adj_cur;   // adjoint region of time 0
+    for (int s = 0; s < 4; ++s) {
+        const SideDev& sd = a.s[s];
+        if (sd.kind == KIND_CHAR) {
+            const double* mub = (const double*)(adj + sd.off_ub);
+            const double* xb = (const double*)(adj + sd.off_strip);
+            for (int e = threadIdx.x; e < sd.len * (M + MS); e += blockDim.x) {
+                const int k = e / sd.len, r = e % sd.len;   // k < M: layer k+1; else strip k-M
+                int x, y;
+                const double* src;
+                if (k < M) { side_node(sd, k + 1, r, x, y); src = &mub[((size_t)k * sd.len + r) * 4]; }
+                else { side_node(sd, -(k - M), r, x, y); src = &xb[((size_t)(k - M) * sd.len + r) * 4]; }
+                const size_t id = (size_t)y * a.nx + x;
+                for (int c = 0; c < 4; ++c) g.grad[c * n + id] += src[c];
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) {
+        for (int ci = 0; ci < 4; ++ci) {
+            const CornerDev& c = a.c[ci];
+            if (!c.active || c.zg) continue;
+            const double* mu = (const double*)(adj + c.off_cu);
+            const double* db = (const double*)(adj + c.off_cd);
+            const int m = threadIdx.x;
+            g.grad[m * n + (size_t)c.yc * a.nx + c.xc] += mu[m];
+            g.grad[m * n + (size_t)(c.yc + c.vy) * a.nx + c.xc + c.vx] += db[m];
+            g.grad[m * n + (size_t)(c.yc + 2 * c.vy) * a.nx + c.xc + 2 * c.vx] += db[4 + m];
+        }
+    }
+}
+
+}  // namespace lbm

@@ -92,6 +92,7 @@ struct BulkArgs {
     unsigned long long pitch;
     float omega_f;
     double omega_d;
+    double* mom;                  // HIST only: (rho, ux, uy, T) planes [4][ny][pitch] of the new state
 };
 
 // One thread per node.  Work-group x-ranges start at x = 0 (multiples of 256), so every
@@ -99,7 +100,8 @@ struct BulkArgs {
 // outside the bulk range do nothing.  Loads are ordinary (cached) loads, issued source row by
 // source row: the shifted pulls of neighbouring wavefronts share cache lines at their edges,
 // which L2 serves once.  Stores are non-temporal: the output is not re-read in this step.
-template <int Q, typename T, bool PX, bool PY>
+// HIST (recomputation for the adjoint) also stores the node's moments.
+template <int Q, typename T, bool PX, bool PY, bool HIST>
 __device__ __forceinline__ void bulk_node(const T* __restrict__ A, T* __restrict__ B, const BulkArgs& g, int x, int y) {
     if (x < g.x0 || x > g.x1) return;
     T d[Q];
@@ -115,6 +117,15 @@ __device__ __forceinline__ void bulk_node(const T* __restrict__ A, T* __restrict
             if (PX) xs = wrapi(xs, g.nx);
             d[i] = Ar[(unsigned long long)i * g.pitch + xs];
         }
+    }
+    if (HIST) {
+        T rm1, u, v, th;
+        moments_dev<Q, T>(d, rm1, u, v, th);
+        const unsigned long long plane = (unsigned long long)g.ny * g.pitch, o = (unsigned long long)y * g.pitch + x;
+        g.mom[o] = 1.0 + (double)rm1;
+        g.mom[plane + o] = (double)u;
+        g.mom[2 * plane + o] = (double)v;
+        g.mom[3 * plane + o] = 1.0 + (double)th;
     }
     const T omega = sizeof(T) == 4 ? (T)g.omega_f : (T)g.omega_d;
     collide_dev<Q, T>(d, omega);
@@ -758,7 +769,7 @@ template <int Q, typename T> struct StepOcc { static constexpr int waves = (Q ==
 // nodes, bpr tiles per row, rows from g.y0, in row-major order (the whole chip sweeps the rows
 // in order, which streams best from HBM; an XCD-aware order that keeps a row's tiles on one L2
 // removes the ~10 % duplicate edge-line fetches but streams slower).
-template <int Q, typename T, bool PX, bool PY>
+template <int Q, typename T, bool PX, bool PY, bool HIST>
 __global__ __launch_bounds__(256, (StepOcc<Q, T>::waves)) void k_step(const T* __restrict__ A, T* __restrict__ B, BndArgs a,
                                                                      BulkArgs g, int nbnd, int bpr) {
     const int b = (int)blockIdx.x;
@@ -767,7 +778,7 @@ __global__ __launch_bounds__(256, (StepOcc<Q, T>::waves)) void k_step(const T* _
         return;
     }
     const int t = b - nbnd;
-    bulk_node<Q, T, PX, PY>(A, B, g, (t % bpr) * 256 + (int)threadIdx.x, g.y0 + t / bpr);
+    bulk_node<Q, T, PX, PY, HIST>(A, B, g, (t % bpr) * 256 + (int)threadIdx.x, g.y0 + t / bpr);
 }
 
 }  // namespace lbm

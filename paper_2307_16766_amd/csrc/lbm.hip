@@ -14,6 +14,7 @@
 #include <string>
 #include <vector>
 
+#include "adjoint.h"
 #include "kernels.h"
 #include "lbm.h"
 
@@ -151,6 +152,17 @@ void make_layout(const lbm_config* c, Layout& L) {
 
 }  // namespace
 
+// Tape of a recorded run (the caller's device buffer): checkpoints every K steps, and the
+// scratch of the reverse sweep.
+struct Tape {
+    char* base = nullptr;
+    int N = 0, K = 0, nchk = 0;
+    long step_end = -1;
+    size_t chk_stride = 0, off_R[2] = {0, 0}, off_V[2] = {0, 0}, off_mom = 0, mom_bytes = 0, off_rh = 0;
+    size_t off_adj[2] = {0, 0}, off_xnew = 0, off_ccon = 0, off_acc = 0, total = 0;
+    int ablk0[4] = {0, 0, 0, 0}, anblk[4] = {0, 0, 0, 0}, arows = 0, nadj = 0, nstrip = 0;
+};
+
 struct lbm_ctx {
     lbm_config cfg;
     Layout L;
@@ -171,6 +183,7 @@ struct lbm_ctx {
     bool timing = false;
     std::vector<hipEvent_t> tev;   // pairs: start, end
     size_t tcount = 0;             // recorded pairs
+    Tape tape;
 };
 
 namespace {
@@ -246,22 +259,30 @@ hipError_t timed_launch(lbm_ctx* c, F&& launch) {
     return hipSuccess;
 }
 
-template <int Q, typename T>
-int launch_step(lbm_ctx* c) {
-    const BndArgs a = make_bnd(c);
-    const T* A = (const T*)c->f[c->cur];
-    T* B = (T*)c->f[c->cur ^ 1];
-    const BulkArgs& g = c->bulk;
+template <int Q, typename T, bool HIST>
+void launch_step_raw(const lbm_ctx* c, const T* A, T* B, char* reg_cur, char* reg_next, double* mom, hipStream_t s) {
+    BndArgs a = make_bnd(c);
+    a.reg_cur = reg_cur;
+    a.reg_next = reg_next;
+    BulkArgs g = c->bulk;
+    g.mom = mom;
     const int bpr = (g.x1 + 1 + 255) / 256;   // bulk tiles per row, aligned to x = 0
     const int nbnd = c->nbnd;
     const int nblk = nbnd + bpr * (g.y1 - g.y0 + 1);
     const bool px = c->cfg.bc[0] == BC_PERIODIC, py = c->cfg.bc[2] == BC_PERIODIC;
-    auto step = [&](hipStream_t s) {
-        if (px && py) hipLaunchKernelGGL((k_step<Q, T, true, true>), dim3(nblk), dim3(256), 0, s, A, B, a, g, nbnd, bpr);
-        else if (px) hipLaunchKernelGGL((k_step<Q, T, true, false>), dim3(nblk), dim3(256), 0, s, A, B, a, g, nbnd, bpr);
-        else if (py) hipLaunchKernelGGL((k_step<Q, T, false, true>), dim3(nblk), dim3(256), 0, s, A, B, a, g, nbnd, bpr);
-        else hipLaunchKernelGGL((k_step<Q, T, false, false>), dim3(nblk), dim3(256), 0, s, A, B, a, g, nbnd, bpr);
-    };
+    if (px && py) hipLaunchKernelGGL((k_step<Q, T, true, true, HIST>), dim3(nblk), dim3(256), 0, s, A, B, a, g, nbnd, bpr);
+    else if (px) hipLaunchKernelGGL((k_step<Q, T, true, false, HIST>), dim3(nblk), dim3(256), 0, s, A, B, a, g, nbnd, bpr);
+    else if (py) hipLaunchKernelGGL((k_step<Q, T, false, true, HIST>), dim3(nblk), dim3(256), 0, s, A, B, a, g, nbnd, bpr);
+    else hipLaunchKernelGGL((k_step<Q, T, false, false, HIST>), dim3(nblk), dim3(256), 0, s, A, B, a, g, nbnd, bpr);
+}
+
+template <int Q, typename T>
+int launch_step(lbm_ctx* c) {
+    const T* A = (const T*)c->f[c->cur];
+    T* B = (T*)c->f[c->cur ^ 1];
+    char* rc = c->region[c->cur];
+    char* rn = c->region[c->cur ^ 1];
+    auto step = [&](hipStream_t s) { launch_step_raw<Q, T, false>(c, A, B, rc, rn, nullptr, s); };
     HIPCHK(c, timed_launch(c, step));
     c->cur ^= 1;
     c->steps += 1;
@@ -286,6 +307,161 @@ int launch_init(lbm_ctx* c, const double* rho, const double* ux, const double* u
         hipLaunchKernelGGL((k_dirichlet<Q, T>), dim3((tot + 255) / 256), dim3(256), 0, c->stream, a, s, c->inlet[s],
                            (T*)c->f[0], (T*)c->f[1]);
         HIPCHK(c, hipGetLastError());
+    }
+    return LBM_OK;
+}
+
+// ---------------------------------------------------------------- discrete adjoint (host side)
+int adjoint_supported(const lbm_config& g, std::string& err) {
+    for (int s = 0; s < 4; ++s)
+        if (g.bc[s] != BC_PERIODIC && g.bc[s] != BC_LODI && g.bc[s] != BC_LODI_RELAX) {
+            err = "the adjoint supports periodic, LODI and LODI-RELAX sides only";
+            return LBM_E_UNSUPPORTED;
+        }
+    if (g.stencil == 9 && g.bc[0] != BC_PERIODIC && g.bc[2] != BC_PERIODIC) {
+        err = "the D2Q9 adjoint needs one periodic axis (no corners)";
+        return LBM_E_UNSUPPORTED;
+    }
+    return LBM_OK;
+}
+
+void tape_layout(const Layout& L, int ny, int N, int K, Tape& t) {
+    t.N = N;
+    t.K = K;
+    t.nchk = (N + K - 1) / K;
+    t.chk_stride = L.f_bytes + L.region_bytes;
+    size_t off = (size_t)t.nchk * t.chk_stride;
+    for (int k = 0; k < 2; ++k) { t.off_R[k] = off; off += L.f_bytes; }
+    const size_t vbytes = align_up((size_t)L.Q * L.pitch * ny * 8);
+    for (int k = 0; k < 2; ++k) { t.off_V[k] = off; off += vbytes; }
+    t.mom_bytes = align_up((size_t)4 * L.pitch * ny * 8);
+    t.off_mom = off; off += (size_t)(K + 1) * t.mom_bytes;
+    t.off_rh = off; off += (size_t)(K + 1) * L.region_bytes;
+    for (int k = 0; k < 2; ++k) { t.off_adj[k] = off; off += L.region_bytes; }
+    t.off_xnew = off; off += L.region_bytes;
+    t.off_ccon = off; off += align_up(4 * 2 * 2 * 4 * 8);
+    t.arows = 256 / L.M - 16;   // must match NR - 2 H in adj_chunk
+    t.nadj = 0;
+    t.nstrip = 0;
+    for (int s = 0; s < 4; ++s) {
+        t.ablk0[s] = t.nadj;
+        t.anblk[s] = L.s[s].kind == KIND_CHAR ? (L.s[s].len + t.arows - 1) / t.arows : 0;
+        t.nadj += t.anblk[s];
+        if (L.s[s].kind == KIND_CHAR) t.nstrip += (L.s[s].len * L.MS + 255) / 256;
+    }
+    t.off_acc = off; off += align_up((size_t)(2 * t.nadj + 4) * 8);
+    t.total = off;
+}
+
+template <int Q, typename T>
+int run_adjoint(lbm_ctx* c, const double* seed, double* grad, double* h_relax) {
+    const Tape& t = c->tape;
+    const Layout& L = c->L;
+    hipStream_t st = c->stream;
+    char* base = t.base;
+    const BulkArgs& bk = c->bulk;
+    const int nx = c->cfg.nx, ny = c->cfg.ny;
+    const int bpr = (nx + 255) / 256;
+    const bool px = c->cfg.bc[0] == BC_PERIODIC, py = c->cfg.bc[2] == BC_PERIODIC;
+    double* V[2] = {(double*)(base + t.off_V[0]), (double*)(base + t.off_V[1])};
+    auto mom_slot = [&](int j) { return (double*)(base + t.off_mom + (size_t)j * t.mom_bytes); };
+    auto reg_slot = [&](int j) { return base + t.off_rh + (size_t)j * L.region_bytes; };
+    T* R[2] = {(T*)(base + t.off_R[0]), (T*)(base + t.off_R[1])};
+
+    hipLaunchKernelGGL((k_adj_seed<Q, T>), dim3(bpr * ny), dim3(256), 0, st, (const T*)c->f[c->cur], seed, V[t.N & 1], bk, bpr);
+    HIPCHK(c, hipGetLastError());
+    for (int k = 0; k < 2; ++k) HIPCHK(c, hipMemsetAsync(base + t.off_adj[k], 0, L.region_bytes, st));
+    HIPCHK(c, hipMemsetAsync(base + t.off_xnew, 0, L.region_bytes, st));
+    HIPCHK(c, hipMemsetAsync(base + t.off_ccon, 0, 4 * 2 * 2 * 4 * 8, st));
+    HIPCHK(c, hipMemsetAsync(base + t.off_acc, 0, (size_t)(2 * t.nadj + 4) * 8, st));
+
+    AdjArgs g;
+    std::memset(&g, 0, sizeof(g));
+    g.b = make_bnd(c);
+    g.xnew = base + t.off_xnew;
+    g.ccon = (double*)(base + t.off_ccon);
+    g.acc = (double*)(base + t.off_acc);
+    g.grad = grad;
+    for (int s = 0; s < 4; ++s) { g.ablk0[s] = t.ablk0[s]; g.anblk[s] = t.anblk[s]; }
+    g.arows = t.arows;
+    g.nadj = t.nadj;
+    for (int ci = 0; ci < 4; ++ci)
+        for (int ax = 0; ax < 2; ++ax) {
+            g.cside[ci][ax] = -1;
+            g.crow[ci][ax] = 0;
+            if (!L.c[ci].active) continue;
+            const int s = ax == 0 ? (ci & 1) : 2 + (ci >> 1);
+            g.cside[ci][ax] = s;
+            g.crow[ci][ax] = L.s[s].corner_lo == ci ? 0 : L.s[s].len - 1;
+        }
+    bool any_char = false, any_corner = false;
+    for (int s = 0; s < 4; ++s) any_char = any_char || L.s[s].kind == KIND_CHAR;
+    for (int ci = 0; ci < 4; ++ci) any_corner = any_corner || L.c[ci].active;
+
+    for (int seg = t.nchk - 1; seg >= 0; --seg) {
+        const int n0 = seg * t.K, n1 = std::min(n0 + t.K, t.N);
+        const char* chk = base + (size_t)seg * t.chk_stride;
+        HIPCHK(c, hipMemcpyAsync(R[0], chk, L.f_bytes, hipMemcpyDeviceToDevice, st));
+        HIPCHK(c, hipMemcpyAsync(reg_slot(0), chk + L.f_bytes, L.region_bytes, hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL((k_adj_moments<Q, T>), dim3(bpr * ny), dim3(256), 0, st, (const T*)R[0], mom_slot(0), bk, bpr);
+        HIPCHK(c, hipGetLastError());
+        for (int j = 0; j < n1 - n0; ++j) {
+            launch_step_raw<Q, T, true>(c, R[j & 1], R[(j + 1) & 1], reg_slot(j), reg_slot(j + 1), mom_slot(j + 1), st);
+            HIPCHK(c, hipGetLastError());
+        }
+        for (int n = n1 - 1; n >= n0; --n) {
+            const int j = n - n0;
+            g.b.reg_cur = reg_slot(j);
+            g.b.reg_next = reg_slot(j + 1);
+            g.adj_cur = base + t.off_adj[n & 1];
+            g.adj_next = base + t.off_adj[(n + 1) & 1];
+            g.V1 = V[(n + 1) & 1];
+            g.V0 = V[n & 1];
+            g.mom = mom_slot(j);
+            if (t.nadj > 0) {
+                hipLaunchKernelGGL((k_adj_side<Q>), dim3(t.nadj), dim3(256), 0, st, g);
+                HIPCHK(c, hipGetLastError());
+            }
+            if (any_char || any_corner) {
+                hipLaunchKernelGGL((k_adj_corner<Q>), dim3(4 + t.nstrip), dim3(256), 0, st, g);
+                HIPCHK(c, hipGetLastError());
+            }
+            const dim3 grid(bpr * ny);
+            if (n > 0) {
+                if (px && py) hipLaunchKernelGGL((k_adj_bulk<Q, true, true, false>), grid, dim3(256), 0, st, g, bk, bpr);
+                else if (px) hipLaunchKernelGGL((k_adj_bulk<Q, true, false, false>), grid, dim3(256), 0, st, g, bk, bpr);
+                else if (py) hipLaunchKernelGGL((k_adj_bulk<Q, false, true, false>), grid, dim3(256), 0, st, g, bk, bpr);
+                else hipLaunchKernelGGL((k_adj_bulk<Q, false, false, false>), grid, dim3(256), 0, st, g, bk, bpr);
+            } else {
+                if (px && py) hipLaunchKernelGGL((k_adj_bulk<Q, true, true, true>), grid, dim3(256), 0, st, g, bk, bpr);
+                else if (px) hipLaunchKernelGGL((k_adj_bulk<Q, true, false, true>), grid, dim3(256), 0, st, g, bk, bpr);
+                else if (py) hipLaunchKernelGGL((k_adj_bulk<Q, false, true, true>), grid, dim3(256), 0, st, g, bk, bpr);
+                else hipLaunchKernelGGL((k_adj_bulk<Q, false, false, true>), grid, dim3(256), 0, st, g, bk, bpr);
+            }
+            HIPCHK(c, hipGetLastError());
+        }
+    }
+    g.adj_cur = base + t.off_adj[0];
+    hipLaunchKernelGGL((k_adj_final<Q>), dim3(1), dim3(256), 0, st, g);
+    HIPCHK(c, hipGetLastError());
+    std::vector<double> acc((size_t)2 * t.nadj + 4);
+    HIPCHK(c, hipMemcpyAsync(acc.data(), base + t.off_acc, acc.size() * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    // dK / dsigma per side, as in make_bnd
+    const double cs2 = Q == 9 ? Lat<9>::cs2 : Lat<37>::cs2;
+    for (int s = 0; s < 4; ++s) {
+        const lbm_relax& p = c->relax[s];
+        const double cinf = Q == 37 ? std::sqrt(2.0 * cs2 * p.T_inf) : std::sqrt(cs2);
+        const double len = p.length > 0 ? p.length : (double)L.s[s].Nn;
+        const double kf = (1.0 - p.mach * p.mach) * cinf / len;
+        double dK = 0.0, dA = 0.0;
+        for (int b = t.ablk0[s]; b < t.ablk0[s] + t.anblk[s]; ++b) { dK += acc[2 * b]; dA += acc[2 * b + 1]; }
+        if (s < 2)
+            for (int ci = 0; ci < 4; ++ci)
+                if (L.c[ci].active && (ci & 1) == s) dK += acc[2 * t.nadj + ci];
+        const bool rel = c->cfg.bc[s] == BC_LODI_RELAX;
+        h_relax[2 * s] = rel ? dK * kf : 0.0;
+        h_relax[2 * s + 1] = rel ? dA : 0.0;
     }
     return LBM_OK;
 }
@@ -465,7 +641,49 @@ int lbm_restore(lbm_ctx* c, const void* d_buf) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->cur = 0;
     c->steps = steps;
+    c->tape = Tape();
     return LBM_OK;
+}
+
+size_t lbm_tape_bytes(const lbm_ctx* c, int nsteps, int every) {
+    if (!c || nsteps < 1 || every < 1) return 0;
+    Tape t;
+    tape_layout(c->L, c->cfg.ny, nsteps, std::min(every, nsteps), t);
+    return t.total;
+}
+
+int lbm_record(lbm_ctx* c, int nsteps, int every, void* d_tape, size_t tape_bytes) {
+    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+    std::string err;
+    const int sup = adjoint_supported(c->cfg, err);
+    if (sup != LBM_OK) return fail(c, sup, err);
+    if (nsteps < 1 || every < 1) return fail(c, LBM_E_ARG, "nsteps and every must be positive");
+    if (!d_tape || ((uintptr_t)d_tape % ALIGN) != 0) return fail(c, LBM_E_ARG, "tape must be non-NULL and 256-byte aligned");
+    if (c->steps != 0) return fail(c, LBM_E_STATE, "recording starts from the initial state (no steps taken)");
+    Tape t;
+    tape_layout(c->L, c->cfg.ny, nsteps, std::min(every, nsteps), t);
+    if (tape_bytes < t.total) return fail(c, LBM_E_ARG, "tape smaller than lbm_tape_bytes");
+    t.base = (char*)d_tape;
+    for (int n = 0; n < nsteps; ++n) {
+        if (n % t.K == 0) {
+            char* chk = t.base + (size_t)(n / t.K) * t.chk_stride;
+            HIPCHK(c, hipMemcpyAsync(chk, c->f[c->cur], c->L.f_bytes, hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(chk + c->L.f_bytes, c->region[c->cur], c->L.region_bytes, hipMemcpyDeviceToDevice, c->stream));
+        }
+        const int rc = dispatch(c, [&]<int Q, typename T>() -> int { return launch_step<Q, T>(c); });
+        if (rc != LBM_OK) return rc;
+    }
+    t.step_end = c->steps;
+    c->tape = t;
+    return LBM_OK;
+}
+
+int lbm_adjoint(lbm_ctx* c, const double* d_seed, double* d_grad_fields, double* h_grad_relax) {
+    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+    if (!d_grad_fields || !h_grad_relax) return fail(c, LBM_E_ARG, "output pointer is NULL");
+    if (!c->tape.base) return fail(c, LBM_E_STATE, "no recorded run (call lbm_record first)");
+    if (c->steps != c->tape.step_end) return fail(c, LBM_E_STATE, "the context has stepped since lbm_record");
+    return dispatch(c, [&]<int Q, typename T>() -> int { return run_adjoint<Q, T>(c, d_seed, d_grad_fields, h_grad_relax); });
 }
 
 long lbm_steps_done(const lbm_ctx* c) { return c ? c->steps : -1; }

@@ -23,7 +23,7 @@ PRECISION = {"fp64": FP64, "fp32dev": FP32DEV}
 SYMBOLS = ["lbm_workspace_bytes", "lbm_init", "lbm_cbc_params", "lbm_dirichlet_profile", "lbm_step",
            "lbm_macroscopic", "lbm_boundary_state", "lbm_diagnostics", "lbm_state_bytes", "lbm_save",
            "lbm_restore", "lbm_steps_done", "lbm_set_kernel_timing", "lbm_bulk_kernel_time",
-           "lbm_lattice_info", "lbm_last_error", "lbm_destroy"]
+           "lbm_tape_bytes", "lbm_record", "lbm_adjoint", "lbm_lattice_info", "lbm_last_error", "lbm_destroy"]
 
 
 class LBMError(RuntimeError):
@@ -73,6 +73,10 @@ def load():
     L.lbm_steps_done.argtypes = [_vp]
     L.lbm_set_kernel_timing.argtypes = [_vp, ctypes.c_int]
     L.lbm_bulk_kernel_time.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_long)]
+    L.lbm_tape_bytes.restype = ctypes.c_size_t
+    L.lbm_tape_bytes.argtypes = [_vp, ctypes.c_int, ctypes.c_int]
+    L.lbm_record.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_size_t]
+    L.lbm_adjoint.argtypes = [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]
     L.lbm_lattice_info.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
                                    ctypes.POINTER(ctypes.c_int)]
@@ -217,3 +221,32 @@ class LBM:
         n = ctypes.c_long()
         self._check(load().lbm_bulk_kernel_time(self.ctx, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    # ---------------------------------------------------------------- discrete adjoint
+    def tape_bytes(self, nsteps, every):
+        return load().lbm_tape_bytes(self.ctx, nsteps, every)
+
+    def record(self, nsteps, every=50):
+        """Advance nsteps steps from the initial state, keeping a checkpoint every `every` steps
+        in a device tape (owned here) for adjoint()."""
+        nbytes = self.tape_bytes(nsteps, every)
+        if nbytes == 0:
+            raise LBMError(LBM_E_ARG, "invalid nsteps / every")
+        self.tape = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
+        self._check(load().lbm_record(self.ctx, nsteps, every, _vp(self.tape.data_ptr()), nbytes))
+
+    def adjoint(self, seed=None):
+        """Gradient of a loss of the final fields (seed = dL/d(rho, ux, uy, T), shape (4, ny, nx);
+        None: the pressure loss of diagnostics()[4]).  Returns (dL/d(rho0, ux0, uy0, T0) as a
+        (4, ny, nx) float64 device tensor, dL/d(sigma, alpha) per side as a (4, 2) array)."""
+        torch = self.torch
+        grad = torch.empty((4, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        sd = None
+        if seed is not None:
+            sd = torch.as_tensor(seed).to(device=self.device, dtype=torch.float64).contiguous()
+            if tuple(sd.shape) != (4, self.ny, self.nx):
+                raise LBMError(LBM_E_ARG, "seed must have shape (4, ny, nx)")
+        rel = (ctypes.c_double * 8)()
+        self._check(load().lbm_adjoint(self.ctx, _vp(sd.data_ptr()) if sd is not None else None,
+                                       _vp(grad.data_ptr()), rel))
+        return grad, np.array(rel[:]).reshape(4, 2)

@@ -93,3 +93,9 @@ def shear_layer(nx, ny, u0=0.1, thickness=10.0, noise=1e-3, seed=16766):
 def uniform_flow(nx, ny, ux=0.0, uy=0.0, rho=1.0, T=1.0):
     one = np.ones((ny, nx))
     return rho * one, ux * one, uy * one, T * one
+
+
+def random_directions(n, nx, ny, seed):
+    """n seeded standard-normal perturbation fields [n][ny][nx] (directional-derivative checks)."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((n, ny, nx))

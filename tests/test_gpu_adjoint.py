@@ -1,0 +1,261 @@
+"""GPU discrete adjoint (lbm_record / lbm_adjoint) against the oracle's forward-mode dual numbers
+and against central finite differences of the GPU forward run.
+
+The adjoint gives the whole gradient; the oracle gives directional derivatives.  They are compared
+through dot products: dL/dsigma and dL/dalpha summed over the sides (the oracle perturbs every
+side together) and sum_x dL/dF0(x) . dF0(x) for seeded perturbations dF0 of the initial fields.
+Both are exact derivatives of the same FP64 discrete map, evaluated along trajectories that
+differ by rounding only, so they agree far below the finite-difference bar of 1e-4."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from gpu_cases import TAU_37, log
+from oracle import oracle as O
+from paper_2307_16766_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c4_tangents.json")
+ADJ_TOL = 1e-9   # adjoint vs dual numbers, relative
+
+
+def _sim(stencil, nx, ny, tau, bc, fields, relax, precision="fp64"):
+    from paper_2307_16766_amd import lbm
+    g = lbm.LBM(stencil, nx, ny, tau, bc, fields, precision=precision)
+    g.set_relax(-1, **relax)
+    return g
+
+
+def _directional(grad, grel, dF, dsig, dalp):
+    """Directional derivative from the adjoint's gradient."""
+    g = grad.cpu().numpy()
+    return dsig * grel[:, 0].sum() + dalp * grel[:, 1].sum() + float((g * dF).sum())
+
+
+def _relerr(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+CASES = {
+    # D2Q37, four LODI-RELAX sides with corners; two row chunks per side in the reverse kernel
+    "d2q37_corners": dict(stencil=37, nx=80, ny=90, tau=TAU_37, bc=["lodi_relax"] * 4, steps=40, every=15,
+                          relax=dict(sigma=0.25, alpha=0.1, mach=0.05)),
+    # D2Q37, LODI outflow / LODI-RELAX inflow, periodic y
+    "d2q37_periodic_y": dict(stencil=37, nx=64, ny=48, tau=TAU_37, bc=["lodi_relax", "lodi", "periodic", "periodic"],
+                             steps=30, every=30, relax=dict(sigma=0.3, alpha=0.2, mach=0.05)),
+    # D2Q9 isothermal, LODI-RELAX at both x sides, periodic y with two row chunks per side
+    "d2q9_periodic_y": dict(stencil=9, nx=40, ny=300, tau=0.6, bc=["lodi_relax", "lodi_relax", "periodic", "periodic"],
+                            steps=40, every=9, relax=dict(sigma=0.25, alpha=0.1, mach=0.05)),
+}
+
+
+def _case_fields(c, seed):
+    nx, ny = c["nx"], c["ny"]
+    rho, ux, uy, T = W.random_temperature(nx, ny, std=1e-3, seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    rho = rho + 1e-3 * rng.standard_normal((ny, nx))
+    ux = ux + 0.02 + 1e-3 * rng.standard_normal((ny, nx))
+    uy = uy - 0.01 + 1e-3 * rng.standard_normal((ny, nx))
+    return [rho, ux, uy, T]
+
+
+def _case_dirs(c, seed):
+    nx, ny = c["nx"], c["ny"]
+    d = W.random_directions(6, nx, ny, seed)
+    dF = np.zeros((3, 4, ny, nx))
+    dF[1, 0], dF[1, 1] = d[0], d[1]             # density and x velocity
+    dF[2, 2], dF[2, 3] = d[2], d[3]             # y velocity and temperature
+    if c["stencil"] == 9:
+        dF[2, 3] = 0.0
+    return dF
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("loss", ["pressure", "linear"])
+def test_adjoint_matches_oracle_tangents(name, loss):
+    c = CASES[name]
+    log(f"[gpu-case] adjoint vs oracle tangents {name} loss={loss}")
+    fields = _case_fields(c, 31)
+    dF = _case_dirs(c, 32)
+    relax = np.tile([c["relax"]["sigma"], c["relax"]["alpha"], 1.0, 1.0, c["relax"]["mach"], 0.0], (4, 1))
+    wlin = None
+    if loss == "linear":
+        wlin = np.random.default_rng(33).standard_normal((4, c["ny"], c["nx"]))
+    # direction 0: sigma and alpha together; 1, 2: field perturbations
+    oloss, od = O.tangent_run_fields(c["stencil"], c["nx"], c["ny"], c["tau"], c["bc"], relax, [1, 0, 0], [0.5, 0, 0],
+                                     fields, dF, c["steps"], wlin)
+    g = _sim(c["stencil"], c["nx"], c["ny"], c["tau"], c["bc"], fields, c["relax"])
+    g.record(c["steps"], c["every"])
+    d = g.diagnostics()
+    if loss == "pressure":
+        assert _relerr(d[4], oloss) < 1e-10
+    grad, grel = g.adjoint(seed=wlin)
+    got = [_directional(grad, grel, dF[0], 1.0, 0.5), _directional(grad, grel, dF[1], 0, 0),
+           _directional(grad, grel, dF[2], 0, 0)]
+    errs = [_relerr(a, b) for a, b in zip(got, od)]
+    log(f"{name} {loss}: oracle {od}, adjoint {got}, rel errors {errs}")
+    assert all(abs(x) > 0 for x in od)
+    assert max(errs) < ADJ_TOL
+    g.close()
+
+
+def test_adjoint_checkpoint_interval_and_repeat():
+    # the gradient does not depend on the checkpoint interval; a second adjoint call with the
+    # same tape reproduces the first bit for bit
+    c = CASES["d2q37_corners"]
+    log("[gpu-case] adjoint checkpoint interval")
+    fields = _case_fields(c, 41)
+    res = []
+    for every in (1, 13, c["steps"]):
+        g = _sim(c["stencil"], c["nx"], c["ny"], c["tau"], c["bc"], fields, c["relax"])
+        g.record(c["steps"], every)
+        a = g.adjoint()
+        if every == 13:
+            b = g.adjoint()
+            assert np.array_equal(a[0].cpu().numpy(), b[0].cpu().numpy()) and np.array_equal(a[1], b[1])
+        res.append((a[0].cpu().numpy(), a[1]))
+        g.close()
+    ref = res[0]
+    for gr, rl in res[1:]:
+        assert np.abs(gr - ref[0]).max() <= 1e-12 * np.abs(ref[0]).max()
+        assert np.abs(rl - ref[1]).max() <= 1e-12 * np.abs(ref[1]).max()
+
+
+def test_adjoint_fp32dev_close_to_fp64():
+    # FP32 deviation storage for the forward (adjoint state in FP64): the gradient is the
+    # derivative along the FP32 trajectory, within 1e-3 of the FP64 one
+    c = CASES["d2q37_corners"]
+    log("[gpu-case] adjoint fp32dev")
+    fields = _case_fields(c, 51)
+    out = {}
+    for prec in ("fp64", "fp32dev"):
+        g = _sim(c["stencil"], c["nx"], c["ny"], c["tau"], c["bc"], fields, c["relax"], precision=prec)
+        g.record(c["steps"], c["every"])
+        gr, rl = g.adjoint()
+        out[prec] = (gr.cpu().numpy(), rl)
+        g.close()
+    a, b = out["fp32dev"], out["fp64"]
+    assert np.linalg.norm(a[0] - b[0]) <= 1e-3 * np.linalg.norm(b[0])
+    assert np.abs(a[1] - b[1]).max() <= 1e-3 * np.abs(b[1]).max()
+
+
+def test_adjoint_argument_and_state_errors():
+    from paper_2307_16766_amd import lbm
+    f = W.temperature_pulse(40, 40)
+    g = lbm.LBM(37, 40, 40, TAU_37, ["lodi_relax", "cbc_relax", "lodi", "lodi"], f)
+    with pytest.raises(lbm.LBMError) as e:
+        g.record(5, 2)
+    assert e.value.code == lbm.LBM_E_UNSUPPORTED
+    g.close()
+    g = lbm.LBM(37, 40, 40, TAU_37, ["lodi_relax"] * 4, f)
+    with pytest.raises(lbm.LBMError) as e:
+        g.adjoint()
+    assert e.value.code == lbm.LBM_E_STATE
+    g.step(1)
+    with pytest.raises(lbm.LBMError) as e:
+        g.record(5, 2)
+    assert e.value.code == lbm.LBM_E_STATE
+    g.close()
+    g = lbm.LBM(37, 40, 40, TAU_37, ["lodi_relax"] * 4, f)
+    g.record(6, 4)
+    g.step(1)
+    with pytest.raises(lbm.LBMError) as e:
+        g.adjoint()
+    assert e.value.code == lbm.LBM_E_STATE
+    g.close()
+
+
+def test_autograd_function_matches_adjoint():
+    # the torch.autograd.Function: a loss computed in torch from the final fields back-propagates
+    # through lbm_adjoint; for the pressure loss over the bulk it equals the built-in seed
+    import torch
+    from paper_2307_16766_amd.autograd import simulate
+    c = CASES["d2q37_corners"]
+    log("[gpu-case] autograd function")
+    fields = _case_fields(c, 61)
+    dev = torch.device("cuda")
+    ts = [torch.tensor(a, dtype=torch.float64, device=dev, requires_grad=True) for a in fields]
+    sig = torch.tensor(c["relax"]["sigma"], dtype=torch.float64, device=dev, requires_grad=True)
+    alp = torch.tensor(c["relax"]["alpha"], dtype=torch.float64, device=dev, requires_grad=True)
+    out = simulate(sig, alp, *ts, stencil=37, nx=c["nx"], ny=c["ny"], tau=c["tau"], bc=c["bc"], nsteps=c["steps"],
+                   every=c["every"], relax=dict(mach=c["relax"]["mach"]))
+    M = 3
+    cs2 = O.lattice(37)[0]
+    P = cs2 * out[0] * out[3]
+    loss = ((P - cs2)[M:-M, M:-M] ** 2).sum()
+    loss.backward()
+    g = _sim(c["stencil"], c["nx"], c["ny"], c["tau"], c["bc"], fields, c["relax"])
+    g.record(c["steps"], c["every"])
+    assert abs(g.diagnostics()[4] - loss.item()) <= 1e-12 * loss.item()
+    grad, grel = g.adjoint()
+    gr = grad.cpu().numpy()
+    for k in range(4):
+        got = ts[k].grad.cpu().numpy()
+        assert np.abs(got - gr[k]).max() <= 1e-9 * np.abs(gr[k]).max() + 1e-300
+    assert _relerr(sig.grad.item(), grel[:, 0].sum()) < 1e-9
+    assert _relerr(alp.grad.item(), grel[:, 1].sum()) < 1e-9
+    g.close()
+
+
+# --- the adjoint workload at full size: D2Q37 256 x 256, 2000 steps, checkpoint every 50
+C4_RELAX = dict(sigma=0.25, alpha=0.0, mach=0.0)   # alpha = Ma = 0 for the fluid at rest
+C4_STEPS, C4_EVERY = 2000, 50
+
+
+def _c4_loss(fields, relax):
+    g = _sim(37, 256, 256, TAU_37, ["lodi_relax"] * 4, fields, relax)
+    g.step(C4_STEPS)
+    loss = g.diagnostics()[4]
+    g.close()
+    return loss
+
+
+def test_c4_adjoint_against_finite_differences_and_oracle():
+    log("[gpu-case] C4 adjoint 256x256 2000 steps")
+    fields = W.random_temperature(256, 256, std=1e-4, seed=2307)
+    raw = W.random_directions(3, 256, 256, 230701)
+    norms = [float(np.linalg.norm(d)) for d in raw]
+    # unit directions: a step h = 1e-6 then moves each node by ~4e-9.  The fluid is at rest, so
+    # the frozen entropy and shear wave directions at the boundary flip with the sign of the
+    # normal velocity; those switches are kinks of the discrete map, and a larger per-node step
+    # crosses more of them (per-node steps of 1e-6 give finite differences off by ~3e-4).
+    dirs = [d / n for d, n in zip(raw, norms)]
+    g = _sim(37, 256, 256, TAU_37, ["lodi_relax"] * 4, fields, C4_RELAX)
+    g.record(C4_STEPS, C4_EVERY)
+    loss = g.diagnostics()[4]
+    grad, grel = g.adjoint()
+    gT = grad[3].cpu().numpy()
+    g.close()
+    adj = {"sigma": grel[:, 0].sum(), "alpha": grel[:, 1].sum()}
+    for k in range(3):
+        adj[f"T{k}"] = float((gT * dirs[k]).sum())
+    # central differences, h = 1e-6, of the GPU FP64 forward run
+    h = 1e-6
+    fd = {}
+    for key, par in (("sigma", "sigma"), ("alpha", "alpha")):
+        rp = dict(C4_RELAX, **{par: C4_RELAX[par] + h})
+        rm = dict(C4_RELAX, **{par: C4_RELAX[par] - h})
+        fd[key] = (_c4_loss(fields, rp) - _c4_loss(fields, rm)) / (2 * h)
+    for k in range(3):
+        fp = list(fields)
+        fm = list(fields)
+        fp[3] = fields[3] + h * dirs[k]
+        fm[3] = fields[3] - h * dirs[k]
+        fd[f"T{k}"] = (_c4_loss(fp, C4_RELAX) - _c4_loss(fm, C4_RELAX)) / (2 * h)
+    log(f"C4 loss {loss}\n adjoint {adj}\n finite differences {fd}")
+    for key in adj:
+        assert _relerr(adj[key], fd[key]) < 1e-4, (key, adj[key], fd[key])
+    if os.path.exists(GOLDEN):
+        gold = json.load(open(GOLDEN))
+        assert _relerr(loss, gold["loss"]) < 1e-10
+        ref = {"sigma": gold["d_sigma"], "alpha": gold["d_alpha"]}
+        for k in range(3):
+            ref[f"T{k}"] = gold["d_T0"][k] / norms[k]
+        errs = {k: _relerr(adj[k], ref[k]) for k in ref}
+        log(f" oracle dual numbers {ref}\n rel errors {errs}")
+        assert max(errs.values()) < 1e-8
+    assert math.isfinite(loss)

@@ -240,6 +240,53 @@ def test_tangent_mode_matches_finite_differences(flow):
         assert abs(a - b) <= t * abs(b), (dl, fd)
 
 
+@pytest.mark.parametrize("stencil", [37, 9])
+def test_field_tangents_match_finite_differences(stencil):
+    # tangents seeded on all four initial fields, for the pressure loss and for a linear loss of
+    # every node's final (rho, u, T), reproduce central differences of the plain solver
+    nx, ny, steps = 22, 20, 20
+    if stencil == 37:
+        bc, tau = ["lodi_relax"] * 4, TAU_37
+    else:
+        bc, tau = ["lodi_relax", "lodi_relax", "periodic", "periodic"], 0.6
+    rho, ux, uy, T = W.random_temperature(nx, ny, std=1e-3, seed=11)
+    rng = np.random.default_rng(12)
+    rho = rho + 1e-3 * rng.standard_normal((ny, nx))
+    ux, uy = ux + 0.02, uy + 0.015
+    base = np.array([0.25, 0.1, 1.0, 1.0, 0.05, 0.0])
+    relax = np.tile(base, (4, 1))
+    dF = np.zeros((3, 4, ny, nx))
+    dF[0, 0] = rng.standard_normal((ny, nx))
+    dF[1, 1] = rng.standard_normal((ny, nx))
+    dF[2, 2] = rng.standard_normal((ny, nx))
+    dF[2, 3] = rng.standard_normal((ny, nx))
+    wlin = rng.standard_normal((4, ny, nx))
+    fields = [rho, ux, uy, T]
+
+    def run(fl, w):
+        o = O.Oracle(stencil, nx, ny, tau, bc)
+        o.set_relax(-1, sigma=0.25, alpha=0.1, mach=0.05)
+        o.init(*fl)
+        o.step(steps)
+        if w is None:
+            return o.loss()
+        return sum(float((w[c] * m).sum()) for c, m in enumerate(o.macro()))
+
+    for w in (None, wlin):
+        loss, dl = O.tangent_run_fields(stencil, nx, ny, tau, bc, relax, [0, 0, 0], [0, 0, 0], fields, dF, steps, w)
+        assert abs(run(fields, w) - loss) <= 1e-14 * max(1.0, abs(loss))
+        h = 1e-6
+        for k in range(3):
+            fp = [a + h * dF[k, c] for c, a in enumerate(fields)]
+            fm = [a - h * dF[k, c] for c, a in enumerate(fields)]
+            fd = (run(fp, w) - run(fm, w)) / (2 * h)
+            if stencil == 9 and k == 2:
+                # D2Q9 is isothermal: only the uy part of this direction acts
+                assert abs(dl[k] - fd) <= 1e-6 * abs(fd) + 1e-9
+            else:
+                assert abs(dl[k] - fd) <= 1e-6 * abs(fd), (k, dl, fd)
+
+
 def test_d2q9_reflection_and_mirror_symmetry():
     # isothermal characteristic system (D2Q9, Sec. 4.4): a planar density pulse leaves through
     # LODI-RELAX sides with far less reflection than zero-gradient; the C1-type pulse setup is
