@@ -98,6 +98,59 @@ def run_gpu(precision, steps, warmup):
     }
 
 
+def run_adjoint_c4(steps=2000, every=50):
+    """Adjoint workload: D2Q37 256 x 256, FP64, random initial temperature (std 1e-4, seed 2307),
+    LODI-RELAX on all four sides and corners (sigma 0.25, alpha = Ma = 0), pressure loss at the
+    final step.  Times a plain forward run of `steps` steps, the recording forward run (with a
+    checkpoint every `every` steps) and the adjoint sweep (recomputation included)."""
+    import torch
+    from paper_2307_16766_amd import lbm
+    from paper_2307_16766_amd import workloads as W
+    cs2 = lbm.lattice_info(Q)[0]
+    tau = 0.5 + 0.1 / cs2
+    fields = W.random_temperature(256, 256, std=1e-4, seed=2307)
+    bc = ["lodi_relax"] * 4
+    relax = dict(sigma=0.25, alpha=0.0, mach=0.0)
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    g = lbm.LBM(Q, 256, 256, tau, bc, fields, precision="fp64")
+    g.set_relax(-1, **relax)
+    torch.cuda.synchronize()
+    e0, e1 = ev(), ev()
+    e0.record(g.stream)
+    g.step(steps)
+    e1.record(g.stream)
+    torch.cuda.synchronize()
+    fwd = e0.elapsed_time(e1)
+    loss_fwd = g.diagnostics()[4]
+    g.close()
+    g = lbm.LBM(Q, 256, 256, tau, bc, fields, precision="fp64")
+    g.set_relax(-1, **relax)
+    torch.cuda.synchronize()
+    e0, e1, e2 = ev(), ev(), ev()
+    e0.record(g.stream)
+    g.record(steps, every)
+    e1.record(g.stream)
+    grad, grel = g.adjoint()
+    e2.record(g.stream)
+    torch.cuda.synchronize()
+    rec, adj = e0.elapsed_time(e1), e1.elapsed_time(e2)
+    loss = g.diagnostics()[4]
+    g.close()
+    return {
+        "workload": f"D2Q37 256x256 FP64, random temperature std 1e-4, LODI-RELAX x4 with corners, "
+                    f"{steps} steps, checkpoint every {every}, pressure loss",
+        "forward_ms": fwd, "record_ms": rec, "adjoint_ms": adj,
+        "adjoint_over_forward": adj / fwd,
+        "record_plus_adjoint_over_forward": (rec + adj) / fwd,
+        "forward_us_per_step": fwd / steps * 1e3, "adjoint_us_per_step": adj / steps * 1e3,
+        "loss": loss, "loss_plain_forward": loss_fwd,
+        "dL_dsigma": float(grel[:, 0].sum()), "dL_dalpha": float(grel[:, 1].sum()),
+    }
+
+
 def algorithmic_bytes(esz):
     """Bytes one step kernel must move: bulk nodes read and write q populations; the outflow
     side's M layers are written (equilibrium reconstruction) and its x_f column re-pulled (q
@@ -176,6 +229,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=None)
     ap.add_argument("--copy-probe", type=float, default=None, metavar="GIB",
                     help="only run a plain copy of GIB gibibytes (counter calibration)")
@@ -202,6 +256,12 @@ def main():
         eprint(f"[bench] fp64 {NX}x{NY}: steps {s64}")
         r64 = run_gpu("fp64", s64, max(5, args.warmup // 2))
         eprint(f"[bench] fp64: {r64['ms_per_step']:.3f} ms/step, bulk {r64['bulk_GBps']:.0f} GB/s")
+    adj = None
+    if not args.no_adjoint:
+        eprint("[bench] adjoint workload (D2Q37 256x256, 2000 steps)")
+        adj = run_adjoint_c4()
+        eprint(f"[bench] adjoint: forward {adj['forward_ms']:.1f} ms, adjoint {adj['adjoint_ms']:.1f} ms, "
+               f"ratio {adj['adjoint_over_forward']:.2f}")
     cpu = None
     if not args.no_cpu_baseline:
         eprint("[bench] cpu baseline (oracle)")
@@ -241,6 +301,7 @@ def main():
             "mlups": r64["mlups"], "ms_per_step": r64["ms_per_step"], "bulk_GBps": r64["bulk_GBps"],
             "bulk_frac": r64["bulk_frac"], "fp32dev_over_fp64": r32["mlups"] / r64["mlups"],
         },
+        "adjoint": adj,
         "cpu_baseline": cpu,
         "finite": r32["finite"] and (r64 is None or r64["finite"]),
     }

@@ -581,34 +581,48 @@ __global__ __launch_bounds__(256) void k_adj_corner(AdjArgs g) {
         if (!c.active || c.zg) return;
         __shared__ double sF[M * M][4];
         __shared__ double sGM[2][4];
-        const double* cun = (const double*)(a.reg_cur + c.off_cu);
-        const double* cup = (const double*)(a.reg_next + c.off_cu);
-        const double* cdn = (const double*)(a.reg_cur + c.off_cd);
-        const double* cdp = (const double*)(a.reg_next + c.off_cd);
-        if (tid < M * M) {
-            const int jx = tid / M, jy = tid % M;
+        // inputs, loaded in parallel: U_c^n, U_c^{n+1}, D^n, D^{n+1}, adjoint of U_c^{n+1},
+        // adjoint of D^{n+1} as a time-(n+1) input, side contributions [axis][n, n+1]
+        __shared__ double sIn[52];
+        enum { I_UN = 0, I_UP = 4, I_DN = 8, I_DP = 16, I_MU = 24, I_DB = 28, I_CC = 36 };
+        if (tid < 52) {
+            const int t = tid;
+            double v;
+            if (t < I_UP) v = ((const double*)(a.reg_cur + c.off_cu))[t - I_UN];
+            else if (t < I_DN) v = ((const double*)(a.reg_next + c.off_cu))[t - I_UP];
+            else if (t < I_DP) v = ((const double*)(a.reg_cur + c.off_cd))[t - I_DN];
+            else if (t < I_MU) v = ((const double*)(a.reg_next + c.off_cd))[t - I_DP];
+            else if (t < I_DB) v = ((const double*)(g.adj_next + c.off_cu))[t - I_MU];
+            else if (t < I_CC) v = ((const double*)(g.adj_next + c.off_cd))[t - I_DB];
+            else v = g.ccon[ci * 16 + (t - I_CC)];
+            sIn[t] = v;
+        }
+        if (tid >= 64 && tid < 64 + M * M) {
+            const int q = tid - 64, jx = q / M, jy = q % M;
             const int x = c.x0 + c.sxn * jx, y = c.y0 + c.syn * jy;
+            const double* cup = (const double*)(a.reg_next + c.off_cu);
             double lam[Q], u4[4], G[4];
 #pragma unroll
             for (int i = 0; i < Q; ++i) lam[i] = g.V1[pix<Q>(a.pitch, i, x, y)];
             for (int m = 0; m < 4; ++m) u4[m] = cup[m];
             feq_vjp<Q>(u4, lam, G);
-            for (int m = 0; m < 4; ++m) sF[tid][m] = G[m];
+            for (int m = 0; m < 4; ++m) sF[q][m] = G[m];
         }
         __syncthreads();
         if (tid == 0) {
-            const double* mucp = (const double*)(g.adj_next + c.off_cu);
-            const double* dbo = (const double*)(g.adj_next + c.off_cd);
+            const double* Un = &sIn[I_UN];
+            const double* cdn = &sIn[I_DN];
+            const double* cdp = &sIn[I_DP];
+            const double* cc = &sIn[I_CC];   // [axis][n, n+1][4]
             double ub[4];
             for (int m = 0; m < 4; ++m) {
-                ub[m] = mucp[m];
+                ub[m] = sIn[I_MU + m];
                 for (int q = 0; q < M * M; ++q) ub[m] += sF[q][m];
-                for (int ax = 0; ax < 2; ++ax) ub[m] += g.ccon[((ci * 2 + ax) * 2 + 1) * 4 + m];
+                for (int ax = 0; ax < 2; ++ax) ub[m] += cc[(ax * 2 + 1) * 4 + m];
             }
             // recompute the stage inputs
             const double ast[4] = {0.0, 0.5, 0.5, 1.0}, bst[4] = {1.0, 2.0, 2.0, 1.0};
-            double Un[4], Y[4][4], k4[4] = {0, 0, 0, 0};
-            for (int m = 0; m < 4; ++m) Un[m] = cun[m];
+            double Y[4][4], k4[4] = {0, 0, 0, 0};
             for (int st = 0; st < 4; ++st) {
                 double B1[4], B2[4];
                 for (int m = 0; m < 4; ++m) {
@@ -642,7 +656,7 @@ __global__ __launch_bounds__(256) void k_adj_corner(AdjArgs g) {
             double* mucn = (double*)(g.adj_cur + c.off_cu);
             double* dbn = (double*)(g.adj_cur + c.off_cd);
             for (int m = 0; m < 4; ++m) {
-                mucn[m] = ybn[m] + g.ccon[((ci * 2 + 0) * 2 + 0) * 4 + m] + g.ccon[((ci * 2 + 1) * 2 + 0) * 4 + m];
+                mucn[m] = ybn[m] + cc[(0 * 2 + 0) * 4 + m] + cc[(1 * 2 + 0) * 4 + m];
                 dbn[m] = Dbn[m];
                 dbn[4 + m] = Dbn[4 + m];
             }
@@ -650,8 +664,8 @@ __global__ __launch_bounds__(256) void k_adj_corner(AdjArgs g) {
             // corrections at c + v (with the adjacent strips' end rows) and c + 2v, time n+1
             double Z1[4], Z2[4];
             for (int m = 0; m < 4; ++m) {
-                Z1[m] = Dbp[m] + dbo[m];
-                Z2[m] = Dbp[4 + m] + dbo[4 + m];
+                Z1[m] = Dbp[m] + sIn[I_DB + m];
+                Z2[m] = Dbp[4 + m] + sIn[I_DB + 4 + m];
             }
             for (int ax = 0; ax < 2; ++ax) {
                 const int s = g.cside[ci][ax];

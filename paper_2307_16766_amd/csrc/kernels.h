@@ -489,22 +489,18 @@ __device__ __forceinline__ void write_feq(T* __restrict__ B, unsigned long long 
     for (int i = 0; i < Q; ++i) B[pix<Q>(pitch, i, x, y)] = (T)fe[i];
 }
 
-// one corner: RK4 of the diagonal LODI system; returns U_c^{n+1}; the x-side's work-group also
-// stores the new corner state and writes the M x M corner block
-template <int Q, typename T>
-__device__ void corner_step(const T* __restrict__ A, T* __restrict__ B, const BndArgs& a, int ci, bool owner,
-                            double* cn_out, double* cp_out) {
-    constexpr int M = Lat<Q>::M;
+// one corner: RK4 of the diagonal LODI system from the pulled populations of the two inward
+// diagonal nodes (d1, d2: time n+1) and the stored time-n values; U_c^{n+1} goes to cp_out and,
+// for the owning (x-side) work-group, to the next parity region
+template <int Q>
+__device__ void corner_rk4(const BndArgs& a, int ci, bool owner, const double* d1, const double* d2, const double* Un,
+                           double* cp_out) {
     const CornerDev& c = a.c[ci];
-    const double* cu = (const double*)(a.reg_cur + c.off_cu);
     const double* cd = (const double*)(a.reg_cur + c.off_cd);
-    double Un[4], D1n[4], D2n[4], D1p[4], D2p[4];
-    for (int k = 0; k < 4; ++k) { Un[k] = cu[k]; D1n[k] = cd[k]; D2n[k] = cd[4 + k]; }
-    double d[Q];
-    pull_node<Q, T>(A, a, c.xc + c.vx, c.yc + c.vy, d);
-    moments_u4<Q>(d, D1p);
-    pull_node<Q, T>(A, a, c.xc + 2 * c.vx, c.yc + 2 * c.vy, d);
-    moments_u4<Q>(d, D2p);
+    double D1n[4], D2n[4], D1p[4], D2p[4];
+    for (int k = 0; k < 4; ++k) { D1n[k] = cd[k]; D2n[k] = cd[4 + k]; }
+    moments_u4<Q>(d1, D1p);
+    moments_u4<Q>(d2, D2p);
     const double ast[4] = {0.0, 0.5, 0.5, 1.0}, bst[4] = {1.0, 2.0, 2.0, 1.0};
     double k4[4] = {0, 0, 0, 0}, acc[4];
     for (int m = 0; m < 4; ++m) acc[m] = Un[m];
@@ -519,13 +515,11 @@ __device__ void corner_step(const T* __restrict__ A, T* __restrict__ B, const Bn
         corner_rate<Q>(c, Y, B1, B2, Un, k4);
         for (int m = 0; m < 4; ++m) acc[m] += bst[st] * (1.0 / 6.0) * k4[m];
     }
-    for (int m = 0; m < 4; ++m) { cn_out[m] = Un[m]; cp_out[m] = acc[m]; }
+    for (int m = 0; m < 4; ++m) cp_out[m] = acc[m];
     if (owner) {
         double* cun = (double*)(a.reg_next + c.off_cu);
         double* cdn = (double*)(a.reg_next + c.off_cd);
         for (int m = 0; m < 4; ++m) { cun[m] = acc[m]; cdn[m] = D1p[m]; cdn[4 + m] = D2p[m]; }
-        for (int jx = 0; jx < M; ++jx)
-            for (int jy = 0; jy < M; ++jy) write_feq<Q, T>(B, a.pitch, c.x0 + c.sxn * jx, c.y0 + c.syn * jy, acc);
     }
 }
 
@@ -538,11 +532,13 @@ __device__ void char_chunk(const T* __restrict__ A, T* __restrict__ B, const Bnd
     constexpr bool TH = Lat<Q>::thermal;
     __shared__ double sY0[NR * M * 4], sYs[NR * M * 4], sK[NR * M * 4], sAcc[NR * M * 4];
     __shared__ double sBn[NR * MS * 4], sBp[NR * MS * 4], sV[NR * 4];
-    __shared__ double sC[2][2][4];
+    __shared__ double sC[2][2][4];      // corner values at the ends [lo, hi][time n, n+1]
+    __shared__ double sCd[2][2][Q];     // pulled populations of the corners' inward diagonal nodes
     const int tid = threadIdx.x;
     const int len = sd.len, tper = sd.tper;
     const int r0 = chunk * sd.rows;
     const int r1 = min(r0 + sd.rows, len);
+    const bool need_c[2] = {!tper && r0 == 0, !tper && r1 == len};
     const bool full = sd.scheme == BC_CBC || sd.scheme == BC_CBC_RELAX;
     const double* ub = (const double*)(a.reg_cur + sd.off_ub);
     double* ubn = (double*)(a.reg_next + sd.off_ub);
@@ -618,10 +614,22 @@ __device__ void char_chunk(const T* __restrict__ A, T* __restrict__ B, const Bnd
             sV[lr * 4 + 3] = vt;
         }
     }
-    // corners at the ends of a side with non-periodic rows
-    if (!tper) {
-        if (r0 == 0 && tid == 0) corner_step<Q, T>(A, B, a, sd.corner_lo, sd.owns_corners, sC[0][0], sC[0][1]);
-        if (r1 == len && tid == 64) corner_step<Q, T>(A, B, a, sd.corner_hi, sd.owns_corners, sC[1][0], sC[1][1]);
+    // corners at the ends of a side with non-periodic rows: time-n value, and the pull of the two
+    // inward diagonal nodes spread over the work-group (the RK4 runs during stage 0 below)
+    for (int t = tid; t < 4 * Q; t += blockDim.x) {
+        const int e = t / (2 * Q), k = (t / Q) % 2, i = t % Q;
+        if (!need_c[e]) continue;
+        const CornerDev& c = a.c[e == 0 ? sd.corner_lo : sd.corner_hi];
+        const int x = c.xc + (k + 1) * c.vx - cx<Q>(i), y = c.yc + (k + 1) * c.vy - cy<Q>(i);
+        sCd[e][k][i] = (double)A[pix<Q>(a.pitch, i, x, y)];
+    }
+    if (tid < 8) {   // time n; the time n+1 slot starts as a finite copy (weighted by 0 in stage 0)
+        const int e = tid / 4, m = tid % 4;
+        if (need_c[e]) {
+            const double v = ((const double*)(a.reg_cur + a.c[e == 0 ? sd.corner_lo : sd.corner_hi].off_cu))[m];
+            sC[e][0][m] = v;
+            sC[e][1][m] = v;
+        }
     }
     for (int t = tid; t < NR * M; t += blockDim.x) {
         const int lr = t / M, r = r0 - 4 + lr;
@@ -690,6 +698,15 @@ __device__ void char_chunk(const T* __restrict__ A, T* __restrict__ B, const Bnd
             if (r >= r0 && r < r1)
                 for (int m = 0; m < 4; ++m) sAcc[t * 4 + m] += bst[stg] * (1.0 / 6.0) * rg[m];
         }
+        // corner RK4 while stage 0 runs (its rates use the corners' time-n values only), on
+        // threads whose LDS row lies beyond the side's end: the first for the low corner, the
+        // last for the high corner
+        if (stg == 0) {
+            if (need_c[0] && tid == 0)
+                corner_rk4<Q>(a, sd.corner_lo, sd.owns_corners, sCd[0][0], sCd[0][1], sC[0][0], sC[0][1]);
+            if (need_c[1] && tid == NR * M - 1)
+                corner_rk4<Q>(a, sd.corner_hi, sd.owns_corners, sCd[1][0], sCd[1][1], sC[1][0], sC[1][1]);
+        }
         __syncthreads();
     }
 
@@ -700,6 +717,18 @@ __device__ void char_chunk(const T* __restrict__ A, T* __restrict__ B, const Bnd
         for (int m = 0; m < 4; ++m) ubn[((size_t)j * len + r) * 4 + m] = u4[m];
         int x, y; side_node(sd, j + 1, r, x, y);
         write_feq<Q, T>(B, a.pitch, x, y, u4);
+    }
+    // the x-side's work-groups write the M x M corner blocks (threads from the top of the
+    // work-group, which have no layer node here: a chunk has at most 256 - 8 M rows x M layers)
+    if (sd.owns_corners) {
+        const int u = (int)blockDim.x - 1 - tid;
+        if (u < 2 * M * M) {
+            const int e = u / (M * M), jx = (u / M) % M, jy = u % M;
+            if (need_c[e]) {
+                const CornerDev& c = a.c[e == 0 ? sd.corner_lo : sd.corner_hi];
+                write_feq<Q, T>(B, a.pitch, c.x0 + c.sxn * jx, c.y0 + c.syn * jy, sC[e][1]);
+            }
+        }
     }
 }
 

@@ -214,16 +214,9 @@ def _c4_loss(fields, relax):
     return loss
 
 
-def test_c4_adjoint_against_finite_differences_and_oracle():
-    log("[gpu-case] C4 adjoint 256x256 2000 steps")
-    fields = W.random_temperature(256, 256, std=1e-4, seed=2307)
-    raw = W.random_directions(3, 256, 256, 230701)
-    norms = [float(np.linalg.norm(d)) for d in raw]
-    # unit directions: a step h = 1e-6 then moves each node by ~4e-9.  The fluid is at rest, so
-    # the frozen entropy and shear wave directions at the boundary flip with the sign of the
-    # normal velocity; those switches are kinks of the discrete map, and a larger per-node step
-    # crosses more of them (per-node steps of 1e-6 give finite differences off by ~3e-4).
-    dirs = [d / n for d, n in zip(raw, norms)]
+def _c4_gradient_and_fd(fields, dirs, h=1e-6):
+    """Adjoint directional derivatives and central differences (step h per node along dirs, and
+    on sigma and alpha) of the GPU FP64 forward run."""
     g = _sim(37, 256, 256, TAU_37, ["lodi_relax"] * 4, fields, C4_RELAX)
     g.record(C4_STEPS, C4_EVERY)
     loss = g.diagnostics()[4]
@@ -231,31 +224,60 @@ def test_c4_adjoint_against_finite_differences_and_oracle():
     gT = grad[3].cpu().numpy()
     g.close()
     adj = {"sigma": grel[:, 0].sum(), "alpha": grel[:, 1].sum()}
-    for k in range(3):
+    for k in range(len(dirs)):
         adj[f"T{k}"] = float((gT * dirs[k]).sum())
-    # central differences, h = 1e-6, of the GPU FP64 forward run
-    h = 1e-6
     fd = {}
-    for key, par in (("sigma", "sigma"), ("alpha", "alpha")):
+    for par in ("sigma", "alpha"):
         rp = dict(C4_RELAX, **{par: C4_RELAX[par] + h})
         rm = dict(C4_RELAX, **{par: C4_RELAX[par] - h})
-        fd[key] = (_c4_loss(fields, rp) - _c4_loss(fields, rm)) / (2 * h)
-    for k in range(3):
-        fp = list(fields)
-        fm = list(fields)
+        fd[par] = (_c4_loss(fields, rp) - _c4_loss(fields, rm)) / (2 * h)
+    for k in range(len(dirs)):
+        fp, fm = list(fields), list(fields)
         fp[3] = fields[3] + h * dirs[k]
         fm[3] = fields[3] - h * dirs[k]
         fd[f"T{k}"] = (_c4_loss(fp, C4_RELAX) - _c4_loss(fm, C4_RELAX)) / (2 * h)
+    return loss, adj, fd
+
+
+def test_c4_adjoint_against_oracle_and_finite_differences():
+    # The workload itself (fluid at rest).  The oracle's dual numbers give the exact derivative
+    # of the same discrete map: the adjoint must match them.  Finite differences are limited by
+    # the map's kinks: the wave directions are frozen per step by the sign of u_n, which at rest
+    # is ~0 at every boundary node, so entropy and shear waves switch between outgoing and
+    # annihilated under any perturbation (continuous, not differentiable).  A scan of the step
+    # from 1e-6 to 1e-10 per node shows finite differences scattering by 1e-5..2e-3 around the
+    # adjoint without converging; sigma and alpha, which barely move u_n, agree to 1e-5.
+    log("[gpu-case] C4 adjoint 256x256 2000 steps (fluid at rest)")
+    fields = W.random_temperature(256, 256, std=1e-4, seed=2307)
+    dirs = W.random_directions(3, 256, 256, 230701)
+    loss, adj, fd = _c4_gradient_and_fd(fields, dirs)
     log(f"C4 loss {loss}\n adjoint {adj}\n finite differences {fd}")
-    for key in adj:
-        assert _relerr(adj[key], fd[key]) < 1e-4, (key, adj[key], fd[key])
-    if os.path.exists(GOLDEN):
-        gold = json.load(open(GOLDEN))
-        assert _relerr(loss, gold["loss"]) < 1e-10
-        ref = {"sigma": gold["d_sigma"], "alpha": gold["d_alpha"]}
-        for k in range(3):
-            ref[f"T{k}"] = gold["d_T0"][k] / norms[k]
-        errs = {k: _relerr(adj[k], ref[k]) for k in ref}
-        log(f" oracle dual numbers {ref}\n rel errors {errs}")
-        assert max(errs.values()) < 1e-8
     assert math.isfinite(loss)
+    for key in ("sigma", "alpha"):
+        assert _relerr(adj[key], fd[key]) < 1e-4, (key, adj[key], fd[key])
+    for k in range(3):
+        assert _relerr(adj[f"T{k}"], fd[f"T{k}"]) < 1e-3, (k, adj[f"T{k}"], fd[f"T{k}"])
+    gold = json.load(open(GOLDEN))
+    assert _relerr(loss, gold["loss"]) < 1e-9
+    ref = {"sigma": gold["d_sigma"], "alpha": gold["d_alpha"]}
+    for k in range(3):
+        ref[f"T{k}"] = gold["d_T0"][k]
+    errs = {k: _relerr(adj[k], ref[k]) for k in ref}
+    log(f" oracle dual numbers {ref}\n rel errors {errs}")
+    # the two trajectories differ by rounding (the losses by ~1e-10 relative after 2000
+    # steps); nodes with u_n ~ 0 may take the other side of a wave-direction switch
+    assert max(errs.values()) < 1e-7
+
+
+def test_c4_with_background_flow_against_finite_differences():
+    # The same workload over a uniform diagonal background flow u = (0.02, 0.015): u_n keeps its
+    # sign at every boundary node, the discrete map is smooth, and central differences with
+    # h = 1e-6 (per node, as specified for the workload) match the adjoint within 1e-4.
+    log("[gpu-case] C4 adjoint with diagonal background flow")
+    rho, ux, uy, T = W.random_temperature(256, 256, std=1e-4, seed=2307)
+    fields = [rho, ux + 0.02, uy + 0.015, T]
+    dirs = W.random_directions(3, 256, 256, 230701)
+    loss, adj, fd = _c4_gradient_and_fd(fields, dirs)
+    errs = {k: _relerr(adj[k], fd[k]) for k in adj}
+    log(f"C4 flow loss {loss}\n adjoint {adj}\n finite differences {fd}\n rel errors {errs}")
+    assert max(errs.values()) < 1e-4
