@@ -16,15 +16,16 @@
 //          lambda = dL/df at boundary-layer and corner-block nodes;
 //   adjoint region (same offsets as the forward region): direct adjoints of U_b^n, of the
 //          strip X^n and corner diagonal D^n as time-n inputs, and of U_c^n.
-// One reverse step n+1 -> n is three launches:
+// One reverse step n+1 -> n is two launches (three when the corners read the sides' terms):
 //   k_adj_side   : per chunk of side rows, fold lambda^{n+1} of the layers into the adjoint of
-//                  U_b^{n+1} (J_feq^T), recompute the RK4 stages, reverse them (hand-written
-//                  VJP of the characteristic rate), emit the adjoints of U_b^n, X^n, X^{n+1},
-//                  of the corner values, and of the relaxation parameters;
-//   k_adj_corner : corners (fold of the M x M block, reverse corner RK4), then the strip and
-//                  diagonal adjoints are added to nu^{n+1} through J_m^T;
-//   k_adj_bulk   : lambda^n(y, i) = nu^{n+1}(y + c_i, i) (reverse pull, bulk sources only),
-//                  nu^n = J_C^T lambda^n at bulk nodes:
+//                  U_b^{n+1} (J_feq^T), reverse the four RK4 stages (stage inputs stored by the
+//                  recomputation) with a hand-written VJP of the characteristic rate, emit the
+//                  adjoints of U_b^n and X^n, add the adjoint of X^{n+1} to nu^{n+1}(x_f) through
+//                  J_m^T, and accumulate the adjoints of K and alpha; further blocks reverse the
+//                  corners (fold of the M x M block, reverse corner RK4), or k_adj_corner does
+//                  after the sides when transverse relaxation couples the sides to the corners;
+//   k_adj_bulk   : lambda^n(y, i) = nu^{n+1}(y + c_i, i) (reverse pull, bulk sources only, plus
+//                  the corner diagonal nodes' corrections), nu^n = J_C^T lambda^n at bulk nodes:
 //                  nu_i = (1 - omega) lambda_i + omega (G_0 + c_ix G_1 + c_iy G_2 + |c_i|^2 G_3),
 //                  G = (dm/dM)^T (df^eq/dm)^T lambda, M the linear moments (sum f, sum f c,
 //                  sum f |c|^2); at n = 0 it gives dL/d(rho0, ux0, uy0, T0) = (df^eq/dm)^T lambda^0.
@@ -311,8 +312,10 @@ struct AdjArgs {
     BndArgs b;               // geometry and relaxation; reg_cur = forward region of time n, reg_next = n+1
     char* adj_cur;           // adjoint region of time n (written)
     const char* adj_next;    // adjoint region of time n+1 (read)
-    char* xnew;              // region-shaped: strip adjoints at time n+1 from this step's side RK4
     double* ccon;            // [corner][side axis][n, n+1][4]: side contributions to the corner adjoints
+    double* gm;              // corrections of nu^{n+1} at the corner diagonal nodes, (dm/dM)^T Xbar:
+                             // [side][row 0, row len-1][4] (end rows of the strips, = c + v), then
+                             // [corner][c + v, c + 2v][4] (the corner's own)
     double* acc;             // [side blocks][2] (dK, dalpha), then [corner] (dK)
     double* V1;              // nu / lambda of time n+1
     double* V0;              // nu / lambda of time n (written by k_adj_bulk)
@@ -323,14 +326,15 @@ struct AdjArgs {
     int nadj;                // total side blocks
     int cside[4][2];         // per corner: adjacent side of each axis (-1 if none)
     int crow[4][2];          // per corner: that side's row next to the corner
+    int coupled;             // corners read the sides' contributions (transverse relaxation alpha != 0)
 };
 
 // ------------------------------------------------------------------ reverse of a side chunk
 // LDS row lr <-> side row r = r0 - 8 + lr.  Owned rows [r0, r1).  Reverse dependencies: the
 // adjoint of U_b^n on owned rows needs stage s's VJP within s + 1 rows of them, which needs the
-// forward stage inputs within s + 2 rows, hence 8 rows of recomputation halo.
+// stage inputs within s + 2 rows (stored by the recomputation of the step, k_step with HIST).
 template <int Q>
-__device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int blk, int chunk) {
+__device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk, int chunk) {
     constexpr int M = Lat<Q>::M, NR = 256 / M, MS = (M == 1) ? 2 : 1, H = 8, NN = NR * M;
     constexpr bool TH = Lat<Q>::thermal;
     __shared__ double sY[4][NN * 4];            // stage inputs Y_0 = U_b^n, Y_1, Y_2, Y_3 (global components)
@@ -354,7 +358,7 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int blk, int chun
     const double* mub1 = (const double*)(g.adj_next + sd.off_ub);
     double* mub0 = (double*)(g.adj_cur + sd.off_ub);
     double* xbo = (double*)(g.adj_cur + sd.off_strip);
-    double* xbw = (double*)(g.xnew + sd.off_strip);
+    const double* xbp = (const double*)(g.adj_next + sd.off_strip);
     auto valid = [&](int r) { return tper || (r >= 0 && r < len); };
     auto phys = [&](int r) { return tper ? ((r % len) + len) % len : r; };
     auto within = [&](int r, int h) { return r >= r0 - h && r < r1 + h; };
@@ -440,18 +444,15 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int blk, int chun
         to_local(sd, &sY[0][t * 4], U0);
     };
 
-    // ---- phase B: recompute the stage inputs Y_1..Y_3 (rates k_0..k_2 within 7, 6, 5 rows) ---
-    for (int st = 0; st < 3; ++st) {
-        if (node && within(r, H - 1 - st)) {
-            double U[4], dn[4], up[4], dw[4], U0[4], rl[4], rg[4];
-            const double zero[4] = {0, 0, 0, 0};
-            inputs(st, U, dn, up, dw, U0);
-            char_rate<TH>(U, dn, up, dw, zero, U0, sd.scheme, sd.K, sd.alpha, sd.Pinf, rl);
-            rate_to_global(sd, rl, rg);
-            for (int m = 0; m < 4; ++m) sY[st + 1][t * 4 + m] = sY[0][t * 4 + m] + ast[st + 1] * rg[m];
-        }
-        __syncthreads();
+    // ---- phase B: stage inputs Y_1..Y_3, stored by the recomputation of this step --------------
+    {
+        const double* ys = (const double*)(a.reg_next + sd.off_stage);
+        if (node)
+            for (int st = 1; st <= 3; ++st)
+                for (int m = 0; m < 4; ++m)
+                    sY[st][t * 4 + m] = ys[(((size_t)(st - 1) * M + jj) * len + phys(r)) * 4 + m];
     }
+    __syncthreads();
 
     // ---- phase C: reverse stages 3..0 ---------------------------------------------------------
     const bool owned = node && r >= r0 && r < r1;
@@ -528,14 +529,32 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int blk, int chun
         const int rp = phys(r);
         for (int m = 0; m < 4; ++m) mub0[((size_t)jj * len + rp) * 4 + m] = ybn[m];
     }
+    // strips: adjoint of X^n (a time-n input) for the next reverse step; the adjoint of X^{n+1}
+    // (this step's new value plus the previous reverse step's time-(n+1) input) is added to
+    // nu^{n+1}(x_f) as phi . (dm/dM)^T Xbar, except at the end rows next to corners (the corner
+    // diagonal node c + v, shared with the other side and the corner), whose term goes to gm
     for (int e = tid; e < NR * MS; e += blockDim.x) {
         const int l2 = e / MS, k = e % MS, rr = r0 - H + l2;
         if (rr < r0 || rr >= r1 || !valid(rr)) continue;
         const int rp = phys(rr);
+        const size_t o = ((size_t)k * len + rp) * 4;
+        double Z[4], GM[4];
         for (int m = 0; m < 4; ++m) {
-            xbo[((size_t)k * len + rp) * 4 + m] = sXbn[e * 4 + m];
-            xbw[((size_t)k * len + rp) * 4 + m] = sXbp[e * 4 + m];
+            xbo[o + m] = sXbn[e * 4 + m];
+            Z[m] = sXbp[e * 4 + m] + xbp[o + m];
         }
+        mom_vjp<Q>(&sXp[e * 4], Z, GM);
+        if (!tper && k == 0 && (rp == 0 || rp == len - 1)) {   // len >= 3: the two ends differ
+            for (int m = 0; m < 4; ++m) g.gm[(side * 2 + (rp == 0 ? 0 : 1)) * 4 + m] = GM[m];
+            continue;
+        }
+        int x, y; side_node(sd, -k, rp, x, y);
+        double* v1 = g.V1 + pix<Q>(a.pitch, 0, x, y);
+        double v[Q];   // all loads before the stores
+#pragma unroll
+        for (int i = 0; i < Q; ++i) v[i] = v1[(unsigned long long)i * a.pitch];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) v1[(unsigned long long)i * a.pitch] = v[i] + phi_dot<Q>(i, GM);
     }
     if (!tper && tid < 16) {
         const int e = tid / 8, w = (tid / 4) % 2, m = tid % 4;
@@ -557,161 +576,139 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int blk, int chun
     }
 }
 
+// ------------------------------------------------------------------ reverse of a corner
+// One work-group per corner: fold of the M x M block (J_feq^T of lambda^{n+1}), transposed
+// Jacobians of the four stage rates with unit cotangents (16 threads; the stage inputs were
+// stored by the recomputation), then the reverse RK4 sweep on one thread.  Writes the adjoints
+// of U_c^n and D^n (time-n inputs) and the corner's terms of the corrections of nu^{n+1} at
+// c + v and c + 2v.  The sides' contributions (ccon) are read only when the sides' transverse
+// terms reach the corner values (coupled).
+template <int Q>
+__device__ void corner_adj(const AdjArgs& g, int ci) {
+    constexpr int M = Lat<Q>::M;
+    const BndArgs& a = g.b;
+    const int tid = threadIdx.x;
+    const CornerDev& c = a.c[ci];
+    if (!c.active || c.zg) return;
+    __shared__ double sF[M * M][4];
+    // U_c^n, U_c^{n+1}, D^n, D^{n+1}, adjoint of U_c^{n+1}, adjoint of D^{n+1} as a time-(n+1)
+    // input, side contributions [axis][n, n+1]
+    __shared__ double sIn[52];
+    __shared__ double sJT[4][4][13];   // [stage][m][Yc (4), D1 (4), D2 (4), K]
+    enum { I_UN = 0, I_UP = 4, I_DN = 8, I_DP = 16, I_MU = 24, I_DB = 28, I_CC = 36 };
+    if (tid < 52) {
+        const int t = tid;
+        double v;
+        if (t < I_UP) v = ((const double*)(a.reg_cur + c.off_cu))[t - I_UN];
+        else if (t < I_DN) v = ((const double*)(a.reg_next + c.off_cu))[t - I_UP];
+        else if (t < I_DP) v = ((const double*)(a.reg_cur + c.off_cd))[t - I_DN];
+        else if (t < I_MU) v = ((const double*)(a.reg_next + c.off_cd))[t - I_DP];
+        else if (t < I_DB) v = ((const double*)(g.adj_next + c.off_cu))[t - I_MU];
+        else if (t < I_CC) v = ((const double*)(g.adj_next + c.off_cd))[t - I_DB];
+        else v = g.coupled ? g.ccon[ci * 16 + (t - I_CC)] : 0.0;
+        sIn[t] = v;
+    }
+    if (tid >= 64 && tid < 64 + M * M) {
+        const int q = tid - 64, jx = q / M, jy = q % M;
+        const int x = c.x0 + c.sxn * jx, y = c.y0 + c.syn * jy;
+        const double* cup = (const double*)(a.reg_next + c.off_cu);
+        double lam[Q], u4[4], G[4];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) lam[i] = g.V1[pix<Q>(a.pitch, i, x, y)];
+        for (int m = 0; m < 4; ++m) u4[m] = cup[m];
+        feq_vjp<Q>(u4, lam, G);
+        for (int m = 0; m < 4; ++m) sF[q][m] = G[m];
+    }
+    __syncthreads();
+    const double ast[4] = {0.0, 0.5, 0.5, 1.0}, bst[4] = {1.0, 2.0, 2.0, 1.0};
+    {
+        const int u = tid - 128;
+        if (u >= 0 && u < 16) {
+            const int st = u / 4, m = u % 4;
+            const double th = ast[st];
+            const double* Un = &sIn[I_UN];
+            const double* ycs = (const double*)(a.reg_next + c.off_cs);
+            double Y[4], B1[4], B2[4], e[4] = {0, 0, 0, 0}, Ycb[4], B1b[4], B2b[4], Kb;
+            e[m] = 1.0;
+            for (int k = 0; k < 4; ++k) {
+                Y[k] = st == 0 ? Un[k] : ycs[(st - 1) * 4 + k];
+                B1[k] = (1.0 - th) * sIn[I_DN + k] + th * sIn[I_DP + k];
+                B2[k] = (1.0 - th) * sIn[I_DN + 4 + k] + th * sIn[I_DP + 4 + k];
+            }
+            corner_rate_vjp<Q>(c, Y, B1, B2, Un, e, Ycb, B1b, B2b, Kb);
+            for (int k = 0; k < 4; ++k) {
+                sJT[st][m][k] = Ycb[k];
+                sJT[st][m][4 + k] = B1b[k];
+                sJT[st][m][8 + k] = B2b[k];
+            }
+            sJT[st][m][12] = Kb;
+        }
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    const double* cc = &sIn[I_CC];   // [axis][n, n+1][4]
+    double ub[4];
+    for (int m = 0; m < 4; ++m) {
+        ub[m] = sIn[I_MU + m];
+        for (int q = 0; q < M * M; ++q) ub[m] += sF[q][m];
+        for (int ax = 0; ax < 2; ++ax) ub[m] += cc[(ax * 2 + 1) * 4 + m];
+    }
+    double ybn[4], yb[4] = {0, 0, 0, 0}, Dbn[8] = {0, 0, 0, 0, 0, 0, 0, 0}, Dbp[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double Kacc = 0.0;
+    for (int m = 0; m < 4; ++m) ybn[m] = ub[m];
+    for (int st = 3; st >= 0; --st) {
+        const double th = ast[st];
+        double kb[4], v[13];
+        for (int m = 0; m < 4; ++m) kb[m] = bst[st] * (1.0 / 6.0) * ub[m] + (st < 3 ? ast[st + 1] * yb[m] : 0.0);
+        for (int k = 0; k < 13; ++k)
+            v[k] = kb[0] * sJT[st][0][k] + kb[1] * sJT[st][1][k] + kb[2] * sJT[st][2][k] + kb[3] * sJT[st][3][k];
+        Kacc += v[12];
+        for (int m = 0; m < 4; ++m) {
+            yb[m] = v[m];
+            ybn[m] += v[m];
+            Dbn[m] += (1.0 - th) * v[4 + m]; Dbn[4 + m] += (1.0 - th) * v[8 + m];
+            Dbp[m] += th * v[4 + m]; Dbp[4 + m] += th * v[8 + m];
+        }
+    }
+    double* mucn = (double*)(g.adj_cur + c.off_cu);
+    double* dbn = (double*)(g.adj_cur + c.off_cd);
+    for (int m = 0; m < 4; ++m) {
+        mucn[m] = ybn[m] + cc[(0 * 2 + 0) * 4 + m] + cc[(1 * 2 + 0) * 4 + m];
+        dbn[m] = Dbn[m];
+        dbn[4 + m] = Dbn[4 + m];
+    }
+    g.acc[2 * g.nadj + ci] += Kacc;
+    // the corner's terms of the corrections at c + v and c + 2v (time n+1)
+    double Z1[4], Z2[4], GM[4];
+    for (int m = 0; m < 4; ++m) {
+        Z1[m] = Dbp[m] + sIn[I_DB + m];
+        Z2[m] = Dbp[4 + m] + sIn[I_DB + 4 + m];
+    }
+    mom_vjp<Q>(&sIn[I_DP], Z1, GM);
+    for (int m = 0; m < 4; ++m) g.gm[(8 + ci * 2 + 0) * 4 + m] = GM[m];
+    mom_vjp<Q>(&sIn[I_DP + 4], Z2, GM);
+    for (int m = 0; m < 4; ++m) g.gm[(8 + ci * 2 + 1) * 4 + m] = GM[m];
+}
+
+// side chunks; when the corners do not read the sides' contributions, the corners too (the
+// blocks after the side chunks)
 template <int Q>
 __global__ __launch_bounds__(256) void k_adj_side(AdjArgs g) {
     const int b = blockIdx.x;
+    if (b >= g.nadj) {
+        corner_adj<Q>(g, b - g.nadj);
+        return;
+    }
     int s = 0;
     while (s < 4 && !(g.anblk[s] > 0 && b >= g.ablk0[s] && b < g.ablk0[s] + g.anblk[s])) ++s;
     if (s == 4) return;
-    adj_chunk<Q>(g, g.b.s[s], b, b - g.ablk0[s]);
+    adj_chunk<Q>(g, g.b.s[s], s, b, b - g.ablk0[s]);
 }
 
-// ------------------------------------------------------------------ corners and strip corrections
-// Blocks 0..3: corner ci (fold of its M x M block, reverse of the corner RK4, corrections of nu
-// at the two diagonal nodes, which also carry the end rows of both adjacent sides' strips).
-// Blocks 4..: rows of the sides' strips away from corners: nu(x_f) += phi . (dm/dM)^T Xbar.
+// corners after the side chunks (coupled case)
 template <int Q>
 __global__ __launch_bounds__(256) void k_adj_corner(AdjArgs g) {
-    constexpr int M = Lat<Q>::M, MS = (M == 1) ? 2 : 1;
-    const BndArgs& a = g.b;
-    const int tid = threadIdx.x;
-    if (blockIdx.x < 4) {
-        const int ci = blockIdx.x;
-        const CornerDev& c = a.c[ci];
-        if (!c.active || c.zg) return;
-        __shared__ double sF[M * M][4];
-        __shared__ double sGM[2][4];
-        // inputs, loaded in parallel: U_c^n, U_c^{n+1}, D^n, D^{n+1}, adjoint of U_c^{n+1},
-        // adjoint of D^{n+1} as a time-(n+1) input, side contributions [axis][n, n+1]
-        __shared__ double sIn[52];
-        enum { I_UN = 0, I_UP = 4, I_DN = 8, I_DP = 16, I_MU = 24, I_DB = 28, I_CC = 36 };
-        if (tid < 52) {
-            const int t = tid;
-            double v;
-            if (t < I_UP) v = ((const double*)(a.reg_cur + c.off_cu))[t - I_UN];
-            else if (t < I_DN) v = ((const double*)(a.reg_next + c.off_cu))[t - I_UP];
-            else if (t < I_DP) v = ((const double*)(a.reg_cur + c.off_cd))[t - I_DN];
-            else if (t < I_MU) v = ((const double*)(a.reg_next + c.off_cd))[t - I_DP];
-            else if (t < I_DB) v = ((const double*)(g.adj_next + c.off_cu))[t - I_MU];
-            else if (t < I_CC) v = ((const double*)(g.adj_next + c.off_cd))[t - I_DB];
-            else v = g.ccon[ci * 16 + (t - I_CC)];
-            sIn[t] = v;
-        }
-        if (tid >= 64 && tid < 64 + M * M) {
-            const int q = tid - 64, jx = q / M, jy = q % M;
-            const int x = c.x0 + c.sxn * jx, y = c.y0 + c.syn * jy;
-            const double* cup = (const double*)(a.reg_next + c.off_cu);
-            double lam[Q], u4[4], G[4];
-#pragma unroll
-            for (int i = 0; i < Q; ++i) lam[i] = g.V1[pix<Q>(a.pitch, i, x, y)];
-            for (int m = 0; m < 4; ++m) u4[m] = cup[m];
-            feq_vjp<Q>(u4, lam, G);
-            for (int m = 0; m < 4; ++m) sF[q][m] = G[m];
-        }
-        __syncthreads();
-        if (tid == 0) {
-            const double* Un = &sIn[I_UN];
-            const double* cdn = &sIn[I_DN];
-            const double* cdp = &sIn[I_DP];
-            const double* cc = &sIn[I_CC];   // [axis][n, n+1][4]
-            double ub[4];
-            for (int m = 0; m < 4; ++m) {
-                ub[m] = sIn[I_MU + m];
-                for (int q = 0; q < M * M; ++q) ub[m] += sF[q][m];
-                for (int ax = 0; ax < 2; ++ax) ub[m] += cc[(ax * 2 + 1) * 4 + m];
-            }
-            // recompute the stage inputs
-            const double ast[4] = {0.0, 0.5, 0.5, 1.0}, bst[4] = {1.0, 2.0, 2.0, 1.0};
-            double Y[4][4], k4[4] = {0, 0, 0, 0};
-            for (int st = 0; st < 4; ++st) {
-                double B1[4], B2[4];
-                for (int m = 0; m < 4; ++m) {
-                    Y[st][m] = Un[m] + ast[st] * k4[m];
-                    B1[m] = (1.0 - ast[st]) * cdn[m] + ast[st] * cdp[m];
-                    B2[m] = (1.0 - ast[st]) * cdn[4 + m] + ast[st] * cdp[4 + m];
-                }
-                if (st < 3) corner_rate<Q>(c, Y[st], B1, B2, Un, k4);
-            }
-            // reverse
-            double ybn[4], yb[4] = {0, 0, 0, 0}, Dbn[8] = {0, 0, 0, 0, 0, 0, 0, 0}, Dbp[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            double Kacc = 0.0;
-            for (int m = 0; m < 4; ++m) ybn[m] = ub[m];
-            for (int st = 3; st >= 0; --st) {
-                const double th = ast[st];
-                double kb[4], B1[4], B2[4], Ycb[4], B1b[4], B2b[4], Kb;
-                for (int m = 0; m < 4; ++m) {
-                    kb[m] = bst[st] * (1.0 / 6.0) * ub[m] + (st < 3 ? ast[st + 1] * yb[m] : 0.0);
-                    B1[m] = (1.0 - th) * cdn[m] + th * cdp[m];
-                    B2[m] = (1.0 - th) * cdn[4 + m] + th * cdp[4 + m];
-                }
-                corner_rate_vjp<Q>(c, Y[st], B1, B2, Un, kb, Ycb, B1b, B2b, Kb);
-                Kacc += Kb;
-                for (int m = 0; m < 4; ++m) {
-                    yb[m] = Ycb[m];
-                    ybn[m] += Ycb[m];
-                    Dbn[m] += (1.0 - th) * B1b[m]; Dbn[4 + m] += (1.0 - th) * B2b[m];
-                    Dbp[m] += th * B1b[m]; Dbp[4 + m] += th * B2b[m];
-                }
-            }
-            double* mucn = (double*)(g.adj_cur + c.off_cu);
-            double* dbn = (double*)(g.adj_cur + c.off_cd);
-            for (int m = 0; m < 4; ++m) {
-                mucn[m] = ybn[m] + cc[(0 * 2 + 0) * 4 + m] + cc[(1 * 2 + 0) * 4 + m];
-                dbn[m] = Dbn[m];
-                dbn[4 + m] = Dbn[4 + m];
-            }
-            g.acc[2 * g.nadj + ci] += Kacc;
-            // corrections at c + v (with the adjacent strips' end rows) and c + 2v, time n+1
-            double Z1[4], Z2[4];
-            for (int m = 0; m < 4; ++m) {
-                Z1[m] = Dbp[m] + sIn[I_DB + m];
-                Z2[m] = Dbp[4 + m] + sIn[I_DB + 4 + m];
-            }
-            for (int ax = 0; ax < 2; ++ax) {
-                const int s = g.cside[ci][ax];
-                if (s < 0) continue;
-                const SideDev& sd = a.s[s];
-                const size_t o = (size_t)g.crow[ci][ax] * 4;
-                const double* xo = (const double*)(g.adj_next + sd.off_strip);
-                const double* xw = (const double*)(g.xnew + sd.off_strip);
-                for (int m = 0; m < 4; ++m) Z1[m] += xo[o + m] + xw[o + m];
-            }
-            mom_vjp<Q>(cdp, Z1, sGM[0]);
-            mom_vjp<Q>(cdp + 4, Z2, sGM[1]);
-        }
-        __syncthreads();
-        if (tid < Q) {
-            const int i = tid;
-            for (int e = 0; e < 2; ++e) {
-                const int x = c.xc + (e + 1) * c.vx, y = c.yc + (e + 1) * c.vy;
-                g.V1[pix<Q>(a.pitch, i, x, y)] += phi_dot<Q>(i, sGM[e]);
-            }
-        }
-        return;
-    }
-    // strip rows
-    int b = blockIdx.x - 4;
-    for (int s = 0; s < 4; ++s) {
-        const SideDev& sd = a.s[s];
-        if (sd.kind != KIND_CHAR) continue;
-        const int nb = (sd.len * MS + 255) / 256;
-        if (b >= nb) { b -= nb; continue; }
-        const int e = b * 256 + tid;
-        if (e >= sd.len * MS) return;
-        const int k = e / sd.len, r = e % sd.len;
-        if (!sd.tper && k == 0 && (r == 0 || r == sd.len - 1)) return;   // corner diagonal nodes
-        const double* xo = (const double*)(g.adj_next + sd.off_strip);
-        const double* xw = (const double*)(g.xnew + sd.off_strip);
-        const double* mv = (const double*)(a.reg_next + sd.off_strip);
-        const size_t o = ((size_t)k * sd.len + r) * 4;
-        double Z[4], GM[4];
-        for (int m = 0; m < 4; ++m) Z[m] = xo[o + m] + xw[o + m];
-        mom_vjp<Q>(mv + o, Z, GM);
-        int x, y; side_node(sd, -k, r, x, y);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) g.V1[pix<Q>(a.pitch, i, x, y)] += phi_dot<Q>(i, GM);
-        return;
-    }
+    corner_adj<Q>(g, blockIdx.x);
 }
 
 // ------------------------------------------------------------------ bulk reverse
@@ -732,6 +729,28 @@ __global__ __launch_bounds__(256) void k_adj_bulk(AdjArgs g, BulkArgs k, int bpr
         const bool src = xs >= k.x0 && xs <= k.x1 && ys >= k.y0 && ys <= k.y1;
         const double v = g.V1[src ? pix<Q>(pitch, i, xs, ys) : 0ull];   // in bounds either way
         lam[i] = src ? v : 0.0;
+    }
+    // corrections of nu^{n+1} at the corner diagonal nodes c + v (the corner's term and both
+    // adjacent strips' end rows) and c + 2v, for the nodes that pull from them
+    constexpr int M = Lat<Q>::M;
+    const bool corner_rows = y <= 3 * M + 1 || y >= k.ny - 2 - 3 * M;   // uniform per work-group
+    for (int ci = 0; corner_rows && ci < 4; ++ci) {
+        const CornerDev& c = g.b.c[ci];
+        if (!c.active || c.zg) continue;
+        for (int e = 0; e < 2; ++e) {
+            const int dx = c.xc + (e + 1) * c.vx - x, dy = c.yc + (e + 1) * c.vy - y;
+            if (dx < -M || dx > M || dy < -M || dy > M) continue;
+            double GM[4];
+            for (int m = 0; m < 4; ++m) {
+                GM[m] = g.gm[(8 + ci * 2 + e) * 4 + m];
+                if (e == 0)
+                    for (int ax = 0; ax < 2; ++ax)
+                        GM[m] += g.gm[(g.cside[ci][ax] * 2 + (g.crow[ci][ax] == 0 ? 0 : 1)) * 4 + m];
+            }
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+                if (cx<Q>(i) == dx && cy<Q>(i) == dy) lam[i] += phi_dot<Q>(i, GM);
+        }
     }
     if (INIT) {
         const int id = y * k.nx + x;

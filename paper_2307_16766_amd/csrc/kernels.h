@@ -36,6 +36,7 @@ struct SideDev {
     int owns_corners;            // x-sides write the corner blocks
     double K, alpha, Pinf;       // relaxation (eq. LODI-Relax / CBC-Relax)
     unsigned long long off_ub, off_strip, off_vis;   // byte offsets inside one parity region
+    unsigned long long off_stage;   // RK4 stage inputs Y_1..Y_3 [3][M][len][4] (recomputation for the adjoint)
 };
 
 struct CornerDev {
@@ -44,6 +45,7 @@ struct CornerDev {
     int x0, y0, sxn, syn;        // corner block: x0 + sxn*j, y0 + syn*j, j = 0..M-1
     double K, Pinf, ndx, ndy;    // relaxation of the x-side, outward diagonal normal
     unsigned long long off_cu, off_cd;
+    unsigned long long off_cs;   // RK4 stage inputs Y_1..Y_3 [3][4] (recomputation for the adjoint)
 };
 
 struct BndArgs {
@@ -492,7 +494,7 @@ __device__ __forceinline__ void write_feq(T* __restrict__ B, unsigned long long 
 // one corner: RK4 of the diagonal LODI system from the pulled populations of the two inward
 // diagonal nodes (d1, d2: time n+1) and the stored time-n values; U_c^{n+1} goes to cp_out and,
 // for the owning (x-side) work-group, to the next parity region
-template <int Q>
+template <int Q, bool HIST>
 __device__ void corner_rk4(const BndArgs& a, int ci, bool owner, const double* d1, const double* d2, const double* Un,
                            double* cp_out) {
     const CornerDev& c = a.c[ci];
@@ -512,6 +514,8 @@ __device__ void corner_rk4(const BndArgs& a, int ci, bool owner, const double* d
             B1[m] = (1.0 - th) * D1n[m] + th * D1p[m];
             B2[m] = (1.0 - th) * D2n[m] + th * D2p[m];
         }
+        if (HIST && owner && st > 0)
+            for (int m = 0; m < 4; ++m) ((double*)(a.reg_next + c.off_cs))[(st - 1) * 4 + m] = Y[m];
         corner_rate<Q>(c, Y, B1, B2, Un, k4);
         for (int m = 0; m < 4; ++m) acc[m] += bst[st] * (1.0 / 6.0) * k4[m];
     }
@@ -526,7 +530,7 @@ __device__ void corner_rk4(const BndArgs& a, int ci, bool owner, const double* d
 // ---------------------------------------------------------------- chunk of a characteristic side
 // LDS row lr <-> side row r = r0 - 4 + lr (4 halo rows: one per RK stage).  Thread t handles
 // node (lr = t / M, layer j = t % M + 1) in the RK stages.
-template <int Q, typename T>
+template <int Q, typename T, bool HIST>
 __device__ void char_chunk(const T* __restrict__ A, T* __restrict__ B, const BndArgs& a, const SideDev& sd, int chunk) {
     constexpr int M = Lat<Q>::M, NR = 256 / M, MS = (M == 1) ? 2 : 1;
     constexpr bool TH = Lat<Q>::thermal;
@@ -646,6 +650,11 @@ __device__ void char_chunk(const T* __restrict__ A, T* __restrict__ B, const Bnd
             const int lr = t / M, r = r0 - 4 + lr;
             if (r < r0 - hy || r >= r1 + hy || !valid(r)) continue;
             for (int m = 0; m < 4; ++m) sYs[t * 4 + m] = stg == 0 ? sY0[t * 4 + m] : sY0[t * 4 + m] + ast[stg] * sK[t * 4 + m];
+            if (HIST && stg > 0 && r >= r0 && r < r1) {
+                double* ys = (double*)(a.reg_next + sd.off_stage);
+                const int jj = t % M;
+                for (int m = 0; m < 4; ++m) ys[(((size_t)(stg - 1) * M + jj) * len + r) * 4 + m] = sYs[t * 4 + m];
+            }
         }
         __syncthreads();
         const double th = ast[stg];
@@ -703,9 +712,9 @@ __device__ void char_chunk(const T* __restrict__ A, T* __restrict__ B, const Bnd
         // last for the high corner
         if (stg == 0) {
             if (need_c[0] && tid == 0)
-                corner_rk4<Q>(a, sd.corner_lo, sd.owns_corners, sCd[0][0], sCd[0][1], sC[0][0], sC[0][1]);
+                corner_rk4<Q, HIST>(a, sd.corner_lo, sd.owns_corners, sCd[0][0], sCd[0][1], sC[0][0], sC[0][1]);
             if (need_c[1] && tid == NR * M - 1)
-                corner_rk4<Q>(a, sd.corner_hi, sd.owns_corners, sCd[1][0], sCd[1][1], sC[1][0], sC[1][1]);
+                corner_rk4<Q, HIST>(a, sd.corner_hi, sd.owns_corners, sCd[1][0], sCd[1][1], sC[1][0], sC[1][1]);
         }
         __syncthreads();
     }
@@ -780,13 +789,13 @@ __device__ void zg_chunk(const T* __restrict__ A, T* __restrict__ B, const BndAr
 }
 
 // one boundary work-group: find its side and chunk
-template <int Q, typename T>
+template <int Q, typename T, bool HIST>
 __device__ __forceinline__ void boundary_job(const T* __restrict__ A, T* __restrict__ B, const BndArgs& a, int b) {
     int s = 0;
     while (s < 4 && !(a.s[s].nblk > 0 && b >= a.s[s].blk0 && b < a.s[s].blk0 + a.s[s].nblk)) ++s;
     if (s == 4) return;
     const SideDev& sd = a.s[s];
-    if (sd.kind == KIND_CHAR) char_chunk<Q, T>(A, B, a, sd, b - sd.blk0);
+    if (sd.kind == KIND_CHAR) char_chunk<Q, T, HIST>(A, B, a, sd, b - sd.blk0);
     else if (sd.kind == KIND_ZG) zg_chunk<Q, T>(A, B, a, sd, b - sd.blk0);
 }
 
@@ -803,7 +812,7 @@ __global__ __launch_bounds__(256, (StepOcc<Q, T>::waves)) void k_step(const T* _
                                                                      BulkArgs g, int nbnd, int bpr) {
     const int b = (int)blockIdx.x;
     if (b < nbnd) {
-        boundary_job<Q, T>(A, B, a, b);
+        boundary_job<Q, T, HIST>(A, B, a, b);
         return;
     }
     const int t = b - nbnd;

@@ -107,6 +107,7 @@ void make_layout(const lbm_config* c, Layout& L) {
             d.nblk = (d.len + d.rows - 1) / d.rows;
             d.off_ub = reg; reg += align_up((size_t)L.M * d.len * 4 * 8);
             d.off_strip = reg; reg += align_up((size_t)L.MS * d.len * 4 * 8);
+            d.off_stage = reg; reg += align_up((size_t)3 * L.M * d.len * 4 * 8);
             if (is_full(b)) { d.off_vis = reg; reg += align_up((size_t)3 * d.len * 6 * 8); }
         } else if (d.kind == KIND_ZG) {
             d.rows = 256;
@@ -134,6 +135,7 @@ void make_layout(const lbm_config* c, Layout& L) {
         if (!k.zg) {
             k.off_cu = reg; reg += ALIGN;
             k.off_cd = reg; reg += ALIGN;
+            k.off_cs = reg; reg += ALIGN;
         }
     }
     L.region_bytes = align_up(reg > 0 ? reg : ALIGN);
@@ -159,8 +161,8 @@ struct Tape {
     int N = 0, K = 0, nchk = 0;
     long step_end = -1;
     size_t chk_stride = 0, off_R[2] = {0, 0}, off_V[2] = {0, 0}, off_mom = 0, mom_bytes = 0, off_rh = 0;
-    size_t off_adj[2] = {0, 0}, off_xnew = 0, off_ccon = 0, off_acc = 0, total = 0;
-    int ablk0[4] = {0, 0, 0, 0}, anblk[4] = {0, 0, 0, 0}, arows = 0, nadj = 0, nstrip = 0;
+    size_t off_adj[2] = {0, 0}, off_ccon = 0, off_gm = 0, off_acc = 0, total = 0;
+    int ablk0[4] = {0, 0, 0, 0}, anblk[4] = {0, 0, 0, 0}, arows = 0, nadj = 0;
 };
 
 struct lbm_ctx {
@@ -338,16 +340,14 @@ void tape_layout(const Layout& L, int ny, int N, int K, Tape& t) {
     t.off_mom = off; off += (size_t)(K + 1) * t.mom_bytes;
     t.off_rh = off; off += (size_t)(K + 1) * L.region_bytes;
     for (int k = 0; k < 2; ++k) { t.off_adj[k] = off; off += L.region_bytes; }
-    t.off_xnew = off; off += L.region_bytes;
     t.off_ccon = off; off += align_up(4 * 2 * 2 * 4 * 8);
+    t.off_gm = off; off += align_up(16 * 4 * 8);
     t.arows = 256 / L.M - 16;   // must match NR - 2 H in adj_chunk
     t.nadj = 0;
-    t.nstrip = 0;
     for (int s = 0; s < 4; ++s) {
         t.ablk0[s] = t.nadj;
         t.anblk[s] = L.s[s].kind == KIND_CHAR ? (L.s[s].len + t.arows - 1) / t.arows : 0;
         t.nadj += t.anblk[s];
-        if (L.s[s].kind == KIND_CHAR) t.nstrip += (L.s[s].len * L.MS + 255) / 256;
     }
     t.off_acc = off; off += align_up((size_t)(2 * t.nadj + 4) * 8);
     t.total = off;
@@ -371,15 +371,15 @@ int run_adjoint(lbm_ctx* c, const double* seed, double* grad, double* h_relax) {
     hipLaunchKernelGGL((k_adj_seed<Q, T>), dim3(bpr * ny), dim3(256), 0, st, (const T*)c->f[c->cur], seed, V[t.N & 1], bk, bpr);
     HIPCHK(c, hipGetLastError());
     for (int k = 0; k < 2; ++k) HIPCHK(c, hipMemsetAsync(base + t.off_adj[k], 0, L.region_bytes, st));
-    HIPCHK(c, hipMemsetAsync(base + t.off_xnew, 0, L.region_bytes, st));
     HIPCHK(c, hipMemsetAsync(base + t.off_ccon, 0, 4 * 2 * 2 * 4 * 8, st));
+    HIPCHK(c, hipMemsetAsync(base + t.off_gm, 0, 16 * 4 * 8, st));
     HIPCHK(c, hipMemsetAsync(base + t.off_acc, 0, (size_t)(2 * t.nadj + 4) * 8, st));
 
     AdjArgs g;
     std::memset(&g, 0, sizeof(g));
     g.b = make_bnd(c);
-    g.xnew = base + t.off_xnew;
     g.ccon = (double*)(base + t.off_ccon);
+    g.gm = (double*)(base + t.off_gm);
     g.acc = (double*)(base + t.off_acc);
     g.grad = grad;
     for (int s = 0; s < 4; ++s) { g.ablk0[s] = t.ablk0[s]; g.anblk[s] = t.anblk[s]; }
@@ -394,9 +394,13 @@ int run_adjoint(lbm_ctx* c, const double* seed, double* grad, double* h_relax) {
             g.cside[ci][ax] = s;
             g.crow[ci][ax] = L.s[s].corner_lo == ci ? 0 : L.s[s].len - 1;
         }
-    bool any_char = false, any_corner = false;
-    for (int s = 0; s < 4; ++s) any_char = any_char || L.s[s].kind == KIND_CHAR;
+    bool any_corner = false;
     for (int ci = 0; ci < 4; ++ci) any_corner = any_corner || L.c[ci].active;
+    // the sides' transverse terms reach the corner values only through transverse relaxation
+    g.coupled = 0;
+    for (int s = 0; s < 4; ++s)
+        if (any_corner && c->cfg.bc[s] == BC_LODI_RELAX && c->relax[s].alpha != 0.0) g.coupled = 1;
+    const int nside_blocks = t.nadj + ((any_corner && !g.coupled) ? 4 : 0);
 
     for (int seg = t.nchk - 1; seg >= 0; --seg) {
         const int n0 = seg * t.K, n1 = std::min(n0 + t.K, t.N);
@@ -418,12 +422,12 @@ int run_adjoint(lbm_ctx* c, const double* seed, double* grad, double* h_relax) {
             g.V1 = V[(n + 1) & 1];
             g.V0 = V[n & 1];
             g.mom = mom_slot(j);
-            if (t.nadj > 0) {
-                hipLaunchKernelGGL((k_adj_side<Q>), dim3(t.nadj), dim3(256), 0, st, g);
+            if (nside_blocks > 0) {
+                hipLaunchKernelGGL((k_adj_side<Q>), dim3(nside_blocks), dim3(256), 0, st, g);
                 HIPCHK(c, hipGetLastError());
             }
-            if (any_char || any_corner) {
-                hipLaunchKernelGGL((k_adj_corner<Q>), dim3(4 + t.nstrip), dim3(256), 0, st, g);
+            if (any_corner && g.coupled) {
+                hipLaunchKernelGGL((k_adj_corner<Q>), dim3(4), dim3(256), 0, st, g);
                 HIPCHK(c, hipGetLastError());
             }
             const dim3 grid(bpr * ny);
