@@ -619,7 +619,7 @@ __device__ void char_chunk(const T* __restrict__ A, T* __restrict__ B, const Bnd
         }
     }
     // corners at the ends of a side with non-periodic rows: time-n value, and the pull of the two
-    // inward diagonal nodes spread over the work-group (the RK4 runs during stage 0 below)
+    // inward diagonal nodes spread over the work-group (the RK4 follows the first barrier)
     for (int t = tid; t < 4 * Q; t += blockDim.x) {
         const int e = t / (2 * Q), k = (t / Q) % 2, i = t % Q;
         if (!need_c[e]) continue;
@@ -627,7 +627,7 @@ __device__ void char_chunk(const T* __restrict__ A, T* __restrict__ B, const Bnd
         const int x = c.xc + (k + 1) * c.vx - cx<Q>(i), y = c.yc + (k + 1) * c.vy - cy<Q>(i);
         sCd[e][k][i] = (double)A[pix<Q>(a.pitch, i, x, y)];
     }
-    if (tid < 8) {   // time n; the time n+1 slot starts as a finite copy (weighted by 0 in stage 0)
+    if (tid < 8) {   // time n (the time n+1 slot is set by the corner RK4)
         const int e = tid / 4, m = tid % 4;
         if (need_c[e]) {
             const double v = ((const double*)(a.reg_cur + a.c[e == 0 ? sd.corner_lo : sd.corner_hi].off_cu))[m];
@@ -642,6 +642,13 @@ __device__ void char_chunk(const T* __restrict__ A, T* __restrict__ B, const Bnd
     }
     __syncthreads();
 
+    // corner RK4 on two threads (as a branch inside the stage loop, overlapping stage 0, it raises
+    // the register pressure of the whole kernel enough to spill in the bulk path)
+    if (need_c[0] && tid == 0)
+        corner_rk4<Q, HIST>(a, sd.corner_lo, sd.owns_corners, sCd[0][0], sCd[0][1], sC[0][0], sC[0][1]);
+    if (need_c[1] && tid == NR * M - 1)
+        corner_rk4<Q, HIST>(a, sd.corner_hi, sd.owns_corners, sCd[1][0], sCd[1][1], sC[1][0], sC[1][1]);
+    __syncthreads();
     // ---- phase B: RK4, stage st valid on rows within 3 - st of the owned range -------------
     const double ast[4] = {0.0, 0.5, 0.5, 1.0}, bst[4] = {1.0, 2.0, 2.0, 1.0};
     for (int stg = 0; stg < 4; ++stg) {
@@ -710,12 +717,6 @@ __device__ void char_chunk(const T* __restrict__ A, T* __restrict__ B, const Bnd
         // corner RK4 while stage 0 runs (its rates use the corners' time-n values only), on
         // threads whose LDS row lies beyond the side's end: the first for the low corner, the
         // last for the high corner
-        if (stg == 0) {
-            if (need_c[0] && tid == 0)
-                corner_rk4<Q, HIST>(a, sd.corner_lo, sd.owns_corners, sCd[0][0], sCd[0][1], sC[0][0], sC[0][1]);
-            if (need_c[1] && tid == NR * M - 1)
-                corner_rk4<Q, HIST>(a, sd.corner_hi, sd.owns_corners, sCd[1][0], sCd[1][1], sC[1][0], sC[1][1]);
-        }
         __syncthreads();
     }
 
@@ -803,20 +804,24 @@ __device__ __forceinline__ void boundary_job(const T* __restrict__ A, T* __restr
 // and matches the 3 work-groups per CU that the boundary LDS allows), 2 otherwise.
 template <int Q, typename T> struct StepOcc { static constexpr int waves = (Q == 37 && sizeof(T) == 4) ? 3 : 2; };
 
-// One full time step: work-groups [0, nbnd) are boundary chunks, the rest bulk tiles of 256
-// nodes, bpr tiles per row, rows from g.y0, in row-major order (the whole chip sweeps the rows
-// in order, which streams best from HBM; an XCD-aware order that keeps a row's tiles on one L2
-// removes the ~10 % duplicate edge-line fetches but streams slower).
+// One full time step: work-groups [0, nbnd) are boundary chunks (dispatched first), the rest bulk
+// tiles of 256 nodes, bpr tiles per row, rows from g.y0, in row-major order (the whole chip
+// sweeps the rows in order, which streams best from HBM; an XCD-aware order that keeps a row's
+// tiles on one L2 removes the ~10 % duplicate edge-line fetches but streams slower).  The row of
+// tile t is t / bpr computed as umulhi(t, magic) with magic = floor(2^32 / bpr) + 1 for bpr > 1
+// (exact while t * bpr < 2^32, checked on the host), which stays on the scalar unit.
 template <int Q, typename T, bool PX, bool PY, bool HIST>
 __global__ __launch_bounds__(256, (StepOcc<Q, T>::waves)) void k_step(const T* __restrict__ A, T* __restrict__ B, BndArgs a,
-                                                                     BulkArgs g, int nbnd, int bpr) {
+                                                                     BulkArgs g, int nbnd, int bpr, unsigned magic) {
     const int b = (int)blockIdx.x;
     if (b < nbnd) {
         boundary_job<Q, T, HIST>(A, B, a, b);
         return;
     }
-    const int t = b - nbnd;
-    bulk_node<Q, T, PX, PY, HIST>(A, B, g, (t % bpr) * 256 + (int)threadIdx.x, g.y0 + t / bpr);
+    const unsigned t = (unsigned)(b - nbnd);
+    const unsigned row = bpr == 1 ? t : __umulhi(t, magic);   // (2^32 + 1 does not fit for bpr = 1)
+    const int tile = (int)(t - row * (unsigned)bpr);
+    bulk_node<Q, T, PX, PY, HIST>(A, B, g, tile * 256 + (int)threadIdx.x, g.y0 + (int)row);
 }
 
 }  // namespace lbm

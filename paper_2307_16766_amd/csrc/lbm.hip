@@ -58,6 +58,10 @@ int validate(const lbm_config* c, std::string& err) {
     const bool xp = c->bc[0] == BC_PERIODIC, yp = c->bc[2] == BC_PERIODIC;
     if (c->nx < (xp ? M + 1 : 2 * M + 3) || c->ny < (yp ? M + 1 : 2 * M + 3)) { err = "grid too small"; return LBM_E_ARG; }
     if ((double)c->nx * (double)c->ny > 2.0e9) { err = "grid too large"; return LBM_E_ARG; }
+    {   // the step kernel's row of bulk tile t is umulhi(t, floor(2^32 / bpr) + 1): exact while t * bpr < 2^32
+        const unsigned long long bpr = ((unsigned long long)c->nx + 255) / 256;
+        if (bpr * bpr * (unsigned long long)c->ny >= (1ull << 32)) { err = "grid too large for the step kernel's tile indexing"; return LBM_E_UNSUPPORTED; }
+    }
     if (!xp && !yp)
         for (int sx = 0; sx < 2; ++sx)
             for (int sy = 2; sy < 4; ++sy) {
@@ -271,11 +275,12 @@ void launch_step_raw(const lbm_ctx* c, const T* A, T* B, char* reg_cur, char* re
     const int bpr = (g.x1 + 1 + 255) / 256;   // bulk tiles per row, aligned to x = 0
     const int nbnd = c->nbnd;
     const int nblk = nbnd + bpr * (g.y1 - g.y0 + 1);
+    const unsigned magic = bpr > 1 ? (unsigned)((1ull << 32) / (unsigned long long)bpr + 1ull) : 0u;   // row = umulhi(t, magic)
     const bool px = c->cfg.bc[0] == BC_PERIODIC, py = c->cfg.bc[2] == BC_PERIODIC;
-    if (px && py) hipLaunchKernelGGL((k_step<Q, T, true, true, HIST>), dim3(nblk), dim3(256), 0, s, A, B, a, g, nbnd, bpr);
-    else if (px) hipLaunchKernelGGL((k_step<Q, T, true, false, HIST>), dim3(nblk), dim3(256), 0, s, A, B, a, g, nbnd, bpr);
-    else if (py) hipLaunchKernelGGL((k_step<Q, T, false, true, HIST>), dim3(nblk), dim3(256), 0, s, A, B, a, g, nbnd, bpr);
-    else hipLaunchKernelGGL((k_step<Q, T, false, false, HIST>), dim3(nblk), dim3(256), 0, s, A, B, a, g, nbnd, bpr);
+    if (px && py) hipLaunchKernelGGL((k_step<Q, T, true, true, HIST>), dim3(nblk), dim3(256), 0, s, A, B, a, g, nbnd, bpr, magic);
+    else if (px) hipLaunchKernelGGL((k_step<Q, T, true, false, HIST>), dim3(nblk), dim3(256), 0, s, A, B, a, g, nbnd, bpr, magic);
+    else if (py) hipLaunchKernelGGL((k_step<Q, T, false, true, HIST>), dim3(nblk), dim3(256), 0, s, A, B, a, g, nbnd, bpr, magic);
+    else hipLaunchKernelGGL((k_step<Q, T, false, false, HIST>), dim3(nblk), dim3(256), 0, s, A, B, a, g, nbnd, bpr, magic);
 }
 
 template <int Q, typename T>
