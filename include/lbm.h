@@ -9,8 +9,9 @@
  *     (Appendix B, Tab. d2q37; 4th-order Hermite equilibrium, eq. feq-4);
  *   - boundary: layerwise characteristic analysis on the M outer layers (Sec. 3.3), wave
  *     amplitudes of eq. thermal_WAV, incoming amplitudes by one of the four schemes of
- *     Tab. CBCs (eq. PNR, LODI-Relax, CBC-PNR, CBC-Relax), RK4 in time, equilibrium Dirichlet
- *     reconstruction of all populations on the layers (Sec. 3.3 "Mesoscopic BC").
+ *     Tab. CBCs (eq. PNR, LODI-Relax, CBC-PNR, CBC-Relax), RK4 in time, equilibrium or NEEP
+ *     Dirichlet reconstruction of all populations on the layers (Sec. 3.3 "Mesoscopic BC",
+ *     eq. NEEP).
  *
  * Conventions
  *   - Grid: nx * ny nodes, row-major, x fastest.  Side order: x = 0, x = nx-1, y = 0, y = ny-1.
@@ -89,6 +90,13 @@ typedef struct lbm_relax {
     double length;
 } lbm_relax;
 
+/* Mesoscopic BC of a characteristic side (Sec. 3.3 "Mesoscopic BC"): the populations of the M
+ * layers are set from the new boundary state U_b either to the equilibrium f^eq(U_b) (default) or,
+ * with NEEP (eq. NEEP), to f^eq(U_b) plus the non-equilibrium part f - f^eq(U) of the adjacent
+ * bulk node x_f of the same row (post-collision, like every stored population).  Corner blocks
+ * stay at equilibrium. */
+enum lbm_recon { LBM_RECON_EQUILIBRIUM = 0, LBM_RECON_NEEP = 1 };
+
 typedef struct lbm_ctx lbm_ctx;
 
 /* Device workspace the caller must provide to lbm_init for this configuration (bytes).
@@ -107,6 +115,10 @@ int lbm_init(const lbm_config* cfg, void* d_workspace, size_t workspace_bytes, v
 /* Set the relaxation parameters of side 0..3, or of every side with side = -1.  Takes effect
  * from the next lbm_step. */
 int lbm_cbc_params(lbm_ctx* ctx, int side, const lbm_relax* p);
+
+/* Reconstruction mode (lbm_recon) of side 0..3, or of every characteristic side with side = -1;
+ * NEEP on a non-characteristic side returns LBM_E_STATE.  Takes effect from the next lbm_step. */
+int lbm_reconstruction(lbm_ctx* ctx, int side, int mode);
 
 /* Fixed profile of a Dirichlet side: d_U is device FP64 [len][4] = (rho, u_x, u_y, T) per row
  * along the side (len = ny for x-sides, nx for y-sides).  Default: the initial fields on the
@@ -152,8 +164,8 @@ int lbm_bulk_kernel_time(lbm_ctx* ctx, double* total_ms, long* launches);
  * the discrete map that lbm_step computes (bulk stream + BGK collide, the RK4 characteristic
  * solve of every side and corner with wave directions frozen at the start of the step, and the
  * equilibrium reconstruction), in FP64 whatever the storage precision.  Supported boundaries:
- * periodic, LODI and LODI_RELAX (D2Q9 additionally needs one periodic axis); other
- * configurations return LBM_E_UNSUPPORTED.
+ * periodic, LODI and LODI_RELAX with the equilibrium reconstruction (D2Q9 additionally needs one
+ * periodic axis); other configurations return LBM_E_UNSUPPORTED.
  *
  * lbm_tape_bytes: device bytes of the tape for nsteps steps with a checkpoint every `every`
  * steps (0 for invalid arguments).  The tape holds ceil(nsteps / every) checkpoints of the

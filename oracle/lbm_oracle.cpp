@@ -385,6 +385,7 @@ struct Sim {
     SideGeo geo[4];
     Relax<S> rp[4];
     std::vector<S> inlet[4];   // Dirichlet profiles [len][4]
+    int meso[4] = {0, 0, 0, 0};   // mesoscopic BC of a characteristic side: 0 equilibrium, 1 NEEP
     std::vector<S> f, fpre, U;  // f, fpre: [q][ny][nx]; U: [4][ny][nx]
     long steps = 0;
 
@@ -826,6 +827,17 @@ struct Sim {
                         S u4[4]; node_moments(fc, x, y, u4); setU(Un, x, y, u4);
                     } else {
                         S u4[4]; getU(Un, x, y, u4); node_feq(fc, x, y, u4);
+                        if (meso[s] == 1) {
+                            // eq. NEEP: add the non-equilibrium part of the adjacent bulk node x_f
+                            // (post-collision populations, so the layer holds the post-collision
+                            // state that the same NEEP populations would reach in the collision)
+                            int xf, yf; node(g, 0, r, xf, yf);
+                            S uf[4]; getU(Un, xf, yf, uf);
+                            std::vector<S> fe(q);
+                            equilibrium(L, uf[0], uf[1], uf[2], uf[3], fe.data());
+                            for (int i = 0; i < q; ++i)
+                                fc[i * P + id(x, y)] = fc[i * P + id(x, y)] + (fc[i * P + id(xf, yf)] - fe[i]);
+                        }
                     }
                 }
         }
@@ -977,6 +989,15 @@ int oracle_set_relax(void* h, int side, const double* p) {
     if (side < 0 || side > 3) return -1;
     s->rp[side].sigma = p[0]; s->rp[side].alpha = p[1]; s->rp[side].rho_inf = p[2];
     s->rp[side].T_inf = p[3]; s->rp[side].mach = p[4]; s->rp[side].length = p[5];
+    return 0;
+}
+
+// Mesoscopic BC of a characteristic side (Sec. 3.3 "Mesoscopic BC"): 0 equilibrium, 1 NEEP.
+int oracle_set_recon(void* h, int side, int mode) {
+    auto* s = static_cast<Sim<double>*>(h);
+    if (side < 0 || side > 3 || mode < 0 || mode > 1) return -1;
+    if (mode == 1 && !(s->bc[side] >= BC_LODI && s->bc[side] <= BC_CBC_RELAX)) return -1;
+    s->meso[side] = mode;
     return 0;
 }
 

@@ -42,6 +42,7 @@ def lib():
         L.oracle_side_len.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.oracle_set_relax.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp]
         L.oracle_set_inlet.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp]
+        L.oracle_set_recon.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
         L.oracle_init.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp]
         L.oracle_step.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.oracle_macro.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp]
@@ -142,6 +143,12 @@ class Oracle:
         U = np.ascontiguousarray(U, dtype=np.float64)
         if lib().oracle_set_inlet(self.h, side, _ptr(U)) != 0:
             raise ValueError("side is not a Dirichlet side")
+
+    def set_recon(self, side, mode):
+        """Mesoscopic BC of a characteristic side: "equilibrium" or "neep" (eq. NEEP)."""
+        m = {"equilibrium": 0, "neep": 1}[mode]
+        if lib().oracle_set_recon(self.h, side, m) != 0:
+            raise ValueError("NEEP needs a characteristic side")
 
     def init(self, rho, ux, uy, T):
         arrs = [np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=np.float64), (self.ny, self.nx)))

@@ -30,6 +30,7 @@ enum { KIND_NONE = 0, KIND_CHAR = 1, KIND_ZG = 2, KIND_DIRICHLET = 3 };
 
 struct SideDev {
     int kind, scheme;
+    int meso;                    // mesoscopic BC of a characteristic side: 0 equilibrium, 1 NEEP
     int nax, sn, Nn, Nt, r0, len, xf, tper;
     int blk0, nblk, rows;        // boundary work-groups of this side in k_step, rows per work-group
     int corner_lo, corner_hi;    // corners at row -1 / row len (non-periodic tangent), else -1
@@ -720,13 +721,28 @@ __device__ void char_chunk(const T* __restrict__ A, T* __restrict__ B, const Bnd
         __syncthreads();
     }
 
-    // ---- phase C: new boundary state and equilibrium reconstruction of the layers ----------
+    // ---- phase C: new boundary state and reconstruction of the layers ------------------------
     for (int t = tid; t < (r1 - r0) * M; t += blockDim.x) {
         const int lr = 4 + t / M, j = t % M, r = r0 + t / M;
         const double* u4 = &sAcc[(lr * M + j) * 4];
         for (int m = 0; m < 4; ++m) ubn[((size_t)j * len + r) * 4 + m] = u4[m];
         int x, y; side_node(sd, j + 1, r, x, y);
-        write_feq<Q, T>(B, a.pitch, x, y, u4);
+        if (sd.meso == 0) {   // equilibrium BC: all populations at equilibrium
+            write_feq<Q, T>(B, a.pitch, x, y, u4);
+        } else {              // eq. NEEP: plus the post-collision non-equilibrium part of x_f
+            int xf, yf; side_node(sd, 0, r, xf, yf);
+            double d[Q], fe[Q];
+            pull_node<Q, T>(A, a, xf, yf, d);
+            double rm1, ux, uy, th;
+            moments_dev<Q, double>(d, rm1, ux, uy, th);
+            feq_dev<Q, double>(rm1, ux, uy, th, fe);
+            const double c = 1.0 - a.omega;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) d[i] = c * (d[i] - fe[i]);
+            feq_dev<Q, double>(u4[0] - 1.0, u4[1], u4[2], Lat<Q>::thermal ? u4[3] - 1.0 : 0.0, fe);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) B[pix<Q>(a.pitch, i, x, y)] = (T)(fe[i] + d[i]);
+        }
     }
     // the x-side's work-groups write the M x M corner blocks (threads from the top of the
     // work-group, which have no layer node here: a chunk has at most 256 - 8 M rows x M layers)

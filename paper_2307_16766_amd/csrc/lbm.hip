@@ -183,6 +183,7 @@ struct lbm_ctx {
     hipStream_t stream = nullptr;
     int nbnd = 0;
     lbm_relax relax[4];
+    int meso[4] = {0, 0, 0, 0};   // mesoscopic BC per side (LBM_RECON_*)
     BulkArgs bulk;
     std::string err;
     // bulk kernel timing (measurement only)
@@ -226,6 +227,7 @@ BndArgs make_bnd(const lbm_ctx* c) {
         const double len = p.length > 0 ? p.length : (double)a.s[s].Nn;
         a.s[s].K = p.sigma * (1.0 - p.mach * p.mach) * cinf / len;
         a.s[s].alpha = p.alpha;
+        a.s[s].meso = c->meso[s];
         a.s[s].Pinf = p.rho_inf * cs2 * (thermal ? p.T_inf : 1.0);
     }
     for (int ci = 0; ci < 4; ++ci) {
@@ -319,7 +321,12 @@ int launch_init(lbm_ctx* c, const double* rho, const double* ux, const double* u
 }
 
 // ---------------------------------------------------------------- discrete adjoint (host side)
-int adjoint_supported(const lbm_config& g, std::string& err) {
+int adjoint_supported(const lbm_config& g, const int* meso, std::string& err) {
+    for (int s = 0; s < 4; ++s)
+        if (meso[s] != LBM_RECON_EQUILIBRIUM) {
+            err = "the adjoint supports the equilibrium reconstruction only";
+            return LBM_E_UNSUPPORTED;
+        }
     for (int s = 0; s < 4; ++s)
         if (g.bc[s] != BC_PERIODIC && g.bc[s] != BC_LODI && g.bc[s] != BC_LODI_RELAX) {
             err = "the adjoint supports periodic, LODI and LODI-RELAX sides only";
@@ -552,6 +559,21 @@ int lbm_cbc_params(lbm_ctx* c, int side, const lbm_relax* p) {
     return LBM_OK;
 }
 
+int lbm_reconstruction(lbm_ctx* c, int side, int mode) {
+    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+    if (side < -1 || side > 3 || (mode != LBM_RECON_EQUILIBRIUM && mode != LBM_RECON_NEEP))
+        return fail(c, LBM_E_ARG, "bad side or reconstruction mode");
+    for (int s = 0; s < 4; ++s) {
+        if (side >= 0 && s != side) continue;
+        if (mode == LBM_RECON_NEEP && c->L.s[s].kind != KIND_CHAR) {
+            if (side >= 0) return fail(c, LBM_E_STATE, "NEEP applies to characteristic sides only");
+            continue;
+        }
+        c->meso[s] = mode;
+    }
+    return LBM_OK;
+}
+
 int lbm_dirichlet_profile(lbm_ctx* c, int side, const double* d_U) {
     if (!c) return fail(nullptr, LBM_E_ARG, "null context");
     if (side < 0 || side > 3 || !d_U) return fail(c, LBM_E_ARG, "bad side or profile pointer");
@@ -664,7 +686,7 @@ size_t lbm_tape_bytes(const lbm_ctx* c, int nsteps, int every) {
 int lbm_record(lbm_ctx* c, int nsteps, int every, void* d_tape, size_t tape_bytes) {
     if (!c) return fail(nullptr, LBM_E_ARG, "null context");
     std::string err;
-    const int sup = adjoint_supported(c->cfg, err);
+    const int sup = adjoint_supported(c->cfg, c->meso, err);
     if (sup != LBM_OK) return fail(c, sup, err);
     if (nsteps < 1 || every < 1) return fail(c, LBM_E_ARG, "nsteps and every must be positive");
     if (!d_tape || ((uintptr_t)d_tape % ALIGN) != 0) return fail(c, LBM_E_ARG, "tape must be non-NULL and 256-byte aligned");

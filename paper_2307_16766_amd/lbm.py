@@ -18,9 +18,10 @@ D2Q9, D2Q37 = 9, 37
 FP64, FP32DEV = 0, 1
 BC = {"periodic": 0, "lodi": 1, "lodi_relax": 2, "cbc": 3, "cbc_relax": 4, "zg": 5, "dirichlet": 6}
 PRECISION = {"fp64": FP64, "fp32dev": FP32DEV}
+RECON = {"equilibrium": 0, "neep": 1}
 
 # exported symbols, as declared in include/lbm.h
-SYMBOLS = ["lbm_workspace_bytes", "lbm_init", "lbm_cbc_params", "lbm_dirichlet_profile", "lbm_step",
+SYMBOLS = ["lbm_workspace_bytes", "lbm_init", "lbm_cbc_params", "lbm_reconstruction", "lbm_dirichlet_profile", "lbm_step",
            "lbm_macroscopic", "lbm_boundary_state", "lbm_diagnostics", "lbm_state_bytes", "lbm_save",
            "lbm_restore", "lbm_steps_done", "lbm_set_kernel_timing", "lbm_bulk_kernel_time",
            "lbm_tape_bytes", "lbm_record", "lbm_adjoint", "lbm_lattice_info", "lbm_last_error", "lbm_destroy"]
@@ -60,6 +61,7 @@ def load():
     L.lbm_init.argtypes = [ctypes.POINTER(Config), _vp, ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp,
                            ctypes.POINTER(_vp)]
     L.lbm_cbc_params.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(Relax)]
+    L.lbm_reconstruction.argtypes = [_vp, ctypes.c_int, ctypes.c_int]
     L.lbm_dirichlet_profile.argtypes = [_vp, ctypes.c_int, _vp]
     L.lbm_step.argtypes = [_vp, ctypes.c_int]
     L.lbm_macroscopic.argtypes = [_vp, _vp, _vp, _vp, _vp]
@@ -165,6 +167,10 @@ class LBM:
     def set_relax(self, side, sigma=0.0, alpha=0.0, rho_inf=1.0, T_inf=1.0, mach=0.0, length=0.0):
         p = Relax(sigma, alpha, rho_inf, T_inf, mach, length)
         self._check(load().lbm_cbc_params(self.ctx, side, ctypes.byref(p)))
+
+    def set_reconstruction(self, side, mode):
+        """Mesoscopic BC of characteristic side(s): "equilibrium" or "neep" (side -1: all)."""
+        self._check(load().lbm_reconstruction(self.ctx, side, RECON[mode]))
 
     def set_inlet(self, side, U):
         t = self.torch.as_tensor(np.asarray(U, dtype=np.float64)).to(self.device).contiguous()

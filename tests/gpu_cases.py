@@ -36,7 +36,10 @@ def rel_errors(gpu, ref):
     return e_rho, e_u, e_T
 
 
-def make_pair(stencil, nx, ny, tau, bc, fields, precision, relax=None, inlet=None):
+CHAR_BCS = ("lodi", "lodi_relax", "cbc", "cbc_relax")
+
+
+def make_pair(stencil, nx, ny, tau, bc, fields, precision, relax=None, inlet=None, recon=None):
     from paper_2307_16766_amd import lbm
     g = lbm.LBM(stencil, nx, ny, tau, bc, fields, precision=precision)
     o = O.Oracle(stencil, nx, ny, tau, bc)
@@ -44,6 +47,11 @@ def make_pair(stencil, nx, ny, tau, bc, fields, precision, relax=None, inlet=Non
     if relax is not None:
         g.set_relax(-1, **relax)
         o.set_relax(-1, **relax)
+    if recon is not None:
+        g.set_reconstruction(-1, recon)
+        for s, b in enumerate(bc):
+            if b in CHAR_BCS:
+                o.set_recon(s, recon)
     if inlet is not None:
         side, U = inlet
         g.set_inlet(side, U)
@@ -63,10 +71,28 @@ def check_fields(name, precision, n, gpu, ref, tol=None):
     return errs
 
 
-def compare_run(name, stencil, nx, ny, tau, bc, fields, precision, steps, relax=None, inlet=None, tol=None):
-    """Step both implementations, comparing after every listed step count.  Returns worst errors."""
-    log(f"[gpu-case] {name} {precision} {nx}x{ny} D2Q{stencil} bc={bc} steps={steps}")
-    g, o = make_pair(stencil, nx, ny, tau, bc, fields, precision, relax, inlet)
+def gpu_pops(g):
+    """Full populations (q, ny, nx) of the GPU state in the oracle's velocity order, decoded from
+    a checkpoint (populations are stored as f - w_i in row-interleaved planes [y][i][x])."""
+    from paper_2307_16766_amd import lbm
+    _, w, cx, cy, _ = lbm.lattice_info(g.stencil)
+    q = len(w)
+    dt = np.float64 if g.cfg.precision == lbm.FP64 else np.float32
+    pitch = (g.nx + 63) // 64 * 64
+    raw = g.save().cpu().numpy()
+    d = raw[256:256 + q * pitch * g.ny * np.dtype(dt).itemsize].view(dt).reshape(g.ny, q, pitch)[:, :, :g.nx]
+    f = d.transpose(1, 0, 2).astype(np.float64) + w[:, None, None]
+    _, _, ocx, ocy, _ = O.lattice(g.stencil)
+    index = {(int(a), int(b)): i for i, (a, b) in enumerate(zip(cx, cy))}
+    return np.stack([f[index[(int(a), int(b))]] for a, b in zip(ocx, ocy)])
+
+
+def compare_run(name, stencil, nx, ny, tau, bc, fields, precision, steps, relax=None, inlet=None, tol=None,
+                recon=None, pops_tol=None):
+    """Step both implementations, comparing after every listed step count (and the populations
+    of every node at the end, absolute tolerance pops_tol, when given).  Returns worst errors."""
+    log(f"[gpu-case] {name} {precision} {nx}x{ny} D2Q{stencil} bc={bc} recon={recon} steps={steps}")
+    g, o = make_pair(stencil, nx, ny, tau, bc, fields, precision, relax, inlet, recon)
     worst = [0.0, 0.0, 0.0]
     done = 0
     for n in steps:
@@ -75,6 +101,10 @@ def compare_run(name, stencil, nx, ny, tau, bc, fields, precision, steps, relax=
         done = n
         errs = check_fields(name, precision, n, g.macro_numpy(), o.macro(), tol)
         worst = [max(a, b) for a, b in zip(worst, errs)]
+    if pops_tol is not None:
+        dmax = float(np.abs(gpu_pops(g) - o.pops()).max())
+        log(f"[gpu-case] {name} {precision} max |f_gpu - f_oracle| = {dmax:.3e}")
+        assert dmax <= pops_tol, (name, dmax)
     g.close()
     log(f"[gpu-case] {name} {precision} ok worst rel errors rho/u/T = {worst}")
     return worst

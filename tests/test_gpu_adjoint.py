@@ -152,6 +152,12 @@ def test_adjoint_argument_and_state_errors():
     assert e.value.code == lbm.LBM_E_UNSUPPORTED
     g.close()
     g = lbm.LBM(37, 40, 40, TAU_37, ["lodi_relax"] * 4, f)
+    g.set_reconstruction(-1, "neep")
+    with pytest.raises(lbm.LBMError) as e:
+        g.record(5, 2)
+    assert e.value.code == lbm.LBM_E_UNSUPPORTED
+    g.close()
+    g = lbm.LBM(37, 40, 40, TAU_37, ["lodi_relax"] * 4, f)
     with pytest.raises(lbm.LBMError) as e:
         g.adjoint()
     assert e.value.code == lbm.LBM_E_STATE

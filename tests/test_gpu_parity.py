@@ -85,3 +85,30 @@ def test_d2q9_multi_tile():
     nx, ny = 600, 300
     f = W.gaussian_density_pulse(nx, ny, amp=1e-3, width=12.0, center=(40.0, 280.0))
     compare_run("d2q9-multitile", 9, nx, ny, 0.6, ["lodi_relax"] * 4, f, "fp64", [1, 5, 20], relax=RELAX)
+
+
+# --- mesoscopic BC: NEEP (eq. NEEP) on every characteristic side; populations compared too
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_d2q37_neep_four_schemes(precision):
+    nx, ny = 44, 38
+    f = W.temperature_pulse(nx, ny, amp=1e-3, width=4.0, center=(18.0, 16.0))
+    rho, ux, uy, T = f
+    fields = (rho, ux + 0.01, uy - 0.004, T)
+    compare_run("d2q37-neep", 37, nx, ny, TAU_37, ["lodi_relax", "cbc_relax", "lodi", "cbc"], fields, precision, EARLY,
+                relax=RELAX, recon="neep", pops_tol=1e-14 if precision == "fp64" else 2e-8)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_d2q9_neep_periodic_y(precision):
+    nx, ny = 40, 24
+    f = W.gaussian_density_pulse(nx, ny, amp=1e-3, width=4.0)
+    compare_run("d2q9-neep", 9, nx, ny, 0.6, ["lodi_relax", "lodi", "periodic", "periodic"], f, precision, EARLY,
+                relax=dict(sigma=0.25), recon="neep", pops_tol=1e-14 if precision == "fp64" else 2e-8)
+
+
+def test_equilibrium_populations_match_oracle():
+    # the default reconstruction, compared population by population as well
+    nx, ny = 40, 36
+    f = W.temperature_pulse(nx, ny, amp=1e-3, width=4.0)
+    compare_run("d2q37-eq-pops", 37, nx, ny, TAU_37, ["lodi_relax"] * 4, f, "fp64", EARLY, relax=RELAX,
+                pops_tol=1e-14)

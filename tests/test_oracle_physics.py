@@ -178,6 +178,69 @@ def test_reflection_lodi_vs_zero_gradient():
     assert lodi < zg / 4 and cbc < zg / 4
 
 
+def test_neep_reflection_like_equilibrium():
+    # Sec. 4: the NEEP mesoscopic BC (eq. NEEP) performs about like the equilibrium BC; at normal
+    # incidence both characteristic schemes stay far below zero-gradient's reflection
+    nx, ny = 240, 6
+    def reflected(bc, recon):
+        o = O.Oracle(37, nx, ny, TAU_37, [bc, bc, "periodic", "periodic"])
+        if recon == "neep":
+            o.set_recon(0, "neep")
+            o.set_recon(1, "neep")
+        o.init(*W.planar_temperature_pulse(nx, ny, amp=1e-3, width=10.0))
+        o.step(40)
+        inc = np.abs(o.macro()[1][:, 60:180]).max()
+        o.step(90)
+        ref = 0.0
+        for _ in range(5):
+            ref = max(ref, np.abs(o.macro()[1][:, 60:180]).max())
+            o.step(10)
+        return ref / inc
+    zg = reflected("zg", "equilibrium")
+    for bc in ("lodi", "cbc"):
+        eq, neep = reflected(bc, "equilibrium"), reflected(bc, "neep")
+        assert neep < zg / 4 and abs(neep - eq) < 0.01, (bc, eq, neep, zg)
+
+
+@pytest.mark.parametrize("bc", ["lodi_relax", "cbc_relax"])
+def test_neep_invariants(bc):
+    # The non-equilibrium part that NEEP adds has no mass, momentum or energy (BGK conserves
+    # them), so the layers' moments stay the characteristic state; a uniform flow has no
+    # non-equilibrium part, so it stays uniform as under the equilibrium BC.
+    nx, ny = 30, 24
+    u0 = 0.1 * math.sqrt(CS2_37)
+    o = O.Oracle(37, nx, ny, TAU_37, [bc] * 4)
+    o.set_relax(-1, sigma=0.25, alpha=0.1, mach=0.1)
+    for s in range(4):
+        o.set_recon(s, "neep")
+    o.init(*W.uniform_flow(nx, ny, ux=u0))
+    o.step(60)
+    r, ux, uy, T = o.macro()
+    assert np.abs(r - 1).max() < 1e-13 and np.abs(ux - u0).max() < 1e-13 and np.abs(uy).max() < 1e-13
+    o = O.Oracle(37, nx, ny, TAU_37, [bc] * 4)
+    o.set_relax(-1, sigma=0.25, alpha=0.1, mach=0.1)
+    for s in range(4):
+        o.set_recon(s, "neep")
+    rho, ux, uy, T = W.temperature_pulse(nx, ny, amp=1e-3, width=4.0, center=(10.0, 9.0))
+    o.init(rho, ux + 0.02, uy, T)
+    o.step(25)
+    U = o.macro()
+    f = o.pops()
+    cs2, w, cx, cy, M = O.lattice(37)
+    rho_f = f.sum(axis=0)
+    jx = (f * cx[:, None, None]).sum(axis=0)
+    e = (f * (cx ** 2 + cy ** 2)[:, None, None]).sum(axis=0)
+    T_f = (e - jx ** 2 / rho_f - ((f * cy[:, None, None]).sum(axis=0)) ** 2 / rho_f) / (2 * rho_f * cs2)
+    layers = np.zeros((ny, nx), bool)
+    layers[:, :M] = layers[:, -M:] = layers[:M, :] = layers[-M:, :] = True
+    assert np.abs(rho_f - U[0])[layers].max() < 1e-13
+    assert np.abs(jx / rho_f - U[1])[layers].max() < 1e-13
+    assert np.abs(T_f - U[3])[layers].max() < 1e-12
+    # and NEEP did change the layers: they are not at equilibrium
+    fe = np.stack([O.feq(37, U[0][y, x], U[1][y, x], U[2][y, x], U[3][y, x]) for y, x in [(ny // 2, 0), (ny // 2, 1)]])
+    assert np.abs(f[:, ny // 2, 0] - fe[0]).max() > 1e-9
+
+
 @pytest.mark.parametrize("mode", ["shear", "entropy"])
 def test_viscous_terms_match_laplacian(mode):
     # eq. LaplaceU / LaplaceT: the mesoscopic viscous terms equal nu lap(u_t) and
