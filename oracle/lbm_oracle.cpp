@@ -26,7 +26,9 @@
  *    xi = c/cs, u/cs, theta = T (dimensionless, T0 = 1); the printed (c^2-4) factor of the
  *    (u.c)^2 (T-1) term of eq. feq-4 is (xi^2-6) in this expansion.
  *  - Lattice constants: the D2Q37 weights are solved from the isotropy conditions up to
- *    degree 9 (Appendix B table is given to 14 digits only).
+ *    degree 9 (Appendix B table is given to 14 digits only), the D2Q17 weights up to degree 7
+ *    (they equal the closed forms of Tab. d2q17; the caption's expression is 1/cs).  D2Q17 uses
+ *    the 3rd-order equilibrium of eq. feq-3, D2Q37 the 4th-order one of eq. feq-4.
  *  - Matrix S (Sec. 3.1): entry S_41 carries cs^2, not cs (S S^-1 = I only then).
  *  - Non-equilibrium part f^neq = f - f^eq (eq. NEEP); viscous stress
  *    Pi' = -(1 - 1/(2 tau)) sum c c f^neq (eq. LaplaceU); physical heat flux
@@ -35,6 +37,11 @@
  *    acoustic amplitude only: -alpha T_x,i + K (P - P_inf) / (4 rho cs^2) (thermal) or
  *    -alpha T_x,i + K (P - P_inf) (isothermal), K = sigma (1 - Ma^2) c_inf / L.  Incoming
  *    entropy and shear waves keep the annihilation value of their scheme.
+ *  - Viscous terms of the -FD variant (Sec. 4.2, "Treatment of viscous terms"): nu lap(u) and
+ *    (nu c_p / (Pr cs^2)) lap(T~) by second differences of the macroscopic values of each layer
+ *    (backward four-point formula at the outermost layer, central elsewhere and along the side),
+ *    plus the viscous heating of eq. NSF-CHAR from first differences; unlike the mesoscopic
+ *    terms they are evaluated from the stage values at every RK4 stage.
  *  - RK4 (Sec. 3.3 "Time integration"): wave directions and viscous terms frozen at time t,
  *    bulk values linearly interpolated in time, all layers and rows of a side advanced as
  *    one coupled system.
@@ -193,6 +200,12 @@ static Lattice make_lattice(int stencil) {
         P.chk = {4, 0};
         lo = 0.65L; hi = 0.75L;
         L.M = 3; L.thermal = true; L.order = 4;
+    } else if (stencil == 17) {  // Tab. d2q17: 7th-order quadrature, 3rd-order equilibrium
+        P.groups = {{0, 0}, {1, 0}, {1, 1}, {2, 2}, {3, 0}};
+        P.lin = {{0, 0}, {1, 0}, {2, 0}, {1, 1}, {3, 0}};
+        P.chk = {2, 1};
+        lo = 0.3L; hi = 0.45L;
+        L.M = 3; L.thermal = true; L.order = 3;
     } else {
         return L;
     }
@@ -235,8 +248,9 @@ static Lattice make_lattice(int stencil) {
 
 static const Lattice& lattice(int stencil) {
     static const Lattice L9 = make_lattice(9);
+    static const Lattice L17 = make_lattice(17);
     static const Lattice L37 = make_lattice(37);
-    return stencil == 9 ? L9 : L37;
+    return stencil == 9 ? L9 : (stencil == 17 ? L17 : L37);
 }
 
 // ---------------------------------------------------------------- equilibrium (eq. feq-3/feq-4)
@@ -262,10 +276,8 @@ static void equilibrium(const Lattice& L, const S& rho, const S& ux, const S& uy
         S s1 = u[0] * L.h1[2 * i] + u[1] * L.h1[2 * i + 1];
         S s2 = 0.0, s3 = 0.0, s4 = 0.0;
         for (int k = 0; k < 4; ++k) s2 += a2[k] * L.h2[4 * i + k];
-        if (L.order >= 4) {
-            for (int k = 0; k < 8; ++k) s3 += a3[k] * L.h3[8 * i + k];
-            for (int k = 0; k < 16; ++k) s4 += a4[k] * L.h4[16 * i + k];
-        }
+        if (L.order >= 3) for (int k = 0; k < 8; ++k) s3 += a3[k] * L.h3[8 * i + k];
+        if (L.order >= 4) for (int k = 0; k < 16; ++k) s4 += a4[k] * L.h4[16 * i + k];
         out[i] = L.w[i] * rho * (1.0 + s1 + s2 / 2.0 + s3 / 6.0 + s4 / 24.0);
     }
 }
@@ -386,6 +398,7 @@ struct Sim {
     Relax<S> rp[4];
     std::vector<S> inlet[4];   // Dirichlet profiles [len][4]
     int meso[4] = {0, 0, 0, 0};   // mesoscopic BC of a characteristic side: 0 equilibrium, 1 NEEP
+    int vfd[4] = {0, 0, 0, 0};    // viscous terms of a CBC side: 0 mesoscopic moments, 1 differences
     std::vector<S> f, fpre, U;  // f, fpre: [q][ny][nx]; U: [4][ny][nx]
     long steps = 0;
 
@@ -644,6 +657,56 @@ struct Sim {
         for (int m = 0; m < 4; ++m) u4[m] = (1.0 - c.theta) * a[m] + c.theta * b[m];
     }
 
+    // V of the -FD variant (Sec. 4.2, treatment of viscous terms) at layer j, row r, from the
+    // stage values: the Laplacians of eq. NSF-CHAR by second differences -- the backward
+    // four-point formula at the outermost layer, the central one at inner layers and along the
+    // side -- and the heating term from the first differences that the amplitudes use.
+    void visc_fd(const SideCtx& c, int j, int r, S* Vv) const {
+        const SideGeo& g = *c.g;
+        auto lv = [&](int k, int rr, S* l) { S u4[4]; side_value(c, k, rr, u4); to_local(g.nax, g.sn, u4, l); };
+        S l0[4], up[4], dw[4], dn[4], d2n[4], d2t[4], dtv[4];
+        lv(j, r, l0); lv(j, r + 1, up); lv(j, r - 1, dw);
+        if (j == M) {
+            S a[4], bb[4], cc[4], dd[4]; lv(M - 1, r, bb); lv(M - 2, r, cc); lv(M - 3, r, dd);
+            for (int m = 0; m < 4; ++m) a[m] = l0[m];
+            for (int m = 0; m < 4; ++m) {
+                d2n[m] = 2.0 * a[m] - 5.0 * bb[m] + 4.0 * cc[m] - dd[m];
+                dn[m] = 0.5 * (3.0 * a[m] - 4.0 * bb[m] + cc[m]);
+            }
+        } else {
+            S a[4], cc[4]; lv(j + 1, r, a); lv(j - 1, r, cc);
+            for (int m = 0; m < 4; ++m) { d2n[m] = a[m] - 2.0 * l0[m] + cc[m]; dn[m] = 0.5 * (a[m] - cc[m]); }
+        }
+        for (int m = 0; m < 4; ++m) { d2t[m] = up[m] - 2.0 * l0[m] + dw[m]; dtv[m] = 0.5 * (up[m] - dw[m]); }
+        const double nu = (tau - 0.5) * L.cs2;
+        const double cp = 2.0, Pr = 1.0;   // c_p = d/2 + 1 in d = 2; BGK fixes Pr = 1
+        Vv[0] = 0.0;
+        Vv[1] = nu * (d2n[1] + d2t[1]);
+        Vv[2] = nu * (d2n[2] + d2t[2]);
+        Vv[3] = 0.0;
+        if (L.thermal) {
+            const S sa = dn[1] - dtv[2], sb = dtv[1] + dn[2];
+            Vv[3] = (nu * cp / Pr) * (d2n[3] + d2t[3]) + (nu / L.cs2) * (sa * sa + sb * sb);
+        }
+    }
+
+    // V of the -FD variant at time t for layer j (1..M), row r of side s, away from the ends
+    // of a side with non-periodic rows
+    void visc_fd_probe(int s, int j, int r, S* V4) {
+        const SideGeo& g = geo[s];
+        std::vector<S> Y0((size_t)M * g.len * 4);
+        for (int jj = 1; jj <= M; ++jj)
+            for (int rr = 0; rr < g.len; ++rr) {
+                int x, y; node(g, jj, rr, x, y);
+                getU(U, x, y, &Y0[((size_t)(jj - 1) * g.len + rr) * 4]);
+            }
+        SideCtx c;
+        c.g = &g; c.s = s; c.Y = &Y0; c.Y0 = &Y0; c.Un = &U; c.V = nullptr;
+        c.corner_lo[0] = c.corner_lo[1] = c.corner_hi[0] = c.corner_hi[1] = nullptr;
+        c.theta = 0.0;
+        visc_fd(c, j, r, V4);
+    }
+
     void side_rhs(const SideCtx& c, int j, int r, S* dU) const {
         const SideGeo& g = *c.g;
         const int n = L.thermal ? 4 : 3;
@@ -672,7 +735,11 @@ struct Sim {
             Tv[3] = 0.0;
         }
         S Vv[4];
-        for (int m = 0; m < 4; ++m) Vv[m] = (*c.V)[(size_t)r * 4 + m];
+        if (is_full_cbc(b) && vfd[c.s]) {
+            visc_fd(c, j, r, Vv);
+        } else {
+            for (int m = 0; m < 4; ++m) Vv[m] = (*c.V)[(size_t)r * 4 + m];
+        }
         // characteristic analysis at the stage value; wave directions from time t
         S vec[4], dv[4], tv[4], vv[4];
         pack(l0, vec); pack(dn, dv);
@@ -717,7 +784,7 @@ struct Sim {
                 int x, y; node(g, j, r, x, y);
                 getU(U, x, y, &Y0[((size_t)(j - 1) * g.len + r) * 4]);
             }
-        if (is_full_cbc(bc[s])) visc_terms(g, V); else V.assign((size_t)g.len * 4, S(0.0));
+        if (is_full_cbc(bc[s]) && !vfd[s]) visc_terms(g, V); else V.assign((size_t)g.len * 4, S(0.0));
         SideCtx c;
         c.g = &g; c.s = s; c.Y0 = &Y0; c.Un = &Un; c.V = &V;
         // corner ids at the two ends of this side
@@ -908,7 +975,7 @@ struct Sim {
 };
 
 int validate(int stencil, int nx, int ny, double tau, const int* bc) {
-    if (stencil != 9 && stencil != 37) { g_err = "stencil must be 9 or 37"; return -1; }
+    if (stencil != 9 && stencil != 17 && stencil != 37) { g_err = "stencil must be 9, 17 or 37"; return -1; }
     const int M = stencil == 9 ? 1 : 3;
     if (!(tau > 0.5)) { g_err = "tau must exceed 1/2"; return -1; }
     for (int s = 0; s < 4; ++s) if (bc[s] < 0 || bc[s] > 6) { g_err = "bad boundary type"; return -1; }
@@ -926,7 +993,7 @@ int validate(int stencil, int nx, int ny, double tau, const int* bc) {
     }
     if (stencil == 9)
         for (int s = 0; s < 4; ++s)
-            if (is_full_cbc(bc[s])) { g_err = "CBC with viscous terms needs the heat-flux moment (D2Q37)"; return -1; }
+            if (is_full_cbc(bc[s])) { g_err = "CBC with viscous terms needs the heat-flux moment (thermal stencils)"; return -1; }
     return 0;
 }
 
@@ -946,7 +1013,7 @@ int oracle_num_threads(void) {
 }
 
 int oracle_lattice(int stencil, int* q, int* M, double* cs2, double* w, int* cx, int* cy) {
-    if (stencil != 9 && stencil != 37) return -1;
+    if (stencil != 9 && stencil != 17 && stencil != 37) return -1;
     const Lattice& L = lattice(stencil);
     *q = L.q; *M = L.M; *cs2 = L.cs2;
     for (int i = 0; i < L.q; ++i) { if (w) w[i] = L.w[i]; if (cx) cx[i] = L.cx[i]; if (cy) cy[i] = L.cy[i]; }
@@ -954,20 +1021,20 @@ int oracle_lattice(int stencil, int* q, int* M, double* cs2, double* w, int* cx,
 }
 
 int oracle_feq(int stencil, double rho, double ux, double uy, double T, double* out) {
-    if (stencil != 9 && stencil != 37) return -1;
+    if (stencil != 9 && stencil != 17 && stencil != 37) return -1;
     equilibrium(lattice(stencil), rho, ux, uy, T, out);
     return 0;
 }
 
 int oracle_moments(int stencil, const double* f, double* u4) {
-    if (stencil != 9 && stencil != 37) return -1;
+    if (stencil != 9 && stencil != 17 && stencil != 37) return -1;
     moments(lattice(stencil), f, u4[0], u4[1], u4[2], u4[3]);
     return 0;
 }
 
 // characteristic matrices at a local-frame state (rho, u_n, u_t, T); n x n row-major
 int oracle_char_matrices(int stencil, const double* U, double* A, double* S, double* Si, double* lam) {
-    if (stencil != 9 && stencil != 37) return -1;
+    if (stencil != 9 && stencil != 17 && stencil != 37) return -1;
     auto c = char_system<double>(lattice(stencil), U);
     for (int k = 0; k < c.n * c.n; ++k) { A[k] = c.A[k]; S[k] = c.Sm[k]; Si[k] = c.Si[k]; }
     for (int k = 0; k < c.n; ++k) lam[k] = c.lam[k];
@@ -998,6 +1065,25 @@ int oracle_set_recon(void* h, int side, int mode) {
     if (side < 0 || side > 3 || mode < 0 || mode > 1) return -1;
     if (mode == 1 && !(s->bc[side] >= BC_LODI && s->bc[side] <= BC_CBC_RELAX)) return -1;
     s->meso[side] = mode;
+    return 0;
+}
+
+// Viscous terms of a CBC side: 0 from the mesoscopic moments (eq. LaplaceU / LaplaceT), 1 by
+// finite differences of the macroscopic values (the -FD variant of Sec. 4.2).
+int oracle_visc_fd_probe(void* h, int side, int j, int r, double* out) {
+    auto* s = static_cast<Sim<double>*>(h);
+    if (side < 0 || side > 3 || s->bc[side] == BC_PERIODIC || j < 1 || j > s->M) return -1;
+    const auto& g = s->geo[side];
+    if (!(g.tper || (r >= 1 && r + 1 < g.len))) return -1;
+    s->visc_fd_probe(side, j, r, out);
+    return 0;
+}
+
+int oracle_set_viscous(void* h, int side, int mode) {
+    auto* s = static_cast<Sim<double>*>(h);
+    if (side < 0 || side > 3 || mode < 0 || mode > 1) return -1;
+    if (mode == 1 && !is_full_cbc(s->bc[side])) return -1;
+    s->vfd[side] = mode;
     return 0;
 }
 

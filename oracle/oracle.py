@@ -43,6 +43,8 @@ def lib():
         L.oracle_set_relax.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp]
         L.oracle_set_inlet.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp]
         L.oracle_set_recon.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
+        L.oracle_set_viscous.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
+        L.oracle_visc_fd_probe.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp]
         L.oracle_init.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp]
         L.oracle_step.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.oracle_macro.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp]
@@ -149,6 +151,19 @@ class Oracle:
         m = {"equilibrium": 0, "neep": 1}[mode]
         if lib().oracle_set_recon(self.h, side, m) != 0:
             raise ValueError("NEEP needs a characteristic side")
+
+    def visc_fd_probe(self, side, j, r):
+        """V (local components) of the -FD variant at layer j, row r of a side, at the current time."""
+        out = np.zeros(4)
+        if lib().oracle_visc_fd_probe(self.h, side, j, r, _ptr(out)) != 0:
+            raise ValueError("bad probe position")
+        return out
+
+    def set_viscous(self, side, mode):
+        """Viscous terms of a CBC side: "meso" (eq. LaplaceU / LaplaceT) or "fd" (Sec. 4.2)."""
+        m = {"meso": 0, "fd": 1}[mode]
+        if lib().oracle_set_viscous(self.h, side, m) != 0:
+            raise ValueError("finite-difference viscous terms need a CBC side")
 
     def init(self, rho, ux, uy, T):
         arrs = [np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=np.float64), (self.ny, self.nx)))

@@ -90,6 +90,20 @@ def shear_layer(nx, ny, u0=0.1, thickness=10.0, noise=1e-3, seed=16766):
     return (one.copy(), ux, uy, one.copy()), prof
 
 
+def temperature_step(nx, ny, cs, mach=0.1, T0=1.0, T1=1.0005, s=0.5, length=None, offset=0.0):
+    """Smooth temperature step T0 -> T1 -> T0 across x in a uniform stream u = (mach cs, 0), rho = 1
+    (Sec. 4.1): tanh fronts of steepness s at length/4 and 3 length/4, length = nx by default.
+    The printed second branch has (tanh - 1); (tanh + 1) is the one that returns to T0, which
+    the text and the figure describe.  offset shifts the fronts (a window of a wider grid)."""
+    L = float(nx if length is None else length)
+    x = np.arange(nx, dtype=np.float64)[None, :] - offset
+    left = T1 + 0.5 * (T1 - T0) * (np.tanh(s * (x - L / 4)) - 1.0)
+    right = T1 - 0.5 * (T1 - T0) * (np.tanh(s * (x - 3 * L / 4)) + 1.0)
+    T = np.broadcast_to(np.where(x <= L / 2, left, right), (ny, nx)).copy()
+    one = np.ones((ny, nx))
+    return one.copy(), mach * cs * one, 0.0 * one, T
+
+
 def uniform_flow(nx, ny, ux=0.0, uy=0.0, rho=1.0, T=1.0):
     one = np.ones((ny, nx))
     return rho * one, ux * one, uy * one, T * one

@@ -38,6 +38,33 @@ def test_d2q37_equilibrium_moments():
         assert max(abs(r - rho), abs(mx - ux), abs(my - uy), abs(mT - T)) < 1e-13
 
 
+def test_d2q17_equilibrium_moments_third_order():
+    # eq. feq-3 on the 7th-order D2Q17 rule: the moments of the Maxwellian up to 3rd order are
+    # exact (rho, rho u, T, zero 3rd central moment), and the equilibrium has no 4th-order
+    # Hermite component (sum_i f_i He4(xi_i) = 0 for every 4th-order tensor Hermite polynomial)
+    cs2, w, cx, cy, _ = O.lattice(17)
+    cs = math.sqrt(cs2)
+    xx, xy = cx / cs, cy / cs
+    he4 = [xx ** 4 - 6 * xx ** 2 + 3, xx ** 3 * xy - 3 * xx * xy, xx ** 2 * xy ** 2 - xx ** 2 - xy ** 2 + 1,
+           xx * xy ** 3 - 3 * xx * xy, xy ** 4 - 6 * xy ** 2 + 3]
+    for rho, ux, uy, T in _states(20, seed=5):
+        f = O.feq(17, rho, ux, uy, T)
+        dx, dy = cx - ux, cy - uy
+        assert abs(f.sum() - rho) < 1e-14
+        assert abs((f * cx).sum() - rho * ux) < 1e-14
+        assert abs((f * cy).sum() - rho * uy) < 1e-14
+        assert abs((f * (dx * dx + dy * dy)).sum() - 2 * rho * cs2 * T) < 1e-14
+        for a, b in [(3, 0), (2, 1), (1, 2), (0, 3)]:
+            assert abs((f * dx ** a * dy ** b).sum()) < 1e-14
+        for h in he4:
+            assert abs((f * h).sum()) < 1e-13
+        r, mx, my, mT = O.moments(17, f)
+        assert max(abs(r - rho), abs(mx - ux), abs(my - uy), abs(mT - T)) < 1e-14
+    # but the 4th central moment is not the Maxwellian's 3 rho T~^2 away from rest
+    f = O.feq(17, 1.0, 0.2, 0.1, 1.05)
+    assert abs((f * (cx - 0.2) ** 4).sum() - 3 * (cs2 * 1.05) ** 2) > 1e-4
+
+
 def _paper_feq4(w, cx, cy, cs2, rho, ux, uy, T, k):
     # eq. feq-3 + feq-4 written in the scaled variables xi = c / cs, u / cs (every printed cs
     # factor equals 1 there); k is the constant of the (u.c)^2 (T-1) term (printed: 4)
@@ -82,9 +109,9 @@ def test_d2q9_equilibrium_textbook():
         assert abs((f * cx).sum() - rho * ux) < 1e-14
 
 
-@pytest.mark.parametrize("stencil", [9, 37])
+@pytest.mark.parametrize("stencil", [9, 17, 37])
 def test_collision_conserves(stencil):
-    # BGK (eq. bgk) conserves mass and momentum; D2Q37 also energy, for arbitrary f
+    # BGK (eq. bgk) conserves mass and momentum; the thermal stencils also energy, for any f
     cs2, w, cx, cy, _ = O.lattice(stencil)
     rng = np.random.default_rng(11)
     tau = 0.8
@@ -96,6 +123,6 @@ def test_collision_conserves(stencil):
         assert abs(fs.sum() - f.sum()) < 1e-15
         assert abs((fs * cx).sum() - (f * cx).sum()) < 1e-15
         assert abs((fs * cy).sum() - (f * cy).sum()) < 1e-15
-        if stencil == 37:
+        if stencil != 9:
             e = cx * cx + cy * cy
             assert abs((fs * e).sum() - (f * e).sum()) < 1e-14

@@ -9,6 +9,8 @@ from paper_2307_16766_amd import workloads as W
 
 CS2_37 = O.lattice(37)[0]
 TAU_37 = 0.5 + W.NU_D2Q37 / CS2_37   # nu = (tau - 1/2) cs^2 = 0.1 (Sec. 2, Sec. 4)
+TAU_17 = 0.9                          # the D2Q17 runs of Sec. 4.1
+TAUS = {9: 0.6, 17: TAU_17, 37: TAU_37}
 
 BC_TYPES = ["lodi", "lodi_relax", "cbc", "cbc_relax", "zg"]
 
@@ -23,15 +25,15 @@ def _smooth_random(nx, ny, seed, amp):
     return out
 
 
-@pytest.mark.parametrize("stencil", [9, 37])
+@pytest.mark.parametrize("stencil", [9, 17, 37])
 def test_periodic_conservation(stencil):
-    # BGK + periodic streaming conserve mass, momentum (and energy for D2Q37) globally
+    # BGK + periodic streaming conserve mass, momentum (and energy for the thermal stencils)
     nx, ny = 24, 20
-    tau = TAU_37 if stencil == 37 else 0.6
+    tau = TAUS[stencil]
     o = O.Oracle(stencil, nx, ny, tau, ["periodic"] * 4)
     rho = 1 + _smooth_random(nx, ny, 1, 0.02)
     ux, uy = _smooth_random(nx, ny, 2, 0.05), _smooth_random(nx, ny, 3, 0.05)
-    T = 1 + (_smooth_random(nx, ny, 4, 0.02) if stencil == 37 else np.zeros((ny, nx)))
+    T = 1 + (_smooth_random(nx, ny, 4, 0.02) if stencil != 9 else np.zeros((ny, nx)))
     o.init(rho, ux, uy, T)
     d0 = o.diag()
     o.step(200)
@@ -39,20 +41,20 @@ def test_periodic_conservation(stencil):
     assert abs(d1[0] - d0[0]) < 1e-13 * d0[0]
     assert abs(d1[1] - d0[1]) < 1e-13 * d0[0]
     assert abs(d1[2] - d0[2]) < 1e-13 * d0[0]
-    if stencil == 37:
+    if stencil != 9:
         assert abs(d1[3] - d0[3]) < 1e-13 * d0[3]
 
 
-@pytest.mark.parametrize("bcs", [
+@pytest.mark.parametrize("stencil,bcs", [(37, b) for b in [
     ["lodi", "lodi_relax", "periodic", "periodic"],
     ["cbc", "cbc_relax", "periodic", "periodic"],
     ["lodi_relax"] * 4, ["cbc_relax"] * 4, ["lodi"] * 4, ["cbc"] * 4, ["zg"] * 4,
     ["dirichlet", "lodi_relax", "periodic", "periodic"],
-])
-def test_uniform_flow_stays_uniform(bcs):
+]] + [(17, b) for b in [["lodi_relax"] * 4, ["cbc_relax"] * 4, ["cbc", "lodi", "periodic", "periodic"]]])
+def test_uniform_flow_stays_uniform(stencil, bcs):
     nx, ny = 30, 24
-    u0 = 0.1 * math.sqrt(CS2_37)
-    o = O.Oracle(37, nx, ny, TAU_37, bcs)
+    u0 = 0.1 * math.sqrt(O.lattice(stencil)[0])
+    o = O.Oracle(stencil, nx, ny, TAUS[stencil], bcs)
     o.set_relax(-1, sigma=0.25, alpha=0.1, mach=0.1)
     o.init(*W.uniform_flow(nx, ny, ux=u0))
     o.step(100)
@@ -79,14 +81,15 @@ def _peak(profile, lo, hi):
     return i + 0.5 * (a - c) / (a - 2 * b + c)
 
 
-@pytest.mark.parametrize("stencil", [9, 37])
+@pytest.mark.parametrize("stencil", [9, 17, 37])
 def test_sound_speed(stencil):
-    # isothermal cs (D2Q9) and adiabatic sqrt(gamma cs^2 T), gamma = c_p / c_v = 2 (D2Q37,
-    # Sec. 2 and the eigenvalues of Sec. 3.1): a planar pulse splits into halves at that speed
+    # isothermal cs (D2Q9) and adiabatic sqrt(gamma cs^2 T), gamma = c_p / c_v = 2 (thermal
+    # stencils, Sec. 2 and the eigenvalues of Sec. 3.1): a planar pulse splits into halves at
+    # that speed
     nx, ny, t = 320, 4, 80
-    tau = TAU_37 if stencil == 37 else 0.6
+    tau = TAUS[stencil]
     cs2 = O.lattice(stencil)[0]
-    c = math.sqrt(2 * cs2) if stencil == 37 else math.sqrt(cs2)
+    c = math.sqrt(2 * cs2) if stencil != 9 else math.sqrt(cs2)
     X, _ = W.grid(nx, ny)
     x0 = 100.0
     # right-moving simple wave: d rho = rho0 d u / c, plus the matching temperature for D2Q37
@@ -94,7 +97,7 @@ def test_sound_speed(stencil):
     g = amp * np.exp(-((X - x0) ** 2) / (2 * 6.0 ** 2))
     rho = 1 + g
     ux = c * g
-    T = 1 + (g if stencil == 37 else 0)   # adiabatic: dT/T = (gamma - 1) d rho / rho
+    T = 1 + (g if stencil != 9 else 0)   # adiabatic: dT/T = (gamma - 1) d rho / rho
     o = O.Oracle(stencil, nx, ny, tau, ["periodic"] * 4)
     o.init(rho, ux, np.zeros_like(g), T)
     o.step(t)
@@ -103,12 +106,13 @@ def test_sound_speed(stencil):
     assert abs((xp - x0) / t - c) < 0.005 * c
 
 
-@pytest.mark.parametrize("stencil,mode", [(9, "shear"), (37, "shear"), (37, "entropy")])
+@pytest.mark.parametrize("stencil,mode", [(9, "shear"), (17, "shear"), (17, "entropy"), (37, "shear"),
+                                          (37, "entropy")])
 def test_mode_decay(stencil, mode):
     # shear mode decays as exp(-nu k^2 t), entropy mode as exp(-alpha k^2 t), nu = alpha =
     # (tau - 1/2) cs^2 (Sec. 2, Pr = 1)
     nx, ny = 96, 4
-    tau = TAU_37 if stencil == 37 else 0.6
+    tau = TAUS[stencil]
     cs2 = O.lattice(stencil)[0]
     nu = (tau - 0.5) * cs2
     k = 2 * math.pi / nx
@@ -138,13 +142,17 @@ def test_mode_decay(stencil, mode):
     assert abs(rate / (nu * k * k) - 1) < 0.01
 
 
-@pytest.mark.parametrize("bc", BC_TYPES)
-def test_d4_symmetry(bc):
+@pytest.mark.parametrize("stencil,bc,visc", [(37, b, "meso") for b in BC_TYPES]
+                         + [(37, "cbc_relax", "fd"), (17, "cbc_relax", "meso"), (17, "cbc", "fd"), (17, "lodi_relax", "meso")])
+def test_d4_symmetry(stencil, bc, visc):
     # a centred pulse with the same boundary on all four sides keeps the square's symmetry,
     # which exercises every side frame and all four corners
     n = 36
-    o = O.Oracle(37, n, n, TAU_37, [bc] * 4)
+    o = O.Oracle(stencil, n, n, TAUS[stencil], [bc] * 4)
     o.set_relax(-1, sigma=0.25, alpha=0.1, mach=0.05)
+    if visc == "fd":
+        for s in range(4):
+            o.set_viscous(s, "fd")
     o.init(*W.temperature_pulse(n, n, amp=1e-3, width=4.0))
     o.step(50)
     r, ux, uy, T = o.macro()
@@ -241,16 +249,16 @@ def test_neep_invariants(bc):
     assert np.abs(f[:, ny // 2, 0] - fe[0]).max() > 1e-9
 
 
-@pytest.mark.parametrize("mode", ["shear", "entropy"])
-def test_viscous_terms_match_laplacian(mode):
+@pytest.mark.parametrize("stencil,mode", [(37, "shear"), (37, "entropy"), (17, "shear"), (17, "entropy")])
+def test_viscous_terms_match_laplacian(stencil, mode):
     # eq. LaplaceU / LaplaceT: the mesoscopic viscous terms equal nu lap(u_t) and
     # (nu c_p / (Pr cs^2)) lap(T~) = 2 nu lap(T) of a resolved wave (FD error O(k^2))
     nx, ny = 64, 8
     k = 2 * math.pi / nx
-    nu = W.NU_D2Q37
+    nu = (TAUS[stencil] - 0.5) * O.lattice(stencil)[0]
     X, _ = W.grid(nx, ny)
     A = 1e-3
-    o = O.Oracle(37, nx, ny, TAU_37, ["periodic"] * 4)
+    o = O.Oracle(stencil, nx, ny, TAUS[stencil], ["periodic"] * 4)
     if mode == "shear":
         o.init(np.ones_like(X), np.zeros_like(X), A * np.sin(k * X), np.ones_like(X))
     else:
@@ -394,3 +402,69 @@ def test_pressure_relaxation_direction(stencil):
         res[bc] = o.macro()[0].mean() - 1.0
     assert abs(res["lodi"] - 1e-3) < 1e-12
     assert 0 < res["lodi_relax"] < 0.8e-3
+
+
+@pytest.mark.parametrize("stencil", [17, 37])
+def test_fd_viscous_terms_match_laplacian(stencil):
+    # the -FD variant (Sec. 4.2, treatment of viscous terms): on the layers of a side, V_t and
+    # V_T of a shear / temperature wave varying along the normal are nu d2 u_t and
+    # (nu c_p / (Pr cs^2)) d2 T~ = 2 nu d2 T.  Inner layers use the central second difference,
+    # exact for sin up to the factor sinc^2(k/2); the outermost layer the backward formula
+    # (error O(k^2)).
+    tau = TAUS[stencil]
+    nu = (tau - 0.5) * O.lattice(stencil)[0]
+    nx, ny, M, A = 64, 12, 3, 1e-6
+    k = 2 * math.pi / nx
+    X, _ = W.grid(nx, ny)
+    o = O.Oracle(stencil, nx, ny, tau, ["cbc", "cbc_relax", "periodic", "periodic"])
+    o.init(np.ones_like(X), np.zeros_like(X), A * np.sin(k * X + 0.3), 1 + A * np.cos(k * X + 0.3))
+    central = (2 * math.sin(k / 2) / k) ** 2
+    for side in (0, 1):
+        for j in (1, 2, 3):
+            x = M - j if side == 0 else nx - 1 - M + j
+            V = o.visc_fd_probe(side, j, 5)
+            rt = V[2] / (-nu * k * k * A * math.sin(k * x + 0.3))
+            rT = V[3] / (-2 * nu * k * k * A * math.cos(k * x + 0.3))
+            if j < M:
+                assert abs(rt - central) < 1e-7 and abs(rT - central) < 1e-5
+            else:
+                assert abs(rt - 1) < 0.02 and abs(rT - 1) < 0.02
+            assert V[0] == 0.0 and abs(V[1]) < 1e-20
+
+
+def test_fd_viscous_heating_of_a_linear_shear():
+    # viscous heating (nu / cs^2) ((d_n u_n - d_t u_t)^2 + (d_t u_n + d_n u_t)^2) of eq. NSF-CHAR,
+    # exact for linear fields (every difference formula is exact and the Laplacians vanish)
+    stencil, tau = 17, TAUS[17]
+    cs2 = O.lattice(stencil)[0]
+    nu = (tau - 0.5) * cs2
+    nx, ny, g1, g2 = 40, 30, 2e-3, -3e-3
+    X, Y = W.grid(nx, ny)
+    o = O.Oracle(stencil, nx, ny, tau, ["cbc", "cbc", "cbc", "cbc"])
+    # u_x = g1 y, u_y = g2 x + g1 x: a shear plus a strain
+    o.init(np.ones_like(X), g1 * Y, (g2 + g1) * X, np.ones_like(X))
+    for side, sn in ((0, -1), (1, 1)):
+        # local frame of an x-side: u_n = sn u_x, u_t = u_y, d_n = sn d_x, d_t = d_y
+        dnun, dtut, dtun, dnut = 0.0, 0.0, sn * g1, sn * (g2 + g1)
+        ref = nu / cs2 * ((dnun - dtut) ** 2 + (dtun + dnut) ** 2)
+        for j in (1, 3):
+            V = o.visc_fd_probe(side, j, 10)
+            assert abs(V[3] / ref - 1) < 1e-9
+            assert abs(V[1]) < 1e-17 and abs(V[2]) < 1e-17
+
+
+@pytest.mark.parametrize("stencil", [17, 37])
+def test_fd_variant_uniform_flow(stencil):
+    # uniform flow stays uniform with the -FD viscous terms
+    tau = TAUS[stencil]
+    cs2 = O.lattice(stencil)[0]
+    nx, ny = 30, 24
+    u0 = 0.1 * math.sqrt(cs2)
+    o = O.Oracle(stencil, nx, ny, tau, ["cbc_relax"] * 4)
+    o.set_relax(-1, sigma=0.25, alpha=0.1, mach=0.1)
+    for s in range(4):
+        o.set_viscous(s, "fd")
+    o.init(*W.uniform_flow(nx, ny, ux=u0))
+    o.step(100)
+    r, ux, uy, T = o.macro()
+    assert max(np.abs(r - 1).max(), np.abs(ux - u0).max(), np.abs(uy).max(), np.abs(T - 1).max()) < 1e-13
