@@ -5,8 +5,9 @@
  * Method: Klass, Gabbana & Bartel, "Characteristic Boundary Condition for Thermal Lattice
  * Boltzmann Methods" (arXiv 2307.16766).
  *   - bulk: BGK lattice Boltzmann equation (Sec. 2, eq. lbe and eq. bgk) on the single-speed
- *     D2Q9 stencil (isothermal, 2nd-order equilibrium) or the multi-speed D2Q37 stencil
- *     (Appendix B, Tab. d2q37; 4th-order Hermite equilibrium, eq. feq-4);
+ *     D2Q9 stencil (isothermal, 2nd-order equilibrium) or the multi-speed D2Q17 (Tab. d2q17;
+ *     3rd-order Hermite equilibrium, eq. feq-3) and D2Q37 stencils (Tab. d2q37; 4th-order
+ *     Hermite equilibrium, eq. feq-4);
  *   - boundary: layerwise characteristic analysis on the M outer layers (Sec. 3.3), wave
  *     amplitudes of eq. thermal_WAV, incoming amplitudes by one of the four schemes of
  *     Tab. CBCs (eq. PNR, LODI-Relax, CBC-PNR, CBC-Relax), RK4 in time, equilibrium or NEEP
@@ -46,7 +47,7 @@ enum lbm_status {
     LBM_E_UNSUPPORTED = -5   /* valid but not supported combination */
 };
 
-enum lbm_stencil { LBM_D2Q9 = 9, LBM_D2Q37 = 37 };
+enum lbm_stencil { LBM_D2Q9 = 9, LBM_D2Q17 = 17, LBM_D2Q37 = 37 };
 
 /* Storage precision of the populations.  FP64 stores f - w_i in double.  FP32DEV stores the
  * deviation f - w_i from the lattice weight in float and runs the bulk update in float; the
@@ -60,14 +61,14 @@ enum lbm_bc {
     LBM_BC_PERIODIC = 0,
     LBM_BC_LODI = 1,        /* eq. thermal_LODI_macro_evo with eq. PNR */
     LBM_BC_LODI_RELAX = 2,  /* eq. thermal_LODI_macro_evo with eq. LODI-Relax */
-    LBM_BC_CBC = 3,         /* eq. thermal_CBC_macro_evo with eq. CBC-PNR (D2Q37 only) */
-    LBM_BC_CBC_RELAX = 4,   /* eq. thermal_CBC_macro_evo with eq. CBC-Relax (D2Q37 only) */
+    LBM_BC_CBC = 3,         /* eq. thermal_CBC_macro_evo with eq. CBC-PNR (thermal stencils) */
+    LBM_BC_CBC_RELAX = 4,   /* eq. thermal_CBC_macro_evo with eq. CBC-Relax (thermal stencils) */
     LBM_BC_ZG = 5,          /* zero-gradient copy of the adjacent bulk node, eq. zg-bc */
     LBM_BC_DIRICHLET = 6    /* equilibrium populations of a fixed profile (inlet) */
 };
 
 typedef struct lbm_config {
-    int stencil;     /* LBM_D2Q9 or LBM_D2Q37 */
+    int stencil;     /* LBM_D2Q9, LBM_D2Q17 or LBM_D2Q37 */
     int precision;   /* lbm_precision */
     int nx, ny;      /* nodes; non-periodic axes need >= 2M+3 nodes, periodic ones >= M+1 */
     double tau;      /* BGK relaxation time, > 1/2; nu = (tau - 1/2) cs^2 (Sec. 2) */
@@ -76,8 +77,8 @@ typedef struct lbm_config {
 
 /* Relaxation parameters of one characteristic side (eq. LODI-Relax / eq. CBC-Relax).  The
  * incoming acoustic amplitude receives  -alpha * T_x,i + K (P - P_inf) / (4 rho cs^2)
- * (D2Q37) or  -alpha * T_x,i + K (P - P_inf)  (D2Q9), with
- * K = sigma (1 - mach^2) c_inf / length, c_inf = sqrt(2 cs^2 T_inf) (D2Q37) or cs (D2Q9),
+ * (thermal stencils) or  -alpha * T_x,i + K (P - P_inf)  (D2Q9), with
+ * K = sigma (1 - mach^2) c_inf / length, c_inf = sqrt(2 cs^2 T_inf) (thermal) or cs (D2Q9),
  * P_inf = rho_inf cs^2 T_inf.  length <= 0 selects the domain extent normal to the side.
  * Sides without relaxation (LODI, CBC) ignore these values.  Defaults: all zero except
  * rho_inf = T_inf = 1. */
@@ -96,6 +97,15 @@ typedef struct lbm_relax {
  * bulk node x_f of the same row (post-collision, like every stored population).  Corner blocks
  * stay at equilibrium. */
 enum lbm_recon { LBM_RECON_EQUILIBRIUM = 0, LBM_RECON_NEEP = 1 };
+
+/* Viscous terms V of a CBC side (eq. NSF-CHAR).  MESO (default): from the non-equilibrium
+ * moments of the populations at x_f, x_f-1, x_f-2 (Sec. 3.3 "Evaluation of viscous terms", eq.
+ * LaplaceU and eq. LaplaceT), frozen at time t during the RK4 stages and shared by the M layers
+ * of a row.  FD: the -FD variant of Sec. 4.2 ("Treatment of viscous terms"): nu lap(u) and
+ * 2 nu lap(T) by second differences of the macroscopic values of each layer (the backward
+ * four-point formula on the outermost layer, central differences on inner layers and along the
+ * side) plus the viscous heating from first differences, evaluated at every RK4 stage. */
+enum lbm_visc { LBM_VISC_MESO = 0, LBM_VISC_FD = 1 };
 
 typedef struct lbm_ctx lbm_ctx;
 
@@ -119,6 +129,10 @@ int lbm_cbc_params(lbm_ctx* ctx, int side, const lbm_relax* p);
 /* Reconstruction mode (lbm_recon) of side 0..3, or of every characteristic side with side = -1;
  * NEEP on a non-characteristic side returns LBM_E_STATE.  Takes effect from the next lbm_step. */
 int lbm_reconstruction(lbm_ctx* ctx, int side, int mode);
+
+/* Viscous-term mode (lbm_visc) of side 0..3, or of every CBC side with side = -1; FD on a side
+ * that is not CBC or CBC_RELAX returns LBM_E_STATE.  Takes effect from the next lbm_step. */
+int lbm_viscous(lbm_ctx* ctx, int side, int mode);
 
 /* Fixed profile of a Dirichlet side: d_U is device FP64 [len][4] = (rho, u_x, u_y, T) per row
  * along the side (len = ny for x-sides, nx for y-sides).  Default: the initial fields on the

@@ -52,7 +52,16 @@ __device__ __forceinline__ void feq_vjp(const double* m, const double* lam, doub
     double C0[L::NG], C1[L::NG], D0[L::NG], C0t[L::NG], C0u[L::NG], C1t[L::NG], D0t[L::NG];
 #pragma unroll
     for (int g = 0; g < L::NG; ++g) {
-        if (L::thermal) {
+        if (L::order == 3) {
+            const double xi2 = L::c2g(g) / L::cs2;
+            C0[g] = 0.5 * (th * (xi2 - 2.0) - u2);
+            C1[g] = 0.5;
+            D0[g] = 1.0 + 0.5 * (th * (xi2 - 4.0) - u2);
+            C0t[g] = 0.5 * (xi2 - 2.0);
+            C0u[g] = -0.5;
+            C1t[g] = 0.0;
+            D0t[g] = 0.5 * (xi2 - 4.0);
+        } else if (L::thermal) {
             const double xi2 = L::c2g(g) / L::cs2;
             const double x4 = xi2 * xi2 - 8.0 * xi2 + 8.0;
             C0[g] = 0.5 * (th * (xi2 - 2.0) - u2) + 0.125 * u2 * u2 + 0.25 * th * u2 * (4.0 - xi2) + 0.125 * th * th * x4;
@@ -79,7 +88,16 @@ __device__ __forceinline__ void feq_vjp(const double* m, const double* lam, doub
         const double a2 = a * a;
         const double S = lam[p] + lam[p + L::NP], D = lam[p] - lam[p + L::NP];
         double E, O, Et, Ot, Eu, Ou, Ea, Oa;
-        if (L::thermal) {
+        if (L::order == 3) {
+            E = C0[g] + a2 * C1[g];
+            O = a * (D0[g] + a2 * (1.0 / 6.0));
+            Et = C0t[g];
+            Ot = a * D0t[g];
+            Eu = C0u[g];
+            Ou = -0.5 * a;
+            Ea = 2.0 * a * C1[g];
+            Oa = D0[g] + 0.5 * a2;
+        } else if (L::thermal) {
             E = C0[g] + a2 * (C1[g] + a2 * (1.0 / 24.0));
             O = a * (D0[g] + a2 * (1.0 / 6.0));
             Et = C0t[g] + a2 * C1t[g];
@@ -141,13 +159,14 @@ __device__ __forceinline__ double phi_dot(int i, const double* GM) {
 // VJP of char_rate (LODI and LODI-RELAX; the CBC variants are not differentiated).  Inputs as
 // char_rate, rb = adjoint of the rate; outputs the adjoints of U, dn, up, dw (side-local
 // components) and of K and alpha.  The wave directions are frozen at time t (no derivative).
-template <bool THERMAL>
+template <int Q>
 __device__ __forceinline__ void char_rate_vjp(const double* U, const double* dn, const double* up, const double* dw,
                                               const double* U0, int scheme, double K, double alpha, double Pinf,
                                               const double* rb, double* Ub, double* dnb, double* upb, double* dwb,
                                               double& Kb, double& alb) {
-    constexpr double cs2 = THERMAL ? Lat<37>::cs2 : Lat<9>::cs2;
-    constexpr double cs = THERMAL ? Lat<37>::cs : Lat<9>::cs;
+    constexpr bool THERMAL = Lat<Q>::thermal;
+    constexpr double cs2 = Lat<Q>::cs2;
+    constexpr double cs = Lat<Q>::cs;
     const bool relax = scheme == BC_LODI_RELAX;
     const double rho = U[0], u = U[1], v = U[2], T = U[3];
     const double ir = 1.0 / rho;
@@ -295,7 +314,7 @@ __device__ __forceinline__ void corner_rate_vjp(const CornerDev& c, const double
     rl[2] = rb[1] * tdx + rb[2] * tdy;
     rl[3] = rb[3];
     double Ub[4], dnb[4], upb[4], dwb[4], alb;
-    char_rate_vjp<Lat<Q>::thermal>(l0, dn, l0, l0, ln, c.relax ? BC_LODI_RELAX : BC_LODI, c.K, 0.0, c.Pinf, rl, Ub,
+    char_rate_vjp<Q>(l0, dn, l0, l0, ln, c.relax ? BC_LODI_RELAX : BC_LODI, c.K, 0.0, c.Pinf, rl, Ub,
                                    dnb, upb, dwb, Kb, alb);
     double a0[4], a1[4], a2[4];
 #pragma unroll
@@ -336,7 +355,6 @@ struct AdjArgs {
 template <int Q>
 __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk, int chunk) {
     constexpr int M = Lat<Q>::M, NR = 256 / M, MS = (M == 1) ? 2 : 1, H = 8, NN = NR * M;
-    constexpr bool TH = Lat<Q>::thermal;
     __shared__ double sY[4][NN * 4];            // stage inputs Y_0 = U_b^n, Y_1, Y_2, Y_3 (global components)
     __shared__ double sYb1[NN * 4];             // adjoint of U_b^{n+1}
     __shared__ double sG[NN * 4];               // adjoint of the stage input of the later stage
@@ -470,7 +488,7 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
             double U[4], dn[4], up[4], dw[4], U0[4];
             inputs(st, U, dn, up, dw, U0);
             double Ubl[4], dnbl[4], upbl[4], dwbl[4], Kb, alb;
-            char_rate_vjp<TH>(U, dn, up, dw, U0, sd.scheme, sd.K, sd.alpha, sd.Pinf, rb, Ubl, dnbl, upbl, dwbl, Kb, alb);
+            char_rate_vjp<Q>(U, dn, up, dw, U0, sd.scheme, sd.K, sd.alpha, sd.Pinf, rb, Ubl, dnbl, upbl, dwbl, Kb, alb);
             double Ubg[4], dnbg[4], upbg[4], dwbg[4];
             rate_to_global(sd, Ubl, Ubg);
             rate_to_global(sd, dnbl, dnbg);

@@ -31,6 +31,7 @@ enum { KIND_NONE = 0, KIND_CHAR = 1, KIND_ZG = 2, KIND_DIRICHLET = 3 };
 struct SideDev {
     int kind, scheme;
     int meso;                    // mesoscopic BC of a characteristic side: 0 equilibrium, 1 NEEP
+    int vfd;                     // viscous terms of a CBC side: 0 mesoscopic moments, 1 differences
     int nax, sn, Nn, Nt, r0, len, xf, tper;
     int blk0, nblk, rows;        // boundary work-groups of this side in k_step, rows per work-group
     int corner_lo, corner_hi;    // corners at row -1 / row len (non-periodic tangent), else -1
@@ -331,12 +332,13 @@ __global__ __launch_bounds__(256) void k_diag_final(const double* __restrict__ p
 // relaxation acting on the incoming acoustic wave, then -S^-1 Lbar (+ T + V for CBC variants).
 // up / dw: node values at the neighbouring rows (transverse central differences); U0: the
 // node's value at time t, which fixes the wave directions.
-template <bool THERMAL>
+template <int Q>
 __device__ __forceinline__ void char_rate(const double* U, const double* dn, const double* up, const double* dw,
                                           const double* V, const double* U0, int scheme, double K, double alpha,
                                           double Pinf, double* rate) {
-    constexpr double cs2 = THERMAL ? Lat<37>::cs2 : Lat<9>::cs2;
-    constexpr double cs = THERMAL ? Lat<37>::cs : Lat<9>::cs;
+    constexpr bool THERMAL = Lat<Q>::thermal;
+    constexpr double cs2 = Lat<Q>::cs2;
+    constexpr double cs = Lat<Q>::cs;
     const bool full = scheme == BC_CBC || scheme == BC_CBC_RELAX;
     const bool relax = scheme == BC_LODI_RELAX || scheme == BC_CBC_RELAX;
     const double rho = U[0], u = U[1], v = U[2], T = U[3];
@@ -477,7 +479,7 @@ __device__ __forceinline__ void corner_rate(const CornerDev& c, const double* Uc
     for (int k = 0; k < 4; ++k) dn[k] = (3.0 * l0[k] - 4.0 * l1[k] + l2[k]) * inv;
     const double zero[4] = {0, 0, 0, 0};
     double rl[4];
-    char_rate<Lat<Q>::thermal>(l0, dn, l0, l0, zero, ln, c.relax ? BC_LODI_RELAX : BC_LODI, c.K, 0.0, c.Pinf, rl);
+    char_rate<Q>(l0, dn, l0, l0, zero, ln, c.relax ? BC_LODI_RELAX : BC_LODI, c.K, 0.0, c.Pinf, rl);
     rate[0] = rl[0];
     rate[1] = rl[1] * c.ndx + rl[2] * tdx;
     rate[2] = rl[1] * c.ndy + rl[2] * tdy;
@@ -593,7 +595,7 @@ __device__ void char_chunk(const T* __restrict__ A, T* __restrict__ B, const Bnd
         }
     }
     // viscous terms of time level n (frozen during the RK stages)
-    if (full) {
+    if (full && !sd.vfd) {
         const double nu = (a.tau - 0.5) * Lat<Q>::cs2;
         for (int lr = tid; lr < NR; lr += blockDim.x) {
             const int r = r0 - 4 + lr;
@@ -693,23 +695,42 @@ __device__ void char_chunk(const T* __restrict__ A, T* __restrict__ B, const Bnd
                 }
                 to_local(sd, g, l);
             };
-            double U[4], dn[4], up[4], dw[4], U0[4], Vl[4] = {0, 0, 0, 0};
+            double U[4], dn[4], up[4], dw[4], U0[4], Vl[4] = {0, 0, 0, 0}, d2n[4] = {0, 0, 0, 0};
             val_n(j, U);
             if (j == M) {   // eq. FD-dx-bw
-                double b1[4], b2[4];
+                double b1[4], b2[4], b3[4];
                 val_n(M - 1, b1); val_n(M - 2, b2);
                 for (int m = 0; m < 4; ++m) dn[m] = 0.5 * (3.0 * U[m] - 4.0 * b1[m] + b2[m]);
+                if (M == 3 && full && sd.vfd) {   // backward second difference (Sec. 4.2)
+                    val_n(M - 3, b3);
+                    for (int m = 0; m < 4; ++m) d2n[m] = 2.0 * U[m] - 5.0 * b1[m] + 4.0 * b2[m] - b3[m];
+                }
             } else {        // eq. FD-dx-center
                 double p1[4], m1[4];
                 val_n(j + 1, p1); val_n(j - 1, m1);
-                for (int m = 0; m < 4; ++m) dn[m] = 0.5 * (p1[m] - m1[m]);
+                for (int m = 0; m < 4; ++m) { dn[m] = 0.5 * (p1[m] - m1[m]); d2n[m] = p1[m] - 2.0 * U[m] + m1[m]; }
             }
             val_t(r + 1, up);
             val_t(r - 1, dw);
             to_local(sd, &sY0[t * 4], U0);
-            if (full) for (int m = 0; m < 4; ++m) Vl[m] = sV[lr * 4 + m];
+            if (full && !sd.vfd) {
+                for (int m = 0; m < 4; ++m) Vl[m] = sV[lr * 4 + m];
+            } else if (full) {
+                // the -FD variant (Sec. 4.2, treatment of viscous terms): Laplacians of eq.
+                // NSF-CHAR by second differences of the stage values, heating from the first
+                // differences; c_p / Pr = 2
+                const double nu = (a.tau - 0.5) * Lat<Q>::cs2;
+                double lap[4];
+                for (int m = 1; m < 4; ++m) lap[m] = d2n[m] + up[m] - 2.0 * U[m] + dw[m];
+                Vl[1] = nu * lap[1];
+                Vl[2] = nu * lap[2];
+                if (TH) {
+                    const double sa = dn[1] - 0.5 * (up[2] - dw[2]), sb = 0.5 * (up[1] - dw[1]) + dn[2];
+                    Vl[3] = 2.0 * nu * lap[3] + nu * (1.0 / Lat<Q>::cs2) * (sa * sa + sb * sb);
+                }
+            }
             double rl[4], rg[4];
-            char_rate<TH>(U, dn, up, dw, Vl, U0, sd.scheme, sd.K, sd.alpha, sd.Pinf, rl);
+            char_rate<Q>(U, dn, up, dw, Vl, U0, sd.scheme, sd.K, sd.alpha, sd.Pinf, rl);
             rate_to_global(sd, rl, rg);
             for (int m = 0; m < 4; ++m) sK[t * 4 + m] = rg[m];
             if (r >= r0 && r < r1)

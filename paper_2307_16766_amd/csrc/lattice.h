@@ -2,6 +2,9 @@
 //
 // Stencils (Appendix B of Klass, Gabbana & Bartel, arXiv 2307.16766):
 //   D2Q9  : single speed, cs^2 = 1/3, 2nd-order isothermal equilibrium.
+//   D2Q17 : 7th-order Gauss-Hermite rule, max displacement 3, 3rd-order equilibrium (eq. feq-3);
+//           the weights are the closed forms in sqrt(193) of Tab. d2q17, cs^2 = 72 / (5 (25 +
+//           sqrt 193)) (the caption's expression is 1 / cs).
 //   D2Q37 : 9th-order Gauss-Hermite rule, max displacement 3, 4th-order equilibrium (eq. feq-4).
 // The D2Q37 weights are the full-precision solution of the isotropy conditions (the table of
 // Appendix B prints 14 digits, which leaks mass at the 1e-13 level per step); cs^2 is the real
@@ -19,7 +22,7 @@ namespace lbm {
 template <int Q> struct Lat;
 
 template <> struct Lat<9> {
-    static constexpr int Q = 9, NP = 4, M = 1, NG = 3;
+    static constexpr int Q = 9, NP = 4, M = 1, NG = 3, order = 2;
     static constexpr bool thermal = false;
     static constexpr double cs2 = 1.0 / 3.0;
     static constexpr double cs = 0.57735026918962576451;
@@ -33,8 +36,26 @@ template <> struct Lat<9> {
     __host__ __device__ static constexpr int c2g(int g) { constexpr int t[3] = {0, 1, 2}; return t[g]; }
 };
 
+template <> struct Lat<17> {
+    static constexpr int Q = 17, NP = 8, M = 3, NG = 5, order = 3;
+    static constexpr bool thermal = true;
+    static constexpr double cs2 = 0.37025186701833984971891509863238152;
+    static constexpr double cs = 0.60848325122252941903029945215239698;
+    __host__ __device__ static constexpr int pcx(int p) { constexpr int t[9] = {0, 1, 0, 1, -1, 2, -2, 3, 0}; return t[p]; }
+    __host__ __device__ static constexpr int pcy(int p) { constexpr int t[9] = {0, 0, 1, 1, 1, 2, 2, 0, 3}; return t[p]; }
+    // symmetry group: 0 (0,0), 1 (1,0), 2 (1,1), 3 (2,2), 4 (3,0)
+    __host__ __device__ static constexpr int grp(int p) { constexpr int t[9] = {0, 1, 1, 2, 2, 3, 3, 4, 4}; return t[p]; }
+    __host__ __device__ static constexpr double wg(int g) {
+        constexpr double t[5] = {0.40200514690911262594166439245907543, 0.11615486649778154387403545662591120,
+                                 0.033006353622986913949753825914721682, 7.9078602165918131237133240548163573e-05,
+                                 0.00025841454978746755955748610405009878};
+        return t[g];
+    }
+    __host__ __device__ static constexpr int c2g(int g) { constexpr int t[5] = {0, 1, 2, 8, 9}; return t[g]; }
+};
+
 template <> struct Lat<37> {
-    static constexpr int Q = 37, NP = 18, M = 3, NG = 8;
+    static constexpr int Q = 37, NP = 18, M = 3, NG = 8, order = 4;
     static constexpr bool thermal = true;
     static constexpr double cs2 = 0.69795332201968308823840905538932529;
     static constexpr double cs = 0.83543600713620375307803652819861195;
@@ -108,7 +129,8 @@ __device__ __forceinline__ void moments_dev(const R* d, R& rm1, R& ux, R& uy, R&
 // eq. feq-3 / feq-4 in the scaled variables xi = c/cs, u/cs (the printed (c^2 - 4) of the
 // (u.c)^2 (T-1) term reads (xi^2 - 6) there).  Split per opposite pair into
 //   H - 1 = E(a^2) + a O(a^2),  a = xi.u/cs,
-//   E = C0 + a^2 (C1 + a^2/24),  O = D0 + a^2/6   (D2Q37)
+//   E = C0 + a^2 (C1 + a^2/24),  O = D0 + a^2/6   (D2Q37, 4th order)
+//   E = C0 + a^2 / 2,            O = D0 + a^2/6   (D2Q17, 3rd order: no 4th-order terms)
 //   E = (a^2 - u^2)/2,  O = 1                    (D2Q9)
 template <int Q, typename R>
 __device__ __forceinline__ void feq_dev(R rm1, R ux, R uy, R th, R* fe) {
@@ -120,12 +142,17 @@ __device__ __forceinline__ void feq_dev(R rm1, R ux, R uy, R th, R* fe) {
     R C0[L::NG], C1[L::NG], D0[L::NG];
 #pragma unroll
     for (int g = 0; g < L::NG; ++g) {
-        if (L::thermal) {
+        if (L::order == 4) {
             const R xi2 = R(L::c2g(g) / L::cs2);
             C0[g] = R(0.5) * (th * (xi2 - R(2)) - u2)
                     + R(0.125) * u2 * u2 + R(0.25) * th * u2 * (R(4) - xi2)
                     + R(0.125) * th * th * (xi2 * xi2 - R(8) * xi2 + R(8));
             C1[g] = R(0.5) + R(0.25) * (th * (xi2 - R(6)) - u2);
+            D0[g] = R(1) + R(0.5) * (th * (xi2 - R(4)) - u2);
+        } else if (L::order == 3) {
+            const R xi2 = R(L::c2g(g) / L::cs2);
+            C0[g] = R(0.5) * (th * (xi2 - R(2)) - u2);
+            C1[g] = R(0.5);
             D0[g] = R(1) + R(0.5) * (th * (xi2 - R(4)) - u2);
         } else {
             C0[g] = R(-0.5) * u2;
@@ -140,8 +167,11 @@ __device__ __forceinline__ void feq_dev(R rm1, R ux, R uy, R th, R* fe) {
         const R a = (R(L::pcx(p)) * vx + R(L::pcy(p)) * vy) * ics;
         const R a2 = a * a;
         R E, O;
-        if (L::thermal) {
+        if (L::order == 4) {
             E = C0[g] + a2 * (C1[g] + a2 * R(1.0 / 24.0));
+            O = a * (D0[g] + a2 * R(1.0 / 6.0));
+        } else if (L::order == 3) {
+            E = C0[g] + a2 * C1[g];
             O = a * (D0[g] + a2 * R(1.0 / 6.0));
         } else {
             E = C0[g] + C1[g] * a2;

@@ -32,6 +32,7 @@ bool is_relax(int b) { return b == BC_LODI_RELAX || b == BC_CBC_RELAX; }
 bool is_full(int b) { return b == BC_CBC || b == BC_CBC_RELAX; }
 
 int stencil_M(int st) { return st == 9 ? 1 : 3; }
+double stencil_cs2(int st) { return st == 9 ? Lat<9>::cs2 : st == 17 ? Lat<17>::cs2 : Lat<37>::cs2; }
 int chunk_rows(int M) { return 256 / M - 8; }   // must match NR - 8 in char_chunk
 
 struct Layout {
@@ -46,7 +47,7 @@ struct Layout {
 
 int validate(const lbm_config* c, std::string& err) {
     if (!c) { err = "null config"; return LBM_E_ARG; }
-    if (c->stencil != 9 && c->stencil != 37) { err = "stencil must be LBM_D2Q9 or LBM_D2Q37"; return LBM_E_ARG; }
+    if (c->stencil != 9 && c->stencil != 17 && c->stencil != 37) { err = "stencil must be LBM_D2Q9, LBM_D2Q17 or LBM_D2Q37"; return LBM_E_ARG; }
     if (c->precision != LBM_FP64 && c->precision != LBM_FP32DEV) { err = "unknown precision"; return LBM_E_ARG; }
     if (!(c->tau > 0.5) || !std::isfinite(c->tau)) { err = "tau must be a finite value above 1/2"; return LBM_E_ARG; }
     for (int s = 0; s < 4; ++s)
@@ -70,7 +71,7 @@ int validate(const lbm_config* c, std::string& err) {
             }
     if (c->stencil == 9)
         for (int s = 0; s < 4; ++s)
-            if (is_full(c->bc[s])) { err = "CBC with viscous terms needs the heat-flux moment (D2Q37 only)"; return LBM_E_UNSUPPORTED; }
+            if (is_full(c->bc[s])) { err = "CBC with viscous terms needs a thermal stencil (D2Q17 or D2Q37)"; return LBM_E_UNSUPPORTED; }
     return LBM_OK;
 }
 
@@ -184,6 +185,7 @@ struct lbm_ctx {
     int nbnd = 0;
     lbm_relax relax[4];
     int meso[4] = {0, 0, 0, 0};   // mesoscopic BC per side (LBM_RECON_*)
+    int vfd[4] = {0, 0, 0, 0};    // viscous terms per CBC side (LBM_VISC_*)
     BulkArgs bulk;
     std::string err;
     // bulk kernel timing (measurement only)
@@ -218,8 +220,8 @@ BndArgs make_bnd(const lbm_ctx* c) {
     a.tau = g.tau;
     a.reg_cur = c->region[c->cur];
     a.reg_next = c->region[c->cur ^ 1];
-    const double cs2 = g.stencil == 9 ? Lat<9>::cs2 : Lat<37>::cs2;
-    const bool thermal = g.stencil == 37;
+    const double cs2 = stencil_cs2(g.stencil);
+    const bool thermal = g.stencil != 9;
     for (int s = 0; s < 4; ++s) {
         a.s[s] = c->L.s[s];
         const lbm_relax& p = c->relax[s];
@@ -228,6 +230,7 @@ BndArgs make_bnd(const lbm_ctx* c) {
         a.s[s].K = p.sigma * (1.0 - p.mach * p.mach) * cinf / len;
         a.s[s].alpha = p.alpha;
         a.s[s].meso = c->meso[s];
+        a.s[s].vfd = c->vfd[s];
         a.s[s].Pinf = p.rho_inf * cs2 * (thermal ? p.T_inf : 1.0);
     }
     for (int ci = 0; ci < 4; ++ci) {
@@ -302,13 +305,13 @@ template <int Q, typename T>
 int launch_init(lbm_ctx* c, const double* rho, const double* ux, const double* uy, const double* Tf) {
     const int n = c->cfg.nx * c->cfg.ny;
     hipLaunchKernelGGL((k_init_fields<Q, T>), dim3((n + 255) / 256), dim3(256), 0, c->stream, rho, ux, uy,
-                       Q == 37 ? Tf : nullptr, (T*)c->f[0], (T*)c->f[1], c->cfg.nx, n, c->L.pitch);
+                       Lat<Q>::thermal ? Tf : nullptr, (T*)c->f[0], (T*)c->f[1], c->cfg.nx, n, c->L.pitch);
     HIPCHK(c, hipGetLastError());
     const BndArgs a = make_bnd(c);
     int maxlen = 1;
     for (int s = 0; s < 4; ++s) maxlen = std::max(maxlen, c->L.s[s].len);
     hipLaunchKernelGGL((k_init_boundary<Q>), dim3((maxlen + 255) / 256, 4), dim3(256), 0, c->stream, a, rho, ux, uy,
-                       Q == 37 ? Tf : nullptr, c->inlet[0], c->inlet[1], c->inlet[2], c->inlet[3]);
+                       Lat<Q>::thermal ? Tf : nullptr, c->inlet[0], c->inlet[1], c->inlet[2], c->inlet[3]);
     HIPCHK(c, hipGetLastError());
     for (int s = 0; s < 4; ++s) {
         if (c->L.s[s].kind != KIND_DIRICHLET) continue;
@@ -464,10 +467,10 @@ int run_adjoint(lbm_ctx* c, const double* seed, double* grad, double* h_relax) {
     HIPCHK(c, hipMemcpyAsync(acc.data(), base + t.off_acc, acc.size() * 8, hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
     // dK / dsigma per side, as in make_bnd
-    const double cs2 = Q == 9 ? Lat<9>::cs2 : Lat<37>::cs2;
+    const double cs2 = Lat<Q>::cs2;
     for (int s = 0; s < 4; ++s) {
         const lbm_relax& p = c->relax[s];
-        const double cinf = Q == 37 ? std::sqrt(2.0 * cs2 * p.T_inf) : std::sqrt(cs2);
+        const double cinf = Lat<Q>::thermal ? std::sqrt(2.0 * cs2 * p.T_inf) : std::sqrt(cs2);
         const double len = p.length > 0 ? p.length : (double)L.s[s].Nn;
         const double kf = (1.0 - p.mach * p.mach) * cinf / len;
         double dK = 0.0, dA = 0.0;
@@ -485,6 +488,7 @@ int run_adjoint(lbm_ctx* c, const double* seed, double* grad, double* h_relax) {
 template <typename F>
 int dispatch(const lbm_ctx* c, F&& f) {
     if (c->cfg.stencil == 9) return c->cfg.precision == LBM_FP64 ? f.template operator()<9, double>() : f.template operator()<9, float>();
+    if (c->cfg.stencil == 17) return c->cfg.precision == LBM_FP64 ? f.template operator()<17, double>() : f.template operator()<17, float>();
     return c->cfg.precision == LBM_FP64 ? f.template operator()<37, double>() : f.template operator()<37, float>();
 }
 
@@ -509,7 +513,7 @@ int lbm_init(const lbm_config* cfg, void* d_workspace, size_t workspace_bytes, v
     const int v = validate(cfg, err);
     if (v != LBM_OK) return fail(nullptr, v, err);
     if (!d_workspace || ((uintptr_t)d_workspace % ALIGN) != 0) return fail(nullptr, LBM_E_ARG, "workspace must be non-NULL and 256-byte aligned");
-    if (!d_rho0 || !d_ux0 || !d_uy0 || (cfg->stencil == 37 && !d_T0)) return fail(nullptr, LBM_E_ARG, "initial field pointer is NULL");
+    if (!d_rho0 || !d_ux0 || !d_uy0 || (cfg->stencil != 9 && !d_T0)) return fail(nullptr, LBM_E_ARG, "initial field pointer is NULL");
     lbm_ctx* c = new (std::nothrow) lbm_ctx();
     if (!c) return fail(nullptr, LBM_E_ARG, "out of host memory");
     c->cfg = *cfg;
@@ -570,6 +574,21 @@ int lbm_reconstruction(lbm_ctx* c, int side, int mode) {
             continue;
         }
         c->meso[s] = mode;
+    }
+    return LBM_OK;
+}
+
+int lbm_viscous(lbm_ctx* c, int side, int mode) {
+    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+    if (side < -1 || side > 3 || (mode != LBM_VISC_MESO && mode != LBM_VISC_FD))
+        return fail(c, LBM_E_ARG, "bad side or viscous mode");
+    for (int s = 0; s < 4; ++s) {
+        if (side >= 0 && s != side) continue;
+        if (mode == LBM_VISC_FD && !is_full(c->cfg.bc[s])) {
+            if (side >= 0) return fail(c, LBM_E_STATE, "finite-difference viscous terms apply to CBC sides only");
+            continue;
+        }
+        c->vfd[s] = mode;
     }
     return LBM_OK;
 }
@@ -747,6 +766,12 @@ int lbm_lattice_info(int stencil, int* M, double* cs2, double* w, int* cxo, int*
         if (cs2) *cs2 = Lat<9>::cs2;
         for (int i = 0; i < 9; ++i) { if (w) w[i] = wt<9>(i); if (cxo) cxo[i] = cx<9>(i); if (cyo) cyo[i] = cy<9>(i); }
         return 9;
+    }
+    if (stencil == 17) {
+        if (M) *M = 3;
+        if (cs2) *cs2 = Lat<17>::cs2;
+        for (int i = 0; i < 17; ++i) { if (w) w[i] = wt<17>(i); if (cxo) cxo[i] = cx<17>(i); if (cyo) cyo[i] = cy<17>(i); }
+        return 17;
     }
     if (stencil == 37) {
         if (M) *M = 3;

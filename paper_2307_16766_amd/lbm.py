@@ -14,14 +14,15 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "liblbm_hip.so")
 
 LBM_OK, LBM_E_ARG, LBM_E_HIP, LBM_E_NONFINITE, LBM_E_STATE, LBM_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
-D2Q9, D2Q37 = 9, 37
+D2Q9, D2Q17, D2Q37 = 9, 17, 37
 FP64, FP32DEV = 0, 1
 BC = {"periodic": 0, "lodi": 1, "lodi_relax": 2, "cbc": 3, "cbc_relax": 4, "zg": 5, "dirichlet": 6}
 PRECISION = {"fp64": FP64, "fp32dev": FP32DEV}
 RECON = {"equilibrium": 0, "neep": 1}
+VISC = {"meso": 0, "fd": 1}
 
 # exported symbols, as declared in include/lbm.h
-SYMBOLS = ["lbm_workspace_bytes", "lbm_init", "lbm_cbc_params", "lbm_reconstruction", "lbm_dirichlet_profile", "lbm_step",
+SYMBOLS = ["lbm_workspace_bytes", "lbm_init", "lbm_cbc_params", "lbm_reconstruction", "lbm_viscous", "lbm_dirichlet_profile", "lbm_step",
            "lbm_macroscopic", "lbm_boundary_state", "lbm_diagnostics", "lbm_state_bytes", "lbm_save",
            "lbm_restore", "lbm_steps_done", "lbm_set_kernel_timing", "lbm_bulk_kernel_time",
            "lbm_tape_bytes", "lbm_record", "lbm_adjoint", "lbm_lattice_info", "lbm_last_error", "lbm_destroy"]
@@ -62,6 +63,7 @@ def load():
                            ctypes.POINTER(_vp)]
     L.lbm_cbc_params.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(Relax)]
     L.lbm_reconstruction.argtypes = [_vp, ctypes.c_int, ctypes.c_int]
+    L.lbm_viscous.argtypes = [_vp, ctypes.c_int, ctypes.c_int]
     L.lbm_dirichlet_profile.argtypes = [_vp, ctypes.c_int, _vp]
     L.lbm_step.argtypes = [_vp, ctypes.c_int]
     L.lbm_macroscopic.argtypes = [_vp, _vp, _vp, _vp, _vp]
@@ -144,7 +146,7 @@ class LBM:
         if isinstance(a, torch.Tensor):
             t = a.to(device=self.device, dtype=torch.float64)
         else:
-            arr = np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=np.float64), (self.ny, self.nx)))
+            arr = np.array(np.broadcast_to(np.asarray(a, dtype=np.float64), (self.ny, self.nx)))
             t = torch.from_numpy(arr).to(self.device)
         return t.contiguous()
 
@@ -171,6 +173,10 @@ class LBM:
     def set_reconstruction(self, side, mode):
         """Mesoscopic BC of characteristic side(s): "equilibrium" or "neep" (side -1: all)."""
         self._check(load().lbm_reconstruction(self.ctx, side, RECON[mode]))
+
+    def set_viscous(self, side, mode):
+        """Viscous terms of CBC side(s): "meso" (eq. LaplaceU / LaplaceT) or "fd" (side -1: all)."""
+        self._check(load().lbm_viscous(self.ctx, side, VISC[mode]))
 
     def set_inlet(self, side, U):
         t = self.torch.as_tensor(np.asarray(U, dtype=np.float64)).to(self.device).contiguous()

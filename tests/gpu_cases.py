@@ -11,6 +11,9 @@ from paper_2307_16766_amd import workloads as W
 CS2_37 = O.lattice(37)[0]
 CS_37 = math.sqrt(CS2_37)
 TAU_37 = 0.5 + W.NU_D2Q37 / CS2_37
+CS2_17 = O.lattice(17)[0]
+CS_17 = math.sqrt(CS2_17)
+TAU_17 = 0.9   # the D2Q17 runs of Sec. 4.1
 
 # Tolerances: relative L2 error bound on rho and T, and on u the same relative bound plus an
 # absolute rounding floor per step.  The floor is needed because u is compared where it is small
@@ -39,7 +42,7 @@ def rel_errors(gpu, ref):
 CHAR_BCS = ("lodi", "lodi_relax", "cbc", "cbc_relax")
 
 
-def make_pair(stencil, nx, ny, tau, bc, fields, precision, relax=None, inlet=None, recon=None):
+def make_pair(stencil, nx, ny, tau, bc, fields, precision, relax=None, inlet=None, recon=None, visc=None):
     from paper_2307_16766_amd import lbm
     g = lbm.LBM(stencil, nx, ny, tau, bc, fields, precision=precision)
     o = O.Oracle(stencil, nx, ny, tau, bc)
@@ -52,6 +55,11 @@ def make_pair(stencil, nx, ny, tau, bc, fields, precision, relax=None, inlet=Non
         for s, b in enumerate(bc):
             if b in CHAR_BCS:
                 o.set_recon(s, recon)
+    if visc is not None:
+        g.set_viscous(-1, visc)
+        for s, b in enumerate(bc):
+            if b in ("cbc", "cbc_relax"):
+                o.set_viscous(s, visc)
     if inlet is not None:
         side, U = inlet
         g.set_inlet(side, U)
@@ -88,11 +96,11 @@ def gpu_pops(g):
 
 
 def compare_run(name, stencil, nx, ny, tau, bc, fields, precision, steps, relax=None, inlet=None, tol=None,
-                recon=None, pops_tol=None):
+                recon=None, pops_tol=None, visc=None):
     """Step both implementations, comparing after every listed step count (and the populations
     of every node at the end, absolute tolerance pops_tol, when given).  Returns worst errors."""
-    log(f"[gpu-case] {name} {precision} {nx}x{ny} D2Q{stencil} bc={bc} recon={recon} steps={steps}")
-    g, o = make_pair(stencil, nx, ny, tau, bc, fields, precision, relax, inlet, recon)
+    log(f"[gpu-case] {name} {precision} {nx}x{ny} D2Q{stencil} bc={bc} recon={recon} visc={visc} steps={steps}")
+    g, o = make_pair(stencil, nx, ny, tau, bc, fields, precision, relax, inlet, recon, visc)
     worst = [0.0, 0.0, 0.0]
     done = 0
     for n in steps:

@@ -47,6 +47,9 @@ CASES = {
     # D2Q37, LODI outflow / LODI-RELAX inflow, periodic y
     "d2q37_periodic_y": dict(stencil=37, nx=64, ny=48, tau=TAU_37, bc=["lodi_relax", "lodi", "periodic", "periodic"],
                              steps=30, every=30, relax=dict(sigma=0.3, alpha=0.2, mach=0.05)),
+    # D2Q17 (3rd-order equilibrium), four LODI-RELAX sides with corners
+    "d2q17_corners": dict(stencil=17, nx=50, ny=46, tau=0.9, bc=["lodi_relax", "lodi", "lodi_relax", "lodi_relax"],
+                          steps=30, every=11, relax=dict(sigma=0.25, alpha=0.1, mach=0.05)),
     # D2Q9 isothermal, LODI-RELAX at both x sides, periodic y with two row chunks per side
     "d2q9_periodic_y": dict(stencil=9, nx=40, ny=300, tau=0.6, bc=["lodi_relax", "lodi_relax", "periodic", "periodic"],
                             steps=40, every=9, relax=dict(sigma=0.25, alpha=0.1, mach=0.05)),
