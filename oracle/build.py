@@ -7,13 +7,13 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "lbm_oracle.cpp")
+SRC = [os.path.join(HERE, "lbm_oracle.cpp"), os.path.join(HERE, "lbm3d_oracle.cpp")]
 LIB = os.path.join(HERE, "liblbm_oracle.so")
 
 
 def build(verbose: bool = False) -> str:
     cmd = ["g++", "-O3", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
-           "-ffp-contract=off", SRC, "-o", LIB + ".tmp"]
+           "-ffp-contract=off", *SRC, "-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

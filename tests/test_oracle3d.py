@@ -1,0 +1,304 @@
+"""Pins of the three-dimensional oracle (Appendix A; D3Q39, x-faces, periodic y and z) against
+Gauss-Hermite theory, closed forms of the linearised Navier-Stokes-Fourier equations in d = 3,
+invariants and the two-dimensional results."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle3d as O3
+
+CS2, W, CX, CY, CZ, M = O3.lattice()
+CS = math.sqrt(CS2)
+TAU = 0.9
+NU = (TAU - 0.5) * CS2
+GAMMA = 5.0 / 3.0   # c_p / c_v in d = 3 (Appendix A)
+
+
+def _gauss_moment(n):
+    return 0.0 if n % 2 else float(np.prod(np.arange(n - 1, 0, -2))) if n > 0 else 1.0
+
+
+def test_d3q39_rule_is_seventh_order():
+    # 39 velocities in the groups (0,0,0), (1,0,0), (1,1,1), (2,0,0), (2,2,0), (3,0,0); Gaussian
+    # moments for every monomial of degree <= 7, not for degree 8
+    assert len(W) == 39 and M == 3
+    groups = sorted({tuple(sorted((abs(a), abs(b), abs(c)))) for a, b, c in zip(CX, CY, CZ)})
+    assert groups == [(0, 0, 0), (0, 0, 1), (0, 0, 2), (0, 0, 3), (0, 2, 2), (1, 1, 1)]
+    xi = [CX / CS, CY / CS, CZ / CS]
+    for a, b, c in itertools.product(range(8), repeat=3):
+        if a + b + c > 7:
+            continue
+        m = np.sum(W * xi[0] ** a * xi[1] ** b * xi[2] ** c)
+        ref = _gauss_moment(a) * _gauss_moment(b) * _gauss_moment(c)
+        assert abs(m - ref) < 1e-12 * max(1.0, abs(ref)), (a, b, c, m, ref)
+    assert abs(W.sum() - 1.0) < 4e-16
+    dev8 = max(abs(np.sum(W * xi[0] ** a * xi[1] ** b * xi[2] ** (8 - a - b))
+                   - _gauss_moment(a) * _gauss_moment(b) * _gauss_moment(8 - a - b))
+               for a in range(9) for b in range(9 - a))
+    assert dev8 > 0.5
+    assert abs(CS2 - 2.0 / 3.0) < 1e-15   # the root of the remaining isotropy condition
+
+
+def _states(n, seed):
+    rng = np.random.default_rng(seed)
+    for _ in range(n):
+        yield 1 + 0.1 * rng.uniform(-1, 1), *(0.2 * rng.uniform(-1, 1, 3)), 1 + 0.1 * rng.uniform(-1, 1)
+
+
+def test_equilibrium_moments_third_order():
+    # eq. feq-3 in d = 3: exact rho, u, T (T = sum f |c-u|^2 / (3 rho cs^2)), zero third central
+    # moments, zero projection on the 4th-order Hermite polynomials
+    xi = [CX / CS, CY / CS, CZ / CS]
+    he4 = [xi[0] ** 4 - 6 * xi[0] ** 2 + 3, xi[0] ** 2 * xi[1] ** 2 - xi[0] ** 2 - xi[1] ** 2 + 1,
+           xi[0] * xi[1] * xi[2] ** 2 - xi[0] * xi[1], xi[0] ** 3 * xi[2] - 3 * xi[0] * xi[2]]
+    for rho, ux, uy, uz, T in _states(20, 3):
+        f = O3.feq(rho, ux, uy, uz, T)
+        d = [CX - ux, CY - uy, CZ - uz]
+        assert abs(f.sum() - rho) < 1e-14
+        for c, u in zip((CX, CY, CZ), (ux, uy, uz)):
+            assert abs((f * c).sum() - rho * u) < 1e-14
+        assert abs((f * (d[0] ** 2 + d[1] ** 2 + d[2] ** 2)).sum() - 3 * rho * CS2 * T) < 1e-14
+        for a, b, c in itertools.product(range(4), repeat=3):
+            if a + b + c == 3:
+                assert abs((f * d[0] ** a * d[1] ** b * d[2] ** c).sum()) < 1e-14
+        for h in he4:
+            assert abs((f * h).sum()) < 1e-13
+        assert np.allclose(O3.moments(f), [rho, ux, uy, uz, T], atol=1e-14, rtol=0)
+
+
+def test_collision_conserves():
+    rng = np.random.default_rng(5)
+    for _ in range(10):
+        f = W * (1 + 0.05 * rng.standard_normal(len(W)))
+        r, ux, uy, uz, T = O3.moments(f)
+        fs = f - (f - O3.feq(r, ux, uy, uz, T)) / TAU
+        for wgt in (np.ones_like(W), CX, CY, CZ, CX ** 2 + CY ** 2 + CZ ** 2):
+            assert abs((fs * wgt).sum() - (f * wgt).sum()) < 1e-14
+
+
+def _euler_jacobian_3d(U):
+    # primitive variables (rho, u_n, u_t1, u_t2, T) of the inviscid NSF system in d = 3 with
+    # P = rho cs^2 T and rho c_v D_t T = -rho T div u (c_v = 3/2), derived here independently:
+    # d_t U + A d_n U = 0 for variations along the normal
+    rho, un, _, _, T = U
+    A = np.diag([un] * 5)
+    A[0, 1] = rho
+    A[1, 0] = CS2 * T / rho
+    A[1, 4] = CS2
+    A[4, 1] = T / 1.5
+    return A
+
+
+def test_appendix_characteristic_matrices():
+    # Appendix A: A equals the Euler Jacobian, S S^-1 = I and S A S^-1 = Lambda with the
+    # acoustic speeds u_n -+ sqrt(gamma cs^2 T)
+    for U in ([1.0, 0.0, 0.0, 0.0, 1.0], [1.05, 0.07, -0.02, 0.03, 0.97], [0.9, -0.1, 0.05, 0.0, 1.1]):
+        A, S, Si, lam = O3.char_matrices(U)
+        assert np.abs(A - _euler_jacobian_3d(U)).max() < 1e-15
+        assert np.abs(S @ Si - np.eye(5)).max() < 1e-14
+        assert np.abs(S @ A @ Si - np.diag(lam)).max() < 1e-14
+        s = math.sqrt(GAMMA * CS2 * U[4])
+        assert np.allclose(lam, [U[1], U[1], U[1], U[1] - s, U[1] + s], atol=1e-15)
+
+
+def _fields(nx, ny, nz, fn):
+    X, Y, Z = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="xy")
+    X, Y, Z = (a.transpose(2, 0, 1) for a in (X, Y, Z))   # [nz][ny][nx]
+    return fn(X.astype(float), Y.astype(float), Z.astype(float))
+
+
+def test_periodic_conservation():
+    nx, ny, nz = 12, 10, 8
+    o = O3.Oracle3D(nx, ny, nz, TAU, ["periodic", "periodic"])
+    sm = lambda X, Y, Z, s: 0.02 * np.sin(2 * np.pi * (X / nx + 2 * Y / ny + Z / nz) + s)
+    o.init(*_fields(nx, ny, nz, lambda X, Y, Z: (1 + sm(X, Y, Z, 0.3), sm(X, Y, Z, 1.0), sm(X, Y, Z, 2.0),
+                                                 sm(X, Y, Z, 3.0), 1 + sm(X, Y, Z, 4.0))))
+    d0 = o.diag()
+    o.step(100)
+    d1 = o.diag()
+    for k in range(5):
+        assert abs(d1[k] - d0[k]) < 1e-13 * d0[0], k
+
+
+def test_sound_speed_adiabatic():
+    # planar pulse along x in a periodic box: halves travel at sqrt(gamma cs^2 T), gamma = 5/3
+    nx, ny, nz, t = 240, 4, 4, 60
+    c = math.sqrt(GAMMA * CS2)
+    amp, x0 = 1e-4, 80.0
+    g = _fields(nx, ny, nz, lambda X, Y, Z: amp * np.exp(-((X - x0) ** 2) / (2 * 5.0 ** 2)))
+    o = O3.Oracle3D(nx, ny, nz, TAU, ["periodic", "periodic"])
+    o.init(1 + g, c * g, 0.0, 0.0, 1 + (GAMMA - 1) * g)
+    o.step(t)
+    r = o.macro()[0][1, 1] - 1
+    lo, hi = int(x0 + 0.5 * c * t), int(x0 + 1.5 * c * t)
+    i = lo + int(np.argmax(r[lo:hi]))
+    xp = i + 0.5 * (r[i - 1] - r[i + 1]) / (r[i - 1] - 2 * r[i] + r[i + 1])
+    assert abs((xp - x0) / t - c) < 0.005 * c
+
+
+@pytest.mark.parametrize("mode", ["shear_y", "shear_z", "entropy"])
+def test_mode_decay(mode):
+    # shear modes decay as exp(-nu k^2 t), the entropy mode as exp(-alpha k^2 t) with
+    # alpha = kappa / (rho c_p) = nu (Pr = 1)
+    nx, ny, nz = 64, 4, 4
+    k = 2 * math.pi / nx
+    A = 1e-4
+    o = O3.Oracle3D(nx, ny, nz, TAU, ["periodic", "periodic"])
+    if mode == "shear_y":
+        o.init(*_fields(nx, ny, nz, lambda X, Y, Z: (1.0, 0.0, A * np.sin(k * X), 0.0, 1.0)))
+    elif mode == "shear_z":
+        o.init(*_fields(nx, ny, nz, lambda X, Y, Z: (1.0, 0.0, 0.0, A * np.sin(k * X), 1.0)))
+    else:
+        o.init(*_fields(nx, ny, nz, lambda X, Y, Z: (1 / (1 + A * np.sin(k * X)), 0.0, 0.0, 0.0, 1 + A * np.sin(k * X))))
+    xs = np.arange(nx)
+
+    def amp():
+        m = o.macro()
+        z = {"shear_y": m[2], "shear_z": m[3], "entropy": m[4] - m[4].mean()}[mode][1, 1]
+        return abs(np.sum(z * np.sin(k * xs)) * 2 / nx)
+
+    ts, logs = [], []
+    o.step(40)
+    for n in range(121):
+        ts.append(40 + 5 * n)
+        logs.append(math.log(amp()))
+        o.step(5)
+    rate = -np.polyfit(ts, logs, 1)[0]
+    assert abs(rate / (NU * k * k) - 1) < 0.01
+
+
+@pytest.mark.parametrize("comp", ["uy", "uz", "T"])
+def test_viscous_terms_match_laplacian(comp):
+    # V of the CBC schemes, evaluated as at x_f: nu lap(u_t) for a resolved shear wave along the
+    # normal, and (nu gamma / Pr) lap(T) = 5/3 nu lap(T) for an entropy wave (Appendix A)
+    nx, ny, nz = 64, 6, 6
+    k = 2 * math.pi / nx
+    A = 1e-3
+    o = O3.Oracle3D(nx, ny, nz, TAU, ["periodic", "periodic"])
+    if comp == "uy":
+        o.init(*_fields(nx, ny, nz, lambda X, Y, Z: (1.0, 0.0, A * np.sin(k * X), 0.0, 1.0)))
+    elif comp == "uz":
+        o.init(*_fields(nx, ny, nz, lambda X, Y, Z: (1.0, 0.0, 0.0, A * np.sin(k * X), 1.0)))
+    else:
+        o.init(*_fields(nx, ny, nz, lambda X, Y, Z: (1 / (1 + A * np.sin(k * X)), 0.0, 0.0, 0.0, 1 + A * np.sin(k * X))))
+    o.step(20)
+    m = o.macro()
+    x = 20
+    for g in (1, -1):
+        V = o.visc_probe(g, x, 2, 3)
+        if comp == "uy":
+            assert abs(V[2] / (-NU * k * k * m[2][3, 2, x]) - 1) < 0.01
+        elif comp == "uz":
+            assert abs(V[3] / (-NU * k * k * m[3][3, 2, x]) - 1) < 0.01
+        else:
+            Tw = m[4][3, 2] - m[4][3, 2].mean()
+            assert abs(V[4] / (-GAMMA * NU * k * k * Tw[x]) - 1) < 0.015
+
+
+@pytest.mark.parametrize("bc", ["lodi", "lodi_relax", "cbc", "cbc_relax", "zg"])
+def test_uniform_flow_stays_uniform(bc):
+    nx, ny, nz = 16, 6, 6
+    u0 = 0.1 * CS
+    o = O3.Oracle3D(nx, ny, nz, TAU, [bc, bc])
+    o.set_relax(-1, sigma=0.25, alpha=0.1, mach=0.1)
+    o.init(1.0, u0, 0.02, -0.01, 1.0)
+    o.step(60)
+    m = o.macro()
+    for c, ref in enumerate([1.0, u0, 0.02, -0.01, 1.0]):
+        assert np.abs(m[c] - ref).max() < 1e-13, c
+
+
+@pytest.mark.parametrize("bc", ["lodi_relax", "cbc_relax"])
+def test_symmetries(bc):
+    # a pulse centred in y and z of a square cross-section, at rest, between two faces of the
+    # same type: mirror symmetric in x, symmetric under y <-> z
+    nx, ny, nz = 20, 8, 8
+    o = O3.Oracle3D(nx, ny, nz, TAU, [bc, bc])
+    o.set_relax(-1, sigma=0.25, alpha=0.1, mach=0.05)
+    o.init(*_fields(nx, ny, nz, lambda X, Y, Z: (
+        1.0, 0.0, 0.0, 0.0,
+        1 + 1e-3 * np.exp(-((X - 9.5) ** 2 + (Y - 3.5) ** 2 + (Z - 3.5) ** 2) / 6.0))))
+    o.step(40)
+    r, ux, uy, uz, T = o.macro()
+    assert np.abs(r - r[:, :, ::-1]).max() < 1e-14
+    assert np.abs(ux + ux[:, :, ::-1]).max() < 1e-14
+    assert np.abs(r - r.transpose(1, 0, 2)).max() < 1e-14
+    assert np.abs(uy - uz.transpose(1, 0, 2)).max() < 1e-14
+    assert np.abs(T - T.transpose(1, 0, 2)).max() < 1e-14
+
+
+def test_reflection_lodi_vs_zero_gradient():
+    # a planar temperature pulse whose acoustic halves leave through the x-faces at normal
+    # incidence; the reflected wave is the difference to a periodic run on a grid three times as
+    # long (the paper's reference construction): zero-gradient reflects several per cent, the
+    # characteristic faces more than ten times less
+    nx, ny, nz = 240, 4, 4
+
+    def run(bc, n, off):
+        o = O3.Oracle3D(n, ny, nz, TAU, [bc, bc])
+        o.init(*_fields(n, ny, nz, lambda X, Y, Z: (
+            1.0, 0.0, 0.0, 0.0, 1 + 1e-3 * np.exp(-((X - off - 119.5) ** 2) / (2 * 10.0 ** 2)))))
+        o.step(40)
+        out = [o.macro()[1][1, 1, off + 60:off + 180].copy()]
+        for _ in range(16):   # the reflected fronts cross the window x in [60, 180) at t ~ 150..200
+            o.step(10)
+            out.append(o.macro()[1][1, 1, off + 60:off + 180].copy())
+        return out
+
+    ref = run("periodic", 3 * nx, nx)
+    inc = np.abs(ref[0]).max()   # both halves still inside the window at t = 40
+    R = {bc: max(np.abs(a - b).max() for a, b in zip(run(bc, nx, 0), ref)) / inc for bc in ("zg", "lodi", "cbc")}
+    assert 0.03 < R["zg"] < 0.12, R
+    assert R["lodi"] < R["zg"] / 10 and R["cbc"] < R["zg"] / 10, R
+
+
+def _transverse_jacobians(U):
+    # d_t U + B d_y U + C d_z U = 0: the y- and z-direction Jacobians of the inviscid NSF system
+    # in the local variables (rho, u_n, u_t1 = u_y, u_t2 = u_z, T), derived here independently
+    rho, un, v, w, T = U
+    B = np.diag([v] * 5)
+    B[0, 2] = rho
+    B[2, 0] = CS2 * T / rho
+    B[2, 4] = CS2
+    B[4, 2] = T / 1.5
+    C = np.diag([w] * 5)
+    C[0, 3] = rho
+    C[3, 0] = CS2 * T / rho
+    C[3, 4] = CS2
+    C[4, 3] = T / 1.5
+    return B, C
+
+
+@pytest.mark.parametrize("side", [0, 1])
+def test_transverse_terms_are_the_tangential_fluxes(side):
+    # the transverse terms of Appendix A equal -B d_y U - C d_z U for a smooth field (central
+    # differences: O(k^2) apart from the product-rule form)
+    nx, ny, nz = 14, 32, 32
+    ky, kz = 2 * math.pi / ny, 2 * math.pi / nz
+    A = 1e-3
+
+    def fields(X, Y, Z):
+        sy, sz = np.sin(ky * Y + 0.4), np.cos(kz * Z + 1.1)
+        return (1 + A * (sy + 0.5 * sz), 0.02 + A * (sz - sy), 0.03 + A * sy * sz + 2 * A * sz,
+                -0.01 + A * (0.7 * sy - sz), 1 + A * (sz + 0.3 * sy))
+
+    o = O3.Oracle3D(nx, ny, nz, TAU, ["cbc", "cbc"])
+    o.init(*_fields(nx, ny, nz, fields))
+    g = -1 if side == 0 else 1
+    for j, (y, z) in itertools.product((1, 3), [(3, 7), (20, 11), (9, 28)]):
+        x = (M - j) if side == 0 else (nx - 1 - M + j)
+        # analytic values and derivatives at the node, in the local frame (u_n = g u_x)
+        h = 1e-6
+        def loc(yy, zz):
+            r, ux, uy, uz, T = fields(0.0, yy, zz)
+            return np.array([r, g * ux, uy, uz, T])
+        U = loc(y, z)
+        dUy = (loc(y + h, z) - loc(y - h, z)) / (2 * h)
+        dUz = (loc(y, z + h) - loc(y, z - h)) / (2 * h)
+        B, C = _transverse_jacobians(U)
+        ref = -(B @ dUy + C @ dUz)
+        got = o.transverse_probe(side, j, y, z)
+        scale = np.abs(ref).max()
+        assert np.abs(got - ref).max() < 0.02 * scale, (side, j, y, z, got, ref)
