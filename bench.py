@@ -151,6 +151,45 @@ def run_adjoint_c4(steps=2000, every=50):
     }
 
 
+def run_3d(precision, steps, warmup, n=(512, 256, 256)):
+    """D3Q39 (Appendix A) on 512 x 256 x 256: LODI-RELAX and CBC-RELAX x-faces, periodic y and z,
+    a temperature blob in a uniform stream.  MLUPS over all nodes and the bulk kernel's fraction
+    of HBM bandwidth (2 q s bytes per bulk node per launch, HIP events on the stream)."""
+    import torch
+    from paper_2307_16766_amd import lbm3d
+    nx, ny, nz = n
+    dev = torch.device("cuda", 0)
+    z = torch.arange(nz, device=dev, dtype=torch.float64)[:, None, None]
+    y = torch.arange(ny, device=dev, dtype=torch.float64)[None, :, None]
+    x = torch.arange(nx, device=dev, dtype=torch.float64)[None, None, :]
+    one = torch.ones((nz, ny, nx), device=dev, dtype=torch.float64)
+    T = one + 1e-3 * torch.exp(-((x - nx / 2) ** 2 + (y - ny / 2) ** 2 + (z - nz / 2) ** 2) / (2 * 20.0 ** 2))
+    cs = math.sqrt(2.0 / 3.0)
+    g = lbm3d.LBM3D(nx, ny, nz, 0.9, ["lodi_relax", "cbc_relax"], [one, 0.05 * cs * one, 0 * one, 0 * one, T],
+                    precision=precision)
+    del one, T
+    g.set_relax(-1, sigma=0.25, alpha=0.05, mach=0.05)
+    g.step(warmup)
+    torch.cuda.synchronize()
+    g.set_kernel_timing(True)
+    t0 = time.perf_counter()
+    g.step(steps)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    ms, launches = g.bulk_kernel_time()
+    d = g.diagnostics(allow_nonfinite=True)
+    g.close()
+    del g
+    torch.cuda.empty_cache()
+    esz = 4 if precision == "fp32dev" else 8
+    bulk_bytes = 2 * 39 * esz * (nx - 6) * ny * nz
+    gbps = bulk_bytes / (ms / launches * 1e-3) / 1e9
+    return {"workload": f"D3Q39 {nx}x{ny}x{nz}, LODI-RELAX / CBC-RELAX x-faces, periodic y and z",
+            "precision": precision, "mlups": nx * ny * nz / dt / 1e6, "ms_per_step": dt * 1e3,
+            "bulk_kernel_ms": ms / launches, "bulk_GBps": gbps, "bulk_frac": gbps / HBM_PEAK_GBPS,
+            "finite": bool(d[7] == 0)}
+
+
 def algorithmic_bytes(esz):
     """Bytes one step kernel must move: bulk nodes read and write q populations; the outflow
     side's M layers are written (equilibrium reconstruction) and its x_f column re-pulled (q
@@ -230,6 +269,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=None)
     ap.add_argument("--copy-probe", type=float, default=None, metavar="GIB",
                     help="only run a plain copy of GIB gibibytes (counter calibration)")
@@ -262,6 +302,11 @@ def main():
         adj = run_adjoint_c4()
         eprint(f"[bench] adjoint: forward {adj['forward_ms']:.1f} ms, adjoint {adj['adjoint_ms']:.1f} ms, "
                f"ratio {adj['adjoint_over_forward']:.2f}")
+    d3 = None
+    if not args.no_3d:
+        eprint("[bench] D3Q39 512x256x256 (fp32dev, fp64)")
+        d3 = {p: run_3d(p, 50 if p == "fp32dev" else 25, 5) for p in ("fp32dev", "fp64")}
+        eprint(f"[bench] d3q39: fp32 {d3['fp32dev']['ms_per_step']:.3f} ms/step, fp64 {d3['fp64']['ms_per_step']:.3f}")
     cpu = None
     if not args.no_cpu_baseline:
         eprint("[bench] cpu baseline (oracle)")
@@ -302,6 +347,7 @@ def main():
             "bulk_frac": r64["bulk_frac"], "fp32dev_over_fp64": r32["mlups"] / r64["mlups"],
         },
         "adjoint": adj,
+        "d3q39": d3,
         "cpu_baseline": cpu,
         "finite": r32["finite"] and (r64 is None or r64["finite"]),
     }

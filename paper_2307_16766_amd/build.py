@@ -5,7 +5,7 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SRC = os.path.join(PKG, "csrc", "lbm.hip")
+SRC = [os.path.join(PKG, "csrc", "lbm.hip"), os.path.join(PKG, "csrc", "lbm3d.hip")]
 LIB = os.path.join(PKG, "liblbm_hip.so")
 
 HIPCC_FLAGS = [
@@ -19,7 +19,7 @@ HIPCC_FLAGS = [
 def build(verbose=False, extra=()):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     cmd = [hipcc, *HIPCC_FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc"),
-           SRC, "-o", LIB + ".tmp"]
+           *SRC, "-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -1,0 +1,545 @@
+// kernels3.h -- HIP kernels of the three-dimensional path (Appendix A): thermal BGK on D3Q39
+// with characteristic (LODI / CBC) boundaries on the two x-faces of a box periodic in y and z.
+//
+// Data layout in HBM: populations as deviations f - w_i, row-interleaved SoA f[z][y][i][x] (a
+// "row" is one (y, z) pair; its q planes are contiguous, the x pitch is padded to 64 elements).
+// Face state (FP64, two parity copies): U_b[M][rows][5], the bulk value of x_f [rows][5] and the
+// viscous moments of x_f, x_f - 1, x_f - 2 [3][rows][10] (CBC schemes); RK4 stage inputs and the
+// viscous terms are single buffers.
+//
+// One time step = bulk kernel (fused pull-stream + moments + BGK, HBM-bound) + face kernels:
+// k3_prep (strip and viscous moments of the new level from pulls of A, viscous terms of the old
+// level), four k3_stage launches (one per RK4 stage of the coupled face system) and k3_final (new
+// layer populations: equilibrium, eq. NEEP or zero gradient).  Separate launches replace the
+// halo recomputation of the two-dimensional boundary chunks: a face couples its rows in y and z,
+// so a chunk's halo would grow in two directions, while the face work is a small fraction of a
+// 3D step.
+#pragma once
+
+#include "lattice3.h"
+
+namespace lbm3 {
+
+enum { F3_PERIODIC = 0, F3_LODI = 1, F3_LODI_RELAX = 2, F3_CBC = 3, F3_CBC_RELAX = 4, F3_ZG = 5 };
+constexpr double CV = 1.5, GAMMA = 5.0 / 3.0;   // c_v = d/2, gamma = c_p / c_v in d = 3
+
+struct Face3 {
+    int scheme, meso, sn, xf;    // xf: bulk node next to the layers; layer j at xf + sn j
+    double K, alpha, Pinf;       // relaxation (eq. LODI-Relax / CBC-Relax)
+    unsigned long long off_ub, off_strip, off_vis;   // byte offsets inside one parity region
+};
+
+struct Args3 {
+    int nx, ny, nz, xper, rows;
+    unsigned long long pitch;
+    double omega, tau;
+    char* reg_cur;
+    char* reg_next;
+    double* Ya;   // RK4 stage inputs [2][M][rows][5]
+    double* Yb;
+    double* V;    // viscous terms of the old level [2][rows][5]
+    Face3 f[2];
+};
+
+__device__ __forceinline__ int wrap3(int v, int n) {
+    v = v < 0 ? v + n : v;
+    return v >= n ? v - n : v;
+}
+
+__device__ __forceinline__ unsigned long long pix3(unsigned long long pitch, int ny, int i, int x, int y, int z) {
+    return (((unsigned long long)z * ny + y) * L3::Q + i) * pitch + x;
+}
+
+__device__ __forceinline__ bool is_char3(int b) { return b >= F3_LODI && b <= F3_CBC_RELAX; }
+__device__ __forceinline__ bool is_full3(int b) { return b == F3_CBC || b == F3_CBC_RELAX; }
+
+// pull of one node at the new level (FP64), periodic in y and z, in x when configured
+template <typename T>
+__device__ __forceinline__ void pull3(const T* __restrict__ A, const Args3& a, int x, int y, int z, double* d) {
+#pragma unroll
+    for (int i = 0; i < L3::Q; ++i) {
+        int xs = x - cx3(i);
+        if (a.xper) xs = wrap3(xs, a.nx);
+        d[i] = (double)A[pix3(a.pitch, a.ny, i, xs, wrap3(y - cy3(i), a.ny), wrap3(z - cz3(i), a.nz))];
+    }
+}
+
+// ================================================================== bulk: fused stream + collide
+struct Bulk3 {
+    int nx, ny, nz, x0, x1;
+    unsigned long long pitch;
+    float omega_f;
+    double omega_d;
+};
+
+// One thread per node of a 256-node x-tile of one row (the tiles cover x = 0 .. nx - 1).  Loads
+// are issued source row by source row (49 (dy, dz) combinations, unrolled; only those holding
+// populations generate loads); stores are non-temporal.  The row of tile t is umulhi(t, magic),
+// magic = floor(2^32 / bpr) + 1 (exact while t * bpr < 2^32, checked on the host), and t itself
+// when bpr == 1.
+// XCD-aware order: work-group b runs on XCD b % 8, so tiles are assigned such that each XCD
+// walks one contiguous range of rows; a node's up to 25 source rows (y - c_y, z - c_z) then sit
+// in the L2 of the XCD that reads them instead of being fetched by several XCDs (measured on
+// 512 x 256 x 256: FP64 62 % -> 72 % of HBM bandwidth, FP32 unchanged within 1 %).
+// Boundary-layer nodes get a placeholder store: k3_final rewrites them after this launch, and
+// the placeholder keeps every plane's first and last cache line of a row written whole (partial-
+// line stores of a streaming kernel cost read-modify-write bandwidth: -8 % on 512 x 256 x 256).
+// Computing the layers' final populations here instead (after the face solve) was measured
+// slower: the FP64 reconstruction diverges inside bulk waves and doubles the register count.
+template <typename T, bool PX>
+__global__ __launch_bounds__(256, (sizeof(T) == 4 ? 3 : 2)) void k3_bulk(const T* __restrict__ A, T* __restrict__ B, Bulk3 g,
+                                                                          int bpr, unsigned magic) {
+    const unsigned t0 = blockIdx.x;
+    const unsigned per = gridDim.x >> 3;
+    const unsigned t = (gridDim.x & 7u) ? t0 : (t0 & 7u) * per + (t0 >> 3);
+    const unsigned row = bpr == 1 ? t : __umulhi(t, magic);
+    const int x = (int)(t - row * (unsigned)bpr) * 256 + (int)threadIdx.x;
+    const int z = (int)(row / (unsigned)g.ny), y = (int)(row - (unsigned)z * (unsigned)g.ny);
+    if (x < g.x0 || x > g.x1) {
+        if (x < g.nx) {
+            T* Bo = B + pix3(g.pitch, g.ny, 0, x, y, z);
+#pragma unroll
+            for (int i = 0; i < L3::Q; ++i) __builtin_nontemporal_store(T(0), Bo + (unsigned long long)i * g.pitch);
+        }
+        return;
+    }
+    T d[L3::Q];
+#pragma unroll
+    for (int dz = -L3::M; dz <= L3::M; ++dz) {
+#pragma unroll
+        for (int dy = -L3::M; dy <= L3::M; ++dy) {
+            bool any = false;
+#pragma unroll
+            for (int i = 0; i < L3::Q; ++i) any = any || (cy3(i) == dy && cz3(i) == dz);
+            if (!any) continue;
+            const int ys = wrap3(y - dy, g.ny), zs = wrap3(z - dz, g.nz);
+            const T* Ar = A + pix3(g.pitch, g.ny, 0, 0, ys, zs);
+#pragma unroll
+            for (int i = 0; i < L3::Q; ++i) {
+                if (cy3(i) != dy || cz3(i) != dz) continue;
+                int xs = x - cx3(i);
+                if (PX) xs = wrap3(xs, g.nx);
+                d[i] = Ar[(unsigned long long)i * g.pitch + xs];
+            }
+        }
+    }
+    const T omega = sizeof(T) == 4 ? (T)g.omega_f : (T)g.omega_d;
+    collide3_dev<T>(d, omega);
+    T* Bo = B + pix3(g.pitch, g.ny, 0, x, y, z);
+#pragma unroll
+    for (int i = 0; i < L3::Q; ++i) __builtin_nontemporal_store(d[i], Bo + (unsigned long long)i * g.pitch);
+}
+
+// ================================================================== initialisation
+template <typename T>
+__global__ __launch_bounds__(256) void k3_init(const double* __restrict__ rho, const double* __restrict__ ux,
+                                               const double* __restrict__ uy, const double* __restrict__ uz,
+                                               const double* __restrict__ Tf, T* __restrict__ A, T* __restrict__ B,
+                                               int nx, int ny, long long n, unsigned long long pitch) {
+    const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (id >= n) return;
+    const int x = (int)(id % nx);
+    const long long r = id / nx;
+    const int y = (int)(r % ny), z = (int)(r / ny);
+    double fe[L3::Q];
+    feq3_dev<double>(rho[id] - 1.0, ux[id], uy[id], uz[id], Tf[id] - 1.0, fe);
+#pragma unroll
+    for (int i = 0; i < L3::Q; ++i) {
+        A[pix3(pitch, ny, i, x, y, z)] = (T)fe[i];
+        B[pix3(pitch, ny, i, x, y, z)] = (T)fe[i];
+    }
+}
+
+// Face state arrays are component-major (structure of arrays over the rows): U_b and the stage
+// buffers [M][5][rows], the strip [5][rows], the viscous moments [3][10][rows], V [5][rows], so
+// that consecutive threads (consecutive rows) read consecutive doubles.
+__device__ __forceinline__ size_t iub(int rows, int j, int m, int r) { return ((size_t)j * 5 + m) * rows + r; }
+__device__ __forceinline__ size_t ivis(int rows, int k, int c, int r) { return ((size_t)k * 10 + c) * rows + r; }
+
+// face state at time 0 from the initial fields (both parities); an equilibrium state has no
+// viscous stress and no heat flux
+__global__ __launch_bounds__(256) void k3_init_faces(Args3 a, const double* __restrict__ rho, const double* __restrict__ ux,
+                                                     const double* __restrict__ uy, const double* __restrict__ uz,
+                                                     const double* __restrict__ Tf) {
+    const int s = blockIdx.y;
+    const Face3& fc = a.f[s];
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (!is_char3(fc.scheme) || r >= a.rows) return;
+    const int y = r % a.ny, z = r / a.ny;
+    auto field = [&](int x, double* u5) {
+        const size_t id = ((size_t)z * a.ny + y) * a.nx + x;
+        u5[0] = rho[id]; u5[1] = ux[id]; u5[2] = uy[id]; u5[3] = uz[id]; u5[4] = Tf[id];
+    };
+    for (int p = 0; p < 2; ++p) {
+        char* reg = p == 0 ? a.reg_cur : a.reg_next;
+        double* ub = (double*)(reg + fc.off_ub);
+        double* st = (double*)(reg + fc.off_strip);
+        double u5[5];
+        for (int j = 1; j <= L3::M; ++j) {
+            field(fc.xf + fc.sn * j, u5);
+            for (int m = 0; m < 5; ++m) ub[iub(a.rows, j - 1, m, r)] = u5[m];
+        }
+        field(fc.xf, u5);
+        for (int m = 0; m < 5; ++m) st[(size_t)m * a.rows + r] = u5[m];
+        if (is_full3(fc.scheme)) {
+            double* vis = (double*)(reg + fc.off_vis);
+            for (int k = 0; k < 3; ++k) {
+                field(fc.xf - fc.sn * k, u5);
+                for (int c = 0; c < 10; ++c) vis[ivis(a.rows, k, c, r)] = c == 0 ? u5[0] : 0.0;
+            }
+        }
+    }
+}
+
+// ================================================================== face: viscous data
+// (rho, Pi'_nn, Pi'_n1, Pi'_n2, Pi'_11, Pi'_12, Pi'_22, q_n, q_1, q_2) in the face frame, from the
+// pre-collision populations: Pi' = -(1 - 1/(2 tau)) sum c c (f - f^eq),
+// q = (1 - 1/(2 tau)) 1/2 sum f |c - u|^2 (c - u)
+__device__ __forceinline__ void visc_moments3(int sn, const double* d, double tau, double* o) {
+    double rm1, u, v, w, th;
+    moments3_dev<double>(d, rm1, u, v, w, th);
+    double fe[L3::Q];
+    feq3_dev<double>(rm1, u, v, w, th, fe);
+    const double fac = 1.0 - 0.5 / tau;
+    double pxx = 0, pxy = 0, pxz = 0, pyy = 0, pyz = 0, pzz = 0, qx = 0, qy = 0, qz = 0;
+#pragma unroll
+    for (int i = 0; i < L3::Q; ++i) {
+        const double c0 = cx3(i), c1 = cy3(i), c2 = cz3(i);
+        const double fn = d[i] - fe[i];
+        pxx -= c0 * c0 * fn; pxy -= c0 * c1 * fn; pxz -= c0 * c2 * fn;
+        pyy -= c1 * c1 * fn; pyz -= c1 * c2 * fn; pzz -= c2 * c2 * fn;
+        const double ex = c0 - u, ey = c1 - v, ez = c2 - w;
+        const double e = (wt3(i) + d[i]) * (ex * ex + ey * ey + ez * ez);
+        qx += e * ex; qy += e * ey; qz += e * ez;
+    }
+    o[0] = 1.0 + rm1;
+    o[1] = fac * pxx; o[2] = sn * fac * pxy; o[3] = sn * fac * pxz;
+    o[4] = fac * pyy; o[5] = fac * pyz; o[6] = fac * pzz;
+    o[7] = sn * 0.5 * fac * qx; o[8] = 0.5 * fac * qy; o[9] = 0.5 * fac * qz;
+}
+
+// Three threads per face row, one per node x_f - sn k (k = 0, 1, 2): consecutive threads pull
+// neighbouring x of the same row, so each load instruction touches a third of the cache lines
+// that one thread per row would.  New level: moments of x_f (the strip) and, for the CBC
+// schemes, the viscous moments of the three nodes, from the pulls of A.  Old level (CBC
+// schemes, thread k = 0): the viscous terms V (eq. NSF-CHAR, Appendix A), frozen during the RK4
+// stages -- div Pi' / rho and (-div q + Pi':Pi' / (2 rho nu)) / (rho c_v cs^2), normal derivatives
+// one-sided over x_f, x_f - 1, x_f - 2 (eq. FD-dx-bw), tangential ones central in y and z
+// (eq. FD-dx-center).
+template <typename T>
+__global__ __launch_bounds__(256) void k3_prep(const T* __restrict__ A, Args3 a) {
+    const int s = blockIdx.y;
+    const Face3& fc = a.f[s];
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (!is_char3(fc.scheme) || t >= 3 * a.rows) return;
+    const int r = t / 3, k = t - 3 * r;
+    const int y = r % a.ny, z = r / a.ny;
+    const bool full = is_full3(fc.scheme);
+    if (!full && k > 0) return;
+    double d[L3::Q];
+    pull3<T>(A, a, fc.xf - fc.sn * k, y, z, d);
+    if (k == 0) {
+        double rm1, u, v, w, th;
+        moments3_dev<double>(d, rm1, u, v, w, th);
+        double* stn = (double*)(a.reg_next + fc.off_strip);
+        const double o[5] = {1.0 + rm1, u, v, w, 1.0 + th};
+        for (int m = 0; m < 5; ++m) stn[(size_t)m * a.rows + r] = o[m];
+    }
+    if (!full) return;
+    {
+        double o[10];
+        visc_moments3(fc.sn, d, a.tau, o);
+        double* visn = (double*)(a.reg_next + fc.off_vis);
+        for (int c = 0; c < 10; ++c) visn[ivis(a.rows, k, c, r)] = o[c];
+    }
+    if (k != 0) return;
+    const double* vis = (const double*)(a.reg_cur + fc.off_vis);
+    auto at = [&](int kk, int yy, int zz, int c) {
+        return vis[ivis(a.rows, kk, c, wrap3(zz, a.nz) * a.ny + wrap3(yy, a.ny))];
+    };
+    auto dn = [&](int c) { return 0.5 * (3.0 * at(0, y, z, c) - 4.0 * at(1, y, z, c) + at(2, y, z, c)); };
+    auto d1 = [&](int c) { return 0.5 * (at(0, y + 1, z, c) - at(0, y - 1, z, c)); };
+    auto d2 = [&](int c) { return 0.5 * (at(0, y, z + 1, c) - at(0, y, z - 1, c)); };
+    double p[10];
+    for (int c = 0; c < 10; ++c) p[c] = at(0, y, z, c);
+    const double rho = p[0];
+    const double nu = (a.tau - 0.5) * L3::cs2;
+    const double pp = p[1] * p[1] + p[4] * p[4] + p[6] * p[6] + 2.0 * (p[2] * p[2] + p[3] * p[3] + p[5] * p[5]);
+    double* V = a.V + (size_t)s * 5 * a.rows;
+    V[r] = 0.0;
+    V[(size_t)1 * a.rows + r] = (dn(1) + d1(2) + d2(3)) / rho;
+    V[(size_t)2 * a.rows + r] = (dn(2) + d1(4) + d2(5)) / rho;
+    V[(size_t)3 * a.rows + r] = (dn(3) + d1(5) + d2(6)) / rho;
+    V[(size_t)4 * a.rows + r] = (-(dn(7) + d1(8) + d2(9)) + pp / (2.0 * rho * nu)) / (rho * CV * L3::cs2);
+}
+
+// ================================================================== face: characteristic rate
+// dU/dt in the face frame (rho, u_n, u_t1, u_t2, T) of one layer node (Appendix A): amplitudes
+// L = Lambda S dU/dn, incoming ones by scheme (Tab. CBCs; relaxation on the incoming acoustic
+// wave with the acoustic rows' pressure coefficient 1/(5 rho cs^2)), then -S^-1 Lbar (+ T + V
+// for the CBC schemes).  yp/ym, zp/zm: the node's neighbours in y and z (same layer); U0: the
+// node at time t, which fixes the wave directions.
+__device__ __forceinline__ void char_rate3(const double* U, const double* dn, const double* yp, const double* ym,
+                                           const double* zp, const double* zm, const double* V, const double* U0,
+                                           int scheme, double K, double alpha, double Pinf, double* rate) {
+    constexpr double cs2 = L3::cs2;
+    const bool full = is_full3(scheme);
+    const bool relax = scheme == F3_LODI_RELAX || scheme == F3_CBC_RELAX;
+    const double rho = U[0], un = U[1], v = U[2], w = U[3], T = U[4];
+    const double ir = 1.0 / rho;
+    auto h = [](double a, double b) { return 0.5 * (a - b); };
+    // transverse terms (Appendix A), central differences in y and z
+    double Tt[5];
+    Tt[0] = -h(yp[0] * yp[2], ym[0] * ym[2]) - h(zp[0] * zp[3], zm[0] * zm[3]);
+    Tt[1] = -(v * h(yp[1], ym[1]) + w * h(zp[1], zm[1]));
+    Tt[2] = -cs2 * ir * h(yp[0] * yp[4], ym[0] * ym[4]) - (v * h(yp[2], ym[2]) + w * h(zp[2], zm[2]));
+    Tt[3] = -cs2 * ir * h(zp[0] * zp[4], zm[0] * zm[4]) - (v * h(yp[3], ym[3]) + w * h(zp[3], zm[3]));
+    Tt[4] = -(T * (1.0 / CV)) * (h(yp[2], ym[2]) + h(zp[3], zm[3])) - (v * h(yp[4], ym[4]) + w * h(zp[4], zm[4]));
+    const double er = T * ir;                          // T~ / (rho cs^2)
+    const double r15 = sqrt(T * (1.0 / (15.0 * cs2)));
+    auto Sx = [&](const double* x, double* o) {
+        o[0] = -0.4 * er * x[0] + 0.6 * x[4];
+        o[1] = x[2];
+        o[2] = x[3];
+        o[3] = 0.2 * er * x[0] - r15 * x[1] + 0.2 * x[4];
+        o[4] = 0.2 * er * x[0] + r15 * x[1] + 0.2 * x[4];
+    };
+    const double s = sqrt(GAMMA * cs2 * T), s0 = sqrt(GAMMA * cs2 * U0[4]), u0 = U0[1];
+    double Sd[5], ST[5];
+    Sx(dn, Sd);
+    Sx(Tt, ST);
+    const double lam[5] = {un, un, un, un - s, un + s};
+    const double lam0[5] = {u0, u0, u0, u0 - s0, u0 + s0};
+    double in[5] = {0, 0, 0, 0, 0};
+    if (full) {
+        double TV[5], STV[5];
+        for (int m = 0; m < 5; ++m) TV[m] = Tt[m] + V[m];
+        Sx(TV, STV);
+        for (int m = 0; m < 5; ++m) in[m] = STV[m];
+    }
+    if (relax) {
+        const double pr = K * (rho * cs2 * T - Pinf) * ir * (1.0 / (5.0 * cs2));
+        in[3] += pr - alpha * ST[3];
+        in[4] += pr - alpha * ST[4];
+    }
+    double Bv[5];
+    for (int m = 0; m < 5; ++m) Bv[m] = lam0[m] >= 0.0 ? lam[m] * Sd[m] : in[m];
+    const double rT = rho / T, q15 = sqrt(15.0 * cs2 / (4.0 * T));
+    rate[0] = rT * Bv[0] - 1.5 * rT * (Bv[3] + Bv[4]);
+    rate[1] = q15 * (Bv[3] - Bv[4]);
+    rate[2] = -Bv[1];
+    rate[3] = -Bv[2];
+    rate[4] = -(Bv[0] + Bv[3] + Bv[4]);
+    if (full)
+        for (int m = 0; m < 5; ++m) rate[m] += Tt[m] + V[m];
+}
+
+// One RK4 stage of the coupled face system, one thread per layer node (face s, layer j, row r;
+// consecutive threads take consecutive rows).  Stage st reads its inputs Y_st (st = 0: U_b^n)
+// and writes Y_{st+1} = U_b^n + a_{st+1} K_st into the other stage buffer and the running sum
+// U_b^{n+1} += b_st K_st / 6 into the next parity region.  Bulk values at stage time
+// t + theta: (1 - theta) strip^n + theta strip^{n+1}.
+__global__ __launch_bounds__(256) void k3_stage(Args3 a, int st) {
+    const int s = blockIdx.y;
+    const Face3& fc = a.f[s];
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (!is_char3(fc.scheme) || t >= L3::M * a.rows) return;
+    const int jj = t / a.rows, r = t - jj * a.rows, j = jj + 1;
+    const int y = r % a.ny, z = r / a.ny;
+    const int R = a.rows;
+    const double thv[4] = {0.0, 0.5, 0.5, 1.0}, bst[4] = {1.0, 2.0, 2.0, 1.0};
+    const double th = thv[st];
+    const double* ub = (const double*)(a.reg_cur + fc.off_ub);
+    double* ubn = (double*)(a.reg_next + fc.off_ub);
+    const size_t fo = (size_t)s * L3::M * 5 * R;   // this face's part of the stage buffers
+    const double* Ys = st == 0 ? ub : (st == 2 ? a.Yb + fo : a.Ya + fo);
+    double* Yd = st == 0 ? a.Ya + fo : (st == 1 ? a.Yb + fo : (st == 2 ? a.Ya + fo : nullptr));
+    const double* sc = (const double*)(a.reg_cur + fc.off_strip);
+    const double* sx = (const double*)(a.reg_next + fc.off_strip);
+    auto loc = [&](const double* g, double* l) { l[0] = g[0]; l[1] = fc.sn * g[1]; l[2] = g[2]; l[3] = g[3]; l[4] = g[4]; };
+    auto val_n = [&](int k, double* l) {   // outward index k at this row (k = 0: x_f)
+        double g[5];
+        if (k >= 1) {
+            for (int m = 0; m < 5; ++m) g[m] = Ys[iub(R, k - 1, m, r)];
+        } else {
+            for (int m = 0; m < 5; ++m) g[m] = (1.0 - th) * sc[(size_t)m * R + r] + th * sx[(size_t)m * R + r];
+        }
+        loc(g, l);
+    };
+    auto val_t = [&](int yy, int zz, double* l) {
+        const int rr = wrap3(zz, a.nz) * a.ny + wrap3(yy, a.ny);
+        double g[5];
+        for (int m = 0; m < 5; ++m) g[m] = Ys[iub(R, jj, m, rr)];
+        loc(g, l);
+    };
+    double U[5], dn[5], yp[5], ym[5], zp[5], zm[5], U0[5];
+    val_n(j, U);
+    if (j == L3::M) {   // eq. FD-dx-bw
+        double b1[5], b2[5];
+        val_n(j - 1, b1); val_n(j - 2, b2);
+        for (int m = 0; m < 5; ++m) dn[m] = 0.5 * (3.0 * U[m] - 4.0 * b1[m] + b2[m]);
+    } else {            // eq. FD-dx-center
+        double p1[5], m1[5];
+        val_n(j + 1, p1); val_n(j - 1, m1);
+        for (int m = 0; m < 5; ++m) dn[m] = 0.5 * (p1[m] - m1[m]);
+    }
+    val_t(y + 1, z, yp); val_t(y - 1, z, ym); val_t(y, z + 1, zp); val_t(y, z - 1, zm);
+    double g0[5];
+    for (int m = 0; m < 5; ++m) g0[m] = ub[iub(R, jj, m, r)];
+    loc(g0, U0);
+    double Vl[5] = {0, 0, 0, 0, 0};
+    if (is_full3(fc.scheme))   // already in the face frame
+        for (int m = 0; m < 5; ++m) Vl[m] = a.V[((size_t)s * 5 + m) * R + r];
+    double rl[5];
+    char_rate3(U, dn, yp, ym, zp, zm, Vl, U0, fc.scheme, fc.K, fc.alpha, fc.Pinf, rl);
+    rl[1] *= fc.sn;   // back to global components
+    for (int m = 0; m < 5; ++m) {
+        const size_t o = iub(R, jj, m, r);
+        const double base = st == 0 ? g0[m] : ubn[o];
+        ubn[o] = base + bst[st] * (1.0 / 6.0) * rl[m];
+        if (Yd) Yd[o] = g0[m] + thv[st + 1] * rl[m];
+    }
+}
+
+// New layer populations, three threads per face row (one per layer; neighbouring x of the same
+// row, so the stores of a plane cover contiguous bytes): the equilibrium of U_b^{n+1}, plus with
+// NEEP (eq. NEEP) the post-collision non-equilibrium part of x_f; zero-gradient faces copy x_f
+// (eq. zg-bc) from the new bulk populations in B.
+template <typename T>
+__global__ __launch_bounds__(256) void k3_final(const T* __restrict__ A, T* __restrict__ B, Args3 a) {
+    const int s = blockIdx.y;
+    const Face3& fc = a.f[s];
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (fc.scheme == F3_PERIODIC || t >= L3::M * a.rows) return;
+    const int r = t / L3::M, jj = t - L3::M * r;
+    const int y = r % a.ny, z = r / a.ny, x = fc.xf + fc.sn * (jj + 1);
+    if (fc.scheme == F3_ZG) {
+#pragma unroll
+        for (int i = 0; i < L3::Q; ++i) B[pix3(a.pitch, a.ny, i, x, y, z)] = B[pix3(a.pitch, a.ny, i, fc.xf, y, z)];
+        return;
+    }
+    const double* ubn = (const double*)(a.reg_next + fc.off_ub);
+    double u5[5];
+    for (int m = 0; m < 5; ++m) u5[m] = ubn[iub(a.rows, jj, m, r)];
+    double fe[L3::Q];
+    feq3_dev<double>(u5[0] - 1.0, u5[1], u5[2], u5[3], u5[4] - 1.0, fe);
+    if (fc.meso == 1) {
+        double d[L3::Q], fx[L3::Q];
+        pull3<T>(A, a, fc.xf, y, z, d);
+        double rm1, u, v, w, th;
+        moments3_dev<double>(d, rm1, u, v, w, th);
+        feq3_dev<double>(rm1, u, v, w, th, fx);
+        const double c = 1.0 - a.omega;
+#pragma unroll
+        for (int i = 0; i < L3::Q; ++i) fe[i] += c * (d[i] - fx[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < L3::Q; ++i) B[pix3(a.pitch, a.ny, i, x, y, z)] = (T)fe[i];
+}
+
+// ================================================================== output and diagnostics
+template <typename T>
+__global__ __launch_bounds__(256) void k3_macro(const T* __restrict__ A, int nx, int ny, long long n, unsigned long long pitch,
+                                                double* __restrict__ rho, double* __restrict__ ux, double* __restrict__ uy,
+                                                double* __restrict__ uz, double* __restrict__ Tf) {
+    const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (id >= n) return;
+    const int x = (int)(id % nx);
+    const long long rr = id / nx;
+    const int y = (int)(rr % ny), z = (int)(rr / ny);
+    double d[L3::Q];
+#pragma unroll
+    for (int i = 0; i < L3::Q; ++i) d[i] = (double)A[pix3(pitch, ny, i, x, y, z)];
+    double rm1, u, v, w, th;
+    moments3_dev<double>(d, rm1, u, v, w, th);
+    rho[id] = 1.0 + rm1; ux[id] = u; uy[id] = v; uz[id] = w; Tf[id] = 1.0 + th;
+}
+
+// full populations f = w_i + d_i in library order, FP64 [q][nz][ny][nx]
+template <typename T>
+__global__ __launch_bounds__(256) void k3_pops(const T* __restrict__ A, int nx, int ny, long long n, unsigned long long pitch,
+                                               double* __restrict__ out) {
+    const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (id >= n) return;
+    const int x = (int)(id % nx);
+    const long long rr = id / nx;
+    const int y = (int)(rr % ny), z = (int)(rr / ny);
+#pragma unroll
+    for (int i = 0; i < L3::Q; ++i) out[(long long)i * n + id] = wt3(i) + (double)A[pix3(pitch, ny, i, x, y, z)];
+}
+
+__device__ __forceinline__ double wsum3(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wmax3(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// partial[blk][8]: mass, jx, jy, jz, energy (1/2 sum f |c|^2), loss (sum over bulk nodes of
+// (P - P_inf)^2, P_inf = cs^2), max |u|, non-finite count
+template <typename T>
+__global__ __launch_bounds__(256) void k3_diag_partial(const T* __restrict__ A, int nx, int ny, long long n,
+                                                       unsigned long long pitch, int bx0, int bx1,
+                                                       double* __restrict__ partial) {
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (long long id = (long long)blockIdx.x * 256 + threadIdx.x; id < n; id += (long long)gridDim.x * 256) {
+        const int x = (int)(id % nx);
+        const long long rr = id / nx;
+        const int y = (int)(rr % ny), z = (int)(rr / ny);
+        double d[L3::Q], bad = 0.0;
+#pragma unroll
+        for (int i = 0; i < L3::Q; ++i) {
+            d[i] = (double)A[pix3(pitch, ny, i, x, y, z)];
+            bad += isfinite(d[i]) ? 0.0 : 1.0;
+        }
+        double rm1, u, v, w, th;
+        moments3_dev<double>(d, rm1, u, v, w, th);
+        const double r = 1.0 + rm1;
+        double e = 1.5 * L3::cs2;   // 1/2 sum w |c|^2
+#pragma unroll
+        for (int i = 0; i < L3::Q; ++i) e += 0.5 * (double)c2_3(i) * d[i];
+        acc[0] += r; acc[1] += r * u; acc[2] += r * v; acc[3] += r * w; acc[4] += e;
+        if (x >= bx0 && x <= bx1) {
+            const double p = L3::cs2 * (rm1 + th + rm1 * th);
+            acc[5] += p * p;
+        }
+        const double um = sqrt(u * u + v * v + w * w);
+        acc[6] = (um == um) ? fmax(acc[6], um) : acc[6];
+        acc[7] += bad;
+    }
+    __shared__ double red[4][8];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int k = 0; k < 8; ++k) {
+        const double v = k == 6 ? wmax3(acc[k]) : wsum3(acc[k]);
+        if (lane == 0) red[wid][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 8) {
+        const int k = threadIdx.x;
+        double v = red[0][k];
+        for (int q = 1; q < 4; ++q) v = k == 6 ? fmax(v, red[q][k]) : v + red[q][k];
+        partial[blockIdx.x * 8 + k] = v;
+    }
+}
+
+// second pass: one work-group per quantity, fixed-order tree (deterministic)
+__global__ __launch_bounds__(256) void k3_diag_final(const double* __restrict__ partial, int nblk, double* __restrict__ out) {
+    const int k = blockIdx.x;
+    __shared__ double red[256];
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) v = k == 6 ? fmax(v, partial[b * 8 + k]) : v + partial[b * 8 + k];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            red[threadIdx.x] = k == 6 ? fmax(red[threadIdx.x], red[threadIdx.x + w]) : red[threadIdx.x] + red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[k] = red[0];
+}
+
+}  // namespace lbm3

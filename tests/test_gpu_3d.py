@@ -1,0 +1,124 @@
+"""GPU parity of the three-dimensional path (Appendix A; D3Q39, characteristic x-faces, periodic y
+and z) against the FP64 3D oracle, node by node on seeded inputs."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_cases import TOL, log
+from oracle import oracle3d as O3
+
+pytestmark = pytest.mark.gpu
+
+TAU = 0.9
+CS2 = O3.lattice()[0]
+RELAX = dict(sigma=0.25, alpha=0.1, mach=0.05)
+EARLY = [1, 2, 3, 5, 10, 30]
+
+
+def _grid(nx, ny, nz):
+    Z, Y, X = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    return X.astype(float), Y.astype(float), Z.astype(float)
+
+
+def drifting_pulse(nx, ny, nz, center, amp=1e-3, width=3.0, u=(0.01, -0.004, 0.006)):
+    X, Y, Z = _grid(nx, ny, nz)
+    g = amp * np.exp(-((X - center[0]) ** 2 + (Y - center[1]) ** 2 + (Z - center[2]) ** 2) / (2 * width ** 2))
+    one = np.ones_like(X)
+    return [one, u[0] * one, u[1] * one, u[2] * one, 1 + g]
+
+
+def smooth_random(nx, ny, nz, seed, amp):
+    rng = np.random.default_rng(seed)
+    X, Y, Z = _grid(nx, ny, nz)
+    out = np.zeros_like(X)
+    for _ in range(4):
+        k = rng.integers(1, 3, 3)
+        out += amp * rng.uniform(-1, 1) * np.sin(2 * np.pi * (k[0] * X / nx + k[1] * Y / ny + k[2] * Z / nz) + rng.uniform(0, 6))
+    return out
+
+
+def rel_errors(g, o):
+    e_rho = np.linalg.norm(g[0] - o[0]) / np.linalg.norm(o[0])
+    du = math.sqrt(sum(np.sum((g[k] - o[k]) ** 2) for k in (1, 2, 3)))
+    nu = math.sqrt(sum(np.sum(o[k] ** 2) for k in (1, 2, 3)))
+    e_T = np.linalg.norm(g[4] - o[4]) / np.linalg.norm(o[4])
+    return e_rho, du / max(nu, 1e-300), e_T, du
+
+
+def compare3(name, nx, ny, nz, bc, fields, precision, steps, relax=None, recon=None, pops_tol=None):
+    from paper_2307_16766_amd import lbm3d
+    log(f"[gpu-case] 3d {name} {precision} {nx}x{ny}x{nz} bc={bc} recon={recon} steps={steps}")
+    g = lbm3d.LBM3D(nx, ny, nz, TAU, bc, fields, precision=precision)
+    o = O3.Oracle3D(nx, ny, nz, TAU, bc)
+    o.init(*fields)
+    if relax:
+        g.set_relax(-1, **relax)
+        o.set_relax(-1, **relax)
+    if recon:
+        g.set_reconstruction(-1, recon)
+        for s, b in enumerate(bc):
+            if b not in ("periodic", "zg"):
+                o.set_recon(s, recon)
+    rel, floor = TOL[precision]
+    done, worst = 0, [0.0, 0.0, 0.0]
+    for n in steps:
+        g.step(n - done)
+        o.step(n - done)
+        done = n
+        gm, om = g.macro_numpy(), o.macro()
+        e_rho, e_u, e_T, du = rel_errors(gm, om)
+        assert all(np.isfinite([e_rho, e_u, e_T])), (name, n)
+        assert e_rho <= rel and e_T <= rel, f"{name} {precision} step {n}: rho {e_rho:.3e} T {e_T:.3e}"
+        uref = math.sqrt(sum(np.sum(om[k] ** 2) for k in (1, 2, 3)))
+        assert du <= rel * uref + floor * (n + 1) * math.sqrt(nx * ny * nz), f"{name} {precision} step {n}: du {du:.3e}"
+        worst = [max(a, b) for a, b in zip(worst, (e_rho, e_u, e_T))]
+    if pops_tol is not None:
+        _, w, cx, cy, cz, _ = lbm3d.lattice_info()
+        fg = g.populations()
+        _, _, ocx, ocy, ocz, _ = O3.lattice()
+        index = {(int(a), int(b), int(c)): i for i, (a, b, c) in enumerate(zip(cx, cy, cz))}
+        fg = np.stack([fg[index[(int(a), int(b), int(c))]] for a, b, c in zip(ocx, ocy, ocz)])
+        dmax = float(np.abs(fg - o.pops()).max())
+        log(f"[gpu-case] 3d {name} max |f_gpu - f_oracle| = {dmax:.3e}")
+        assert dmax <= pops_tol, (name, dmax)
+    d_g, d_o = g.diagnostics(), o.diag()
+    assert abs(d_g[0] - d_o[0]) < 1e-12 * d_o[0] * (1 if precision == "fp64" else 1e5)
+    g.close()
+    log(f"[gpu-case] 3d {name} {precision} ok worst rel errors rho/u/T = {worst}")
+    return worst
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+def test_3d_periodic_box(precision):
+    nx, ny, nz = 20, 12, 10
+    f = [1 + smooth_random(nx, ny, nz, 1, 0.01), smooth_random(nx, ny, nz, 2, 0.03), smooth_random(nx, ny, nz, 3, 0.03),
+         smooth_random(nx, ny, nz, 4, 0.03), 1 + smooth_random(nx, ny, nz, 5, 0.01)]
+    compare3("periodic", nx, ny, nz, ["periodic", "periodic"], f, precision, EARLY)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+def test_3d_relax_faces(precision):
+    nx, ny, nz = 28, 10, 8
+    compare3("lodi_relax|cbc_relax", nx, ny, nz, ["lodi_relax", "cbc_relax"], drifting_pulse(nx, ny, nz, (14, 4, 3)),
+             precision, EARLY, relax=RELAX)
+
+
+@pytest.mark.parametrize("bc", ["lodi", "cbc", "zg"])
+def test_3d_schemes(bc):
+    nx, ny, nz = 24, 9, 7
+    compare3(bc, nx, ny, nz, [bc, bc], drifting_pulse(nx, ny, nz, (10, 4, 3)), "fp64", EARLY, relax=RELAX)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+def test_3d_neep(precision):
+    nx, ny, nz = 26, 8, 9
+    compare3("neep", nx, ny, nz, ["cbc_relax", "lodi"], drifting_pulse(nx, ny, nz, (12, 3, 4)), precision, EARLY,
+             relax=RELAX, recon="neep", pops_tol=1e-14 if precision == "fp64" else 2e-8)
+
+
+def test_3d_multi_tile():
+    # 300 nodes along x: two bulk tiles per row with a ragged tail; 30 rows
+    nx, ny, nz = 300, 6, 5
+    compare3("multitile", nx, ny, nz, ["lodi_relax", "cbc_relax"], drifting_pulse(nx, ny, nz, (280, 2, 2), width=4.0),
+             "fp64", [1, 5, 20], relax=RELAX)
