@@ -302,3 +302,21 @@ def test_transverse_terms_are_the_tangential_fluxes(side):
         got = o.transverse_probe(side, j, y, z)
         scale = np.abs(ref).max()
         assert np.abs(got - ref).max() < 0.02 * scale, (side, j, y, z, got, ref)
+
+
+def test_normal_viscous_term_of_a_compressional_wave():
+    # V_n = (1/rho) d_n Pi'_nn with Pi'_nn = mu (2 d_n u_n - (2/3) div u) (BGK, c_v = 3/2: no bulk
+    # viscosity) = (4/3) nu d2 u_n for a longitudinal wave, the appendix's nu (lap u_x + 1/3
+    # d_x div u).  The non-equilibrium of an oscillating sound wave also carries a time-lag part:
+    # the ratio oscillates by a few per cent around 1 (a wrong 4/3 or sign is off by 25 % or more)
+    nx, ny, nz = 64, 6, 6
+    k, A, x = 2 * math.pi / 64, 1e-4, 20
+    o = O3.Oracle3D(nx, ny, nz, TAU, ["periodic", "periodic"])
+    o.init(*_fields(nx, ny, nz, lambda X, Y, Z: (1.0, A * np.sin(k * X), 0.0, 0.0, 1.0)))
+    for _ in range(3):
+        o.step(10)
+        ux = o.macro()[1][3, 2]
+        d2 = np.fft.irfft(-(np.fft.rfftfreq(nx) * 2 * np.pi) ** 2 * np.fft.rfft(ux), nx)
+        for g in (1, -1):
+            V = o.visc_probe(g, x, 2, 3)
+            assert abs(V[1] / (g * 4 / 3 * NU * d2[x]) - 1) < 0.07
