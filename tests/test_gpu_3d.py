@@ -122,3 +122,29 @@ def test_3d_multi_tile():
     nx, ny, nz = 300, 6, 5
     compare3("multitile", nx, ny, nz, ["lodi_relax", "cbc_relax"], drifting_pulse(nx, ny, nz, (280, 2, 2), width=4.0),
              "fp64", [1, 5, 20], relax=RELAX)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+def test_3d_minimum_grid(precision):
+    # the smallest accepted box: nx = 2M + 3 = 9 with two faces (the strips of both faces share
+    # the three bulk columns), ny = nz = M + 1 = 4 (every periodic wrap of a 3-step pull)
+    nx, ny, nz = 9, 4, 4
+    compare3("minimum", nx, ny, nz, ["cbc_relax", "lodi_relax"], drifting_pulse(nx, ny, nz, (4, 1.5, 2.0), width=1.5),
+             precision, [1, 2, 5, 20], relax=RELAX)
+
+
+def test_3d_zero_steps_and_errors():
+    from paper_2307_16766_amd import lbm, lbm3d
+    nx, ny, nz = 12, 5, 4
+    f = drifting_pulse(nx, ny, nz, (6, 2, 2))
+    g = lbm3d.LBM3D(nx, ny, nz, TAU, ["lodi", "zg"], f)
+    before = g.macro_numpy()
+    g.step(0)
+    assert np.array_equal(g.macro_numpy(), before)
+    with pytest.raises(lbm.LBMError):
+        g.step(-1)
+    with pytest.raises(lbm.LBMError):
+        g.set_reconstruction(1, "neep")      # NEEP on a zero-gradient face
+    with pytest.raises(lbm.LBMError):
+        g.set_relax(0, sigma=0.1, rho_inf=-1.0)
+    g.close()

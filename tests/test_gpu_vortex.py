@@ -42,12 +42,14 @@ def _fields(n, off):
     return [np.ones((n, n)), ux, uy, T]
 
 
-def _run(bcs, recon="equilibrium", n=L, off=0, alpha=MA):
+def _run(bcs, recon="equilibrium", n=L, off=0, alpha=MA, visc=None):
     from paper_2307_16766_amd import lbm
     g = lbm.LBM(37, n, n, TAU_37, bcs, _fields(n, off))
     g.set_relax(-1, sigma=0.0, alpha=alpha, mach=MA)
     if recon != "equilibrium":
         g.set_reconstruction(-1, recon)
+    if visc is not None:
+        g.set_viscous(-1, visc)
     out, t = [], 0
     for tt in TIMES:
         g.step(tt - t)
@@ -61,12 +63,12 @@ def _run(bcs, recon="equilibrium", n=L, off=0, alpha=MA):
 _REF = []
 
 
-def errors(bcs, recon="equilibrium", alpha=MA):
+def errors(bcs, recon="equilibrium", alpha=MA, visc=None):
     """e_Z(t) for Z = rho, u_x, T at TIMES: array [len(TIMES)][3]."""
     if not _REF:
         _REF.append(_run(["periodic"] * 4, n=EXT * L, off=L))
     ref = _REF[0]
-    res = _run(bcs, recon, alpha=alpha)
+    res = _run(bcs, recon, alpha=alpha, visc=visc)
     return np.array([[math.sqrt(np.sum(((a - b) / b) ** 2)) for a, b in zip(r, q)] for r, q in zip(res, ref)])
 
 
@@ -120,3 +122,34 @@ if __name__ == "__main__":
     for a in (MA, 2 * MA / 3):
         e = errors(SCHEMES["lodi_relax"], alpha=a)
         sys.stdout.write(f"lodi_relax alpha={a:.4f} mean e_ux(600..1000) {e[WINDOW, 1].mean():.4e}\n")
+
+
+def _viscous_run(nu, visc, steps):
+    from paper_2307_16766_amd import lbm
+    tau = 0.5 + nu / CS_37 ** 2
+    g = lbm.LBM(37, L, L, tau, SCHEMES["cbc"], _fields(L, 0))
+    g.set_relax(-1, sigma=0.0, alpha=MA, mach=MA)
+    g.set_reconstruction(1, "neep")
+    g.set_viscous(1, visc)
+    g.step(steps)
+    d = g.diagnostics(allow_nonfinite=True)
+    T = g.macro_numpy()[3]
+    g.close()
+    return d[6] == 0, T
+
+
+@pytest.mark.gpu
+def test_viscous_terms_mesoscopic_vs_finite_differences():
+    # Sec. 4.2, treatment of viscous terms: at nu = 0.1 the mesoscopic and the finite-difference
+    # viscous terms give about the same temperature error; at nu = 0.3 the finite-difference
+    # variant becomes unstable while the mesoscopic one does not (CBC outlet with NEEP)
+    log("[gpu-case] vortex, mesoscopic vs FD viscous terms")
+    k = TIMES.index(1200)
+    e_m = errors(SCHEMES["cbc"], "neep", visc="meso")[k, 2]
+    e_f = errors(SCHEMES["cbc"], "neep", visc="fd")[k, 2]
+    log(f"nu = 0.1, e_T at t = 1200: mesoscopic {e_m:.3e}, finite differences {e_f:.3e}")
+    assert abs(e_f / e_m - 1) < 0.3
+    ok_m3, T_m3 = _viscous_run(0.3, "meso", 1200)
+    assert ok_m3 and np.abs(T_m3 - 1).max() < 0.01
+    ok_f3, _ = _viscous_run(0.3, "fd", 400)
+    assert not ok_f3
