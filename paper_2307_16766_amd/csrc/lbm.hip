@@ -279,7 +279,8 @@ void launch_step_raw(const lbm_ctx* c, const T* A, T* B, char* reg_cur, char* re
     g.mom = mom;
     const int bpr = (g.x1 + 1 + 255) / 256;   // bulk tiles per row, aligned to x = 0
     const int nbnd = c->nbnd;
-    const int nblk = nbnd + bpr * (g.y1 - g.y0 + 1);
+    const int nbnd_pad = sizeof(T) == 8 ? (nbnd + 7) & ~7 : nbnd;   // FP64 tile order, see k_step
+    const int nblk = nbnd_pad + bpr * (g.y1 - g.y0 + 1);
     const unsigned magic = bpr > 1 ? (unsigned)((1ull << 32) / (unsigned long long)bpr + 1ull) : 0u;   // row = umulhi(t, magic)
     const bool px = c->cfg.bc[0] == BC_PERIODIC, py = c->cfg.bc[2] == BC_PERIODIC;
     if (px && py) hipLaunchKernelGGL((k_step<Q, T, true, true, HIST>), dim3(nblk), dim3(256), 0, s, A, B, a, g, nbnd, bpr, magic);
