@@ -275,7 +275,7 @@ def main():
                     help="only run a plain copy of GIB gibibytes (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path (sharding is a design note)",
               file=sys.stderr)
         sys.exit(2)
     if args.copy_probe is not None:
