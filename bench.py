@@ -221,13 +221,22 @@ def cpu_baseline(steps=None):
     t = time.perf_counter()
     o.step(steps)
     dt = time.perf_counter() - t
+    cores = O.num_threads()
+    # the same oracle on one core, over a quarter of the steps
+    O.set_threads(1)
+    s1 = max(2, steps // 4)
+    t = time.perf_counter()
+    o.step(s1)
+    dt1 = time.perf_counter() - t
+    O.set_threads(cores)
     return {
         "value": nx * ny * steps / dt / 1e6,
         "unit": "MLUPS",
-        "cores": O.num_threads(),
+        "cores": cores,
         "kind": "oracle",
         "sample": f"{nx}x{ny} slab of the same workload (D2Q37, Dirichlet inlet + LODI-RELAX outflow, periodic y), "
-                  f"{steps} steps, {dt:.1f} s",
+                  f"{steps} steps, {dt:.1f} s; one core: {s1} steps, {dt1:.1f} s",
+        "value_one_core": nx * ny * s1 / dt1 / 1e6,
     }
 
 

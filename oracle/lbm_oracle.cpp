@@ -1012,6 +1012,15 @@ int oracle_num_threads(void) {
 #endif
 }
 
+// Threads for the OpenMP loops from now on (timing of the CPU baseline on one core).
+void oracle_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int oracle_lattice(int stencil, int* q, int* M, double* cs2, double* w, int* cx, int* cy) {
     if (stencil != 9 && stencil != 17 && stencil != 37) return -1;
     const Lattice& L = lattice(stencil);

@@ -32,6 +32,7 @@ def lib():
         L = ctypes.CDLL(path)
         L.oracle_error.restype = ctypes.c_char_p
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_lattice.argtypes = [ctypes.c_int, _ip, _ip, _dp, _dp, _ip, _ip]
         L.oracle_feq.argtypes = [ctypes.c_int] + [ctypes.c_double] * 4 + [_dp]
         L.oracle_moments.argtypes = [ctypes.c_int, _dp, _dp]
@@ -64,6 +65,11 @@ def lib():
 def num_threads():
     """Threads the oracle's OpenMP loops use."""
     return lib().oracle_num_threads()
+
+
+def set_threads(n):
+    """Threads for the oracle's OpenMP loops from now on."""
+    lib().oracle_set_threads(int(n))
 
 
 def lattice(stencil):
