@@ -2,14 +2,24 @@
 GPU path as the paper does: global relative L2 errors e_Z (eq. errors) of rho, u_x and T against
 a fully periodic run of the same initial state on an extended grid.
 
-Setup (Sec. 4.2): D2Q37, nu = 0.1, 150 x 150 nodes, normalised coordinates
-xh = 2 x / (L - 1) - 1 (x from 0), vortex centre at the domain centre (the printed position
-parameter K is garbled; K = 0 puts the centre on the boundary at t ~ 900, as the paper's time
-line says), radius 0.7, b = 3/20, Ma = 0.1, u0 = (Ma cs, 0), v = 5/2 cs Ma 2^(-r^2/b^2) (y, -x),
-T = 1 + y theta.  The scheme under test is on the right side (outlet), LODI on the three others
-with corners; ZG is applied on all four sides.  Relaxation: alpha = Ma, no pressure relaxation
-(Sec. 4.2, following the paper).  Reference: a periodic 450 x 450 grid holding the same state
-in its central 150 x 150 window.
+Setup (Sec. 4.2): D2Q37 (and D2Q17 for the stencil table), nu = 0.1, 150 x 150 nodes,
+normalised coordinates xh = 2 x / (L - 1) - 1 (x from 0), vortex centre at the domain centre
+(the printed position parameter K is garbled; K = 0 puts the centre on the boundary at t ~ 900,
+as the paper's time line says), radius 0.7, b = 3/20, Ma = 0.1, u0 = (Ma cs, 0),
+v = 5/2 cs Ma 2^(-r^2/b^2) (y, -x), T = 1 + y theta.  The scheme under test is on the right side
+(outlet), LODI on the three others with corners; ZG is applied on all four sides.  Relaxation:
+alpha = Ma, no pressure relaxation (Sec. 4.2, following the paper).
+
+Reference: a periodic (13 L) x (13 L) grid holding the same state in a 150 x 150 window.  The
+extended grid must be large enough that nothing leaving the window comes back into it before the
+last sample (Sec. 4.2): the fastest signal is sound at the adiabatic speed sqrt(gamma) cs
+(gamma = 2 in two dimensions) carried by u0, so N - L > (sqrt(2) cs + Ma cs) t_max = 1645 nodes
+for D2Q37 at t_max = 1300.  A 3 L grid is contaminated from t ~ 240 on, a 9 L one from t ~ 950.
+
+The paper's table of averaged errors (Sec. 4.2, D2Q17 vs D2Q37) is compared with e_Z divided by
+the node count's square root (the root mean square of the pointwise relative errors): with that
+normalisation the zero-gradient values land within 30 % of the printed ones, while the sum in
+eq. errors taken literally would be 150 times larger.
 
 Run as a script to print e_Z(t) for every scheme and reconstruction.
 """
@@ -21,13 +31,16 @@ import numpy as np
 import pytest
 
 sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
-from gpu_cases import CS_37, TAU_37, log  # noqa: E402
+from gpu_cases import CS_17, CS_37, TAU_37, log  # noqa: E402
 
-L, EXT, MA = 150, 3, 0.1
+# nu = 0.1 on both stencils (Sec. 4.2)
+STENCIL = {37: (CS_37, TAU_37), 17: (CS_17, 0.5 + 0.1 / CS_17 ** 2)}
+
+L, EXT, MA = 150, 13, 0.1
 TIMES = list(range(100, 1301, 100))
 
 
-def _fields(n, off):
+def _fields(n, off, cs=CS_37):
     x = np.arange(n)[None, :] - off
     y = np.arange(n)[:, None] - off
     xh = 2 * x / (L - 1) - 1
@@ -35,16 +48,17 @@ def _fields(n, off):
     b, rr = 3 / 20, 0.7
     r2 = xh ** 2 + yh ** 2
     inside = r2 < rr * rr
-    amp = 2.5 * CS_37 * MA * 2.0 ** (-r2 / b ** 2)
-    ux = MA * CS_37 + np.where(inside, amp * yh, 0.0)
+    amp = 2.5 * cs * MA * 2.0 ** (-r2 / b ** 2)
+    ux = MA * cs + np.where(inside, amp * yh, 0.0)
     uy = np.where(inside, -amp * xh, 0.0)
     T = 1 + np.where(inside, yh * amp, 0.0)
     return [np.ones((n, n)), ux, uy, T]
 
 
-def _run(bcs, recon="equilibrium", n=L, off=0, alpha=MA, visc=None):
+def _run(bcs, recon="equilibrium", n=L, off=0, alpha=MA, visc=None, stencil=37):
     from paper_2307_16766_amd import lbm
-    g = lbm.LBM(37, n, n, TAU_37, bcs, _fields(n, off))
+    cs, tau = STENCIL[stencil]
+    g = lbm.LBM(stencil, n, n, tau, bcs, _fields(n, off, cs))
     g.set_relax(-1, sigma=0.0, alpha=alpha, mach=MA)
     if recon != "equilibrium":
         g.set_reconstruction(-1, recon)
@@ -60,15 +74,15 @@ def _run(bcs, recon="equilibrium", n=L, off=0, alpha=MA, visc=None):
     return out
 
 
-_REF = []
+_REF = {}
 
 
-def errors(bcs, recon="equilibrium", alpha=MA, visc=None):
+def errors(bcs, recon="equilibrium", alpha=MA, visc=None, stencil=37):
     """e_Z(t) for Z = rho, u_x, T at TIMES: array [len(TIMES)][3]."""
-    if not _REF:
-        _REF.append(_run(["periodic"] * 4, n=EXT * L, off=L))
-    ref = _REF[0]
-    res = _run(bcs, recon, alpha=alpha, visc=visc)
+    if stencil not in _REF:
+        _REF[stencil] = _run(["periodic"] * 4, n=EXT * L, off=L, stencil=stencil)
+    ref = _REF[stencil]
+    res = _run(bcs, recon, alpha=alpha, visc=visc, stencil=stencil)
     return np.array([[math.sqrt(np.sum(((a - b) / b) ** 2)) for a, b in zip(r, q)] for r, q in zip(res, ref)])
 
 
@@ -79,49 +93,102 @@ SCHEMES = {
     "cbc": ["lodi", "cbc", "lodi", "lodi"],
     "cbc_relax": ["lodi", "cbc_relax", "lodi", "lodi"],
 }
-WINDOW = slice(TIMES.index(600), TIMES.index(1000) + 1)   # the vortex crosses the outlet
+
+
+def rms(e):
+    """e_Z of eq. errors divided by sqrt(L * L): the root mean square relative error."""
+    return e / L
+
+
+def _ratio(e, z):
+    return e.mean(0) / z.mean(0)
 
 
 @pytest.mark.gpu
 def test_vortex_accuracy_claims():
+    # the statements of Sec. 4.2 on the D2Q37 vortex, each on the time range it names
     log("[gpu-case] thermal vortex accuracy")
     e = {name: errors(bcs) for name, bcs in SCHEMES.items() if name not in ("cbc", "cbc_relax")}
     e["cbc_relax_neep"] = errors(SCHEMES["cbc_relax"], "neep")
     e["lodi_neep"] = errors(SCHEMES["lodi"], "neep")
     e["lodi_relax_neep"] = errors(SCHEMES["lodi_relax"], "neep")
-    mean_ux = {k: float(v[WINDOW, 1].mean()) for k, v in e.items()}
-    mean_T = {k: float(v[TIMES.index(500):, 2].mean()) for k, v in e.items()}
-    log(f"mean e_ux over t = 600..1000: {mean_ux}\nmean e_T over t = 500..1300: {mean_T}")
-    # relaxing the incoming wave toward the transverse target cuts the error several times
-    assert mean_ux["lodi_relax"] < mean_ux["lodi"] / 2.5
-    assert mean_ux["cbc_relax_neep"] < mean_ux["lodi"] / 2.5
-    # zero-gradient gives the largest errors in T, but a smaller e_ux than LODI while the
-    # vortex centre crosses the outlet (t = 800..1000)
-    assert mean_T["zg"] > max(mean_T[k] for k in ("lodi", "lodi_relax"))
+    for k, v in e.items():
+        log(f"{k:16s} mean e_Z/L (rho, ux, T) = {rms(v).mean(0)}")
+    # relaxing the incoming wave toward the transverse target lowers every e_Z several times
+    # against LODI while the vortex crosses the outlet (t = 400..1000; the paper: about ten times)
+    w = slice(TIMES.index(400), TIMES.index(1000) + 1)
+    for k in ("lodi_relax", "cbc_relax_neep"):
+        gain = e["lodi"][w].mean(0) / e[k][w].mean(0)
+        log(f"LODI / {k} over t = 400..1000: {gain}")
+        assert gain[1] > 3.5, (k, gain)
+        if k == "lodi_relax":
+            assert gain.min() > 2.5, (k, gain)
+    # ZG is close to the characteristic schemes in the first 200 steps ...
+    for k in (0, 1):
+        r = e["zg"][k] / e["lodi_relax"][k]
+        assert np.all((r > 0.5) & (r < 2.0)), (TIMES[k], r)
+    # ... then has the largest rho and T errors, but a smaller e_ux than LODI while the vortex
+    # centre crosses the outlet (the paper: t = 700..1100)
+    late = slice(TIMES.index(300), None)
+    for z in (0, 2):
+        assert e["zg"][late, z].mean() > max(e[k][late, z].mean() for k in ("lodi", "lodi_relax", "cbc_relax_neep"))
     for t in (800, 900, 1000):
         k = TIMES.index(t)
         assert e["zg"][k, 1] < e["lodi"][k, 1]
     # NEEP and the equilibrium BC give about the same accuracy
     for k in ("lodi", "lodi_relax"):
-        assert abs(mean_ux[k + "_neep"] / mean_ux[k] - 1) < 0.25
-    # Sec. 4.2: alpha = 2/3 Ma lowers the averaged error by about a third compared with alpha = Ma
-    e23 = errors(SCHEMES["lodi_relax"], alpha=2 * MA / 3)
-    gain = 1 - float(e23[WINDOW, 1].mean()) / mean_ux["lodi_relax"]
-    log(f"alpha = 2/3 Ma: mean e_ux lower by {gain:.3f}")
-    assert 0.2 < gain < 0.45
+        r = e[k + "_neep"].mean(0) / e[k].mean(0)
+        assert np.all(np.abs(r - 1) < 0.15), (k, r)
+    # a scan of alpha around Ma: alpha = 2/3 Ma lowers the averaged e_Z by about a third, more than
+    # alpha = Ma / 2 or 5/4 Ma do
+    gains = {}
+    for f in (0.5, 2 / 3, 1.25):
+        ea = errors(SCHEMES["lodi_relax"], alpha=f * MA)
+        gains[f] = 1 - ea.mean(0) / e["lodi_relax"].mean(0)
+        log(f"alpha = {f:.3f} Ma: mean e_Z lower by {gains[f]}")
+    assert 0.2 < gains[2 / 3].mean() < 0.45, gains[2 / 3]
+    assert np.all(gains[2 / 3] > gains[0.5]) and np.all(gains[2 / 3] > gains[1.25])
 
 
-if __name__ == "__main__":
-    sys.stdout.write("t: " + " ".join(str(t) for t in TIMES) + "\n")
-    for name, bcs in SCHEMES.items():
-        for recon in (("equilibrium", "neep") if name != "zg" else ("equilibrium",)):
-            e = errors(bcs, recon)
-            for k, z in enumerate(("rho", "ux", "T")):
-                sys.stdout.write(f"{name:10s} {recon:11s} {z:3s} " + " ".join(f"{x:.2e}" for x in e[:, k]) + "\n")
-            sys.stdout.flush()
-    for a in (MA, 2 * MA / 3):
-        e = errors(SCHEMES["lodi_relax"], alpha=a)
-        sys.stdout.write(f"lodi_relax alpha={a:.4f} mean e_ux(600..1000) {e[WINDOW, 1].mean():.4e}\n")
+# Sec. 4.2, table of averaged errors: zero-gradient means (rho, u_x, T) and the scheme / ZG
+# ratios of the means, per stencil
+PAPER_ZG = {17: (6.4e-5, 2.5e-3, 6.3e-5), 37: (7.5e-5, 3.0e-3, 7.4e-5)}
+PAPER_ZG_MAX = {17: (1.3e-4, 6.3e-3, 1.3e-4), 37: (1.6e-4, 7.4e-3, 1.6e-4)}
+PAPER_RATIO = {17: {"lodi": (0.32, 0.82, 0.32), "lodi_relax": (0.18, 0.22, 0.17), "cbc_relax": (0.16, 0.18, 0.15)},
+               37: {"lodi": (0.33, 0.78, 0.34), "lodi_relax": (0.18, 0.22, 0.18), "cbc_relax": (0.18, 0.18, 0.17)}}
+
+
+@pytest.mark.gpu
+def test_vortex_table_vs_paper():
+    # Sec. 4.2, "Effect of the underlying velocity stencil": both stencils, ZG and the three
+    # characteristic schemes.  CBC-RELAX runs with the -FD viscous terms: with the mesoscopic ones
+    # and the equilibrium BC it does not stay bounded here (the mesoscopic variant is checked with
+    # NEEP)
+    zg_mean = {}
+    for st in (37, 17):
+        log(f"[gpu-case] thermal vortex table, D2Q{st}")
+        z = rms(errors(SCHEMES["zg"], stencil=st))
+        zg_mean[st] = z.mean(0)
+        q = {"lodi": errors(SCHEMES["lodi"], stencil=st),
+             "lodi_relax": errors(SCHEMES["lodi_relax"], stencil=st),
+             "cbc_relax": errors(SCHEMES["cbc_relax"], visc="fd", stencil=st),
+             "cbc_relax_meso_neep": errors(SCHEMES["cbc_relax"], "neep", stencil=st)}
+        r = {k: _ratio(rms(v), z) for k, v in q.items()}
+        log(f"D2Q{st} ZG mean {z.mean(0)} max {z.max(0)}; ratios {r}; paper {PAPER_RATIO[st]}")
+        for got, ref in ((z.mean(0), PAPER_ZG[st]), (z.max(0), PAPER_ZG_MAX[st])):
+            f = got / np.array(ref)
+            assert np.all((f > 1 / 1.5) & (f < 1.5)), (st, f)
+        # LODI: rho and T errors fall to well under half of ZG's, u_x barely improves
+        assert np.all(r["lodi"][[0, 2]] < 0.5) and 0.7 < r["lodi"][1] < 0.95, r["lodi"]
+        # relaxing the incoming wave brings every e_Z to about a fifth of ZG's
+        for k in ("lodi_relax", "cbc_relax"):
+            assert np.all(r[k] < 0.3), (k, r[k])
+        # solving the full CBC system on the boundary improves u_x a little further
+        assert r["cbc_relax"][1] < r["lodi_relax"][1] and r["cbc_relax_meso_neep"][1] < r["lodi_relax"][1]
+    # rho and T errors are about the same for the two stencils (the paper: D2Q37 / D2Q17 = 1.17)
+    f = zg_mean[37] / zg_mean[17]
+    log(f"ZG mean D2Q37 / D2Q17: {f}")
+    assert np.all((f > 0.9) & (f < 1.4)), f
 
 
 def _viscous_run(nu, visc, steps):
@@ -153,3 +220,18 @@ def test_viscous_terms_mesoscopic_vs_finite_differences():
     assert ok_m3 and np.abs(T_m3 - 1).max() < 0.01
     ok_f3, _ = _viscous_run(0.3, "fd", 400)
     assert not ok_f3
+
+
+if __name__ == "__main__":
+    for st in (37, 17):
+        sys.stdout.write(f"D2Q{st}, e_Z / L at t = " + " ".join(str(t) for t in TIMES) + "\n")
+        for name, bcs in SCHEMES.items():
+            for recon in (("equilibrium", "neep") if name != "zg" else ("equilibrium",)):
+                e = rms(errors(bcs, recon, stencil=st))
+                for k, z in enumerate(("rho", "ux", "T")):
+                    sys.stdout.write(f"{name:10s} {recon:11s} {z:3s} mean {e[:, k].mean():.2e} | "
+                                     + " ".join(f"{x:.2e}" for x in e[:, k]) + "\n")
+                sys.stdout.flush()
+        for a in (0.5, 2 / 3, 0.8, 1.0, 1.25):
+            e = rms(errors(SCHEMES["lodi_relax"], alpha=a * MA, stencil=st))
+            sys.stdout.write(f"lodi_relax alpha = {a:.3f} Ma: mean e_Z / L {e.mean(0)}\n")
