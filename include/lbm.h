@@ -183,8 +183,9 @@ int lbm_bulk_kernel_time(lbm_ctx* ctx, double* total_ms, long* launches);
  *
  * lbm_tape_bytes: device bytes of the tape for nsteps steps with a checkpoint every `every`
  * steps (0 for invalid arguments).  The tape holds ceil(nsteps / every) checkpoints of the
- * state plus the reverse sweep's scratch: two adjoint population buffers, two recomputation
- * buffers and (every + 1) slots of per-node moments and boundary state.
+ * state plus the reverse sweep's scratch: two adjoint population buffers and two recomputation
+ * sets, each of two population buffers and (every + 1) slots of per-node moments and boundary
+ * state.
  *
  * lbm_record: from the initial state (no step taken since lbm_init; else LBM_E_STATE), advance
  * nsteps steps exactly as lbm_step does while storing the checkpoints in d_tape (caller-owned,
@@ -199,9 +200,12 @@ int lbm_bulk_kernel_time(lbm_ctx* ctx, double* total_ms, long* launches);
  * dL/d(rho0, u_x0, u_y0, T0) of the fields given to lbm_init; h_grad_relax (host [4][2])
  * receives dL/dsigma and dL/dalpha of each side (0 for sides without relaxation).  Runs the
  * reverse sweep segment by segment from the last checkpoint: each segment is recomputed from
- * its checkpoint, then reversed step by step.  The context must not have stepped since
- * lbm_record (LBM_E_STATE); its state is left unchanged, and the call may be repeated with
- * other seeds.  Synchronises the stream before returning. */
+ * its checkpoint, then reversed step by step.  The recomputation runs on a second stream that
+ * the library makes on the context's first lbm_adjoint (non-blocking, default priority, on the
+ * device current at that call, which must be the context's; released by lbm_destroy), one
+ * segment ahead of the reverse sweep on the context's stream; events order the two.  The
+ * context must not have stepped since lbm_record (LBM_E_STATE); its state is left unchanged,
+ * and the call may be repeated with other seeds.  Synchronises the stream before returning. */
 size_t lbm_tape_bytes(const lbm_ctx* ctx, int nsteps, int every);
 int lbm_record(lbm_ctx* ctx, int nsteps, int every, void* d_tape, size_t tape_bytes);
 int lbm_adjoint(lbm_ctx* ctx, const double* d_seed, double* d_grad_fields, double* h_grad_relax);

@@ -165,7 +165,9 @@ struct Tape {
     char* base = nullptr;
     int N = 0, K = 0, nchk = 0;
     long step_end = -1;
-    size_t chk_stride = 0, off_R[2] = {0, 0}, off_V[2] = {0, 0}, off_mom = 0, mom_bytes = 0, off_rh = 0;
+    // two recomputation sets (populations R, moments, boundary states), so that the recomputation
+    // of one segment overlaps the reverse sweep of the next one
+    size_t chk_stride = 0, off_R[2][2] = {{0, 0}, {0, 0}}, off_V[2] = {0, 0}, off_mom[2] = {0, 0}, mom_bytes = 0, off_rh[2] = {0, 0};
     size_t off_adj[2] = {0, 0}, off_ccon = 0, off_gm = 0, off_acc = 0, total = 0;
     int ablk0[4] = {0, 0, 0, 0}, anblk[4] = {0, 0, 0, 0}, arows = 0, nadj = 0;
 };
@@ -193,6 +195,10 @@ struct lbm_ctx {
     std::vector<hipEvent_t> tev;   // pairs: start, end
     size_t tcount = 0;             // recorded pairs
     Tape tape;
+    // the adjoint's second stream (non-blocking, default priority) and its events, made on the
+    // first lbm_adjoint: ev[0..1] recomputation set b ready, ev[2..3] set b released, ev[4] start
+    hipStream_t aux = nullptr;
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
 namespace {
@@ -349,12 +355,13 @@ void tape_layout(const Layout& L, int ny, int N, int K, Tape& t) {
     t.nchk = (N + K - 1) / K;
     t.chk_stride = L.f_bytes + L.region_bytes;
     size_t off = (size_t)t.nchk * t.chk_stride;
-    for (int k = 0; k < 2; ++k) { t.off_R[k] = off; off += L.f_bytes; }
+    for (int b = 0; b < 2; ++b)
+        for (int k = 0; k < 2; ++k) { t.off_R[b][k] = off; off += L.f_bytes; }
     const size_t vbytes = align_up((size_t)L.Q * L.pitch * ny * 8);
     for (int k = 0; k < 2; ++k) { t.off_V[k] = off; off += vbytes; }
     t.mom_bytes = align_up((size_t)4 * L.pitch * ny * 8);
-    t.off_mom = off; off += (size_t)(K + 1) * t.mom_bytes;
-    t.off_rh = off; off += (size_t)(K + 1) * L.region_bytes;
+    for (int b = 0; b < 2; ++b) { t.off_mom[b] = off; off += (size_t)(K + 1) * t.mom_bytes; }
+    for (int b = 0; b < 2; ++b) { t.off_rh[b] = off; off += (size_t)(K + 1) * L.region_bytes; }
     for (int k = 0; k < 2; ++k) { t.off_adj[k] = off; off += L.region_bytes; }
     t.off_ccon = off; off += align_up(4 * 2 * 2 * 4 * 8);
     t.off_gm = off; off += align_up(16 * 4 * 8);
@@ -380,9 +387,13 @@ int run_adjoint(lbm_ctx* c, const double* seed, double* grad, double* h_relax) {
     const int bpr = (nx + 255) / 256;
     const bool px = c->cfg.bc[0] == BC_PERIODIC, py = c->cfg.bc[2] == BC_PERIODIC;
     double* V[2] = {(double*)(base + t.off_V[0]), (double*)(base + t.off_V[1])};
-    auto mom_slot = [&](int j) { return (double*)(base + t.off_mom + (size_t)j * t.mom_bytes); };
-    auto reg_slot = [&](int j) { return base + t.off_rh + (size_t)j * L.region_bytes; };
-    T* R[2] = {(T*)(base + t.off_R[0]), (T*)(base + t.off_R[1])};
+    auto mom_slot = [&](int b, int j) { return (double*)(base + t.off_mom[b] + (size_t)j * t.mom_bytes); };
+    auto reg_slot = [&](int b, int j) { return base + t.off_rh[b] + (size_t)j * L.region_bytes; };
+    if (!c->aux) {
+        HIPCHK(c, hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+        for (hipEvent_t& e : c->ev) HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    hipStream_t ax = c->aux;
 
     hipLaunchKernelGGL((k_adj_seed<Q, T>), dim3(bpr * ny), dim3(256), 0, st, (const T*)c->f[c->cur], seed, V[t.N & 1], bk, bpr);
     HIPCHK(c, hipGetLastError());
@@ -418,26 +429,49 @@ int run_adjoint(lbm_ctx* c, const double* seed, double* grad, double* h_relax) {
         if (any_corner && c->cfg.bc[s] == BC_LODI_RELAX && c->relax[s].alpha != 0.0) g.coupled = 1;
     const int nside_blocks = t.nadj + ((any_corner && !g.coupled) ? 4 : 0);
 
-    for (int seg = t.nchk - 1; seg >= 0; --seg) {
+    // Segment seg is recomputed from its checkpoint on the second stream into recomputation set
+    // seg & 1 (populations, and per step the moments and boundary states the reverse sweep
+    // reads), while the caller's stream sweeps segment seg + 1 backwards from the other set.
+    // Events order the two: the sweep of seg waits for its set to be filled, the recomputation
+    // of seg - 1 waits for the sweep of seg + 1 to have released that set.
+    auto recompute = [&](int seg) -> int {
+        const int b = seg & 1;
         const int n0 = seg * t.K, n1 = std::min(n0 + t.K, t.N);
         const char* chk = base + (size_t)seg * t.chk_stride;
-        HIPCHK(c, hipMemcpyAsync(R[0], chk, L.f_bytes, hipMemcpyDeviceToDevice, st));
-        HIPCHK(c, hipMemcpyAsync(reg_slot(0), chk + L.f_bytes, L.region_bytes, hipMemcpyDeviceToDevice, st));
-        hipLaunchKernelGGL((k_adj_moments<Q, T>), dim3(bpr * ny), dim3(256), 0, st, (const T*)R[0], mom_slot(0), bk, bpr);
+        T* R[2] = {(T*)(base + t.off_R[b][0]), (T*)(base + t.off_R[b][1])};
+        HIPCHK(c, hipMemcpyAsync(R[0], chk, L.f_bytes, hipMemcpyDeviceToDevice, ax));
+        HIPCHK(c, hipMemcpyAsync(reg_slot(b, 0), chk + L.f_bytes, L.region_bytes, hipMemcpyDeviceToDevice, ax));
+        hipLaunchKernelGGL((k_adj_moments<Q, T>), dim3(bpr * ny), dim3(256), 0, ax, (const T*)R[0], mom_slot(b, 0), bk, bpr);
         HIPCHK(c, hipGetLastError());
         for (int j = 0; j < n1 - n0; ++j) {
-            launch_step_raw<Q, T, true>(c, R[j & 1], R[(j + 1) & 1], reg_slot(j), reg_slot(j + 1), mom_slot(j + 1), st);
+            launch_step_raw<Q, T, true>(c, R[j & 1], R[(j + 1) & 1], reg_slot(b, j), reg_slot(b, j + 1), mom_slot(b, j + 1), ax);
             HIPCHK(c, hipGetLastError());
+        }
+        HIPCHK(c, hipEventRecord(c->ev[b], ax));
+        return LBM_OK;
+    };
+    HIPCHK(c, hipEventRecord(c->ev[4], st));   // the seed and the clears above come first
+    HIPCHK(c, hipStreamWaitEvent(ax, c->ev[4], 0));
+    int rc = recompute(t.nchk - 1);
+    if (rc != LBM_OK) return rc;
+    for (int seg = t.nchk - 1; seg >= 0; --seg) {
+        const int b = seg & 1;
+        const int n0 = seg * t.K, n1 = std::min(n0 + t.K, t.N);
+        HIPCHK(c, hipStreamWaitEvent(st, c->ev[b], 0));
+        if (seg > 0) {
+            if (seg + 1 < t.nchk) HIPCHK(c, hipStreamWaitEvent(ax, c->ev[2 + (b ^ 1)], 0));
+            rc = recompute(seg - 1);
+            if (rc != LBM_OK) return rc;
         }
         for (int n = n1 - 1; n >= n0; --n) {
             const int j = n - n0;
-            g.b.reg_cur = reg_slot(j);
-            g.b.reg_next = reg_slot(j + 1);
+            g.b.reg_cur = reg_slot(b, j);
+            g.b.reg_next = reg_slot(b, j + 1);
             g.adj_cur = base + t.off_adj[n & 1];
             g.adj_next = base + t.off_adj[(n + 1) & 1];
             g.V1 = V[(n + 1) & 1];
             g.V0 = V[n & 1];
-            g.mom = mom_slot(j);
+            g.mom = mom_slot(b, j);
             if (nside_blocks > 0) {
                 hipLaunchKernelGGL((k_adj_side<Q>), dim3(nside_blocks), dim3(256), 0, st, g);
                 HIPCHK(c, hipGetLastError());
@@ -460,6 +494,7 @@ int run_adjoint(lbm_ctx* c, const double* seed, double* grad, double* h_relax) {
             }
             HIPCHK(c, hipGetLastError());
         }
+        HIPCHK(c, hipEventRecord(c->ev[2 + b], st));
     }
     g.adj_cur = base + t.off_adj[0];
     hipLaunchKernelGGL((k_adj_final<Q>), dim3(1), dim3(256), 0, st, g);
@@ -789,6 +824,11 @@ const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : g_err
 void lbm_destroy(lbm_ctx* c) {
     if (!c) return;
     for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
+    if (c->aux) {
+        (void)hipStreamSynchronize(c->aux);
+        for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+        (void)hipStreamDestroy(c->aux);
+    }
     delete c;
 }
 
