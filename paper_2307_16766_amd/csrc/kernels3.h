@@ -81,11 +81,15 @@ struct Bulk3 {
 // walks one contiguous range of rows; a node's up to 25 source rows (y - c_y, z - c_z) then sit
 // in the L2 of the XCD that reads them instead of being fetched by several XCDs (measured on
 // 512 x 256 x 256: FP64 62 % -> 72 % of HBM bandwidth, FP32 unchanged within 1 %).
-// Boundary-layer nodes get a placeholder store: k3_final rewrites them after this launch, and
-// the placeholder keeps every plane's first and last cache line of a row written whole (partial-
-// line stores of a streaming kernel cost read-modify-write bandwidth: -8 % on 512 x 256 x 256).
-// Computing the layers' final populations here instead (after the face solve) was measured
-// slower: the FP64 reconstruction diverges inside bulk waves and doubles the register count.
+// Boundary-layer nodes get a placeholder (zero) store that k3_final rewrites after this launch.
+// Layer lanes run the same instruction stream as bulk lanes: they pull with the periodic wrap in
+// x (always in bounds; a bulk lane has M <= x <= nx - 1 - M and |c_x| <= M, so the wrap never
+// acts for it), and select zero at the store.  Each plane's first and last cache line of a row is then
+// written whole by one store instruction (partial-line stores of a streaming kernel cost read-
+// modify-write bandwidth: -8 % on 512 x 256 x 256 without the placeholder, -7 % with it in a
+// separate branch).  Computing the layers' final populations here instead (after the face
+// solve) was measured slower: the FP64 reconstruction diverges inside bulk waves and doubles the
+// register count.
 template <typename T, bool PX>
 __global__ __launch_bounds__(256, (sizeof(T) == 4 ? 3 : 2)) void k3_bulk(const T* __restrict__ A, T* __restrict__ B, Bulk3 g,
                                                                           int bpr, unsigned magic) {
@@ -95,14 +99,8 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 ? 3 : 2)) void k3_bulk(const T
     const unsigned row = bpr == 1 ? t : __umulhi(t, magic);
     const int x = (int)(t - row * (unsigned)bpr) * 256 + (int)threadIdx.x;
     const int z = (int)(row / (unsigned)g.ny), y = (int)(row - (unsigned)z * (unsigned)g.ny);
-    if (x < g.x0 || x > g.x1) {
-        if (x < g.nx) {
-            T* Bo = B + pix3(g.pitch, g.ny, 0, x, y, z);
-#pragma unroll
-            for (int i = 0; i < L3::Q; ++i) __builtin_nontemporal_store(T(0), Bo + (unsigned long long)i * g.pitch);
-        }
-        return;
-    }
+    if (x >= g.nx) return;
+    const bool act = PX || (x >= g.x0 && x <= g.x1);
     T d[L3::Q];
 #pragma unroll
     for (int dz = -L3::M; dz <= L3::M; ++dz) {
@@ -117,8 +115,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 ? 3 : 2)) void k3_bulk(const T
 #pragma unroll
             for (int i = 0; i < L3::Q; ++i) {
                 if (cy3(i) != dy || cz3(i) != dz) continue;
-                int xs = x - cx3(i);
-                if (PX) xs = wrap3(xs, g.nx);
+                const int xs = wrap3(x - cx3(i), g.nx);
                 d[i] = Ar[(unsigned long long)i * g.pitch + xs];
             }
         }
@@ -127,7 +124,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 ? 3 : 2)) void k3_bulk(const T
     collide3_dev<T>(d, omega);
     T* Bo = B + pix3(g.pitch, g.ny, 0, x, y, z);
 #pragma unroll
-    for (int i = 0; i < L3::Q; ++i) __builtin_nontemporal_store(d[i], Bo + (unsigned long long)i * g.pitch);
+    for (int i = 0; i < L3::Q; ++i) __builtin_nontemporal_store(act ? d[i] : T(0), Bo + (unsigned long long)i * g.pitch);
 }
 
 // ================================================================== initialisation
