@@ -1,8 +1,10 @@
 """torch.autograd.Function over the library's recorded run and discrete adjoint.
 
 ``simulate(sigma, alpha, rho0, ux0, uy0, T0, ...)`` runs ``nsteps`` steps from the given initial
-fields with the relaxation parameters sigma and alpha on every LODI-RELAX side and returns the
-final macroscopic fields stacked as a (4, ny, nx) float64 tensor (rho, ux, uy, T).  Its backward
+fields with the relaxation parameters sigma and alpha on every LODI-RELAX and CBC-RELAX side and
+returns the final macroscopic fields stacked as a (4, ny, nx) float64 tensor (rho, ux, uy, T).
+CBC and CBC-RELAX sides run with the finite-difference viscous terms (Sec. 4.2, "Treatment of
+viscous terms"), the variant the adjoint differentiates.  Its backward
 calls ``lbm_adjoint`` with dL/d(output) as the seed: the gradient flows to sigma, alpha and the
 four initial fields.  Forward and backward both run in the HIP library; torch supplies memory,
 the stream and the autograd graph.
@@ -18,9 +20,11 @@ class ThermalLBMFunction(torch.autograd.Function):
         sim = lbm.LBM(spec["stencil"], spec["nx"], spec["ny"], spec["tau"], spec["bc"],
                       (rho0.detach(), ux0.detach(), uy0.detach(), T0.detach()), precision=spec.get("precision", "fp64"))
         relax = dict(spec.get("relax", {}))
-        relax_sides = [s for s, b in enumerate(spec["bc"]) if b == "lodi_relax"]
+        relax_sides = [s for s, b in enumerate(spec["bc"]) if b in ("lodi_relax", "cbc_relax")]
         for s in relax_sides:
             sim.set_relax(s, sigma=float(sigma), alpha=float(alpha), **relax)
+        if any(b in ("cbc", "cbc_relax") for b in spec["bc"]):
+            sim.set_viscous(-1, "fd")
         sim.record(spec["nsteps"], spec.get("every", 50))
         out = torch.stack(sim.macroscopic())
         ctx.sim = sim

@@ -156,29 +156,45 @@ __device__ __forceinline__ double phi_dot(int i, const double* GM) {
     return v;
 }
 
-// VJP of char_rate (LODI and LODI-RELAX; the CBC variants are not differentiated).  Inputs as
-// char_rate, rb = adjoint of the rate; outputs the adjoints of U, dn, up, dw (side-local
-// components) and of K and alpha.  The wave directions are frozen at time t (no derivative).
+// VJP of char_rate for the four schemes of Tab. CBCs; the CBC variants with the viscous terms of
+// the -FD variant (Sec. 4.2), evaluated from the stage values as in the forward step:
+// V = (0, nu lap u_n, nu lap u_t, 2 nu lap T + (nu / cs^2)(sa^2 + sb^2)), lap = d2n + up - 2 U +
+// dw, sa = dn u_n - d_t u_t, sb = d_t u_n + dn u_t.  Inputs as char_rate plus the second normal
+// difference d2n; rb = adjoint of the rate; outputs the adjoints of U, dn, d2n, up, dw
+// (side-local components) and of K and alpha.  The wave directions are frozen at time t (no
+// derivative).
 template <int Q>
-__device__ __forceinline__ void char_rate_vjp(const double* U, const double* dn, const double* up, const double* dw,
-                                              const double* U0, int scheme, double K, double alpha, double Pinf,
-                                              const double* rb, double* Ub, double* dnb, double* upb, double* dwb,
-                                              double& Kb, double& alb) {
+__device__ __forceinline__ void char_rate_vjp(const double* U, const double* dn, const double* d2n, const double* up,
+                                              const double* dw, const double* U0, int scheme, double nu, double K,
+                                              double alpha, double Pinf, const double* rb, double* Ub, double* dnb,
+                                              double* d2nb, double* upb, double* dwb, double& Kb, double& alb) {
     constexpr bool THERMAL = Lat<Q>::thermal;
     constexpr double cs2 = Lat<Q>::cs2;
     constexpr double cs = Lat<Q>::cs;
-    const bool relax = scheme == BC_LODI_RELAX;
+    const bool full = THERMAL && (scheme == BC_CBC || scheme == BC_CBC_RELAX);
+    const bool relax = scheme == BC_LODI_RELAX || scheme == BC_CBC_RELAX;
     const double rho = U[0], u = U[1], v = U[2], T = U[3];
     const double ir = 1.0 / rho;
     const double T1 = -0.5 * (up[0] * up[2] - dw[0] * dw[2]);
     const double T2 = -v * 0.5 * (up[1] - dw[1]);
+    const double T3 = THERMAL ? -cs2 * ir * 0.5 * (up[0] * up[3] - dw[0] * dw[3]) - v * 0.5 * (up[2] - dw[2]) : 0.0;
     const double T4 = THERMAL ? -0.5 * (up[3] * up[2] - dw[3] * dw[2]) : 0.0;
     const double u0 = U0[1];
-    double rhob = 0.0, ub = 0.0, vb = 0.0, Tb = 0.0, T1b = 0.0, T2b = 0.0, T4b = 0.0;
-    for (int m = 0; m < 4; ++m) dnb[m] = 0.0;
+    double rhob = 0.0, ub = 0.0, vb = 0.0, Tb = 0.0, T1b = 0.0, T2b = 0.0, T3b = 0.0, T4b = 0.0;
+    for (int m = 0; m < 4; ++m) { dnb[m] = 0.0; d2nb[m] = 0.0; upb[m] = 0.0; dwb[m] = 0.0; }
     Kb = 0.0;
     alb = 0.0;
     if (THERMAL) {
+        // viscous terms of the -FD variant (zero for the LODI schemes)
+        double lap[4] = {0.0, 0.0, 0.0, 0.0}, V1 = 0.0, V2 = 0.0, V3 = 0.0, sa = 0.0, sh = 0.0;
+        if (full) {
+            for (int m = 1; m < 4; ++m) lap[m] = d2n[m] + up[m] - 2.0 * U[m] + dw[m];
+            sa = dn[1] - 0.5 * (up[2] - dw[2]);
+            sh = 0.5 * (up[1] - dw[1]) + dn[2];
+            V1 = nu * lap[1];
+            V2 = nu * lap[2];
+            V3 = 2.0 * nu * lap[3] + nu * (1.0 / cs2) * (sa * sa + sh * sh);
+        }
         const double s = sqrt(2.0 * cs2 * T);
         const double s0 = sqrt(2.0 * cs2 * U0[3]);
         const double a = 0.25 * T * ir, b = s * (0.25 / cs2);
@@ -186,11 +202,21 @@ __device__ __forceinline__ void char_rate_vjp(const double* U, const double* dn,
         const double W4 = a * dn[0] + b * dn[1] + 0.25 * dn[3];
         const double L1 = u * (-2.0 * a * dn[0] + 0.5 * dn[3]);
         const double L3 = (u - s) * W3, L4 = (u + s) * W4;
+        const double ST1 = -2.0 * a * T1 + 0.5 * T4;
         const double ST3 = a * T1 - b * T2 + 0.25 * T4, ST4 = a * T1 + b * T2 + 0.25 * T4;
+        double in1 = 0.0, in3 = 0.0, in4 = 0.0;
+        if (full) {
+            in1 = ST1 + 0.5 * V3;
+            in3 = ST3 - b * V1 + 0.25 * V3;
+            in4 = ST4 + b * V1 + 0.25 * V3;
+        }
         const double pr = relax ? K * (rho * cs2 * T - Pinf) * ir * (0.25 / cs2) : 0.0;
-        const double in3 = relax ? pr - alpha * ST3 : 0.0, in4 = relax ? pr - alpha * ST4 : 0.0;
+        if (relax) {
+            in3 += pr - alpha * ST3;
+            in4 += pr - alpha * ST4;
+        }
         const bool o1 = u0 >= 0.0, o3 = u0 - s0 >= 0.0, o4 = u0 + s0 >= 0.0;
-        const double B1 = o1 ? L1 : 0.0, B3 = o3 ? L3 : in3, B4 = o4 ? L4 : in4;
+        const double B1 = o1 ? L1 : in1, B3 = o3 ? L3 : in3, B4 = o4 ? L4 : in4;
         const double rhoT = rho / T, q = 2.0 * cs2 / s;
         const double Bb1 = rb[0] * rhoT - rb[3];
         const double Bb2 = -rb[2];
@@ -201,18 +227,36 @@ __device__ __forceinline__ void char_rate_vjp(const double* U, const double* dn,
         Tb += -rb[0] * rho * Bs / (T * T);
         double sb = -rb[1] * q * (B3 - B4) / s;
         const double L1b = o1 ? Bb1 : 0.0, L2b = o1 ? Bb2 : 0.0, L3b = o3 ? Bb3 : 0.0, L4b = o4 ? Bb4 : 0.0;
+        const double in1b = o1 ? 0.0 : Bb1, in2b = o1 ? 0.0 : Bb2;
         const double in3b = o3 ? 0.0 : Bb3, in4b = o4 ? 0.0 : Bb4;
-        double ab = 0.0, bb = 0.0, ST3b = 0.0, ST4b = 0.0;
+        double ab = 0.0, bb = 0.0, ST1b = 0.0, ST3b = 0.0, ST4b = 0.0, V1b = 0.0, V2b = 0.0, V3b = 0.0;
         if (relax) {
             const double prb = in3b + in4b;
             alb = -(in3b * ST3 + in4b * ST4);
-            ST3b = -alpha * in3b;
-            ST4b = -alpha * in4b;
+            ST3b -= alpha * in3b;
+            ST4b -= alpha * in4b;
             Kb = prb * (rho * cs2 * T - Pinf) * ir * (0.25 / cs2);
             // pr = K (T / 4 - Pinf / (4 cs^2 rho))
             Tb += prb * K * 0.25;
             rhob += prb * K * 0.25 * Pinf * ir * ir / cs2;
         }
+        if (full) {
+            // incoming amplitudes S (T + V) (in2 = T3 + V2) and the direct T + V of the rate
+            ST1b += in1b;
+            V3b += 0.5 * in1b + 0.25 * (in3b + in4b) + rb[3];
+            T3b += in2b + rb[2];
+            V2b += in2b + rb[2];
+            ST3b += in3b;
+            ST4b += in4b;
+            bb += V1 * (in4b - in3b);
+            V1b += b * (in4b - in3b) + rb[1];
+            T1b += rb[0];
+            T2b += rb[1];
+            T4b += rb[3];
+        }
+        ab += -2.0 * T1 * ST1b;
+        T1b += -2.0 * a * ST1b;
+        T4b += 0.5 * ST1b;
         ab += T1 * (ST3b + ST4b);
         T1b += a * (ST3b + ST4b);
         bb += T2 * (ST4b - ST3b);
@@ -238,6 +282,34 @@ __device__ __forceinline__ void char_rate_vjp(const double* U, const double* dn,
         Tb += ab * 0.25 * ir;
         rhob += -ab * 0.25 * T * ir * ir;
         Tb += sb * cs2 / s;
+        if (full) {
+            // viscous terms: lap = d2n + up - 2 U + dw; heating from sa and sh
+            const double lb[4] = {0.0, nu * V1b, nu * V2b, 2.0 * nu * V3b};
+            const double sab = 2.0 * nu * (1.0 / cs2) * sa * V3b, shb = 2.0 * nu * (1.0 / cs2) * sh * V3b;
+            for (int m = 1; m < 4; ++m) {
+                d2nb[m] += lb[m];
+                upb[m] += lb[m];
+                dwb[m] += lb[m];
+            }
+            ub += -2.0 * lb[1];
+            vb += -2.0 * lb[2];
+            Tb += -2.0 * lb[3];
+            dnb[1] += sab;
+            upb[2] += -0.5 * sab;
+            dwb[2] += 0.5 * sab;
+            upb[1] += 0.5 * shb;
+            dwb[1] += -0.5 * shb;
+            dnb[2] += shb;
+            // T3 = -cs^2 / rho * (d_t (rho T)) - v d_t u_t (central differences)
+            rhob += cs2 * ir * ir * 0.5 * (up[0] * up[3] - dw[0] * dw[3]) * T3b;
+            upb[0] += -cs2 * ir * 0.5 * up[3] * T3b;
+            upb[3] += -cs2 * ir * 0.5 * up[0] * T3b;
+            dwb[0] += cs2 * ir * 0.5 * dw[3] * T3b;
+            dwb[3] += cs2 * ir * 0.5 * dw[0] * T3b;
+            vb += -0.5 * (up[2] - dw[2]) * T3b;
+            upb[2] += -0.5 * v * T3b;
+            dwb[2] += 0.5 * v * T3b;
+        }
     } else {
         const double c = cs;
         const double Wm = cs2 * dn[0] - rho * c * dn[1], Wp = cs2 * dn[0] + rho * c * dn[1];
@@ -271,21 +343,18 @@ __device__ __forceinline__ void char_rate_vjp(const double* U, const double* dn,
         }
     }
     // transverse terms T1, T2, T4 (eq. NSF-CHAR, central differences)
-    upb[0] = -0.5 * up[2] * T1b;
-    upb[2] = -0.5 * up[0] * T1b;
-    dwb[0] = 0.5 * dw[2] * T1b;
-    dwb[2] = 0.5 * dw[0] * T1b;
+    upb[0] += -0.5 * up[2] * T1b;
+    upb[2] += -0.5 * up[0] * T1b;
+    dwb[0] += 0.5 * dw[2] * T1b;
+    dwb[2] += 0.5 * dw[0] * T1b;
     vb += -0.5 * (up[1] - dw[1]) * T2b;
-    upb[1] = -0.5 * v * T2b;
-    dwb[1] = 0.5 * v * T2b;
+    upb[1] += -0.5 * v * T2b;
+    dwb[1] += 0.5 * v * T2b;
     if (THERMAL) {
-        upb[3] = -0.5 * up[2] * T4b;
+        upb[3] += -0.5 * up[2] * T4b;
         upb[2] += -0.5 * up[3] * T4b;
-        dwb[3] = 0.5 * dw[2] * T4b;
+        dwb[3] += 0.5 * dw[2] * T4b;
         dwb[2] += 0.5 * dw[3] * T4b;
-    } else {
-        upb[3] = 0.0;
-        dwb[3] = 0.0;
     }
     Ub[0] = rhob; Ub[1] = ub; Ub[2] = vb; Ub[3] = THERMAL ? Tb : 0.0;
 }
@@ -313,9 +382,10 @@ __device__ __forceinline__ void corner_rate_vjp(const CornerDev& c, const double
     rl[1] = rb[1] * c.ndx + rb[2] * c.ndy;
     rl[2] = rb[1] * tdx + rb[2] * tdy;
     rl[3] = rb[3];
-    double Ub[4], dnb[4], upb[4], dwb[4], alb;
-    char_rate_vjp<Q>(l0, dn, l0, l0, ln, c.relax ? BC_LODI_RELAX : BC_LODI, c.K, 0.0, c.Pinf, rl, Ub,
-                                   dnb, upb, dwb, Kb, alb);
+    double Ub[4], dnb[4], d2nb[4], upb[4], dwb[4], alb;
+    const double zero4[4] = {0.0, 0.0, 0.0, 0.0};
+    char_rate_vjp<Q>(l0, dn, zero4, l0, l0, ln, c.relax ? BC_LODI_RELAX : BC_LODI, 0.0, c.K, 0.0, c.Pinf, rl, Ub,
+                     dnb, d2nb, upb, dwb, Kb, alb);
     double a0[4], a1[4], a2[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -359,6 +429,7 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
     __shared__ double sYb1[NN * 4];             // adjoint of U_b^{n+1}
     __shared__ double sG[NN * 4];               // adjoint of the stage input of the later stage
     __shared__ double sGn[NN * 4], sGu[NN * 4], sGd[NN * 4];   // per node: adjoints of dn, up, dw
+    __shared__ double sG2[(M == 3 ? NN : 1) * 4];              // per node: adjoint of d2n (-FD viscous terms)
     __shared__ double sXn[NR * MS * 4], sXp[NR * MS * 4];       // strip values at n, n+1
     __shared__ double sXbn[NR * MS * 4], sXbp[NR * MS * 4];     // strip adjoints (owned rows)
     __shared__ double sC[2][2][4];
@@ -421,7 +492,7 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
 
     const double ast[4] = {0.0, 0.5, 0.5, 1.0}, bst[4] = {1.0, 2.0, 2.0, 1.0};
     // side-local stage-st inputs of this thread's node
-    auto inputs = [&](int st, double* U, double* dn, double* up, double* dw, double* U0) {
+    auto inputs = [&](int st, double* U, double* dn, double* d2n, double* up, double* dw, double* U0) {
         const double th = ast[st];
         const double* Ys = sY[st];
         auto val_n = [&](int k, double* l) {
@@ -448,19 +519,26 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
             to_local(sd, gv, l);
         };
         val_n(j, U);
+        for (int m = 0; m < 4; ++m) d2n[m] = 0.0;
         if (j == M) {
             double b1[4], b2[4];
             val_n(M - 1, b1); val_n(M - 2, b2);
             for (int m = 0; m < 4; ++m) dn[m] = 0.5 * (3.0 * U[m] - 4.0 * b1[m] + b2[m]);
+            if (M == 3) {   // backward second difference of the -FD viscous terms (Sec. 4.2)
+                double b3[4];
+                val_n(M - 3, b3);
+                for (int m = 0; m < 4; ++m) d2n[m] = 2.0 * U[m] - 5.0 * b1[m] + 4.0 * b2[m] - b3[m];
+            }
         } else {
             double p1[4], m1[4];
             val_n(j + 1, p1); val_n(j - 1, m1);
-            for (int m = 0; m < 4; ++m) dn[m] = 0.5 * (p1[m] - m1[m]);
+            for (int m = 0; m < 4; ++m) { dn[m] = 0.5 * (p1[m] - m1[m]); d2n[m] = p1[m] - 2.0 * U[m] + m1[m]; }
         }
         val_t(r + 1, up);
         val_t(r - 1, dw);
         to_local(sd, &sY[0][t * 4], U0);
     };
+    const double nu = (a.tau - 0.5) * Lat<Q>::cs2;
 
     // ---- phase B: stage inputs Y_1..Y_3, stored by the recomputation of this step --------------
     {
@@ -485,13 +563,15 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
             for (int m = 0; m < 4; ++m)
                 kb[m] = bst[st] * (1.0 / 6.0) * sYb1[t * 4 + m] + (st < 3 ? ast[st + 1] * sG[t * 4 + m] : 0.0);
             to_local(sd, kb, rb);
-            double U[4], dn[4], up[4], dw[4], U0[4];
-            inputs(st, U, dn, up, dw, U0);
-            double Ubl[4], dnbl[4], upbl[4], dwbl[4], Kb, alb;
-            char_rate_vjp<Q>(U, dn, up, dw, U0, sd.scheme, sd.K, sd.alpha, sd.Pinf, rb, Ubl, dnbl, upbl, dwbl, Kb, alb);
-            double Ubg[4], dnbg[4], upbg[4], dwbg[4];
+            double U[4], dn[4], d2n[4], up[4], dw[4], U0[4];
+            inputs(st, U, dn, d2n, up, dw, U0);
+            double Ubl[4], dnbl[4], d2nbl[4], upbl[4], dwbl[4], Kb, alb;
+            char_rate_vjp<Q>(U, dn, d2n, up, dw, U0, sd.scheme, nu, sd.K, sd.alpha, sd.Pinf, rb, Ubl, dnbl, d2nbl, upbl,
+                             dwbl, Kb, alb);
+            double Ubg[4], dnbg[4], d2nbg[4], upbg[4], dwbg[4];
             rate_to_global(sd, Ubl, Ubg);
             rate_to_global(sd, dnbl, dnbg);
+            rate_to_global(sd, d2nbl, d2nbg);
             rate_to_global(sd, upbl, upbg);
             rate_to_global(sd, dwbl, dwbg);
             for (int m = 0; m < 4; ++m) {
@@ -500,6 +580,11 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
                 sGu[t * 4 + m] = upbg[m];
                 sGd[t * 4 + m] = dwbg[m];
             }
+            if constexpr (M == 3)
+                for (int m = 0; m < 4; ++m) {
+                    gself[m] += (j == M ? 2.0 : -2.0) * d2nbg[m];
+                    sG2[t * 4 + m] = d2nbg[m];
+                }
             if (owned) {
                 aK += Kb;
                 aA += alb;
@@ -533,6 +618,22 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
                 else cf = (j == q + 1) ? 0.5 : (j == q - 1 ? -0.5 : 0.0);
                 if (cf != 0.0)
                     for (int m = 0; m < 4; ++m) yb[m] += cf * sGn[((lr * M) + q - 1) * 4 + m];
+                if constexpr (M == 3) {   // second differences: backward (2, -5, 4, -1) at q = M, central below
+                    const double c2 = q == M ? (j == M - 1 ? -5.0 : (j == M - 2 ? 4.0 : 0.0))
+                                             : ((j == q + 1 || j == q - 1) ? 1.0 : 0.0);
+                    if (c2 != 0.0)
+                        for (int m = 0; m < 4; ++m) yb[m] += c2 * sG2[((lr * M) + q - 1) * 4 + m];
+                }
+            }
+            if constexpr (M == 3) {
+                // the strip x_f is layer 0 of the second differences: +1 in layer 1's central one,
+                // -1 in layer M's backward one (owned rows, as the first differences' strip terms)
+                if (owned && jj == 0)
+                    for (int m = 0; m < 4; ++m) {
+                        const double xb = sG2[(lr * M) * 4 + m] - sG2[(lr * M + M - 1) * 4 + m];
+                        sXbn[(lr * MS) * 4 + m] += (1.0 - th) * xb;
+                        sXbp[(lr * MS) * 4 + m] += th * xb;
+                    }
             }
             if (valid(r - 1)) for (int m = 0; m < 4; ++m) yb[m] += sGu[((lr - 1) * M + jj) * 4 + m];
             if (valid(r + 1)) for (int m = 0; m < 4; ++m) yb[m] += sGd[((lr + 1) * M + jj) * 4 + m];

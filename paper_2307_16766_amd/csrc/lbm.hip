@@ -331,17 +331,23 @@ int launch_init(lbm_ctx* c, const double* rho, const double* ux, const double* u
 }
 
 // ---------------------------------------------------------------- discrete adjoint (host side)
-int adjoint_supported(const lbm_config& g, const int* meso, std::string& err) {
+int adjoint_supported(const lbm_config& g, const int* meso, const int* vfd, std::string& err) {
     for (int s = 0; s < 4; ++s)
         if (meso[s] != LBM_RECON_EQUILIBRIUM) {
             err = "the adjoint supports the equilibrium reconstruction only";
             return LBM_E_UNSUPPORTED;
         }
-    for (int s = 0; s < 4; ++s)
-        if (g.bc[s] != BC_PERIODIC && g.bc[s] != BC_LODI && g.bc[s] != BC_LODI_RELAX) {
-            err = "the adjoint supports periodic, LODI and LODI-RELAX sides only";
+    for (int s = 0; s < 4; ++s) {
+        const int b = g.bc[s];
+        if (b != BC_PERIODIC && b != BC_LODI && b != BC_LODI_RELAX && !is_full(b)) {
+            err = "the adjoint supports periodic, LODI, LODI-RELAX, CBC and CBC-RELAX sides only";
             return LBM_E_UNSUPPORTED;
         }
+        if (is_full(b) && vfd[s] != LBM_VISC_FD) {
+            err = "the adjoint of a CBC side needs the finite-difference viscous terms (lbm_viscous, LBM_VISC_FD)";
+            return LBM_E_UNSUPPORTED;
+        }
+    }
     if (g.stencil == 9 && g.bc[0] != BC_PERIODIC && g.bc[2] != BC_PERIODIC) {
         err = "the D2Q9 adjoint needs one periodic axis (no corners)";
         return LBM_E_UNSUPPORTED;
@@ -423,10 +429,12 @@ int run_adjoint(lbm_ctx* c, const double* seed, double* grad, double* h_relax) {
         }
     bool any_corner = false;
     for (int ci = 0; ci < 4; ++ci) any_corner = any_corner || L.c[ci].active;
-    // the sides' transverse terms reach the corner values only through transverse relaxation
+    // the sides' transverse terms reach the corner values through transverse relaxation (LODI-RELAX)
+    // and always on CBC sides
     g.coupled = 0;
     for (int s = 0; s < 4; ++s)
-        if (any_corner && c->cfg.bc[s] == BC_LODI_RELAX && c->relax[s].alpha != 0.0) g.coupled = 1;
+        if (any_corner && ((c->cfg.bc[s] == BC_LODI_RELAX && c->relax[s].alpha != 0.0) || is_full(c->cfg.bc[s])))
+            g.coupled = 1;
     const int nside_blocks = t.nadj + ((any_corner && !g.coupled) ? 4 : 0);
 
     // Segment seg is recomputed from its checkpoint on the second stream into recomputation set
@@ -514,7 +522,7 @@ int run_adjoint(lbm_ctx* c, const double* seed, double* grad, double* h_relax) {
         if (s < 2)
             for (int ci = 0; ci < 4; ++ci)
                 if (L.c[ci].active && (ci & 1) == s) dK += acc[2 * t.nadj + ci];
-        const bool rel = c->cfg.bc[s] == BC_LODI_RELAX;
+        const bool rel = is_relax(c->cfg.bc[s]);
         h_relax[2 * s] = rel ? dK * kf : 0.0;
         h_relax[2 * s + 1] = rel ? dA : 0.0;
     }
@@ -741,7 +749,7 @@ size_t lbm_tape_bytes(const lbm_ctx* c, int nsteps, int every) {
 int lbm_record(lbm_ctx* c, int nsteps, int every, void* d_tape, size_t tape_bytes) {
     if (!c) return fail(nullptr, LBM_E_ARG, "null context");
     std::string err;
-    const int sup = adjoint_supported(c->cfg, c->meso, err);
+    const int sup = adjoint_supported(c->cfg, c->meso, c->vfd, err);
     if (sup != LBM_OK) return fail(c, sup, err);
     if (nsteps < 1 || every < 1) return fail(c, LBM_E_ARG, "nsteps and every must be positive");
     if (!d_tape || ((uintptr_t)d_tape % ALIGN) != 0) return fail(c, LBM_E_ARG, "tape must be non-NULL and 256-byte aligned");
@@ -769,6 +777,9 @@ int lbm_adjoint(lbm_ctx* c, const double* d_seed, double* d_grad_fields, double*
     if (!d_grad_fields || !h_grad_relax) return fail(c, LBM_E_ARG, "output pointer is NULL");
     if (!c->tape.base) return fail(c, LBM_E_STATE, "no recorded run (call lbm_record first)");
     if (c->steps != c->tape.step_end) return fail(c, LBM_E_STATE, "the context has stepped since lbm_record");
+    std::string err;
+    const int sup = adjoint_supported(c->cfg, c->meso, c->vfd, err);
+    if (sup != LBM_OK) return fail(c, sup, err);
     return dispatch(c, [&]<int Q, typename T>() -> int { return run_adjoint<Q, T>(c, d_seed, d_grad_fields, h_grad_relax); });
 }
 

@@ -23,10 +23,12 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c4_
 ADJ_TOL = 1e-9   # adjoint vs dual numbers, relative
 
 
-def _sim(stencil, nx, ny, tau, bc, fields, relax, precision="fp64"):
+def _sim(stencil, nx, ny, tau, bc, fields, relax, precision="fp64", visc=None):
     from paper_2307_16766_amd import lbm
     g = lbm.LBM(stencil, nx, ny, tau, bc, fields, precision=precision)
     g.set_relax(-1, **relax)
+    if visc is not None:
+        g.set_viscous(-1, visc)
     return g
 
 
@@ -53,7 +55,21 @@ CASES = {
     # D2Q9 isothermal, LODI-RELAX at both x sides, periodic y with two row chunks per side
     "d2q9_periodic_y": dict(stencil=9, nx=40, ny=300, tau=0.6, bc=["lodi_relax", "lodi_relax", "periodic", "periodic"],
                             steps=40, every=9, relax=dict(sigma=0.25, alpha=0.1, mach=0.05)),
+    # D2Q37, CBC-RELAX / CBC / LODI-RELAX / CBC-RELAX sides with corners, -FD viscous terms
+    # (Sec. 4.2): transverse and viscous terms in the rate and in the incoming amplitudes
+    "d2q37_cbc_corners": dict(stencil=37, nx=70, ny=96, tau=TAU_37, bc=["cbc_relax", "cbc", "lodi_relax", "cbc_relax"],
+                              steps=30, every=11, relax=dict(sigma=0.25, alpha=0.1, mach=0.05), visc="fd"),
+    # D2Q17, CBC outflow and CBC-RELAX inflow, periodic y, -FD viscous terms
+    "d2q17_cbc_periodic_y": dict(stencil=17, nx=48, ny=40, tau=0.9, bc=["cbc_relax", "cbc", "periodic", "periodic"],
+                                 steps=30, every=30, relax=dict(sigma=0.3, alpha=0.2, mach=0.05), visc="fd"),
 }
+
+
+def _visc(c):
+    """Viscous-term mode per side for the oracle (None when the case has no CBC side)."""
+    if "visc" not in c:
+        return None
+    return [c["visc"] if b in ("cbc", "cbc_relax") else "meso" for b in c["bc"]]
 
 
 def _case_fields(c, seed):
@@ -90,8 +106,8 @@ def test_adjoint_matches_oracle_tangents(name, loss):
         wlin = np.random.default_rng(33).standard_normal((4, c["ny"], c["nx"]))
     # direction 0: sigma and alpha together; 1, 2: field perturbations
     oloss, od = O.tangent_run_fields(c["stencil"], c["nx"], c["ny"], c["tau"], c["bc"], relax, [1, 0, 0], [0.5, 0, 0],
-                                     fields, dF, c["steps"], wlin)
-    g = _sim(c["stencil"], c["nx"], c["ny"], c["tau"], c["bc"], fields, c["relax"])
+                                     fields, dF, c["steps"], wlin, visc=_visc(c))
+    g = _sim(c["stencil"], c["nx"], c["ny"], c["tau"], c["bc"], fields, c["relax"], visc=c.get("visc"))
     g.record(c["steps"], c["every"])
     d = g.diagnostics()
     if loss == "pressure":
@@ -150,8 +166,14 @@ def test_adjoint_argument_and_state_errors():
     from paper_2307_16766_amd import lbm
     f = W.temperature_pulse(40, 40)
     g = lbm.LBM(37, 40, 40, TAU_37, ["lodi_relax", "cbc_relax", "lodi", "lodi"], f)
-    with pytest.raises(lbm.LBMError) as e:
+    with pytest.raises(lbm.LBMError) as e:   # CBC with the mesoscopic viscous terms
         g.record(5, 2)
+    assert e.value.code == lbm.LBM_E_UNSUPPORTED
+    g.set_viscous(1, "fd")
+    g.record(5, 2)
+    g.set_viscous(1, "meso")                 # settings changed after the recording
+    with pytest.raises(lbm.LBMError) as e:
+        g.adjoint()
     assert e.value.code == lbm.LBM_E_UNSUPPORTED
     g.close()
     g = lbm.LBM(37, 40, 40, TAU_37, ["lodi_relax"] * 4, f)
@@ -289,4 +311,51 @@ def test_c4_with_background_flow_against_finite_differences():
     loss, adj, fd = _c4_gradient_and_fd(fields, dirs)
     errs = {k: _relerr(adj[k], fd[k]) for k in adj}
     log(f"C4 flow loss {loss}\n adjoint {adj}\n finite differences {fd}\n rel errors {errs}")
+    assert max(errs.values()) < 1e-4
+
+
+def test_cbc_adjoint_against_finite_differences():
+    # CBC-RELAX / CBC / CBC-RELAX / LODI-RELAX sides with corners and the -FD viscous terms
+    # (Sec. 4.2), 128 x 128 D2Q37 over a diagonal background flow (u_n keeps its sign at every
+    # boundary node, so the map is smooth): central differences of the GPU FP64 forward run with
+    # h = 1e-6 on sigma, alpha and three T0 directions match the adjoint within 1e-4.
+    log("[gpu-case] CBC adjoint against finite differences, 128x128, 300 steps")
+    n, steps = 128, 300
+    bc = ["cbc_relax", "cbc", "cbc_relax", "lodi_relax"]
+    relax0 = dict(sigma=0.25, alpha=0.1, mach=0.05)
+    rho, ux, uy, T = W.random_temperature(n, n, std=1e-4, seed=4213)
+    fields = [rho, ux + 0.02, uy + 0.015, T]
+    dirs = W.random_directions(3, n, n, 4214)
+
+    def loss_of(f, relax):
+        g = _sim(37, n, n, TAU_37, bc, f, relax, visc="fd")
+        g.step(steps)
+        v = g.diagnostics()[4]
+        g.close()
+        return v
+
+    g = _sim(37, n, n, TAU_37, bc, fields, relax0, visc="fd")
+    g.record(steps, 40)
+    loss = g.diagnostics()[4]
+    grad, grel = g.adjoint()
+    gT = grad[3].cpu().numpy()
+    g.close()
+    assert _relerr(loss, loss_of(fields, relax0)) < 1e-13
+    # sigma and alpha act on the relaxed sides only (the sum over sides is the derivative)
+    adj = {"sigma": grel[:, 0].sum(), "alpha": grel[:, 1].sum()}
+    for k in range(3):
+        adj[f"T{k}"] = float((gT * dirs[k]).sum())
+    h = 1e-6
+    fd = {}
+    for par in ("sigma", "alpha"):
+        fd[par] = (loss_of(fields, dict(relax0, **{par: relax0[par] + h}))
+                   - loss_of(fields, dict(relax0, **{par: relax0[par] - h}))) / (2 * h)
+    for k in range(3):
+        fp, fm = list(fields), list(fields)
+        fp[3] = fields[3] + h * dirs[k]
+        fm[3] = fields[3] - h * dirs[k]
+        fd[f"T{k}"] = (loss_of(fp, relax0) - loss_of(fm, relax0)) / (2 * h)
+    errs = {k: _relerr(adj[k], fd[k]) for k in adj}
+    log(f"CBC loss {loss}\n adjoint {adj}\n finite differences {fd}\n rel errors {errs}")
+    assert all(abs(v) > 0 for v in adj.values())
     assert max(errs.values()) < 1e-4
