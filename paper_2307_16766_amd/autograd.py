@@ -3,8 +3,8 @@
 ``simulate(sigma, alpha, rho0, ux0, uy0, T0, ...)`` runs ``nsteps`` steps from the given initial
 fields with the relaxation parameters sigma and alpha on every LODI-RELAX and CBC-RELAX side and
 returns the final macroscopic fields stacked as a (4, ny, nx) float64 tensor (rho, ux, uy, T).
-CBC and CBC-RELAX sides run with the finite-difference viscous terms (Sec. 4.2, "Treatment of
-viscous terms"), the variant the adjoint differentiates.  Its backward
+CBC and CBC-RELAX sides take the mesoscopic viscous terms, or with ``visc="fd"`` those of the
+-FD variant (Sec. 4.2, "Treatment of viscous terms").  Its backward
 calls ``lbm_adjoint`` with dL/d(output) as the seed: the gradient flows to sigma, alpha and the
 four initial fields.  Forward and backward both run in the HIP library; torch supplies memory,
 the stream and the autograd graph.
@@ -23,8 +23,8 @@ class ThermalLBMFunction(torch.autograd.Function):
         relax_sides = [s for s, b in enumerate(spec["bc"]) if b in ("lodi_relax", "cbc_relax")]
         for s in relax_sides:
             sim.set_relax(s, sigma=float(sigma), alpha=float(alpha), **relax)
-        if any(b in ("cbc", "cbc_relax") for b in spec["bc"]):
-            sim.set_viscous(-1, "fd")
+        if spec.get("visc"):
+            sim.set_viscous(-1, spec["visc"])
         sim.record(spec["nsteps"], spec.get("every", 50))
         out = torch.stack(sim.macroscopic())
         ctx.sim = sim
@@ -46,9 +46,9 @@ class ThermalLBMFunction(torch.autograd.Function):
 
 
 def simulate(sigma, alpha, rho0, ux0, uy0, T0, *, stencil, nx, ny, tau, bc, nsteps, every=50, precision="fp64",
-             relax=None):
+             relax=None, visc=None):
     """Final (rho, ux, uy, T) after nsteps steps, differentiable with respect to sigma, alpha
     (0-d tensors) and the initial fields ((ny, nx) tensors on the GPU)."""
     spec = dict(stencil=stencil, nx=nx, ny=ny, tau=tau, bc=list(bc), nsteps=nsteps, every=every,
-                precision=precision, relax=relax or {})
+                precision=precision, relax=relax or {}, visc=visc)
     return ThermalLBMFunction.apply(sigma, alpha, rho0, ux0, uy0, T0, spec)

@@ -156,18 +156,20 @@ __device__ __forceinline__ double phi_dot(int i, const double* GM) {
     return v;
 }
 
-// VJP of char_rate for the four schemes of Tab. CBCs; the CBC variants with the viscous terms of
-// the -FD variant (Sec. 4.2), evaluated from the stage values as in the forward step:
+// VJP of char_rate for the four schemes of Tab. CBCs.  Viscous terms of the CBC variants: with
+// vfd, those of the -FD variant (Sec. 4.2), evaluated from the stage values as in the forward step:
 // V = (0, nu lap u_n, nu lap u_t, 2 nu lap T + (nu / cs^2)(sa^2 + sb^2)), lap = d2n + up - 2 U +
-// dw, sa = dn u_n - d_t u_t, sb = d_t u_n + dn u_t.  Inputs as char_rate plus the second normal
-// difference d2n; rb = adjoint of the rate; outputs the adjoints of U, dn, d2n, up, dw
-// (side-local components) and of K and alpha.  The wave directions are frozen at time t (no
-// derivative).
+// dw, sa = dn u_n - d_t u_t, sb = d_t u_n + dn u_t, differentiated through the stage values;
+// without vfd, the mesoscopic terms Vin (frozen over the stages, an input), whose adjoint is
+// returned in Vb.  Inputs as char_rate plus the second normal difference d2n; rb = adjoint of
+// the rate; outputs the adjoints of U, dn, d2n, up, dw (side-local components), of V and of K
+// and alpha.  The wave directions are frozen at time t (no derivative).
 template <int Q>
 __device__ __forceinline__ void char_rate_vjp(const double* U, const double* dn, const double* d2n, const double* up,
-                                              const double* dw, const double* U0, int scheme, double nu, double K,
-                                              double alpha, double Pinf, const double* rb, double* Ub, double* dnb,
-                                              double* d2nb, double* upb, double* dwb, double& Kb, double& alb) {
+                                              const double* dw, const double* Vin, const double* U0, int scheme,
+                                              int vfd, double nu, double K, double alpha, double Pinf, const double* rb,
+                                              double* Ub, double* dnb, double* d2nb, double* upb, double* dwb,
+                                              double* Vb, double& Kb, double& alb) {
     constexpr bool THERMAL = Lat<Q>::thermal;
     constexpr double cs2 = Lat<Q>::cs2;
     constexpr double cs = Lat<Q>::cs;
@@ -177,23 +179,27 @@ __device__ __forceinline__ void char_rate_vjp(const double* U, const double* dn,
     const double ir = 1.0 / rho;
     const double T1 = -0.5 * (up[0] * up[2] - dw[0] * dw[2]);
     const double T2 = -v * 0.5 * (up[1] - dw[1]);
-    const double T3 = THERMAL ? -cs2 * ir * 0.5 * (up[0] * up[3] - dw[0] * dw[3]) - v * 0.5 * (up[2] - dw[2]) : 0.0;
+    // T3 enters the rate and in2 linearly: only its adjoint T3b is needed
     const double T4 = THERMAL ? -0.5 * (up[3] * up[2] - dw[3] * dw[2]) : 0.0;
     const double u0 = U0[1];
     double rhob = 0.0, ub = 0.0, vb = 0.0, Tb = 0.0, T1b = 0.0, T2b = 0.0, T3b = 0.0, T4b = 0.0;
-    for (int m = 0; m < 4; ++m) { dnb[m] = 0.0; d2nb[m] = 0.0; upb[m] = 0.0; dwb[m] = 0.0; }
+    for (int m = 0; m < 4; ++m) { dnb[m] = 0.0; d2nb[m] = 0.0; upb[m] = 0.0; dwb[m] = 0.0; Vb[m] = 0.0; }
     Kb = 0.0;
     alb = 0.0;
     if (THERMAL) {
-        // viscous terms of the -FD variant (zero for the LODI schemes)
+        // viscous terms (zero for the LODI schemes)
         double lap[4] = {0.0, 0.0, 0.0, 0.0}, V1 = 0.0, V2 = 0.0, V3 = 0.0, sa = 0.0, sh = 0.0;
-        if (full) {
+        if (full && vfd) {
             for (int m = 1; m < 4; ++m) lap[m] = d2n[m] + up[m] - 2.0 * U[m] + dw[m];
             sa = dn[1] - 0.5 * (up[2] - dw[2]);
             sh = 0.5 * (up[1] - dw[1]) + dn[2];
             V1 = nu * lap[1];
             V2 = nu * lap[2];
             V3 = 2.0 * nu * lap[3] + nu * (1.0 / cs2) * (sa * sa + sh * sh);
+        } else if (full) {
+            V1 = Vin[1];
+            V2 = Vin[2];
+            V3 = Vin[3];
         }
         const double s = sqrt(2.0 * cs2 * T);
         const double s0 = sqrt(2.0 * cs2 * U0[3]);
@@ -282,7 +288,12 @@ __device__ __forceinline__ void char_rate_vjp(const double* U, const double* dn,
         Tb += ab * 0.25 * ir;
         rhob += -ab * 0.25 * T * ir * ir;
         Tb += sb * cs2 / s;
-        if (full) {
+        if (full && !vfd) {
+            Vb[1] = V1b;
+            Vb[2] = V2b;
+            Vb[3] = V3b;
+        }
+        if (full && vfd) {
             // viscous terms: lap = d2n + up - 2 U + dw; heating from sa and sh
             const double lb[4] = {0.0, nu * V1b, nu * V2b, 2.0 * nu * V3b};
             const double sab = 2.0 * nu * (1.0 / cs2) * sa * V3b, shb = 2.0 * nu * (1.0 / cs2) * sh * V3b;
@@ -300,6 +311,8 @@ __device__ __forceinline__ void char_rate_vjp(const double* U, const double* dn,
             upb[1] += 0.5 * shb;
             dwb[1] += -0.5 * shb;
             dnb[2] += shb;
+        }
+        if (full) {
             // T3 = -cs^2 / rho * (d_t (rho T)) - v d_t u_t (central differences)
             rhob += cs2 * ir * ir * 0.5 * (up[0] * up[3] - dw[0] * dw[3]) * T3b;
             upb[0] += -cs2 * ir * 0.5 * up[3] * T3b;
@@ -382,10 +395,10 @@ __device__ __forceinline__ void corner_rate_vjp(const CornerDev& c, const double
     rl[1] = rb[1] * c.ndx + rb[2] * c.ndy;
     rl[2] = rb[1] * tdx + rb[2] * tdy;
     rl[3] = rb[3];
-    double Ub[4], dnb[4], d2nb[4], upb[4], dwb[4], alb;
+    double Ub[4], dnb[4], d2nb[4], upb[4], dwb[4], Vb[4], alb;
     const double zero4[4] = {0.0, 0.0, 0.0, 0.0};
-    char_rate_vjp<Q>(l0, dn, zero4, l0, l0, ln, c.relax ? BC_LODI_RELAX : BC_LODI, 0.0, c.K, 0.0, c.Pinf, rl, Ub,
-                     dnb, d2nb, upb, dwb, Kb, alb);
+    char_rate_vjp<Q>(l0, dn, zero4, l0, l0, zero4, ln, c.relax ? BC_LODI_RELAX : BC_LODI, 0, 0.0, c.K, 0.0, c.Pinf, rl,
+                     Ub, dnb, d2nb, upb, dwb, Vb, Kb, alb);
     double a0[4], a1[4], a2[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -416,6 +429,7 @@ struct AdjArgs {
     int cside[4][2];         // per corner: adjacent side of each axis (-1 if none)
     int crow[4][2];          // per corner: that side's row next to the corner
     int coupled;             // corners read the sides' contributions (transverse relaxation alpha != 0)
+    int vism;                // some CBC side uses the mesoscopic viscous terms
 };
 
 // ------------------------------------------------------------------ reverse of a side chunk
@@ -430,6 +444,7 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
     __shared__ double sG[NN * 4];               // adjoint of the stage input of the later stage
     __shared__ double sGn[NN * 4], sGu[NN * 4], sGd[NN * 4];   // per node: adjoints of dn, up, dw
     __shared__ double sG2[(M == 3 ? NN : 1) * 4];              // per node: adjoint of d2n (-FD viscous terms)
+    __shared__ double sVr[NR * 4];                             // per row: mesoscopic viscous terms of time n
     __shared__ double sXn[NR * MS * 4], sXp[NR * MS * 4];       // strip values at n, n+1
     __shared__ double sXbn[NR * MS * 4], sXbp[NR * MS * 4];     // strip adjoints (owned rows)
     __shared__ double sC[2][2][4];
@@ -488,6 +503,17 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
         sC[e][w][m] = ((const double*)(reg + a.c[ci].off_cu))[m];
     }
     if (tid < 2 * 2 * M * 4) (&sCb[0][0][0][0])[tid] = 0.0;
+    // mesoscopic viscous terms of time n (CBC sides without -FD), as in the forward step
+    const bool meso_v = (sd.scheme == BC_CBC || sd.scheme == BC_CBC_RELAX) && !sd.vfd;
+    const double nu = (a.tau - 0.5) * Lat<Q>::cs2;
+    const double* visn = meso_v ? (const double*)(a.reg_cur + sd.off_vis) : nullptr;
+    for (int l2 = tid; l2 < NR; l2 += blockDim.x) {
+        const int rr = r0 - H + l2;
+        for (int m = 0; m < 4; ++m) sVr[l2 * 4 + m] = 0.0;
+        if (meso_v && valid(rr))
+            visc_terms_row<Q>(visn, len, phys(rr), valid(rr + 1) ? phys(rr + 1) : -1, valid(rr - 1) ? phys(rr - 1) : -1,
+                              nu, &sVr[l2 * 4]);
+    }
     __syncthreads();
 
     const double ast[4] = {0.0, 0.5, 0.5, 1.0}, bst[4] = {1.0, 2.0, 2.0, 1.0};
@@ -538,7 +564,6 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
         val_t(r - 1, dw);
         to_local(sd, &sY[0][t * 4], U0);
     };
-    const double nu = (a.tau - 0.5) * Lat<Q>::cs2;
 
     // ---- phase B: stage inputs Y_1..Y_3, stored by the recomputation of this step --------------
     {
@@ -555,6 +580,7 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
     double ybn[4];   // adjoint of U_b^n (owned rows)
     for (int m = 0; m < 4; ++m) ybn[m] = owned ? sYb1[t * 4 + m] : 0.0;
     double aK = 0.0, aA = 0.0;
+    double vacc[4] = {0.0, 0.0, 0.0, 0.0};   // adjoint of this node's mesoscopic V, summed over the stages
     for (int st = 3; st >= 0; --st) {
         const double th = ast[st];
         double gself[4] = {0, 0, 0, 0};
@@ -565,9 +591,10 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
             to_local(sd, kb, rb);
             double U[4], dn[4], d2n[4], up[4], dw[4], U0[4];
             inputs(st, U, dn, d2n, up, dw, U0);
-            double Ubl[4], dnbl[4], d2nbl[4], upbl[4], dwbl[4], Kb, alb;
-            char_rate_vjp<Q>(U, dn, d2n, up, dw, U0, sd.scheme, nu, sd.K, sd.alpha, sd.Pinf, rb, Ubl, dnbl, d2nbl, upbl,
-                             dwbl, Kb, alb);
+            double Ubl[4], dnbl[4], d2nbl[4], upbl[4], dwbl[4], Vbl[4], Kb, alb;
+            char_rate_vjp<Q>(U, dn, d2n, up, dw, &sVr[lr * 4], U0, sd.scheme, sd.vfd, nu, sd.K, sd.alpha, sd.Pinf, rb,
+                             Ubl, dnbl, d2nbl, upbl, dwbl, Vbl, Kb, alb);
+            for (int m = 0; m < 4; ++m) vacc[m] += Vbl[m];
             double Ubg[4], dnbg[4], d2nbg[4], upbg[4], dwbg[4];
             rate_to_global(sd, Ubl, Ubg);
             rate_to_global(sd, dnbl, dnbg);
@@ -647,6 +674,71 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
     if (owned) {
         const int rp = phys(r);
         for (int m = 0; m < 4; ++m) mub0[((size_t)jj * len + rp) * 4 + m] = ybn[m];
+    }
+    if (meso_v) {
+        // adjoint of the viscous moments of time n at x_f, x_f - 1, x_f - 2 of the owned rows, from
+        // the adjoints of V of rows r - 1, r, r + 1 (complete on rows within one of the owned
+        // range); k_adj_bulk adds it to nu^n through the moments' derivatives
+        if (t < NN)
+            for (int m = 0; m < 4; ++m) sGn[t * 4 + m] = node ? vacc[m] : 0.0;
+        __syncthreads();
+        constexpr double cs2 = Lat<Q>::cs2;
+        double* visb = (double*)(g.adj_cur + sd.off_vis);
+        for (int e = tid; e < r1 - r0; e += blockDim.x) {
+            const int rr = r0 + e, l2 = H + e, rp = phys(rr);
+            auto vsum = [&](int l, double* o) {
+                for (int m = 0; m < 4; ++m) {
+                    o[m] = 0.0;
+                    for (int q = 0; q < M; ++q) o[m] += sGn[(l * M + q) * 4 + m];
+                }
+            };
+            const bool hm = valid(rr - 1), hp = valid(rr + 1);
+            double Vb0[4], Vbm[4] = {0.0, 0.0, 0.0, 0.0}, Vbp[4] = {0.0, 0.0, 0.0, 0.0};
+            vsum(l2, Vb0);
+            if (hm) vsum(l2 - 1, Vbm);
+            if (hp) vsum(l2 + 1, Vbp);
+            const double* w0 = &visn[((size_t)0 * len + rp) * 6];
+            const double* w1 = &visn[((size_t)1 * len + rp) * 6];
+            const double* w2 = &visn[((size_t)2 * len + rp) * 6];
+            double upv[6] = {0, 0, 0, 0, 0, 0}, dwv[6] = {0, 0, 0, 0, 0, 0};
+            if (hp) for (int m = 0; m < 6; ++m) upv[m] = visn[((size_t)0 * len + phys(rr + 1)) * 6 + m];
+            if (hm) for (int m = 0; m < 6; ++m) dwv[m] = visn[((size_t)0 * len + phys(rr - 1)) * 6 + m];
+            auto dn_ = [&](int m) { return 0.5 * (3.0 * w0[m] - 4.0 * w1[m] + w2[m]); };
+            auto dt_ = [&](int m) { return 0.5 * (upv[m] - dwv[m]); };
+            const double ir = 1.0 / w0[0];
+            const double X1 = dn_(1) + dt_(2), X2 = dn_(2) + dt_(3), X3 = dn_(4) + dt_(5);
+            const double heat = (0.5 * (w0[1] * w0[1] + w0[3] * w0[3]) + w0[2] * w0[2]) * ir * ir / (nu * cs2);
+            // V_n = X1 / rho, V_t = X2 / rho, V_T = -X3 / (rho cs^2) + heat, heat ~ 1 / rho^2
+            const double A1 = Vb0[1] * ir, A2 = Vb0[2] * ir, A3 = -Vb0[3] * ir / cs2;
+            const double ck[3] = {1.5, -2.0, 0.5};
+            double vb[3][6];
+            for (int k = 0; k < 3; ++k) {
+                for (int m = 0; m < 6; ++m) vb[k][m] = 0.0;
+                vb[k][1] = ck[k] * A1;
+                vb[k][2] = ck[k] * A2;
+                vb[k][4] = ck[k] * A3;
+            }
+            vb[0][0] = -(Vb0[1] * X1 + Vb0[2] * X2) * ir * ir + Vb0[3] * (X3 * ir * ir / cs2 - 2.0 * heat * ir);
+            const double hh = Vb0[3] * ir * ir / (nu * cs2);
+            vb[0][1] += hh * w0[1];
+            vb[0][2] += 2.0 * hh * w0[2];
+            vb[0][3] += hh * w0[3];
+            // rows r - 1 and r + 1 take this row's x_f moments in their differences along the side
+            if (hm) {
+                const double irm = 1.0 / dwv[0];
+                vb[0][2] += 0.5 * Vbm[1] * irm;
+                vb[0][3] += 0.5 * Vbm[2] * irm;
+                vb[0][5] += -0.5 * Vbm[3] * irm / cs2;
+            }
+            if (hp) {
+                const double irp = 1.0 / upv[0];
+                vb[0][2] -= 0.5 * Vbp[1] * irp;
+                vb[0][3] -= 0.5 * Vbp[2] * irp;
+                vb[0][5] -= -0.5 * Vbp[3] * irp / cs2;
+            }
+            for (int k = 0; k < 3; ++k)
+                for (int m = 0; m < 6; ++m) visb[((size_t)k * len + rp) * 6 + m] = vb[k][m];
+        }
     }
     // strips: adjoint of X^n (a time-n input) for the next reverse step; the adjoint of X^{n+1}
     // (this step's new value plus the previous reverse step's time-(n+1) input) is added to
@@ -896,6 +988,40 @@ __global__ __launch_bounds__(256) void k_adj_bulk(AdjArgs g, BulkArgs k, int bpr
     const double om = k.omega_d;
 #pragma unroll
     for (int i = 0; i < Q; ++i) out[(unsigned long long)i * pitch] = (1.0 - om) * lam[i] + om * phi_dot<Q>(i, GM);
+    if (Lat<Q>::thermal && g.vism) {
+        // nodes x_f, x_f - 1, x_f - 2 of a CBC side with the mesoscopic viscous terms: the moments
+        // Pi' and q of eq. LaplaceU / LaplaceT taken from g^n there (time-n inputs of the next
+        // step's V); with d = c_i - u, f = 1 - 1/(2 tau):
+        //   d Pi'_ab / d g_i = -f (d_a d_b - |d|^2 delta_ab / 2),
+        //   d q_a / d g_i = f (|d|^2 / 2 - 2 cs^2 T) d_a + Pi'_ab d_b / rho,  d rho / d g_i = 1
+#pragma unroll
+        for (int sd = 0; sd < 4; ++sd) {
+            const SideDev& S = g.b.s[sd];
+            if (S.kind != KIND_CHAR || !(S.scheme == BC_CBC || S.scheme == BC_CBC_RELAX) || S.vfd) continue;
+            const bool xn = S.nax == 0;
+            const int nc = xn ? x : y, tc = xn ? y : x;
+            const int kk = (S.xf - nc) * S.sn, rr = tc - S.r0;
+            if (kk < 0 || kk > 2 || rr < 0 || rr >= S.len) continue;
+            const size_t o6 = ((size_t)kk * S.len + rr) * 6;
+            const double* vb = (const double*)(g.adj_cur + S.off_vis) + o6;
+            const double* w = (const double*)(g.b.reg_cur + S.off_vis) + o6;
+            // side-local (n, t) components to global (x, y)
+            const double sn = S.sn;
+            const double Pbxx = xn ? vb[1] : vb[3], Pbyy = xn ? vb[3] : vb[1], Pbxy = sn * vb[2];
+            const double Qbx = xn ? sn * vb[4] : vb[5], Qby = xn ? vb[5] : sn * vb[4];
+            const double Pxx = xn ? w[1] : w[3], Pyy = xn ? w[3] : w[1], Pxy = sn * w[2];
+            const double Rb = vb[0];
+            const double fac = 1.0 - 0.5 / g.b.tau, ir = 1.0 / m[0], ct = 2.0 * Lat<Q>::cs2 * m[3];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const double d0 = cx<Q>(i) - m[1], d1 = cy<Q>(i) - m[2], h = 0.5 * (d0 * d0 + d1 * d1);
+                double v = Rb - fac * (Pbxx * (d0 * d0 - h) + Pbyy * (d1 * d1 - h) + Pbxy * d0 * d1);
+                v += Qbx * (fac * (h - ct) * d0 + (Pxx * d0 + Pxy * d1) * ir);
+                v += Qby * (fac * (h - ct) * d1 + (Pxy * d0 + Pyy * d1) * ir);
+                out[(unsigned long long)i * pitch] += v;
+            }
+        }
+    }
 }
 
 // ------------------------------------------------------------------ seed at the final step

@@ -463,6 +463,34 @@ __device__ __forceinline__ void visc_moments(const SideDev& s, const double* d, 
     o6[5] = s.nax == 0 ? qy : qx;
 }
 
+// Mesoscopic viscous terms V (side-local: 0, V_n, V_t, V_T of eq. NSF-CHAR with eq. LaplaceU /
+// LaplaceT) of one side row rp from the viscous moments vis[k][len][6] of x_f, x_f - 1, x_f - 2:
+// divergence of Pi' and q one-sided along the normal at x_f (eq. FD-dx-bw) and central along the
+// side between rows rup and rdw (-1: no row there, its moments taken as 0), plus the viscous
+// heating Pi':Pi' / mu.
+template <int Q>
+__device__ __forceinline__ void visc_terms_row(const double* vis, int len, int rp, int rup, int rdw, double nu,
+                                               double* V) {
+    const double* v0 = &vis[((size_t)0 * len + rp) * 6];
+    const double* v1 = &vis[((size_t)1 * len + rp) * 6];
+    const double* v2 = &vis[((size_t)2 * len + rp) * 6];
+    double upv[6] = {0, 0, 0, 0, 0, 0}, dwv[6] = {0, 0, 0, 0, 0, 0};
+    if (rup >= 0) for (int m = 0; m < 6; ++m) upv[m] = vis[((size_t)0 * len + rup) * 6 + m];
+    if (rdw >= 0) for (int m = 0; m < 6; ++m) dwv[m] = vis[((size_t)0 * len + rdw) * 6 + m];
+    auto dn_ = [&](int m) { return 0.5 * (3.0 * v0[m] - 4.0 * v1[m] + v2[m]); };
+    auto dt_ = [&](int m) { return 0.5 * (upv[m] - dwv[m]); };
+    const double rho = v0[0];
+    V[0] = 0.0;
+    V[1] = (dn_(1) + dt_(2)) / rho;
+    V[2] = (dn_(2) + dt_(3)) / rho;
+    double vt = 0.0;
+    if (Lat<Q>::thermal) {
+        const double heat = (0.5 * (v0[1] * v0[1] + v0[3] * v0[3]) + v0[2] * v0[2]) / (rho * rho * nu * Lat<Q>::cs2);
+        vt = -(dn_(4) + dt_(5)) / (rho * Lat<Q>::cs2) + heat;
+    }
+    V[3] = vt;
+}
+
 // corner LODI along the outward diagonal, rate in global components
 template <int Q>
 __device__ __forceinline__ void corner_rate(const CornerDev& c, const double* Uc, const double* U1, const double* U2,
@@ -600,25 +628,8 @@ __device__ void char_chunk(const T* __restrict__ A, T* __restrict__ B, const Bnd
         for (int lr = tid; lr < NR; lr += blockDim.x) {
             const int r = r0 - 4 + lr;
             if (!valid(r)) continue;
-            const int rp = phys(r);
-            const double* v0 = &vis[((size_t)0 * len + rp) * 6];
-            const double* v1 = &vis[((size_t)1 * len + rp) * 6];
-            const double* v2 = &vis[((size_t)2 * len + rp) * 6];
-            double upv[6] = {0, 0, 0, 0, 0, 0}, dwv[6] = {0, 0, 0, 0, 0, 0};
-            if (valid(r + 1)) for (int m = 0; m < 6; ++m) upv[m] = vis[((size_t)0 * len + phys(r + 1)) * 6 + m];
-            if (valid(r - 1)) for (int m = 0; m < 6; ++m) dwv[m] = vis[((size_t)0 * len + phys(r - 1)) * 6 + m];
-            auto dn_ = [&](int m) { return 0.5 * (3.0 * v0[m] - 4.0 * v1[m] + v2[m]); };
-            auto dt_ = [&](int m) { return 0.5 * (upv[m] - dwv[m]); };
-            const double rho = v0[0];
-            sV[lr * 4 + 0] = 0.0;
-            sV[lr * 4 + 1] = (dn_(1) + dt_(2)) / rho;
-            sV[lr * 4 + 2] = (dn_(2) + dt_(3)) / rho;
-            double vt = 0.0;
-            if (TH) {
-                const double heat = (0.5 * (v0[1] * v0[1] + v0[3] * v0[3]) + v0[2] * v0[2]) / (rho * rho * nu * Lat<Q>::cs2);
-                vt = -(dn_(4) + dt_(5)) / (rho * Lat<Q>::cs2) + heat;
-            }
-            sV[lr * 4 + 3] = vt;
+            visc_terms_row<Q>(vis, len, phys(r), valid(r + 1) ? phys(r + 1) : -1, valid(r - 1) ? phys(r - 1) : -1, nu,
+                              &sV[lr * 4]);
         }
     }
     // corners at the ends of a side with non-periodic rows: time-n value, and the pull of the two

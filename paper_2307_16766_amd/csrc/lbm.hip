@@ -331,7 +331,7 @@ int launch_init(lbm_ctx* c, const double* rho, const double* ux, const double* u
 }
 
 // ---------------------------------------------------------------- discrete adjoint (host side)
-int adjoint_supported(const lbm_config& g, const int* meso, const int* vfd, std::string& err) {
+int adjoint_supported(const lbm_config& g, const int* meso, std::string& err) {
     for (int s = 0; s < 4; ++s)
         if (meso[s] != LBM_RECON_EQUILIBRIUM) {
             err = "the adjoint supports the equilibrium reconstruction only";
@@ -341,10 +341,6 @@ int adjoint_supported(const lbm_config& g, const int* meso, const int* vfd, std:
         const int b = g.bc[s];
         if (b != BC_PERIODIC && b != BC_LODI && b != BC_LODI_RELAX && !is_full(b)) {
             err = "the adjoint supports periodic, LODI, LODI-RELAX, CBC and CBC-RELAX sides only";
-            return LBM_E_UNSUPPORTED;
-        }
-        if (is_full(b) && vfd[s] != LBM_VISC_FD) {
-            err = "the adjoint of a CBC side needs the finite-difference viscous terms (lbm_viscous, LBM_VISC_FD)";
             return LBM_E_UNSUPPORTED;
         }
     }
@@ -435,6 +431,9 @@ int run_adjoint(lbm_ctx* c, const double* seed, double* grad, double* h_relax) {
     for (int s = 0; s < 4; ++s)
         if (any_corner && ((c->cfg.bc[s] == BC_LODI_RELAX && c->relax[s].alpha != 0.0) || is_full(c->cfg.bc[s])))
             g.coupled = 1;
+    g.vism = 0;
+    for (int s = 0; s < 4; ++s)
+        if (is_full(c->cfg.bc[s]) && c->vfd[s] == LBM_VISC_MESO) g.vism = 1;
     const int nside_blocks = t.nadj + ((any_corner && !g.coupled) ? 4 : 0);
 
     // Segment seg is recomputed from its checkpoint on the second stream into recomputation set
@@ -749,7 +748,7 @@ size_t lbm_tape_bytes(const lbm_ctx* c, int nsteps, int every) {
 int lbm_record(lbm_ctx* c, int nsteps, int every, void* d_tape, size_t tape_bytes) {
     if (!c) return fail(nullptr, LBM_E_ARG, "null context");
     std::string err;
-    const int sup = adjoint_supported(c->cfg, c->meso, c->vfd, err);
+    const int sup = adjoint_supported(c->cfg, c->meso, err);
     if (sup != LBM_OK) return fail(c, sup, err);
     if (nsteps < 1 || every < 1) return fail(c, LBM_E_ARG, "nsteps and every must be positive");
     if (!d_tape || ((uintptr_t)d_tape % ALIGN) != 0) return fail(c, LBM_E_ARG, "tape must be non-NULL and 256-byte aligned");
@@ -778,7 +777,7 @@ int lbm_adjoint(lbm_ctx* c, const double* d_seed, double* d_grad_fields, double*
     if (!c->tape.base) return fail(c, LBM_E_STATE, "no recorded run (call lbm_record first)");
     if (c->steps != c->tape.step_end) return fail(c, LBM_E_STATE, "the context has stepped since lbm_record");
     std::string err;
-    const int sup = adjoint_supported(c->cfg, c->meso, c->vfd, err);
+    const int sup = adjoint_supported(c->cfg, c->meso, err);
     if (sup != LBM_OK) return fail(c, sup, err);
     return dispatch(c, [&]<int Q, typename T>() -> int { return run_adjoint<Q, T>(c, d_seed, d_grad_fields, h_grad_relax); });
 }

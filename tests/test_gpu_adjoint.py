@@ -62,6 +62,12 @@ CASES = {
     # D2Q17, CBC outflow and CBC-RELAX inflow, periodic y, -FD viscous terms
     "d2q17_cbc_periodic_y": dict(stencil=17, nx=48, ny=40, tau=0.9, bc=["cbc_relax", "cbc", "periodic", "periodic"],
                                  steps=30, every=30, relax=dict(sigma=0.3, alpha=0.2, mach=0.05), visc="fd"),
+    # the same two with the mesoscopic viscous terms (eq. LaplaceU / LaplaceT): their moments at
+    # x_f, x_f - 1, x_f - 2 feed the adjoint populations of three bulk columns
+    "d2q37_cbc_meso_corners": dict(stencil=37, nx=70, ny=96, tau=TAU_37, bc=["cbc_relax", "cbc", "lodi_relax", "cbc_relax"],
+                                   steps=30, every=11, relax=dict(sigma=0.25, alpha=0.1, mach=0.05)),
+    "d2q17_cbc_meso_periodic_y": dict(stencil=17, nx=48, ny=40, tau=0.9, bc=["cbc_relax", "cbc", "periodic", "periodic"],
+                                      steps=30, every=30, relax=dict(sigma=0.3, alpha=0.2, mach=0.05)),
 }
 
 
@@ -165,13 +171,14 @@ def test_adjoint_fp32dev_close_to_fp64():
 def test_adjoint_argument_and_state_errors():
     from paper_2307_16766_amd import lbm
     f = W.temperature_pulse(40, 40)
-    g = lbm.LBM(37, 40, 40, TAU_37, ["lodi_relax", "cbc_relax", "lodi", "lodi"], f)
-    with pytest.raises(lbm.LBMError) as e:   # CBC with the mesoscopic viscous terms
+    g = lbm.LBM(37, 40, 40, TAU_37, ["lodi_relax", "zg", "periodic", "periodic"], f)
+    with pytest.raises(lbm.LBMError) as e:   # zero-gradient side
         g.record(5, 2)
     assert e.value.code == lbm.LBM_E_UNSUPPORTED
-    g.set_viscous(1, "fd")
+    g.close()
+    g = lbm.LBM(37, 40, 40, TAU_37, ["lodi_relax", "cbc_relax", "lodi", "lodi"], f)
     g.record(5, 2)
-    g.set_viscous(1, "meso")                 # settings changed after the recording
+    g.set_reconstruction(1, "neep")          # settings changed after the recording
     with pytest.raises(lbm.LBMError) as e:
         g.adjoint()
     assert e.value.code == lbm.LBM_E_UNSUPPORTED
@@ -200,26 +207,27 @@ def test_adjoint_argument_and_state_errors():
     g.close()
 
 
-def test_autograd_function_matches_adjoint():
+@pytest.mark.parametrize("name", ["d2q37_corners", "d2q37_cbc_meso_corners", "d2q37_cbc_corners"])
+def test_autograd_function_matches_adjoint(name):
     # the torch.autograd.Function: a loss computed in torch from the final fields back-propagates
     # through lbm_adjoint; for the pressure loss over the bulk it equals the built-in seed
     import torch
     from paper_2307_16766_amd.autograd import simulate
-    c = CASES["d2q37_corners"]
-    log("[gpu-case] autograd function")
+    c = CASES[name]
+    log(f"[gpu-case] autograd function {name}")
     fields = _case_fields(c, 61)
     dev = torch.device("cuda")
     ts = [torch.tensor(a, dtype=torch.float64, device=dev, requires_grad=True) for a in fields]
     sig = torch.tensor(c["relax"]["sigma"], dtype=torch.float64, device=dev, requires_grad=True)
     alp = torch.tensor(c["relax"]["alpha"], dtype=torch.float64, device=dev, requires_grad=True)
     out = simulate(sig, alp, *ts, stencil=37, nx=c["nx"], ny=c["ny"], tau=c["tau"], bc=c["bc"], nsteps=c["steps"],
-                   every=c["every"], relax=dict(mach=c["relax"]["mach"]))
+                   every=c["every"], relax=dict(mach=c["relax"]["mach"]), visc=c.get("visc"))
     M = 3
     cs2 = O.lattice(37)[0]
     P = cs2 * out[0] * out[3]
     loss = ((P - cs2)[M:-M, M:-M] ** 2).sum()
     loss.backward()
-    g = _sim(c["stencil"], c["nx"], c["ny"], c["tau"], c["bc"], fields, c["relax"])
+    g = _sim(c["stencil"], c["nx"], c["ny"], c["tau"], c["bc"], fields, c["relax"], visc=c.get("visc"))
     g.record(c["steps"], c["every"])
     assert abs(g.diagnostics()[4] - loss.item()) <= 1e-12 * loss.item()
     grad, grel = g.adjoint()
@@ -314,13 +322,18 @@ def test_c4_with_background_flow_against_finite_differences():
     assert max(errs.values()) < 1e-4
 
 
-def test_cbc_adjoint_against_finite_differences():
-    # CBC-RELAX / CBC / CBC-RELAX / LODI-RELAX sides with corners and the -FD viscous terms
-    # (Sec. 4.2), 128 x 128 D2Q37 over a diagonal background flow (u_n keeps its sign at every
-    # boundary node, so the map is smooth): central differences of the GPU FP64 forward run with
-    # h = 1e-6 on sigma, alpha and three T0 directions match the adjoint within 1e-4.
-    log("[gpu-case] CBC adjoint against finite differences, 128x128, 300 steps")
-    n, steps = 128, 300
+@pytest.mark.parametrize("visc,steps", [("fd", 300), ("meso", 100)])
+def test_cbc_adjoint_against_finite_differences(visc, steps):
+    # CBC-RELAX / CBC / CBC-RELAX / LODI-RELAX sides with corners, -FD (Sec. 4.2) or mesoscopic
+    # (eq. LaplaceU / LaplaceT) viscous terms, 128 x 128 D2Q37 over a diagonal background flow
+    # (u_n keeps its sign at every boundary node, so the map is smooth): central differences of
+    # the GPU FP64 forward run with h = 1e-6 on sigma, alpha and three T0 directions match the
+    # adjoint within 1e-4.  The mesoscopic run is checked over 100 steps: with the equilibrium
+    # BC its boundary error grows (the pressure loss goes from 3.6e-7 at step 100 to 6.7e-3 at
+    # step 300), and the grown run amplifies rounding enough that central differences with
+    # h <= 1e-6 drift from the adjoint by 2e-4 while h = 1e-4 still matches it to 3e-6.
+    log(f"[gpu-case] CBC adjoint ({visc} viscous terms) against finite differences, 128x128, {steps} steps")
+    n = 128
     bc = ["cbc_relax", "cbc", "cbc_relax", "lodi_relax"]
     relax0 = dict(sigma=0.25, alpha=0.1, mach=0.05)
     rho, ux, uy, T = W.random_temperature(n, n, std=1e-4, seed=4213)
@@ -328,13 +341,13 @@ def test_cbc_adjoint_against_finite_differences():
     dirs = W.random_directions(3, n, n, 4214)
 
     def loss_of(f, relax):
-        g = _sim(37, n, n, TAU_37, bc, f, relax, visc="fd")
+        g = _sim(37, n, n, TAU_37, bc, f, relax, visc=visc)
         g.step(steps)
         v = g.diagnostics()[4]
         g.close()
         return v
 
-    g = _sim(37, n, n, TAU_37, bc, fields, relax0, visc="fd")
+    g = _sim(37, n, n, TAU_37, bc, fields, relax0, visc=visc)
     g.record(steps, 40)
     loss = g.diagnostics()[4]
     grad, grel = g.adjoint()
