@@ -1176,18 +1176,24 @@ int oracle_tangent_run(int stencil, int nx, int ny, double tau, const int* bc, c
 // alpha as above and (rho0, ux0, uy0, T0) by dF[k][4][ny][nx].  The loss is the pressure loss
 // above, or with wlin != NULL the linear functional sum over all nodes of
 // wlin[c][y][x] * (rho, ux, uy, T)_c at the final step.  out: loss, then NTAN derivatives.
-// visc: NULL, or the viscous-term mode per side (0 mesoscopic, 1 finite differences; CBC sides)
-int oracle_tangent_run_fields_visc(int stencil, int nx, int ny, double tau, const int* bc, const double* relax,
-                                   const double* dsigma, const double* dalpha, const double* rho, const double* ux,
-                                   const double* uy, const double* T, const double* dF, const double* wlin,
-                                   const int* visc, int nsteps, double* out) {
+// visc: NULL, or the viscous-term mode per side (0 mesoscopic, 1 finite differences; CBC sides);
+// recon: NULL, or the mesoscopic BC per side (0 equilibrium, 1 NEEP; characteristic sides)
+int oracle_tangent_run_fields_ex(int stencil, int nx, int ny, double tau, const int* bc, const double* relax,
+                                 const double* dsigma, const double* dalpha, const double* rho, const double* ux,
+                                 const double* uy, const double* T, const double* dF, const double* wlin,
+                                 const int* visc, const int* recon, int nsteps, double* out) {
     if (validate(stencil, nx, ny, tau, bc) != 0) return -1;
     Sim<Dual> s(lattice(stencil), nx, ny, tau, bc);
-    if (visc)
-        for (int side = 0; side < 4; ++side) {
+    for (int side = 0; side < 4; ++side) {
+        if (visc) {
             if (visc[side] != 0 && !is_full_cbc(bc[side])) { g_err = "finite-difference viscous terms need a CBC side"; return -1; }
             s.vfd[side] = visc[side];
         }
+        if (recon) {
+            if (recon[side] != 0 && !(bc[side] >= BC_LODI && bc[side] <= BC_CBC_RELAX)) { g_err = "NEEP needs a characteristic side"; return -1; }
+            s.meso[side] = recon[side];
+        }
+    }
     for (int side = 0; side < 4; ++side) {
         const double* p = relax + 6 * side;
         Dual sg(p[0]), al(p[1]);
@@ -1221,8 +1227,8 @@ int oracle_tangent_run_fields(int stencil, int nx, int ny, double tau, const int
                               const double* dsigma, const double* dalpha, const double* rho, const double* ux,
                               const double* uy, const double* T, const double* dF, const double* wlin, int nsteps,
                               double* out) {
-    return oracle_tangent_run_fields_visc(stencil, nx, ny, tau, bc, relax, dsigma, dalpha, rho, ux, uy, T, dF, wlin,
-                                          nullptr, nsteps, out);
+    return oracle_tangent_run_fields_ex(stencil, nx, ny, tau, bc, relax, dsigma, dalpha, rho, ux, uy, T, dF, wlin,
+                                        nullptr, nullptr, nsteps, out);
 }
 
 // Viscous terms V = (0, V_n, V_t, V_T) (local frame) at bulk node (x, y) of a domain whose

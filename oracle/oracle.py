@@ -58,8 +58,8 @@ def lib():
                                          _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int, _dp]
         L.oracle_tangent_run_fields.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, _ip,
                                                 _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int, _dp]
-        L.oracle_tangent_run_fields_visc.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, _ip,
-                                                     _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _ip, ctypes.c_int, _dp]
+        L.oracle_tangent_run_fields_ex.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, _ip,
+                                                   _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _ip, _ip, ctypes.c_int, _dp]
         _LIB = L
     return _LIB
 
@@ -229,13 +229,14 @@ def tangent_run(stencil, nx, ny, tau, bc, relax, dsigma, dalpha, fields, dT, nst
     return out[0], out[1:].copy()
 
 
-def tangent_run_fields(stencil, nx, ny, tau, bc, relax, dsigma, dalpha, fields, dF, nsteps, wlin=None, visc=None):
+def tangent_run_fields(stencil, nx, ny, tau, bc, relax, dsigma, dalpha, fields, dF, nsteps, wlin=None, visc=None,
+                       recon=None):
     """Loss and its NTAN directional derivatives with tangents on all four initial fields.
 
     dF: [NTAN][4][ny][nx] perturbation of (rho0, ux0, uy0, T0) per direction.  wlin: None for
     the pressure loss, or [4][ny][nx] weights of the linear loss sum w . (rho, ux, uy, T) of the
     final fields over every node.  visc: None, or the viscous terms of each side ("meso" or "fd",
-    CBC sides).
+    CBC sides).  recon: None, or the mesoscopic BC of each side ("equilibrium" or "neep").
     """
     codes = (ctypes.c_int * 4)(*_bc_codes(bc))
     relax = np.ascontiguousarray(relax, dtype=np.float64).reshape(4, 6)
@@ -246,9 +247,10 @@ def tangent_run_fields(stencil, nx, ny, tau, bc, relax, dsigma, dalpha, fields, 
     w = None if wlin is None else np.ascontiguousarray(wlin, dtype=np.float64).reshape(4, ny, nx)
     out = np.zeros(1 + NTAN)
     vm = None if visc is None else (ctypes.c_int * 4)(*[{"meso": 0, "fd": 1}[v] for v in visc])
-    rc = lib().oracle_tangent_run_fields_visc(stencil, nx, ny, tau, codes, _ptr(relax), _ptr(ds), _ptr(da),
-                                              *[_ptr(a) for a in fl], _ptr(dF), _ptr(w) if w is not None else None,
-                                              vm, nsteps, _ptr(out))
+    rm = None if recon is None else (ctypes.c_int * 4)(*[{"equilibrium": 0, "neep": 1}[v] for v in recon])
+    rc = lib().oracle_tangent_run_fields_ex(stencil, nx, ny, tau, codes, _ptr(relax), _ptr(ds), _ptr(da),
+                                            *[_ptr(a) for a in fl], _ptr(dF), _ptr(w) if w is not None else None,
+                                            vm, rm, nsteps, _ptr(out))
     if rc != 0:
         raise ValueError(lib().oracle_error().decode())
     return out[0], out[1:].copy()

@@ -430,6 +430,9 @@ struct AdjArgs {
     int crow[4][2];          // per corner: that side's row next to the corner
     int coupled;             // corners read the sides' contributions (transverse relaxation alpha != 0)
     int vism;                // some CBC side uses the mesoscopic viscous terms
+    int neep_any;            // some characteristic side uses NEEP (eq. NEEP)
+    double* neep[4];         // per NEEP side, row r: (1 - omega) sum_j lambda^{n+1}(x_b,j) [Q], then its
+                             // projection (dm/dM)^T (df^eq/dm)^T of the same [4]; NULL otherwise
 };
 
 // ------------------------------------------------------------------ reverse of a side chunk
@@ -515,6 +518,32 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
                               nu, &sVr[l2 * 4]);
     }
     __syncthreads();
+    // NEEP (eq. NEEP): the layers of row r hold f^eq(U_b) + (1 - omega)(g - f^eq(m(g))) with g
+    // pulled at x_f, so the adjoint of that g gets (1 - omega)(Lambda - phi . GM), Lambda = the sum
+    // of lambda^{n+1} over the layers, GM = (dm/dM)^T (df^eq/dm)^T Lambda at the strip's moments;
+    // k_adj_bulk adds it where it pulls from x_f (owned rows; the layers are read-only here)
+    if (sd.meso == 1 && g.neep[side]) {
+        const double cn = 1.0 - a.omega;
+        double* nb = g.neep[side];
+        for (int e = tid; e < r1 - r0; e += blockDim.x) {
+            const int rr = r0 + e, l2 = H + e;
+            double lam[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) lam[i] = 0.0;
+            for (int q = 1; q <= M; ++q) {
+                int x, y; side_node(sd, q, rr, x, y);
+#pragma unroll
+                for (int i = 0; i < Q; ++i) lam[i] += g.V1[pix<Q>(a.pitch, i, x, y)];
+            }
+            double G[4], GM[4];
+            feq_vjp<Q>(&sXp[(l2 * MS) * 4], lam, G);
+            mom_vjp<Q>(&sXp[(l2 * MS) * 4], G, GM);
+            double* o = nb + (size_t)rr * (Q + 4);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) o[i] = cn * lam[i];
+            for (int m = 0; m < 4; ++m) o[Q + m] = cn * GM[m];
+        }
+    }
 
     const double ast[4] = {0.0, 0.5, 0.5, 1.0}, bst[4] = {1.0, 2.0, 2.0, 1.0};
     // side-local stage-st inputs of this thread's node
@@ -940,6 +969,28 @@ __global__ __launch_bounds__(256) void k_adj_bulk(AdjArgs g, BulkArgs k, int bpr
         const bool src = xs >= k.x0 && xs <= k.x1 && ys >= k.y0 && ys <= k.y1;
         const double v = g.V1[src ? pix<Q>(pitch, i, xs, ys) : 0ull];   // in bounds either way
         lam[i] = src ? v : 0.0;
+    }
+    if (g.neep_any) {
+        // NEEP terms of nu^{n+1} at the x_f nodes of NEEP sides (written by the side chunks)
+#pragma unroll
+        for (int sd = 0; sd < 4; ++sd) {
+            const double* nb = g.neep[sd];
+            if (!nb) continue;
+            const SideDev& S = g.b.s[sd];
+            const bool xn = S.nax == 0;
+            const int own = xn ? x : y;
+            if (own < S.xf - 3 || own > S.xf + 3) continue;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                int xs = x + cx<Q>(i), ys = y + cy<Q>(i);
+                if (PX) xs = wrapi(xs, k.nx);
+                if (PY) ys = wrapi(ys, k.ny);
+                const int nc = xn ? xs : ys, r = (xn ? ys : xs) - S.r0;
+                if (nc != S.xf || r < 0 || r >= S.len) continue;
+                const double* o = nb + (size_t)r * (Q + 4);
+                lam[i] += o[i] - phi_dot<Q>(i, o + Q);
+            }
+        }
     }
     // corrections of nu^{n+1} at the corner diagonal nodes c + v (the corner's term and both
     // adjacent strips' end rows) and c + 2v, for the nodes that pull from them

@@ -169,6 +169,7 @@ struct Tape {
     // of one segment overlaps the reverse sweep of the next one
     size_t chk_stride = 0, off_R[2][2] = {{0, 0}, {0, 0}}, off_V[2] = {0, 0}, off_mom[2] = {0, 0}, mom_bytes = 0, off_rh[2] = {0, 0};
     size_t off_adj[2] = {0, 0}, off_ccon = 0, off_gm = 0, off_acc = 0, total = 0;
+    size_t off_neep[4] = {0, 0, 0, 0};   // per characteristic side: [len][Q + 4] NEEP terms of nu^{n+1}(x_f)
     int ablk0[4] = {0, 0, 0, 0}, anblk[4] = {0, 0, 0, 0}, arows = 0, nadj = 0;
 };
 
@@ -331,12 +332,7 @@ int launch_init(lbm_ctx* c, const double* rho, const double* ux, const double* u
 }
 
 // ---------------------------------------------------------------- discrete adjoint (host side)
-int adjoint_supported(const lbm_config& g, const int* meso, std::string& err) {
-    for (int s = 0; s < 4; ++s)
-        if (meso[s] != LBM_RECON_EQUILIBRIUM) {
-            err = "the adjoint supports the equilibrium reconstruction only";
-            return LBM_E_UNSUPPORTED;
-        }
+int adjoint_supported(const lbm_config& g, std::string& err) {
     for (int s = 0; s < 4; ++s) {
         const int b = g.bc[s];
         if (b != BC_PERIODIC && b != BC_LODI && b != BC_LODI_RELAX && !is_full(b)) {
@@ -375,6 +371,8 @@ void tape_layout(const Layout& L, int ny, int N, int K, Tape& t) {
         t.nadj += t.anblk[s];
     }
     t.off_acc = off; off += align_up((size_t)(2 * t.nadj + 4) * 8);
+    for (int s = 0; s < 4; ++s)
+        if (L.s[s].kind == KIND_CHAR) { t.off_neep[s] = off; off += align_up((size_t)L.s[s].len * (L.Q + 4) * 8); }
     t.total = off;
 }
 
@@ -434,6 +432,14 @@ int run_adjoint(lbm_ctx* c, const double* seed, double* grad, double* h_relax) {
     g.vism = 0;
     for (int s = 0; s < 4; ++s)
         if (is_full(c->cfg.bc[s]) && c->vfd[s] == LBM_VISC_MESO) g.vism = 1;
+    g.neep_any = 0;
+    for (int s = 0; s < 4; ++s) {
+        g.neep[s] = nullptr;
+        if (L.s[s].kind == KIND_CHAR && c->meso[s] == LBM_RECON_NEEP) {
+            g.neep[s] = (double*)(base + t.off_neep[s]);
+            g.neep_any = 1;
+        }
+    }
     const int nside_blocks = t.nadj + ((any_corner && !g.coupled) ? 4 : 0);
 
     // Segment seg is recomputed from its checkpoint on the second stream into recomputation set
@@ -748,7 +754,7 @@ size_t lbm_tape_bytes(const lbm_ctx* c, int nsteps, int every) {
 int lbm_record(lbm_ctx* c, int nsteps, int every, void* d_tape, size_t tape_bytes) {
     if (!c) return fail(nullptr, LBM_E_ARG, "null context");
     std::string err;
-    const int sup = adjoint_supported(c->cfg, c->meso, err);
+    const int sup = adjoint_supported(c->cfg, err);
     if (sup != LBM_OK) return fail(c, sup, err);
     if (nsteps < 1 || every < 1) return fail(c, LBM_E_ARG, "nsteps and every must be positive");
     if (!d_tape || ((uintptr_t)d_tape % ALIGN) != 0) return fail(c, LBM_E_ARG, "tape must be non-NULL and 256-byte aligned");
@@ -777,7 +783,7 @@ int lbm_adjoint(lbm_ctx* c, const double* d_seed, double* d_grad_fields, double*
     if (!c->tape.base) return fail(c, LBM_E_STATE, "no recorded run (call lbm_record first)");
     if (c->steps != c->tape.step_end) return fail(c, LBM_E_STATE, "the context has stepped since lbm_record");
     std::string err;
-    const int sup = adjoint_supported(c->cfg, c->meso, err);
+    const int sup = adjoint_supported(c->cfg, err);
     if (sup != LBM_OK) return fail(c, sup, err);
     return dispatch(c, [&]<int Q, typename T>() -> int { return run_adjoint<Q, T>(c, d_seed, d_grad_fields, h_grad_relax); });
 }

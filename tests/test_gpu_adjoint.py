@@ -23,12 +23,14 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c4_
 ADJ_TOL = 1e-9   # adjoint vs dual numbers, relative
 
 
-def _sim(stencil, nx, ny, tau, bc, fields, relax, precision="fp64", visc=None):
+def _sim(stencil, nx, ny, tau, bc, fields, relax, precision="fp64", visc=None, recon=None):
     from paper_2307_16766_amd import lbm
     g = lbm.LBM(stencil, nx, ny, tau, bc, fields, precision=precision)
     g.set_relax(-1, **relax)
     if visc is not None:
         g.set_viscous(-1, visc)
+    if recon is not None:
+        g.set_reconstruction(-1, recon)
     return g
 
 
@@ -68,14 +70,27 @@ CASES = {
                                    steps=30, every=11, relax=dict(sigma=0.25, alpha=0.1, mach=0.05)),
     "d2q17_cbc_meso_periodic_y": dict(stencil=17, nx=48, ny=40, tau=0.9, bc=["cbc_relax", "cbc", "periodic", "periodic"],
                                       steps=30, every=30, relax=dict(sigma=0.3, alpha=0.2, mach=0.05)),
+    # NEEP reconstruction (eq. NEEP) on every characteristic side: the layers depend on the
+    # populations pulled at x_f (the corner blocks keep the equilibrium)
+    "d2q37_neep_corners": dict(stencil=37, nx=64, ny=72, tau=TAU_37, bc=["lodi_relax", "lodi", "lodi_relax", "lodi_relax"],
+                               steps=30, every=11, relax=dict(sigma=0.25, alpha=0.1, mach=0.05), recon="neep"),
+    "d2q17_cbc_neep_periodic_y": dict(stencil=17, nx=48, ny=40, tau=0.9, bc=["cbc_relax", "cbc", "periodic", "periodic"],
+                                      steps=30, every=30, relax=dict(sigma=0.3, alpha=0.2, mach=0.05), recon="neep"),
 }
 
 
 def _visc(c):
-    """Viscous-term mode per side for the oracle (None when the case has no CBC side)."""
+    """Viscous-term mode per side for the oracle (None: the mesoscopic default)."""
     if "visc" not in c:
         return None
     return [c["visc"] if b in ("cbc", "cbc_relax") else "meso" for b in c["bc"]]
+
+
+def _recon(c):
+    """Mesoscopic BC per side for the oracle (None: the equilibrium BC everywhere)."""
+    if "recon" not in c:
+        return None
+    return [c["recon"] if b not in ("periodic", "zg", "dirichlet") else "equilibrium" for b in c["bc"]]
 
 
 def _case_fields(c, seed):
@@ -112,8 +127,9 @@ def test_adjoint_matches_oracle_tangents(name, loss):
         wlin = np.random.default_rng(33).standard_normal((4, c["ny"], c["nx"]))
     # direction 0: sigma and alpha together; 1, 2: field perturbations
     oloss, od = O.tangent_run_fields(c["stencil"], c["nx"], c["ny"], c["tau"], c["bc"], relax, [1, 0, 0], [0.5, 0, 0],
-                                     fields, dF, c["steps"], wlin, visc=_visc(c))
-    g = _sim(c["stencil"], c["nx"], c["ny"], c["tau"], c["bc"], fields, c["relax"], visc=c.get("visc"))
+                                     fields, dF, c["steps"], wlin, visc=_visc(c), recon=_recon(c))
+    g = _sim(c["stencil"], c["nx"], c["ny"], c["tau"], c["bc"], fields, c["relax"], visc=c.get("visc"),
+             recon=c.get("recon"))
     g.record(c["steps"], c["every"])
     d = g.diagnostics()
     if loss == "pressure":
@@ -176,16 +192,8 @@ def test_adjoint_argument_and_state_errors():
         g.record(5, 2)
     assert e.value.code == lbm.LBM_E_UNSUPPORTED
     g.close()
-    g = lbm.LBM(37, 40, 40, TAU_37, ["lodi_relax", "cbc_relax", "lodi", "lodi"], f)
-    g.record(5, 2)
-    g.set_reconstruction(1, "neep")          # settings changed after the recording
-    with pytest.raises(lbm.LBMError) as e:
-        g.adjoint()
-    assert e.value.code == lbm.LBM_E_UNSUPPORTED
-    g.close()
-    g = lbm.LBM(37, 40, 40, TAU_37, ["lodi_relax"] * 4, f)
-    g.set_reconstruction(-1, "neep")
-    with pytest.raises(lbm.LBMError) as e:
+    g = lbm.LBM(37, 40, 40, TAU_37, ["dirichlet", "lodi", "periodic", "periodic"], f)
+    with pytest.raises(lbm.LBMError) as e:   # Dirichlet side
         g.record(5, 2)
     assert e.value.code == lbm.LBM_E_UNSUPPORTED
     g.close()
