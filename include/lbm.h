@@ -166,11 +166,14 @@ int lbm_restore(lbm_ctx* ctx, const void* d_buf);
 /* Number of steps taken since lbm_init (or the restored checkpoint's count). */
 long lbm_steps_done(const lbm_ctx* ctx);
 
-/* Kernel timing for measurement.  With enable != 0, lbm_step records a pair of HIP events
- * around every step kernel launch (fused bulk stream-collide and boundary solve) on the
- * caller's stream (resetting earlier records); lbm_bulk_kernel_time synchronises on them and
- * returns the summed elapsed milliseconds and the number of timed launches.  Disabled by
- * default; at most 65536 launches are recorded. */
+/* Kernel timing for measurement.  With enable = n > 0, lbm_step records a pair of HIP events
+ * around every n-th step kernel launch (fused bulk stream-collide and boundary solve; the first
+ * launch after this call is timed) on the caller's stream, resetting earlier records; 0 turns
+ * timing off, a negative value returns LBM_E_ARG.  Each timed launch adds about 7 us of event
+ * work to the stream, so a stride above 1 keeps a timed run's step rate close to an untimed
+ * one.  lbm_bulk_kernel_time synchronises on the events and returns the summed elapsed
+ * milliseconds and the number of timed launches.  Disabled by default; at most 65536 launches
+ * are recorded. */
 int lbm_set_kernel_timing(lbm_ctx* ctx, int enable);
 int lbm_bulk_kernel_time(lbm_ctx* ctx, double* total_ms, long* launches);
 

@@ -80,7 +80,10 @@ int lbm3d_populations(lbm3d_ctx* ctx, double* d_out);
  * LBM_E_NONFINITE when that count is non-zero. */
 int lbm3d_diagnostics(lbm3d_ctx* ctx, double* h_out);
 
-/* Bulk-kernel timing with HIP events on the context's stream (measurement only). */
+/* Bulk-kernel timing with HIP events on the context's stream (measurement only): enable = n > 0
+ * times every n-th bulk launch (the first after this call included), 0 turns it off, negative
+ * values return LBM_E_ARG; lbm3d_bulk_kernel_time returns the summed milliseconds and the number
+ * of timed launches. */
 int lbm3d_set_kernel_timing(lbm3d_ctx* ctx, int enable);
 int lbm3d_bulk_kernel_time(lbm3d_ctx* ctx, double* total_ms, long* launches);
 

@@ -164,7 +164,7 @@ __device__ __forceinline__ double phi_dot(int i, const double* GM) {
 // returned in Vb.  Inputs as char_rate plus the second normal difference d2n; rb = adjoint of
 // the rate; outputs the adjoints of U, dn, d2n, up, dw (side-local components), of V and of K
 // and alpha.  The wave directions are frozen at time t (no derivative).
-template <int Q>
+template <int Q, bool CBC>
 __device__ __forceinline__ void char_rate_vjp(const double* U, const double* dn, const double* d2n, const double* up,
                                               const double* dw, const double* Vin, const double* U0, int scheme,
                                               int vfd, double nu, double K, double alpha, double Pinf, const double* rb,
@@ -173,8 +173,8 @@ __device__ __forceinline__ void char_rate_vjp(const double* U, const double* dn,
     constexpr bool THERMAL = Lat<Q>::thermal;
     constexpr double cs2 = Lat<Q>::cs2;
     constexpr double cs = Lat<Q>::cs;
-    const bool full = THERMAL && (scheme == BC_CBC || scheme == BC_CBC_RELAX);
-    const bool relax = scheme == BC_LODI_RELAX || scheme == BC_CBC_RELAX;
+    const bool full = CBC && THERMAL && (scheme == BC_CBC || scheme == BC_CBC_RELAX);
+    const bool relax = scheme == BC_LODI_RELAX || (CBC && scheme == BC_CBC_RELAX);
     const double rho = U[0], u = U[1], v = U[2], T = U[3];
     const double ir = 1.0 / rho;
     const double T1 = -0.5 * (up[0] * up[2] - dw[0] * dw[2]);
@@ -397,7 +397,7 @@ __device__ __forceinline__ void corner_rate_vjp(const CornerDev& c, const double
     rl[3] = rb[3];
     double Ub[4], dnb[4], d2nb[4], upb[4], dwb[4], Vb[4], alb;
     const double zero4[4] = {0.0, 0.0, 0.0, 0.0};
-    char_rate_vjp<Q>(l0, dn, zero4, l0, l0, zero4, ln, c.relax ? BC_LODI_RELAX : BC_LODI, 0, 0.0, c.K, 0.0, c.Pinf, rl,
+    char_rate_vjp<Q, false>(l0, dn, zero4, l0, l0, zero4, ln, c.relax ? BC_LODI_RELAX : BC_LODI, 0, 0.0, c.K, 0.0, c.Pinf, rl,
                      Ub, dnb, d2nb, upb, dwb, Vb, Kb, alb);
     double a0[4], a1[4], a2[4];
 #pragma unroll
@@ -439,7 +439,7 @@ struct AdjArgs {
 // LDS row lr <-> side row r = r0 - 8 + lr.  Owned rows [r0, r1).  Reverse dependencies: the
 // adjoint of U_b^n on owned rows needs stage s's VJP within s + 1 rows of them, which needs the
 // stage inputs within s + 2 rows (stored by the recomputation of the step, k_step with HIST).
-template <int Q>
+template <int Q, bool CBC>
 __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk, int chunk) {
     constexpr int M = Lat<Q>::M, NR = 256 / M, MS = (M == 1) ? 2 : 1, H = 8, NN = NR * M;
     __shared__ double sY[4][NN * 4];            // stage inputs Y_0 = U_b^n, Y_1, Y_2, Y_3 (global components)
@@ -507,7 +507,8 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
     }
     if (tid < 2 * 2 * M * 4) (&sCb[0][0][0][0])[tid] = 0.0;
     // mesoscopic viscous terms of time n (CBC sides without -FD), as in the forward step
-    const bool meso_v = (sd.scheme == BC_CBC || sd.scheme == BC_CBC_RELAX) && !sd.vfd;
+    const bool meso_v = CBC && (sd.scheme == BC_CBC || sd.scheme == BC_CBC_RELAX) && !sd.vfd;
+    const bool fd_v = CBC && (sd.scheme == BC_CBC || sd.scheme == BC_CBC_RELAX) && sd.vfd;   // second differences enter
     const double nu = (a.tau - 0.5) * Lat<Q>::cs2;
     const double* visn = meso_v ? (const double*)(a.reg_cur + sd.off_vis) : nullptr;
     for (int l2 = tid; l2 < NR; l2 += blockDim.x) {
@@ -579,7 +580,7 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
             double b1[4], b2[4];
             val_n(M - 1, b1); val_n(M - 2, b2);
             for (int m = 0; m < 4; ++m) dn[m] = 0.5 * (3.0 * U[m] - 4.0 * b1[m] + b2[m]);
-            if (M == 3) {   // backward second difference of the -FD viscous terms (Sec. 4.2)
+            if (M == 3 && fd_v) {   // backward second difference of the -FD viscous terms (Sec. 4.2)
                 double b3[4];
                 val_n(M - 3, b3);
                 for (int m = 0; m < 4; ++m) d2n[m] = 2.0 * U[m] - 5.0 * b1[m] + 4.0 * b2[m] - b3[m];
@@ -587,7 +588,9 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
         } else {
             double p1[4], m1[4];
             val_n(j + 1, p1); val_n(j - 1, m1);
-            for (int m = 0; m < 4; ++m) { dn[m] = 0.5 * (p1[m] - m1[m]); d2n[m] = p1[m] - 2.0 * U[m] + m1[m]; }
+            for (int m = 0; m < 4; ++m) dn[m] = 0.5 * (p1[m] - m1[m]);
+            if (fd_v)
+                for (int m = 0; m < 4; ++m) d2n[m] = p1[m] - 2.0 * U[m] + m1[m];
         }
         val_t(r + 1, up);
         val_t(r - 1, dw);
@@ -621,9 +624,10 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
             double U[4], dn[4], d2n[4], up[4], dw[4], U0[4];
             inputs(st, U, dn, d2n, up, dw, U0);
             double Ubl[4], dnbl[4], d2nbl[4], upbl[4], dwbl[4], Vbl[4], Kb, alb;
-            char_rate_vjp<Q>(U, dn, d2n, up, dw, &sVr[lr * 4], U0, sd.scheme, sd.vfd, nu, sd.K, sd.alpha, sd.Pinf, rb,
+            char_rate_vjp<Q, CBC>(U, dn, d2n, up, dw, &sVr[lr * 4], U0, sd.scheme, sd.vfd, nu, sd.K, sd.alpha, sd.Pinf, rb,
                              Ubl, dnbl, d2nbl, upbl, dwbl, Vbl, Kb, alb);
-            for (int m = 0; m < 4; ++m) vacc[m] += Vbl[m];
+            if (meso_v)
+                for (int m = 0; m < 4; ++m) vacc[m] += Vbl[m];
             double Ubg[4], dnbg[4], d2nbg[4], upbg[4], dwbg[4];
             rate_to_global(sd, Ubl, Ubg);
             rate_to_global(sd, dnbl, dnbg);
@@ -637,10 +641,11 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
                 sGd[t * 4 + m] = dwbg[m];
             }
             if constexpr (M == 3)
-                for (int m = 0; m < 4; ++m) {
-                    gself[m] += (j == M ? 2.0 : -2.0) * d2nbg[m];
-                    sG2[t * 4 + m] = d2nbg[m];
-                }
+                if (fd_v)
+                    for (int m = 0; m < 4; ++m) {
+                        gself[m] += (j == M ? 2.0 : -2.0) * d2nbg[m];
+                        sG2[t * 4 + m] = d2nbg[m];
+                    }
             if (owned) {
                 aK += Kb;
                 aA += alb;
@@ -674,14 +679,14 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
                 else cf = (j == q + 1) ? 0.5 : (j == q - 1 ? -0.5 : 0.0);
                 if (cf != 0.0)
                     for (int m = 0; m < 4; ++m) yb[m] += cf * sGn[((lr * M) + q - 1) * 4 + m];
-                if constexpr (M == 3) {   // second differences: backward (2, -5, 4, -1) at q = M, central below
+                if constexpr (M == 3) if (fd_v) {   // second differences: backward (2, -5, 4, -1) at q = M, central below
                     const double c2 = q == M ? (j == M - 1 ? -5.0 : (j == M - 2 ? 4.0 : 0.0))
                                              : ((j == q + 1 || j == q - 1) ? 1.0 : 0.0);
                     if (c2 != 0.0)
                         for (int m = 0; m < 4; ++m) yb[m] += c2 * sG2[((lr * M) + q - 1) * 4 + m];
                 }
             }
-            if constexpr (M == 3) {
+            if constexpr (M == 3) if (fd_v) {
                 // the strip x_f is layer 0 of the second differences: +1 in layer 1's central one,
                 // -1 in layer M's backward one (owned rows, as the first differences' strip terms)
                 if (owned && jj == 0)
@@ -931,8 +936,9 @@ __device__ void corner_adj(const AdjArgs& g, int ci) {
 }
 
 // side chunks; when the corners do not read the sides' contributions, the corners too (the
-// blocks after the side chunks)
-template <int Q>
+// blocks after the side chunks).  CBC: compiled with the CBC variants' terms (some side is CBC
+// or CBC-RELAX); without them the LODI schemes run a leaner kernel.
+template <int Q, bool CBC>
 __global__ __launch_bounds__(256) void k_adj_side(AdjArgs g) {
     const int b = blockIdx.x;
     if (b >= g.nadj) {
@@ -942,7 +948,7 @@ __global__ __launch_bounds__(256) void k_adj_side(AdjArgs g) {
     int s = 0;
     while (s < 4 && !(g.anblk[s] > 0 && b >= g.ablk0[s] && b < g.ablk0[s] + g.anblk[s])) ++s;
     if (s == 4) return;
-    adj_chunk<Q>(g, g.b.s[s], s, b, b - g.ablk0[s]);
+    adj_chunk<Q, CBC>(g, g.b.s[s], s, b, b - g.ablk0[s]);
 }
 
 // corners after the side chunks (coupled case)

@@ -192,7 +192,8 @@ struct lbm_ctx {
     BulkArgs bulk;
     std::string err;
     // bulk kernel timing (measurement only)
-    bool timing = false;
+    int timing = 0;                // time every timing-th step launch (0: off)
+    size_t tcalls = 0;             // step launches since timing was set
     std::vector<hipEvent_t> tev;   // pairs: start, end
     size_t tcount = 0;             // recorded pairs
     Tape tape;
@@ -255,7 +256,7 @@ constexpr size_t MAX_TIMED = 65536;
 // launch the step kernel, bracketed by timing events when kernel timing is on
 template <typename F>
 hipError_t timed_launch(lbm_ctx* c, F&& launch) {
-    const bool rec = c->timing && c->tcount < MAX_TIMED;
+    const bool rec = c->timing > 0 && (c->tcalls++ % (size_t)c->timing) == 0 && c->tcount < MAX_TIMED;
     if (rec) {
         while (c->tev.size() < 2 * (c->tcount + 1)) {
             hipEvent_t e;
@@ -429,6 +430,8 @@ int run_adjoint(lbm_ctx* c, const double* seed, double* grad, double* h_relax) {
     for (int s = 0; s < 4; ++s)
         if (any_corner && ((c->cfg.bc[s] == BC_LODI_RELAX && c->relax[s].alpha != 0.0) || is_full(c->cfg.bc[s])))
             g.coupled = 1;
+    bool any_full = false;
+    for (int s = 0; s < 4; ++s) any_full = any_full || is_full(c->cfg.bc[s]);
     g.vism = 0;
     for (int s = 0; s < 4; ++s)
         if (is_full(c->cfg.bc[s]) && c->vfd[s] == LBM_VISC_MESO) g.vism = 1;
@@ -486,7 +489,8 @@ int run_adjoint(lbm_ctx* c, const double* seed, double* grad, double* h_relax) {
             g.V0 = V[n & 1];
             g.mom = mom_slot(b, j);
             if (nside_blocks > 0) {
-                hipLaunchKernelGGL((k_adj_side<Q>), dim3(nside_blocks), dim3(256), 0, st, g);
+                if (any_full) hipLaunchKernelGGL((k_adj_side<Q, true>), dim3(nside_blocks), dim3(256), 0, st, g);
+                else hipLaunchKernelGGL((k_adj_side<Q, false>), dim3(nside_blocks), dim3(256), 0, st, g);
                 HIPCHK(c, hipGetLastError());
             }
             if (any_corner && g.coupled) {
@@ -792,8 +796,10 @@ long lbm_steps_done(const lbm_ctx* c) { return c ? c->steps : -1; }
 
 int lbm_set_kernel_timing(lbm_ctx* c, int enable) {
     if (!c) return fail(nullptr, LBM_E_ARG, "null context");
-    c->timing = enable != 0;
+    if (enable < 0) return fail(c, LBM_E_ARG, "enable must be 0 or a positive stride");
+    c->timing = enable;
     c->tcount = 0;
+    c->tcalls = 0;
     return LBM_OK;
 }
 

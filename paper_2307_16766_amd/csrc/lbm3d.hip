@@ -98,7 +98,8 @@ struct lbm3d_ctx {
     lbm_relax relax[2];
     int meso[2] = {0, 0};
     std::string err;
-    bool timing = false;
+    int timing = 0;                // time every timing-th bulk launch (0: off)
+    size_t tcalls = 0;             // bulk launches since timing was set
     std::vector<hipEvent_t> tev;
     size_t tcount = 0;
 };
@@ -170,7 +171,7 @@ int launch_step3(lbm3d_ctx* c) {
     const int bpr = (g.nx + 255) / 256;
     const unsigned magic = bpr > 1 ? (unsigned)((1ull << 32) / (unsigned long long)bpr + 1ull) : 0u;
     const unsigned nblk = (unsigned)bpr * (unsigned)rows;
-    const bool rec = c->timing && c->tcount < 65536;
+    const bool rec = c->timing > 0 && (c->tcalls++ % (size_t)c->timing) == 0 && c->tcount < 65536;
     if (rec) {
         while (c->tev.size() < 2 * (c->tcount + 1)) {
             hipEvent_t e;
@@ -353,8 +354,10 @@ int lbm3d_diagnostics(lbm3d_ctx* c, double* h_out) {
 
 int lbm3d_set_kernel_timing(lbm3d_ctx* c, int enable) {
     if (!c) return fail3(nullptr, LBM_E_ARG, "null context");
-    c->timing = enable != 0;
+    if (enable < 0) return fail3(c, LBM_E_ARG, "enable must be 0 or a positive stride");
+    c->timing = enable;
     c->tcount = 0;
+    c->tcalls = 0;
     return LBM_OK;
 }
 

@@ -224,8 +224,9 @@ class LBM:
     def steps_done(self):
         return load().lbm_steps_done(self.ctx)
 
-    def set_kernel_timing(self, enable=True):
-        self._check(load().lbm_set_kernel_timing(self.ctx, 1 if enable else 0))
+    def set_kernel_timing(self, enable=True, every=1):
+        """Time every `every`-th step kernel launch with HIP events (enable False: off)."""
+        self._check(load().lbm_set_kernel_timing(self.ctx, int(every) if enable else 0))
 
     def bulk_kernel_time(self):
         """(summed milliseconds, launches) of the timed bulk kernel launches."""

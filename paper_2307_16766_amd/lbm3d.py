@@ -152,8 +152,9 @@ class LBM3D:
             self._check(rc)
         return np.array(out[:8])
 
-    def set_kernel_timing(self, enable):
-        self._check(load().lbm3d_set_kernel_timing(self.ctx, 1 if enable else 0))
+    def set_kernel_timing(self, enable, every=1):
+        """Time every `every`-th bulk kernel launch with HIP events (enable False: off)."""
+        self._check(load().lbm3d_set_kernel_timing(self.ctx, int(every) if enable else 0))
 
     def bulk_kernel_time(self):
         ms, n = ctypes.c_double(), ctypes.c_long()

@@ -119,7 +119,13 @@ def test_kernel_timing():
     g.step(7)
     ms, n = g.bulk_kernel_time()
     assert n == 7 and ms > 0
+    g.set_kernel_timing(True, every=3)      # launches 0, 3, 6, 9 of the next ten
+    g.step(10)
+    ms, n = g.bulk_kernel_time()
+    assert n == 4 and ms > 0
     g.set_kernel_timing(False)
     g.step(2)
     assert g.bulk_kernel_time()[1] == 0
+    with pytest.raises(lbm.LBMError):
+        g.set_kernel_timing(True, every=-1)
     g.close()
