@@ -466,7 +466,9 @@ struct Sim {
                 setU(U, x, y, u4);
                 node_feq(f, x, y, u4);
             }
-        fpre = f;
+        // Dirichlet sides: the default profile is the initial state of the first layer, and a
+        // profile takes effect when it is set: every layer of the row holds its equilibrium from
+        // time 0 on (as with an explicit profile, oracle_set_inlet)
         for (int s = 0; s < 4; ++s) {
             if (bc[s] != BC_DIRICHLET) continue;
             const SideGeo& g = geo[s];
@@ -474,8 +476,14 @@ struct Sim {
                 int x, y; node(g, 1, r, x, y);
                 S u4[4]; getU(U, x, y, u4);
                 for (int c = 0; c < 4; ++c) inlet[s][r * 4 + c] = u4[c];
+                for (int j = 2; j <= M; ++j) {
+                    int xj, yj; node(g, j, r, xj, yj);
+                    setU(U, xj, yj, u4);
+                    node_feq(f, xj, yj, u4);
+                }
             }
         }
+        fpre = f;
         steps = 0;
     }
 

@@ -64,6 +64,18 @@ def test_d2q37_dirichlet_inlet(precision):
                 EARLY, relax=dict(sigma=0.25, mach=0.05), inlet=(0, prof))
 
 
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_d2q37_dirichlet_default_profile(precision):
+    # no explicit profile: the inlet is the initial state of the first layer, applied to every
+    # layer from time 0 on; the fields vary across the layers, so a layer left at its own initial
+    # equilibrium for the first step would show
+    nx, ny = 40, 24
+    f = (1 + smooth_random(nx, ny, 11, 0.01), 0.03 + smooth_random(nx, ny, 12, 0.02), smooth_random(nx, ny, 13, 0.02),
+         1 + smooth_random(nx, ny, 14, 0.01))
+    compare_run("d2q37-inlet-default", 37, nx, ny, TAU_37, ["dirichlet", "lodi_relax", "periodic", "periodic"], f,
+                precision, EARLY, relax=dict(sigma=0.25, mach=0.05))
+
+
 def test_d2q37_periodic():
     nx, ny = 40, 30
     f = (1 + smooth_random(nx, ny, 1, 0.01), smooth_random(nx, ny, 2, 0.03), smooth_random(nx, ny, 3, 0.03),
