@@ -182,8 +182,10 @@ int lbm_bulk_kernel_time(lbm_ctx* ctx, double* total_ms, long* launches);
  * solve of every side and corner with wave directions frozen at the start of the step, and the
  * equilibrium reconstruction), in FP64 whatever the storage precision.  Supported boundaries:
  * periodic, LODI, LODI_RELAX, CBC and CBC_RELAX (mesoscopic or finite-difference viscous
- * terms), with the equilibrium or the NEEP reconstruction (D2Q9 additionally needs one periodic
- * axis); zero-gradient and Dirichlet sides return LBM_E_UNSUPPORTED.  The boundary settings
+ * terms), with the equilibrium or the NEEP reconstruction, and Dirichlet sides whose profile was
+ * given with lbm_dirichlet_profile (their layers are constants; the gradient with respect to the
+ * initial fields is 0 on them); D2Q9 additionally needs one periodic axis.  Zero-gradient sides
+ * and Dirichlet sides with the default profile return LBM_E_UNSUPPORTED.  The boundary settings
  * (relaxation, reconstruction, viscous terms) must stay those of the recording: lbm_adjoint
  * recomputes the recorded steps with the settings current at its call.
  *

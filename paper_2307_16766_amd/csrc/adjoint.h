@@ -1026,6 +1026,15 @@ __global__ __launch_bounds__(256) void k_adj_bulk(AdjArgs g, BulkArgs k, int bpr
         const double m[4] = {g.mom[o], g.mom[plane + o], g.mom[2 * plane + o], Lat<Q>::thermal ? g.mom[3 * plane + o] : 1.0};
         double G[4];
         feq_vjp<Q>(m, lam, G);
+        // the layers of a Dirichlet side hold the equilibrium of the given profile, not of the
+        // initial fields there
+        for (int sd = 0; sd < 4; ++sd) {
+            const SideDev& S = g.b.s[sd];
+            if (S.kind != KIND_DIRICHLET) continue;
+            const int j = ((S.nax == 0 ? x : y) - S.xf) * S.sn;
+            if (j >= 1 && j <= M)
+                for (int a = 0; a < 4; ++a) G[a] = 0.0;
+        }
         const size_t n = (size_t)k.nx * k.ny;
         for (int a = 0; a < 4; ++a) g.grad[a * n + id] = G[a];
         return;

@@ -180,6 +180,7 @@ struct lbm_ctx {
     void* f[2] = {nullptr, nullptr};
     char* region[2] = {nullptr, nullptr};
     double* inlet[4] = {nullptr, nullptr, nullptr, nullptr};
+    int inlet_set[4] = {0, 0, 0, 0};   // Dirichlet profile given by lbm_dirichlet_profile
     double* diag = nullptr;
     int cur = 0;
     long steps = 0;
@@ -333,11 +334,18 @@ int launch_init(lbm_ctx* c, const double* rho, const double* ux, const double* u
 }
 
 // ---------------------------------------------------------------- discrete adjoint (host side)
-int adjoint_supported(const lbm_config& g, std::string& err) {
+int adjoint_supported(const lbm_ctx* c, std::string& err) {
+    const lbm_config& g = c->cfg;
     for (int s = 0; s < 4; ++s) {
         const int b = g.bc[s];
-        if (b != BC_PERIODIC && b != BC_LODI && b != BC_LODI_RELAX && !is_full(b)) {
-            err = "the adjoint supports periodic, LODI, LODI-RELAX, CBC and CBC-RELAX sides only";
+        if (b == BC_ZG) {
+            err = "the adjoint does not support zero-gradient sides";
+            return LBM_E_UNSUPPORTED;
+        }
+        if (b == BC_DIRICHLET && !c->inlet_set[s]) {
+            // a default profile is the initial state of the first layer: the layers would depend
+            // on the initial fields at every step
+            err = "the adjoint needs the Dirichlet profile set with lbm_dirichlet_profile";
             return LBM_E_UNSUPPORTED;
         }
     }
@@ -459,6 +467,14 @@ int run_adjoint(lbm_ctx* c, const double* seed, double* grad, double* h_relax) {
         HIPCHK(c, hipMemcpyAsync(reg_slot(b, 0), chk + L.f_bytes, L.region_bytes, hipMemcpyDeviceToDevice, ax));
         hipLaunchKernelGGL((k_adj_moments<Q, T>), dim3(bpr * ny), dim3(256), 0, ax, (const T*)R[0], mom_slot(b, 0), bk, bpr);
         HIPCHK(c, hipGetLastError());
+        // the step kernel never writes Dirichlet layers (their profile is fixed): give the second
+        // recomputation buffer the same layers as the checkpoint
+        for (int s = 0; s < 4; ++s) {
+            if (L.s[s].kind != KIND_DIRICHLET) continue;
+            const int tot = L.s[s].len * L.M;
+            hipLaunchKernelGGL((k_dirichlet<Q, T>), dim3((tot + 255) / 256), dim3(256), 0, ax, g.b, s, c->inlet[s], R[0], R[1]);
+            HIPCHK(c, hipGetLastError());
+        }
         for (int j = 0; j < n1 - n0; ++j) {
             launch_step_raw<Q, T, true>(c, R[j & 1], R[(j + 1) & 1], reg_slot(b, j), reg_slot(b, j + 1), mom_slot(b, j + 1), ax);
             HIPCHK(c, hipGetLastError());
@@ -652,6 +668,7 @@ int lbm_dirichlet_profile(lbm_ctx* c, int side, const double* d_U) {
     if (c->L.s[side].kind != KIND_DIRICHLET) return fail(c, LBM_E_STATE, "side is not a Dirichlet side");
     const size_t bytes = (size_t)c->L.s[side].len * 4 * 8;
     HIPCHK(c, hipMemcpyAsync(c->inlet[side], d_U, bytes, hipMemcpyDeviceToDevice, c->stream));
+    c->inlet_set[side] = 1;
     return dispatch(c, [&]<int Q, typename T>() -> int {
         const BndArgs a = make_bnd(c);
         const int tot = c->L.s[side].len * c->L.M;
@@ -758,7 +775,7 @@ size_t lbm_tape_bytes(const lbm_ctx* c, int nsteps, int every) {
 int lbm_record(lbm_ctx* c, int nsteps, int every, void* d_tape, size_t tape_bytes) {
     if (!c) return fail(nullptr, LBM_E_ARG, "null context");
     std::string err;
-    const int sup = adjoint_supported(c->cfg, err);
+    const int sup = adjoint_supported(c, err);
     if (sup != LBM_OK) return fail(c, sup, err);
     if (nsteps < 1 || every < 1) return fail(c, LBM_E_ARG, "nsteps and every must be positive");
     if (!d_tape || ((uintptr_t)d_tape % ALIGN) != 0) return fail(c, LBM_E_ARG, "tape must be non-NULL and 256-byte aligned");
@@ -787,7 +804,7 @@ int lbm_adjoint(lbm_ctx* c, const double* d_seed, double* d_grad_fields, double*
     if (!c->tape.base) return fail(c, LBM_E_STATE, "no recorded run (call lbm_record first)");
     if (c->steps != c->tape.step_end) return fail(c, LBM_E_STATE, "the context has stepped since lbm_record");
     std::string err;
-    const int sup = adjoint_supported(c->cfg, err);
+    const int sup = adjoint_supported(c, err);
     if (sup != LBM_OK) return fail(c, sup, err);
     return dispatch(c, [&]<int Q, typename T>() -> int { return run_adjoint<Q, T>(c, d_seed, d_grad_fields, h_grad_relax); });
 }

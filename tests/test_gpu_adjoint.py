@@ -76,6 +76,11 @@ CASES = {
                                steps=30, every=11, relax=dict(sigma=0.25, alpha=0.1, mach=0.05), recon="neep"),
     "d2q17_cbc_neep_periodic_y": dict(stencil=17, nx=48, ny=40, tau=0.9, bc=["cbc_relax", "cbc", "periodic", "periodic"],
                                       steps=30, every=30, relax=dict(sigma=0.3, alpha=0.2, mach=0.05), recon="neep"),
+    # Dirichlet inlet with a given profile (the layers are constants) and a LODI-RELAX outflow, as
+    # in the throughput workload; the profile equals the first layer's initial state, which is
+    # the oracle's default, and the perturbations leave the layer nodes alone
+    "d2q37_inlet_periodic_y": dict(stencil=37, nx=60, ny=44, tau=TAU_37, bc=["dirichlet", "lodi_relax", "periodic", "periodic"],
+                                   steps=30, every=12, relax=dict(sigma=0.3, alpha=0.2, mach=0.05), inlet=True),
 }
 
 
@@ -111,6 +116,8 @@ def _case_dirs(c, seed):
     dF[2, 2], dF[2, 3] = d[2], d[3]             # y velocity and temperature
     if c["stencil"] == 9:
         dF[2, 3] = 0.0
+    if c.get("inlet"):
+        dF[..., :3] = 0.0   # the Dirichlet layers x = 0, 1, 2
     return dF
 
 
@@ -130,6 +137,8 @@ def test_adjoint_matches_oracle_tangents(name, loss):
                                      fields, dF, c["steps"], wlin, visc=_visc(c), recon=_recon(c))
     g = _sim(c["stencil"], c["nx"], c["ny"], c["tau"], c["bc"], fields, c["relax"], visc=c.get("visc"),
              recon=c.get("recon"))
+    if c.get("inlet"):
+        g.set_inlet(0, np.stack([np.asarray(a)[:, 2] for a in fields], axis=1))
     g.record(c["steps"], c["every"])
     d = g.diagnostics()
     if loss == "pressure":
@@ -193,7 +202,7 @@ def test_adjoint_argument_and_state_errors():
     assert e.value.code == lbm.LBM_E_UNSUPPORTED
     g.close()
     g = lbm.LBM(37, 40, 40, TAU_37, ["dirichlet", "lodi", "periodic", "periodic"], f)
-    with pytest.raises(lbm.LBMError) as e:   # Dirichlet side
+    with pytest.raises(lbm.LBMError) as e:   # Dirichlet side with the default profile
         g.record(5, 2)
     assert e.value.code == lbm.LBM_E_UNSUPPORTED
     g.close()
