@@ -1239,6 +1239,20 @@ int oracle_tangent_run_fields(int stencil, int nx, int ny, double tau, const int
                                         nullptr, nullptr, nsteps, out);
 }
 
+// Right-hand side of the corner LODI analysis (Sec. 3.3, corner treatment) of corner cidx
+// (0 = (x0, y0), 1 = (x1, y0), 2 = (x0, y1), 3 = (x1, y1)) for given states (global components
+// rho, ux, uy, T): Uc at the innermost corner node, Ucn the state fixing the wave directions, B1
+// and B2 at the two inward diagonal nodes.  Exposed to pin the diagonal analysis.
+int oracle_corner_rhs_probe(void* h, int cidx, const double* Uc, const double* Ucn, const double* B1,
+                            const double* B2, double* out) {
+    auto* s = static_cast<Sim<double>*>(h);
+    if (cidx < 0 || cidx > 3) return -1;
+    const auto c = s->corner(cidx);
+    if (!c.active || c.zg) return -1;
+    s->corner_rhs(c, Uc, Ucn, B1, B2, out);
+    return 0;
+}
+
 // Viscous terms V = (0, V_n, V_t, V_T) (local frame) at bulk node (x, y) of a domain whose
 // direction along the side is periodic, as if a boundary with outward normal along axis nax
 // (0 = x, 1 = y) and sign sn sat just beyond (x, y).  Exposed to pin eq. LaplaceU/LaplaceT.

@@ -52,6 +52,7 @@ def lib():
         L.oracle_pops.argtypes = [ctypes.c_void_p, _dp]
         L.oracle_diag.argtypes = [ctypes.c_void_p, _dp]
         L.oracle_visc_probe.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp]
+        L.oracle_corner_rhs_probe.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp, _dp, _dp, _dp]
         L.oracle_loss.restype = ctypes.c_double
         L.oracle_loss.argtypes = [ctypes.c_void_p]
         L.oracle_tangent_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, _ip,
@@ -153,6 +154,14 @@ class Oracle:
         U = np.ascontiguousarray(U, dtype=np.float64)
         if lib().oracle_set_inlet(self.h, side, _ptr(U)) != 0:
             raise ValueError("side is not a Dirichlet side")
+
+    def corner_rhs_probe(self, cidx, Uc, Ucn, B1, B2):
+        """Corner LODI right-hand side (Sec. 3.3, corner treatment) for given states."""
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (Uc, Ucn, B1, B2)]
+        out = np.zeros(4)
+        if lib().oracle_corner_rhs_probe(self.h, cidx, *[_ptr(a) for a in arrs], _ptr(out)) != 0:
+            raise ValueError("no characteristic corner there")
+        return out
 
     def set_recon(self, side, mode):
         """Mesoscopic BC of a characteristic side: "equilibrium" or "neep" (eq. NEEP)."""
