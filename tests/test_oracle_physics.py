@@ -277,6 +277,44 @@ def test_viscous_terms_match_laplacian(stencil, mode):
             assert abs(V[3] / ref - 1) < 0.015
 
 
+@pytest.mark.parametrize("stencil,mode", [(37, "longitudinal"), (37, "heating"), (17, "longitudinal"), (17, "heating")])
+def test_viscous_normal_term_and_heating(stencil, mode):
+    # eq. LaplaceU along the normal: a longitudinal wave u_x = A sin(k x) has, for the BGK gas
+    # without bulk viscosity, Pi'_xx = rho nu d_x u_x, so V_n = nu d_xx u_x (times the side's sign
+    # sn in the local frame).  The viscous heating of eq. NSF: for a shear wave u_y = A sin(k x)
+    # of finite amplitude V_T = 2 nu lap(T) + (nu / cs^2)(d_x u_y)^2 (c_v = 1); both checked
+    # against central differences of the oracle's own macroscopic fields (FD error O(k^2)).  The
+    # longitudinal wave is a standing sound wave whose stress lags the velocity by about
+    # (tau - 1/2) steps: it is sampled after half an acoustic period, at full amplitude
+    nx, ny = 64, 8
+    k = 2 * math.pi / nx
+    cs2 = O.lattice(stencil)[0]
+    nu = (TAUS[stencil] - 0.5) * cs2
+    X, _ = W.grid(nx, ny)
+    o = O.Oracle(stencil, nx, ny, TAUS[stencil], ["periodic"] * 4)
+    one = np.ones_like(X)
+    if mode == "longitudinal":
+        o.init(one, 1e-3 * np.sin(k * X), 0 * X, one)
+    else:
+        o.init(one, 0 * X, 0.03 * np.sin(k * X), one)
+    o.step(round(math.pi / (math.sqrt(2 * cs2) * k)) if mode == "longitudinal" else 20)
+    r, ux, uy, T = o.macro()
+    x = 20
+    d2 = lambda a: a[3, x + 1] - 2 * a[3, x] + a[3, x - 1]
+    d1 = lambda a: 0.5 * (a[3, x + 1] - a[3, x - 1])
+    for sn in (1, -1):
+        V = o.visc_probe(0, sn, x, 3)
+        if mode == "longitudinal":
+            ref = sn * nu * d2(ux)
+            assert abs(V[1] / ref - 1) < 0.02, (sn, V[1], ref)
+        else:
+            heat = nu / cs2 * d1(uy) ** 2
+            ref = 2 * nu * d2(T) + heat
+            assert abs(heat) > 3 * abs(2 * nu * d2(T))   # the heating dominates here
+            assert abs(V[3] / ref - 1) < 0.02, (sn, V[3], ref)
+    o.close()
+
+
 @pytest.mark.parametrize("flow", ["rest", "diagonal"])
 def test_tangent_mode_matches_finite_differences(flow):
     # the dual-number instantiation reproduces central differences of the plain solver.  At rest
