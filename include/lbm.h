@@ -184,8 +184,9 @@ int lbm_bulk_kernel_time(lbm_ctx* ctx, double* total_ms, long* launches);
  * periodic, LODI, LODI_RELAX, CBC and CBC_RELAX (mesoscopic or finite-difference viscous
  * terms), with the equilibrium or the NEEP reconstruction, and Dirichlet sides whose profile was
  * given with lbm_dirichlet_profile (their layers are constants; the gradient with respect to the
- * initial fields is 0 on them); D2Q9 additionally needs one periodic axis.  Zero-gradient sides
- * and Dirichlet sides with the default profile return LBM_E_UNSUPPORTED.  The boundary settings
+ * initial fields is 0 on them), and zero-gradient sides with their corners; D2Q9 additionally
+ * needs one periodic axis.  Dirichlet sides with the default profile return LBM_E_UNSUPPORTED.
+ * The boundary settings
  * (relaxation, reconstruction, viscous terms) must stay those of the recording: lbm_adjoint
  * recomputes the recorded steps with the settings current at its call.
  *

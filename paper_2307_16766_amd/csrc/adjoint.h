@@ -422,6 +422,7 @@ struct AdjArgs {
     double* V1;              // nu / lambda of time n+1
     double* V0;              // nu / lambda of time n (written by k_adj_bulk)
     const double* mom;       // moments of time n, planes [4][ny][pitch]
+    const double* mom1;      // moments of time n + 1 (bulk nodes), same layout
     double* grad;            // n = 0: dL/d(rho0, ux0, uy0, T0), [4][ny][nx]
     int ablk0[4], anblk[4];  // side blocks of k_adj_side
     int arows;               // owned rows per side block
@@ -431,8 +432,10 @@ struct AdjArgs {
     int coupled;             // corners read the sides' contributions (transverse relaxation alpha != 0)
     int vism;                // some CBC side uses the mesoscopic viscous terms
     int neep_any;            // some characteristic side uses NEEP (eq. NEEP)
-    double* neep[4];         // per NEEP side, row r: (1 - omega) sum_j lambda^{n+1}(x_b,j) [Q], then its
-                             // projection (dm/dM)^T (df^eq/dm)^T of the same [4]; NULL otherwise
+    double* neep[4];         // per NEEP or zero-gradient side, row r: the terms a_i [Q] and GM [4] that
+                             // nu^{n+1}(x_f) gets as a_i - phi_i . GM; NULL for other sides
+    double* zgc;             // per zero-gradient corner: the same terms for nu^{n+1}(c + v), [4][Q + 4]
+    int zgc_any;
 };
 
 // ------------------------------------------------------------------ reverse of a side chunk
@@ -935,6 +938,62 @@ __device__ void corner_adj(const AdjArgs& g, int ci) {
     for (int m = 0; m < 4; ++m) g.gm[(8 + ci * 2 + 1) * 4 + m] = GM[m];
 }
 
+// ------------------------------------------------------------------ reverse of a zero-gradient side
+// The layers of row r hold the post-collision populations C(g) of x_f (eq. zg-bc), the corner
+// blocks those of the inward diagonal node c + v: the adjoint of that g gets C^T Lambda =
+// (1 - omega) Lambda + omega phi . GM, Lambda = the sum of lambda^{n+1} over the copies, GM =
+// (dm/dM)^T (df^eq/dm)^T Lambda at g's moments (time n + 1).  Written as (a, -GM') with a =
+// (1 - omega) Lambda, GM' = omega GM for k_adj_bulk, which adds a_i - phi_i . GM' where it pulls
+// from these nodes.  One thread per row; the corners on the first thread of the owning side.
+template <int Q>
+__device__ void zg_adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int chunk) {
+    constexpr int M = Lat<Q>::M;
+    const BndArgs& a = g.b;
+    const double om = a.omega;
+    const unsigned long long plane = (unsigned long long)a.ny * a.pitch;
+    auto emit = [&](int x, int y, const double* lam, double* o) {
+        const unsigned long long id = (unsigned long long)y * a.pitch + x;
+        const double m[4] = {g.mom1[id], g.mom1[plane + id], g.mom1[2 * plane + id],
+                             Lat<Q>::thermal ? g.mom1[3 * plane + id] : 1.0};
+        double G[4], GM[4];
+        feq_vjp<Q>(m, lam, G);
+        mom_vjp<Q>(m, G, GM);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) o[i] = (1.0 - om) * lam[i];
+        for (int k = 0; k < 4; ++k) o[Q + k] = -om * GM[k];
+    };
+    const int r = chunk * 256 + (int)threadIdx.x;
+    if (r < sd.len) {
+        double lam[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) lam[i] = 0.0;
+        for (int j = 1; j <= M; ++j) {
+            int x, y; side_node(sd, j, r, x, y);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) lam[i] += g.V1[pix<Q>(a.pitch, i, x, y)];
+        }
+        int xf, yf; side_node(sd, 0, r, xf, yf);
+        emit(xf, yf, lam, g.neep[side] + (size_t)r * (Q + 4));
+    }
+    if (!sd.tper && sd.owns_corners && threadIdx.x == 0) {
+        for (int e = 0; e < 2; ++e) {
+            const int ci = e == 0 ? sd.corner_lo : sd.corner_hi;
+            const bool mine = e == 0 ? (chunk == 0) : ((chunk + 1) * 256 >= sd.len);
+            if (ci < 0 || !mine || !a.c[ci].active || !a.c[ci].zg) continue;
+            const CornerDev& c = a.c[ci];
+            double lam[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) lam[i] = 0.0;
+            for (int jx = 0; jx < M; ++jx)
+                for (int jy = 0; jy < M; ++jy) {
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) lam[i] += g.V1[pix<Q>(a.pitch, i, c.x0 + c.sxn * jx, c.y0 + c.syn * jy)];
+                }
+            emit(c.xc + c.vx, c.yc + c.vy, lam, g.zgc + (size_t)ci * (Q + 4));
+        }
+    }
+}
+
 // side chunks; when the corners do not read the sides' contributions, the corners too (the
 // blocks after the side chunks).  CBC: compiled with the CBC variants' terms (some side is CBC
 // or CBC-RELAX); without them the LODI schemes run a leaner kernel.
@@ -948,7 +1007,8 @@ __global__ __launch_bounds__(256) void k_adj_side(AdjArgs g) {
     int s = 0;
     while (s < 4 && !(g.anblk[s] > 0 && b >= g.ablk0[s] && b < g.ablk0[s] + g.anblk[s])) ++s;
     if (s == 4) return;
-    adj_chunk<Q, CBC>(g, g.b.s[s], s, b, b - g.ablk0[s]);
+    if (g.b.s[s].kind == KIND_ZG) zg_adj_chunk<Q>(g, g.b.s[s], s, b - g.ablk0[s]);
+    else adj_chunk<Q, CBC>(g, g.b.s[s], s, b, b - g.ablk0[s]);
 }
 
 // corners after the side chunks (coupled case)
@@ -996,6 +1056,19 @@ __global__ __launch_bounds__(256) void k_adj_bulk(AdjArgs g, BulkArgs k, int bpr
                 const double* o = nb + (size_t)r * (Q + 4);
                 lam[i] += o[i] - phi_dot<Q>(i, o + Q);
             }
+        }
+    }
+    if (g.zgc_any) {
+        // zero-gradient corner blocks: terms of nu^{n+1} at the inward diagonal node c + v
+        for (int ci = 0; ci < 4; ++ci) {
+            const CornerDev& c = g.b.c[ci];
+            if (!c.active || !c.zg) continue;
+            const int dx = c.xc + c.vx - x, dy = c.yc + c.vy - y;
+            if (dx < -3 || dx > 3 || dy < -3 || dy > 3) continue;
+            const double* o = g.zgc + (size_t)ci * (Q + 4);
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+                if (cx<Q>(i) == dx && cy<Q>(i) == dy) lam[i] += o[i] - phi_dot<Q>(i, o + Q);
         }
     }
     // corrections of nu^{n+1} at the corner diagonal nodes c + v (the corner's term and both

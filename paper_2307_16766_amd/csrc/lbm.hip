@@ -169,7 +169,8 @@ struct Tape {
     // of one segment overlaps the reverse sweep of the next one
     size_t chk_stride = 0, off_R[2][2] = {{0, 0}, {0, 0}}, off_V[2] = {0, 0}, off_mom[2] = {0, 0}, mom_bytes = 0, off_rh[2] = {0, 0};
     size_t off_adj[2] = {0, 0}, off_ccon = 0, off_gm = 0, off_acc = 0, total = 0;
-    size_t off_neep[4] = {0, 0, 0, 0};   // per characteristic side: [len][Q + 4] NEEP terms of nu^{n+1}(x_f)
+    size_t off_neep[4] = {0, 0, 0, 0};   // per characteristic / ZG side: [len][Q + 4] terms of nu^{n+1}(x_f)
+    size_t off_zgc = 0;                  // per zero-gradient corner: [Q + 4] terms of nu^{n+1}(c + v)
     int ablk0[4] = {0, 0, 0, 0}, anblk[4] = {0, 0, 0, 0}, arows = 0, nadj = 0;
 };
 
@@ -338,10 +339,6 @@ int adjoint_supported(const lbm_ctx* c, std::string& err) {
     const lbm_config& g = c->cfg;
     for (int s = 0; s < 4; ++s) {
         const int b = g.bc[s];
-        if (b == BC_ZG) {
-            err = "the adjoint does not support zero-gradient sides";
-            return LBM_E_UNSUPPORTED;
-        }
         if (b == BC_DIRICHLET && !c->inlet_set[s]) {
             // a default profile is the initial state of the first layer: the layers would depend
             // on the initial fields at every step
@@ -376,12 +373,17 @@ void tape_layout(const Layout& L, int ny, int N, int K, Tape& t) {
     t.nadj = 0;
     for (int s = 0; s < 4; ++s) {
         t.ablk0[s] = t.nadj;
-        t.anblk[s] = L.s[s].kind == KIND_CHAR ? (L.s[s].len + t.arows - 1) / t.arows : 0;
+        t.anblk[s] = L.s[s].kind == KIND_CHAR ? (L.s[s].len + t.arows - 1) / t.arows
+                   : L.s[s].kind == KIND_ZG ? (L.s[s].len + 255) / 256 : 0;
         t.nadj += t.anblk[s];
     }
     t.off_acc = off; off += align_up((size_t)(2 * t.nadj + 4) * 8);
     for (int s = 0; s < 4; ++s)
-        if (L.s[s].kind == KIND_CHAR) { t.off_neep[s] = off; off += align_up((size_t)L.s[s].len * (L.Q + 4) * 8); }
+        if (L.s[s].kind == KIND_CHAR || L.s[s].kind == KIND_ZG) {
+            t.off_neep[s] = off;
+            off += align_up((size_t)L.s[s].len * (L.Q + 4) * 8);
+        }
+    t.off_zgc = off; off += align_up((size_t)4 * (L.Q + 4) * 8);
     t.total = off;
 }
 
@@ -410,6 +412,7 @@ int run_adjoint(lbm_ctx* c, const double* seed, double* grad, double* h_relax) {
     HIPCHK(c, hipMemsetAsync(base + t.off_ccon, 0, 4 * 2 * 2 * 4 * 8, st));
     HIPCHK(c, hipMemsetAsync(base + t.off_gm, 0, 16 * 4 * 8, st));
     HIPCHK(c, hipMemsetAsync(base + t.off_acc, 0, (size_t)(2 * t.nadj + 4) * 8, st));
+    HIPCHK(c, hipMemsetAsync(base + t.off_zgc, 0, (size_t)4 * (L.Q + 4) * 8, st));
 
     AdjArgs g;
     std::memset(&g, 0, sizeof(g));
@@ -446,11 +449,14 @@ int run_adjoint(lbm_ctx* c, const double* seed, double* grad, double* h_relax) {
     g.neep_any = 0;
     for (int s = 0; s < 4; ++s) {
         g.neep[s] = nullptr;
-        if (L.s[s].kind == KIND_CHAR && c->meso[s] == LBM_RECON_NEEP) {
+        if ((L.s[s].kind == KIND_CHAR && c->meso[s] == LBM_RECON_NEEP) || L.s[s].kind == KIND_ZG) {
             g.neep[s] = (double*)(base + t.off_neep[s]);
             g.neep_any = 1;
         }
     }
+    g.zgc = (double*)(base + t.off_zgc);
+    g.zgc_any = 0;
+    for (int ci = 0; ci < 4; ++ci) g.zgc_any = g.zgc_any || (L.c[ci].active && L.c[ci].zg);
     const int nside_blocks = t.nadj + ((any_corner && !g.coupled) ? 4 : 0);
 
     // Segment seg is recomputed from its checkpoint on the second stream into recomputation set
@@ -504,6 +510,7 @@ int run_adjoint(lbm_ctx* c, const double* seed, double* grad, double* h_relax) {
             g.V1 = V[(n + 1) & 1];
             g.V0 = V[n & 1];
             g.mom = mom_slot(b, j);
+            g.mom1 = mom_slot(b, j + 1);
             if (nside_blocks > 0) {
                 if (any_full) hipLaunchKernelGGL((k_adj_side<Q, true>), dim3(nside_blocks), dim3(256), 0, st, g);
                 else hipLaunchKernelGGL((k_adj_side<Q, false>), dim3(nside_blocks), dim3(256), 0, st, g);
