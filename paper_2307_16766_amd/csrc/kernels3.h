@@ -7,10 +7,12 @@
 // viscous moments of x_f, x_f - 1, x_f - 2 [3][rows][10] (CBC schemes); RK4 stage inputs and the
 // viscous terms are single buffers.
 //
-// One time step = bulk kernel (fused pull-stream + moments + BGK, HBM-bound) + face kernels:
-// k3_prep (strip and viscous moments of the new level from pulls of A, viscous terms of the old
-// level), four k3_stage launches (one per RK4 stage of the coupled face system) and k3_final (new
-// layer populations: equilibrium, eq. NEEP or zero gradient).  Separate launches replace the
+// One time step = face kernels, which need only the old level A: k3_prep (strip and viscous
+// moments of the new level from pulls of A, viscous terms of the old level), four k3_stage
+// launches (one per RK4 stage of the coupled face system) and k3_final (new layer populations:
+// equilibrium, eq. NEEP or zero gradient, staged in a small buffer); then the bulk kernel (fused
+// pull-stream + moments + BGK, HBM-bound), whose boundary-layer lanes store the staged layer
+// populations with the bulk's own whole-line stores.  Separate launches replace the
 // halo recomputation of the two-dimensional boundary chunks: a face couples its rows in y and z,
 // so a chunk's halo would grow in two directions, while the face work is a small fraction of a
 // 3D step.
@@ -66,10 +68,11 @@ __device__ __forceinline__ void pull3(const T* __restrict__ A, const Args3& a, i
 
 // ================================================================== bulk: fused stream + collide
 struct Bulk3 {
-    int nx, ny, nz, x0, x1;
+    int nx, ny, nz, x0, x1, rows;
     unsigned long long pitch;
     float omega_f;
     double omega_d;
+    const void* lay;   // layer populations of the new level staged by k3_final, [face][rows][M][Q] of T
 };
 
 // One thread per node of a 256-node x-tile of one row (the tiles cover x = 0 .. nx - 1).  Loads
@@ -81,15 +84,15 @@ struct Bulk3 {
 // walks one contiguous range of rows; a node's up to 25 source rows (y - c_y, z - c_z) then sit
 // in the L2 of the XCD that reads them instead of being fetched by several XCDs (measured on
 // 512 x 256 x 256: FP64 62 % -> 72 % of HBM bandwidth, FP32 unchanged within 1 %).
-// Boundary-layer nodes get a placeholder (zero) store that k3_final rewrites after this launch.
-// Layer lanes run the same instruction stream as bulk lanes: they pull with the periodic wrap in
-// x (always in bounds; a bulk lane has M <= x <= nx - 1 - M and |c_x| <= M, so the wrap never
-// acts for it), and select zero at the store.  Each plane's first and last cache line of a row is then
-// written whole by one store instruction (partial-line stores of a streaming kernel cost read-
-// modify-write bandwidth: -8 % on 512 x 256 x 256 without the placeholder, -7 % with it in a
-// separate branch).  Computing the layers' final populations here instead (after the face
-// solve) was measured slower: the FP64 reconstruction diverges inside bulk waves and doubles the
-// register count.
+// Boundary-layer lanes store the layers' new populations, which k3_final has staged before this
+// launch (the faces are solved from the old level alone), so every plane's first and last cache
+// line of a row is written whole by one store instruction: layer lanes run the bulk lanes'
+// instruction stream (pulls with the periodic wrap in x, always in bounds; a bulk lane has
+// M <= x <= nx - 1 - M and |c_x| <= M, so the wrap never acts for it) and take the staged values
+// before the stores.  Partial-line stores cost read-modify-write bandwidth: k3_final writing 12
+// bytes per plane row into lines the bulk had written took 180 us per step on 512 x 256 x 256;
+// computing the layers' populations here instead doubles the bulk kernel's registers (the FP64
+// reconstruction) and was slower.
 template <typename T, bool PX>
 __global__ __launch_bounds__(256, (sizeof(T) == 4 ? 3 : 2)) void k3_bulk(const T* __restrict__ A, T* __restrict__ B, Bulk3 g,
                                                                           int bpr, unsigned magic) {
@@ -122,9 +125,15 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 ? 3 : 2)) void k3_bulk(const T
     }
     const T omega = sizeof(T) == 4 ? (T)g.omega_f : (T)g.omega_d;
     collide3_dev<T>(d, omega);
+    if (!act) {   // a boundary-layer node: its staged new populations
+        const int face = x < g.x0 ? 0 : 1, j = face == 0 ? g.x0 - x : x - g.x1;
+        const T* Ls = (const T*)g.lay + (((size_t)face * g.rows + (size_t)row) * L3::M + (j - 1)) * L3::Q;
+#pragma unroll
+        for (int i = 0; i < L3::Q; ++i) d[i] = Ls[i];
+    }
     T* Bo = B + pix3(g.pitch, g.ny, 0, x, y, z);
 #pragma unroll
-    for (int i = 0; i < L3::Q; ++i) __builtin_nontemporal_store(act ? d[i] : T(0), Bo + (unsigned long long)i * g.pitch);
+    for (int i = 0; i < L3::Q; ++i) __builtin_nontemporal_store(d[i], Bo + (unsigned long long)i * g.pitch);
 }
 
 // ================================================================== initialisation
@@ -403,16 +412,23 @@ __global__ __launch_bounds__(256) void k3_stage(Args3 a, int st) {
 // NEEP (eq. NEEP) the post-collision non-equilibrium part of x_f; zero-gradient faces copy x_f
 // (eq. zg-bc) from the new bulk populations in B.
 template <typename T>
-__global__ __launch_bounds__(256) void k3_final(const T* __restrict__ A, T* __restrict__ B, Args3 a) {
+__global__ __launch_bounds__(256) void k3_final(const T* __restrict__ A, T* __restrict__ S, Args3 a) {
     const int s = blockIdx.y;
     const Face3& fc = a.f[s];
     const int t = blockIdx.x * 256 + threadIdx.x;
     if (fc.scheme == F3_PERIODIC || t >= L3::M * a.rows) return;
     const int r = t / L3::M, jj = t - L3::M * r;
-    const int y = r % a.ny, z = r / a.ny, x = fc.xf + fc.sn * (jj + 1);
+    const int y = r % a.ny, z = r / a.ny;
+    T* o = S + (((size_t)s * a.rows + r) * L3::M + jj) * L3::Q;
     if (fc.scheme == F3_ZG) {
+        // eq. zg-bc: the post-collision populations of x_f, as the bulk kernel computes them
+        T d[L3::Q];
 #pragma unroll
-        for (int i = 0; i < L3::Q; ++i) B[pix3(a.pitch, a.ny, i, x, y, z)] = B[pix3(a.pitch, a.ny, i, fc.xf, y, z)];
+        for (int i = 0; i < L3::Q; ++i)
+            d[i] = A[pix3(a.pitch, a.ny, i, fc.xf - cx3(i), wrap3(y - cy3(i), a.ny), wrap3(z - cz3(i), a.nz))];
+        collide3_dev<T>(d, (T)a.omega);
+#pragma unroll
+        for (int i = 0; i < L3::Q; ++i) o[i] = d[i];
         return;
     }
     const double* ubn = (const double*)(a.reg_next + fc.off_ub);
@@ -431,7 +447,7 @@ __global__ __launch_bounds__(256) void k3_final(const T* __restrict__ A, T* __re
         for (int i = 0; i < L3::Q; ++i) fe[i] += c * (d[i] - fx[i]);
     }
 #pragma unroll
-    for (int i = 0; i < L3::Q; ++i) B[pix3(a.pitch, a.ny, i, x, y, z)] = (T)fe[i];
+    for (int i = 0; i < L3::Q; ++i) o[i] = (T)fe[i];
 }
 
 // ================================================================== output and diagnostics

@@ -28,6 +28,7 @@ struct Layout3 {
     unsigned long long pitch = 0;
     int rows = 0;
     size_t f_bytes = 0, region_bytes = 0, off_region = 0, off_Ya = 0, off_Yb = 0, off_V = 0, off_diag = 0, total = 0;
+    size_t off_lay = 0;   // staged layer populations of the new level [face][rows][M][Q] (storage type)
     int diag_blocks = 0;
     Face3 f[2];
 };
@@ -80,7 +81,8 @@ void make_layout3(const lbm3d_config* c, Layout3& L) {
     L.off_V = L.off_Yb + al3((size_t)2 * L3::M * L.rows * 5 * 8);
     L.off_diag = L.off_V + al3((size_t)2 * L.rows * 5 * 8);
     L.diag_blocks = 1024;
-    L.total = L.off_diag + al3((size_t)(L.diag_blocks + 1) * 8 * 8);
+    L.off_lay = L.off_diag + al3((size_t)(L.diag_blocks + 1) * 8 * 8);
+    L.total = L.off_lay + al3((size_t)2 * L.rows * L3::M * L3::Q * L.esz);
 }
 
 }  // namespace
@@ -153,6 +155,8 @@ Bulk3 make_bulk3(const lbm3d_ctx* c) {
     g.pitch = c->L.pitch;
     g.omega_d = 1.0 / c->cfg.tau;
     g.omega_f = (float)(1.0 / c->cfg.tau);
+    g.rows = c->L.rows;
+    g.lay = c->ws + c->L.off_lay;
     return g;
 }
 
@@ -171,6 +175,21 @@ int launch_step3(lbm3d_ctx* c) {
     const int bpr = (g.nx + 255) / 256;
     const unsigned magic = bpr > 1 ? (unsigned)((1ull << 32) / (unsigned long long)bpr + 1ull) : 0u;
     const unsigned nblk = (unsigned)bpr * (unsigned)rows;
+    // faces first (they read only A): characteristic solve, then the layers' new populations,
+    // staged for the bulk kernel's boundary-layer lanes
+    if (!a.xper) {
+        if (c->cfg.bc[0] != LBM_BC_ZG || c->cfg.bc[1] != LBM_BC_ZG) {
+            hipLaunchKernelGGL((k3_prep<T>), dim3((3 * rows + 255) / 256, 2), dim3(256), 0, c->stream, A, a);
+            HIPCHK3(c, hipGetLastError());
+            for (int st = 0; st < 4; ++st) {
+                hipLaunchKernelGGL(k3_stage, dim3((L3::M * rows + 255) / 256, 2), dim3(256), 0, c->stream, a, st);
+                HIPCHK3(c, hipGetLastError());
+            }
+        }
+        hipLaunchKernelGGL((k3_final<T>), dim3((L3::M * rows + 255) / 256, 2), dim3(256), 0, c->stream, A,
+                           (T*)(c->ws + c->L.off_lay), a);
+        HIPCHK3(c, hipGetLastError());
+    }
     const bool rec = c->timing > 0 && (c->tcalls++ % (size_t)c->timing) == 0 && c->tcount < 65536;
     if (rec) {
         while (c->tev.size() < 2 * (c->tcount + 1)) {
@@ -190,18 +209,6 @@ int launch_step3(lbm3d_ctx* c) {
     if (rec) {
         HIPCHK3(c, hipEventRecord(c->tev[2 * c->tcount + 1], c->stream));
         c->tcount += 1;
-    }
-    if (!a.xper) {
-        if (c->cfg.bc[0] != LBM_BC_ZG || c->cfg.bc[1] != LBM_BC_ZG) {
-            hipLaunchKernelGGL((k3_prep<T>), dim3((3 * rows + 255) / 256, 2), dim3(256), 0, c->stream, A, a);
-            HIPCHK3(c, hipGetLastError());
-            for (int st = 0; st < 4; ++st) {
-                hipLaunchKernelGGL(k3_stage, dim3((L3::M * rows + 255) / 256, 2), dim3(256), 0, c->stream, a, st);
-                HIPCHK3(c, hipGetLastError());
-            }
-        }
-        hipLaunchKernelGGL((k3_final<T>), dim3((L3::M * rows + 255) / 256, 2), dim3(256), 0, c->stream, A, B, a);
-        HIPCHK3(c, hipGetLastError());
     }
     c->cur ^= 1;
     c->steps += 1;
