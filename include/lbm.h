@@ -136,7 +136,8 @@ int lbm_viscous(lbm_ctx* ctx, int side, int mode);
 
 /* Fixed profile of a Dirichlet side: d_U is device FP64 [len][4] = (rho, u_x, u_y, T) per row
  * along the side (len = ny for x-sides, nx for y-sides).  Default: the initial fields on the
- * first boundary layer.  Writes the equilibrium populations of every layer immediately. */
+ * first boundary layer.  Writes the equilibrium populations of every layer immediately, and
+ * discards a run recorded with lbm_record (lbm_adjoint then returns LBM_E_STATE). */
 int lbm_dirichlet_profile(lbm_ctx* ctx, int side, const double* d_U);
 
 /* Advance nsteps time steps: fused stream + collide on the bulk, characteristic boundary solve
@@ -182,11 +183,12 @@ int lbm_bulk_kernel_time(lbm_ctx* ctx, double* total_ms, long* launches);
  * solve of every side and corner with wave directions frozen at the start of the step, and the
  * equilibrium reconstruction), in FP64 whatever the storage precision.  Supported boundaries:
  * periodic, LODI, LODI_RELAX, CBC and CBC_RELAX (mesoscopic or finite-difference viscous
- * terms), with the equilibrium or the NEEP reconstruction, and Dirichlet sides whose profile was
- * given with lbm_dirichlet_profile (their layers are constants; the gradient with respect to the
- * initial fields is 0 on them), and zero-gradient sides with their corners; D2Q9 additionally
- * needs one periodic axis.  Dirichlet sides with the default profile return LBM_E_UNSUPPORTED.
- * The boundary settings
+ * terms), with the equilibrium or the NEEP reconstruction, zero-gradient sides with their
+ * corners, and Dirichlet sides: with a profile given by lbm_dirichlet_profile the layers are
+ * constants and the gradient with respect to the initial fields is 0 on them; with the default
+ * profile every layer of a row holds, at every step, the equilibrium of the initial fields on the
+ * first layer, which then carry the whole row's gradient (the other layers 0).  D2Q9
+ * additionally needs one periodic axis (else LBM_E_UNSUPPORTED).  The boundary settings
  * (relaxation, reconstruction, viscous terms) must stay those of the recording: lbm_adjoint
  * recomputes the recorded steps with the settings current at its call.
  *

@@ -29,8 +29,10 @@
 //                  nu_i = (1 - omega) lambda_i + omega (G_0 + c_ix G_1 + c_iy G_2 + |c_i|^2 G_3),
 //                  G = (dm/dM)^T (df^eq/dm)^T lambda, M the linear moments (sum f, sum f c,
 //                  sum f |c|^2); at n = 0 it gives dL/d(rho0, ux0, uy0, T0) = (df^eq/dm)^T lambda^0.
-// Supported boundaries: periodic, LODI and LODI-RELAX (the CBC variants' viscous terms and the
-// zero-gradient / Dirichlet sides have no adjoint here).
+// Supported boundaries: all of them.  CBC sides with the mesoscopic viscous terms add their VJP
+// at the nodes x_f .. x_f - 2, NEEP and zero-gradient sides add terms of nu^{n+1}(x_f); the layers
+// of a Dirichlet side are constants of the given profile, or, with the default profile (the
+// initial state of the first layer), collect the adjoint of that profile (k_adj_dir_collect).
 #pragma once
 
 #include "kernels.h"
@@ -436,6 +438,10 @@ struct AdjArgs {
                              // nu^{n+1}(x_f) gets as a_i - phi_i . GM; NULL for other sides
     double* zgc;             // per zero-gradient corner: the same terms for nu^{n+1}(c + v), [4][Q + 4]
     int zgc_any;
+    double* dacc[4];         // per Dirichlet side with the default profile: [M][len][4] adjoint of the
+                             // row's profile collected per layer node; NULL for other sides
+    const double* dprof[4];  // that side's profile [len][4] (rho, ux, uy, T)
+    int dir_any;
 };
 
 // ------------------------------------------------------------------ reverse of a side chunk
@@ -1017,6 +1023,54 @@ __global__ __launch_bounds__(256) void k_adj_corner(AdjArgs g) {
     corner_adj<Q>(g, blockIdx.x);
 }
 
+// Layer node (x, y) of a Dirichlet side with the default profile: its slot of the side's
+// accumulator and its row's profile, or NULL.  Such a side has a periodic transverse axis, so its
+// rows are all the nodes along it (r0 = 0).
+template <int Q>
+__device__ __forceinline__ double* dir_slot(const AdjArgs& g, int x, int y, const double*& prof) {
+    constexpr int M = Lat<Q>::M;
+#pragma unroll
+    for (int sd = 0; sd < 4; ++sd) {
+        double* acc = g.dacc[sd];
+        if (!acc) continue;
+        const SideDev& S = g.b.s[sd];
+        const int j = ((S.nax == 0 ? x : y) - S.xf) * S.sn;
+        if (j < 1 || j > M) continue;
+        const int r = (S.nax == 0 ? y : x) - S.r0;
+        prof = g.dprof[sd] + (size_t)r * 4;
+        return acc + ((size_t)(j - 1) * S.len + r) * 4;
+    }
+    return nullptr;
+}
+
+// a += (d f^eq / d(rho, ux, uy, T))^T lam at the profile values u
+template <int Q>
+__device__ __forceinline__ void dir_fold(const double* u, const double* lam, double* a) {
+    const double m[4] = {u[0], u[1], u[2], Lat<Q>::thermal ? u[3] : 1.0};
+    double G[4];
+    feq_vjp<Q>(m, lam, G);
+    for (int c = 0; c < 4; ++c) a[c] += G[c];
+}
+
+// Per row of a Dirichlet side with the default profile: the profile is the initial state of the
+// first layer node, so its collected adjoint is dL/d(rho0, ux0, uy0, T0) there (after the INIT
+// pass, which leaves the gradient of every layer node of such a side at zero).
+template <int Q>
+__global__ __launch_bounds__(256) void k_adj_dir_collect(AdjArgs g, int s, int nx, int ny) {
+    constexpr int M = Lat<Q>::M;
+    const SideDev& S = g.b.s[s];
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= S.len) return;
+    int x, y;
+    side_node(S, 1, r, x, y);
+    const size_t n = (size_t)nx * ny, id = (size_t)y * nx + x;
+    for (int c = 0; c < 4; ++c) {
+        double v = 0.0;
+        for (int j = 0; j < M; ++j) v += g.dacc[s][((size_t)j * S.len + r) * 4 + c];
+        g.grad[c * n + id] = v;
+    }
+}
+
 // ------------------------------------------------------------------ bulk reverse
 // One thread per node (all nodes; 256-node tiles of one row).  INIT: the reverse of the
 // initialisation f^0 = f^eq(fields) at every node; the fields are read back as the moments of
@@ -1097,10 +1151,20 @@ __global__ __launch_bounds__(256) void k_adj_bulk(AdjArgs g, BulkArgs k, int bpr
         const int id = y * k.nx + x;
         const unsigned long long plane = (unsigned long long)k.ny * pitch, o = (unsigned long long)y * pitch + x;
         const double m[4] = {g.mom[o], g.mom[plane + o], g.mom[2 * plane + o], Lat<Q>::thermal ? g.mom[3 * plane + o] : 1.0};
+        if (g.dir_any) {
+            // lambda^1 and lambda^0 of a default-profile layer node go to its row's profile
+            const double* prof;
+            double* a = dir_slot<Q>(g, x, y, prof);
+            if (a) {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) lam[i] += g.V1[pix<Q>(pitch, i, x, y)];
+                dir_fold<Q>(prof, lam, a);
+            }
+        }
         double G[4];
         feq_vjp<Q>(m, lam, G);
-        // the layers of a Dirichlet side hold the equilibrium of the given profile, not of the
-        // initial fields there
+        // the layers of a Dirichlet side hold the equilibrium of the profile, not of the initial
+        // fields there
         for (int sd = 0; sd < 4; ++sd) {
             const SideDev& S = g.b.s[sd];
             if (S.kind != KIND_DIRICHLET) continue;
@@ -1117,6 +1181,17 @@ __global__ __launch_bounds__(256) void k_adj_bulk(AdjArgs g, BulkArgs k, int bpr
     if (!bulk) {
 #pragma unroll
         for (int i = 0; i < Q; ++i) out[(unsigned long long)i * pitch] = lam[i];
+        if (g.dir_any) {
+            // lambda^{n+1} of a default-profile layer node goes to its row's profile (lambda^n is
+            // taken by the next reverse step, lambda^0 by the INIT pass)
+            const double* prof;
+            double* a = dir_slot<Q>(g, x, y, prof);
+            if (a) {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) lam[i] = g.V1[pix<Q>(pitch, i, x, y)];
+                dir_fold<Q>(prof, lam, a);
+            }
+        }
         return;
     }
     const unsigned long long plane = (unsigned long long)k.ny * pitch, o = (unsigned long long)y * pitch + x;

@@ -171,6 +171,7 @@ struct Tape {
     size_t off_adj[2] = {0, 0}, off_ccon = 0, off_gm = 0, off_acc = 0, total = 0;
     size_t off_neep[4] = {0, 0, 0, 0};   // per characteristic / ZG side: [len][Q + 4] terms of nu^{n+1}(x_f)
     size_t off_zgc = 0;                  // per zero-gradient corner: [Q + 4] terms of nu^{n+1}(c + v)
+    size_t off_dacc[4] = {0, 0, 0, 0};   // per Dirichlet side: [M][len][4] adjoint of a default profile
     int ablk0[4] = {0, 0, 0, 0}, anblk[4] = {0, 0, 0, 0}, arows = 0, nadj = 0;
 };
 
@@ -337,15 +338,6 @@ int launch_init(lbm_ctx* c, const double* rho, const double* ux, const double* u
 // ---------------------------------------------------------------- discrete adjoint (host side)
 int adjoint_supported(const lbm_ctx* c, std::string& err) {
     const lbm_config& g = c->cfg;
-    for (int s = 0; s < 4; ++s) {
-        const int b = g.bc[s];
-        if (b == BC_DIRICHLET && !c->inlet_set[s]) {
-            // a default profile is the initial state of the first layer: the layers would depend
-            // on the initial fields at every step
-            err = "the adjoint needs the Dirichlet profile set with lbm_dirichlet_profile";
-            return LBM_E_UNSUPPORTED;
-        }
-    }
     if (g.stencil == 9 && g.bc[0] != BC_PERIODIC && g.bc[2] != BC_PERIODIC) {
         err = "the D2Q9 adjoint needs one periodic axis (no corners)";
         return LBM_E_UNSUPPORTED;
@@ -384,6 +376,11 @@ void tape_layout(const Layout& L, int ny, int N, int K, Tape& t) {
             off += align_up((size_t)L.s[s].len * (L.Q + 4) * 8);
         }
     t.off_zgc = off; off += align_up((size_t)4 * (L.Q + 4) * 8);
+    for (int s = 0; s < 4; ++s)
+        if (L.s[s].kind == KIND_DIRICHLET) {
+            t.off_dacc[s] = off;
+            off += align_up((size_t)L.M * L.s[s].len * 4 * 8);
+        }
     t.total = off;
 }
 
@@ -457,6 +454,17 @@ int run_adjoint(lbm_ctx* c, const double* seed, double* grad, double* h_relax) {
     g.zgc = (double*)(base + t.off_zgc);
     g.zgc_any = 0;
     for (int ci = 0; ci < 4; ++ci) g.zgc_any = g.zgc_any || (L.c[ci].active && L.c[ci].zg);
+    // Dirichlet sides with the default profile: the layers follow the initial fields of the first
+    // layer at every time level
+    g.dir_any = 0;
+    for (int s = 0; s < 4; ++s) {
+        g.dacc[s] = nullptr;
+        g.dprof[s] = c->inlet[s];
+        if (L.s[s].kind != KIND_DIRICHLET || c->inlet_set[s]) continue;
+        g.dacc[s] = (double*)(base + t.off_dacc[s]);
+        g.dir_any = 1;
+        HIPCHK(c, hipMemsetAsync(g.dacc[s], 0, (size_t)L.M * L.s[s].len * 4 * 8, st));
+    }
     const int nside_blocks = t.nadj + ((any_corner && !g.coupled) ? 4 : 0);
 
     // Segment seg is recomputed from its checkpoint on the second stream into recomputation set
@@ -535,6 +543,11 @@ int run_adjoint(lbm_ctx* c, const double* seed, double* grad, double* h_relax) {
             HIPCHK(c, hipGetLastError());
         }
         HIPCHK(c, hipEventRecord(c->ev[2 + b], st));
+    }
+    for (int s = 0; s < 4; ++s) {
+        if (!g.dacc[s]) continue;
+        hipLaunchKernelGGL((k_adj_dir_collect<Q>), dim3((L.s[s].len + 255) / 256), dim3(256), 0, st, g, s, nx, ny);
+        HIPCHK(c, hipGetLastError());
     }
     g.adj_cur = base + t.off_adj[0];
     hipLaunchKernelGGL((k_adj_final<Q>), dim3(1), dim3(256), 0, st, g);
@@ -676,6 +689,7 @@ int lbm_dirichlet_profile(lbm_ctx* c, int side, const double* d_U) {
     const size_t bytes = (size_t)c->L.s[side].len * 4 * 8;
     HIPCHK(c, hipMemcpyAsync(c->inlet[side], d_U, bytes, hipMemcpyDeviceToDevice, c->stream));
     c->inlet_set[side] = 1;
+    c->tape = Tape{};   // a recorded run no longer matches the boundary data
     return dispatch(c, [&]<int Q, typename T>() -> int {
         const BndArgs a = make_bnd(c);
         const int tot = c->L.s[side].len * c->L.M;

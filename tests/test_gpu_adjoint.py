@@ -81,6 +81,15 @@ CASES = {
     # the oracle's default, and the perturbations leave the layer nodes alone
     "d2q37_inlet_periodic_y": dict(stencil=37, nx=60, ny=44, tau=TAU_37, bc=["dirichlet", "lodi_relax", "periodic", "periodic"],
                                    steps=30, every=12, relax=dict(sigma=0.3, alpha=0.2, mach=0.05), inlet=True),
+    # Dirichlet sides with the default profile, the initial state of the first layer: every
+    # layer's populations at every step depend on the initial fields there (x = 2 here, y = ny - 2
+    # below), and the perturbations reach them
+    "d2q37_dirichlet_default_periodic_y": dict(stencil=37, nx=60, ny=44, tau=TAU_37,
+                                               bc=["dirichlet", "lodi_relax", "periodic", "periodic"],
+                                               steps=30, every=12, relax=dict(sigma=0.3, alpha=0.2, mach=0.05)),
+    "d2q17_dirichlet_default_periodic_x": dict(stencil=17, nx=40, ny=46, tau=0.9,
+                                               bc=["periodic", "periodic", "lodi_relax", "dirichlet"],
+                                               steps=30, every=30, relax=dict(sigma=0.3, alpha=0.2, mach=0.05)),
     # zero-gradient sides (eq. zg-bc): the layers copy the post-collision populations of x_f, the
     # corner blocks those of the inward diagonal node
     "d2q37_zg_corners": dict(stencil=37, nx=46, ny=52, tau=TAU_37, bc=["zg"] * 4, steps=30, every=11,
@@ -160,6 +169,41 @@ def test_adjoint_matches_oracle_tangents(name, loss):
     g.close()
 
 
+@pytest.mark.parametrize("name", ["d2q37_dirichlet_default_periodic_y", "d2q17_dirichlet_default_periodic_x"])
+def test_dirichlet_default_profile_gradient_on_layers(name):
+    """With the default profile the first layer's initial fields carry the gradient of every layer
+    of their row over every step, and the other layers' initial fields have none: directions
+    supported on the first layer only, and on the outer layers only, against the oracle."""
+    c = CASES[name]
+    log(f"[gpu-case] default Dirichlet profile, layer directions {name}")
+    nx, ny = c["nx"], c["ny"]
+    fields = _case_fields(c, 41)
+    side = c["bc"].index("dirichlet")
+    M = 1 if c["stencil"] == 9 else 3                  # largest displacement of the stencil
+    nn = nx if side < 2 else ny
+    pos = [M - j if side % 2 == 0 else nn - 1 - M + j for j in range(1, M + 1)]   # layers j = 1..M
+    d = W.random_directions(4, nx, ny, 42)
+    dF = np.zeros((3, 4, ny, nx))
+    for k, sel in ((1, pos[:1]), (2, pos[1:])):        # first layer; the outer layers
+        for a in range(4 if c["stencil"] != 9 else 3):
+            if side < 2:
+                dF[k, a][:, sel] = d[a][:, sel]
+            else:
+                dF[k, a][sel, :] = d[a][sel, :]
+    relax = np.tile([c["relax"]["sigma"], c["relax"]["alpha"], 1.0, 1.0, c["relax"]["mach"], 0.0], (4, 1))
+    _, od = O.tangent_run_fields(c["stencil"], nx, ny, c["tau"], c["bc"], relax, [1, 0, 0], [0.5, 0, 0], fields, dF,
+                                 c["steps"])
+    g = _sim(c["stencil"], nx, ny, c["tau"], c["bc"], fields, c["relax"])
+    g.record(c["steps"], c["every"])
+    grad, grel = g.adjoint()
+    first = _directional(grad, grel, dF[1], 0, 0)
+    outer = _directional(grad, grel, dF[2], 0, 0)
+    log(f"{name}: first layer oracle {od[1]} adjoint {first}; outer layers oracle {od[2]} adjoint {outer}")
+    assert abs(od[1]) > 0 and _relerr(first, od[1]) < ADJ_TOL
+    assert od[2] == 0.0 and outer == 0.0
+    g.close()
+
+
 def test_adjoint_checkpoint_interval_and_repeat():
     # the gradient does not depend on the checkpoint interval; a second adjoint call with the
     # same tape reproduces the first bit for bit
@@ -203,10 +247,17 @@ def test_adjoint_fp32dev_close_to_fp64():
 def test_adjoint_argument_and_state_errors():
     from paper_2307_16766_amd import lbm
     f = W.temperature_pulse(40, 40)
-    g = lbm.LBM(37, 40, 40, TAU_37, ["dirichlet", "lodi", "periodic", "periodic"], f)
-    with pytest.raises(lbm.LBMError) as e:   # Dirichlet side with the default profile
+    g = lbm.LBM(9, 40, 40, 0.6, ["lodi"] * 4, f)
+    with pytest.raises(lbm.LBMError) as e:   # D2Q9 with corners
         g.record(5, 2)
     assert e.value.code == lbm.LBM_E_UNSUPPORTED
+    g.close()
+    g = lbm.LBM(37, 40, 40, TAU_37, ["dirichlet", "lodi", "periodic", "periodic"], f)
+    g.record(5, 2)
+    g.set_inlet(0, np.tile([1.0, 0.01, 0.0, 1.0], (40, 1)))   # the recorded run no longer applies
+    with pytest.raises(lbm.LBMError) as e:
+        g.adjoint()
+    assert e.value.code == lbm.LBM_E_STATE
     g.close()
     g = lbm.LBM(37, 40, 40, TAU_37, ["lodi_relax"] * 4, f)
     with pytest.raises(lbm.LBMError) as e:
