@@ -190,17 +190,15 @@ __device__ __forceinline__ void char_rate_vjp(const double* U, const double* dn,
     alb = 0.0;
     if (THERMAL) {
         // viscous terms (zero for the LODI schemes)
-        double lap[4] = {0.0, 0.0, 0.0, 0.0}, V1 = 0.0, V2 = 0.0, V3 = 0.0, sa = 0.0, sh = 0.0;
+        double lap[4] = {0.0, 0.0, 0.0, 0.0}, V1 = 0.0, V3 = 0.0, sa = 0.0, sh = 0.0;   // V2 enters the rate only
         if (full && vfd) {
             for (int m = 1; m < 4; ++m) lap[m] = d2n[m] + up[m] - 2.0 * U[m] + dw[m];
             sa = dn[1] - 0.5 * (up[2] - dw[2]);
             sh = 0.5 * (up[1] - dw[1]) + dn[2];
             V1 = nu * lap[1];
-            V2 = nu * lap[2];
             V3 = 2.0 * nu * lap[3] + nu * (1.0 / cs2) * (sa * sa + sh * sh);
         } else if (full) {
             V1 = Vin[1];
-            V2 = Vin[2];
             V3 = Vin[3];
         }
         const double s = sqrt(2.0 * cs2 * T);

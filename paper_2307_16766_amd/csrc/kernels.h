@@ -264,16 +264,19 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// partial[blk][8]: mass, jx, jy, energy, loss, max|u|, non-finite count, 0
+// partial[8][nblk] (component-major, nblk = gridDim.x): mass, jx, jy, energy, loss, max|u|,
+// non-finite count, 0.  One work-group per
+// 256-node x tile of one row (bpr tiles per row), one node per thread: a grid-stride loop over
+// fewer work-groups keeps fewer loads in flight and read 60 % of the HBM rate in FP32 against
+// ~85 % for this mapping (measured on 4096 x 2048).
 template <int Q, typename T>
-__global__ __launch_bounds__(256) void k_diag_partial(const T* __restrict__ A, int nx, int ny, unsigned long long pitch,
+__global__ __launch_bounds__(256) void k_diag_partial(const T* __restrict__ A, int nx, int bpr, unsigned long long pitch,
                                                       int bx0, int bx1, int by0, int by1, double* __restrict__ partial) {
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-    const int n = nx * ny;
-    for (int id = blockIdx.x * 256 + threadIdx.x; id < n; id += gridDim.x * 256) {
+    const int x = (blockIdx.x % bpr) * 256 + threadIdx.x, y = blockIdx.x / bpr;
+    if (x < nx) {
         double d[Q];
         double bad = 0.0;
-        const int x = id % nx, y = id / nx;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             d[i] = (double)A[pix<Q>(pitch, i, x, y)];
@@ -305,20 +308,32 @@ __global__ __launch_bounds__(256) void k_diag_partial(const T* __restrict__ A, i
         const int k = threadIdx.x;
         double v = red[0][k];
         for (int w = 1; w < 4; ++w) v = (k == 5) ? fmax(v, red[w][k]) : v + red[w][k];
-        partial[blockIdx.x * 8 + k] = v;
+        partial[(size_t)k * gridDim.x + blockIdx.x] = v;
     }
-    if (threadIdx.x == 7) partial[blockIdx.x * 8 + 7] = 0.0;
+    if (threadIdx.x == 7) partial[(size_t)7 * gridDim.x + blockIdx.x] = 0.0;
 }
 
-// second pass: one work-group per quantity, fixed-order tree over the partials (deterministic)
-__global__ __launch_bounds__(256) void k_diag_final(const double* __restrict__ partial, int nblk, double* __restrict__ out) {
+// second pass: one 1024-thread work-group per quantity (k = 5 is a maximum, the others sums).
+// Thread t folds partials t, t + 1024, ... in that order, eight loads in flight at a time, then a
+// fixed tree over the threads: the result does not depend on timing (deterministic).
+__global__ __launch_bounds__(1024) void k_diag_final(const double* __restrict__ partial, int nblk, double* __restrict__ out) {
     const int k = blockIdx.x;   // 0..7
-    __shared__ double red[256];
-    double v = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += 256) v = (k == 5) ? fmax(v, partial[b * 8 + k]) : v + partial[b * 8 + k];
+    __shared__ double red[1024];
+    const double* pk = partial + (size_t)k * nblk;
+    double v = 0.0;   // identity of both (the maximum is over |u| >= 0)
+    for (int b0 = threadIdx.x; b0 < nblk; b0 += 8 * 1024) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int b = b0 + u * 1024;
+            t[u] = b < nblk ? pk[b] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v = (k == 5) ? fmax(v, t[u]) : v + t[u];
+    }
     red[threadIdx.x] = v;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
+    for (int w = 512; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w)
             red[threadIdx.x] = (k == 5) ? fmax(red[threadIdx.x], red[threadIdx.x + w]) : red[threadIdx.x] + red[threadIdx.x + w];
         __syncthreads();

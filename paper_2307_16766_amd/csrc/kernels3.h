@@ -492,8 +492,10 @@ __device__ __forceinline__ double wmax3(double v) {
     return v;
 }
 
-// partial[blk][8]: mass, jx, jy, jz, energy (1/2 sum f |c|^2), loss (sum over bulk nodes of
-// (P - P_inf)^2, P_inf = cs^2), max |u|, non-finite count
+// partial[8][nblk] (component-major, nblk = gridDim.x): mass, jx, jy, jz, energy
+// (1/2 sum f |c|^2), loss (sum over bulk nodes of (P - P_inf)^2, P_inf = cs^2), max |u|,
+// non-finite count.  A grid-stride loop over the nodes (one work-group per 256-node row tile, as
+// in 2D, measured no faster here and needs a longer second pass).
 template <typename T>
 __global__ __launch_bounds__(256) void k3_diag_partial(const T* __restrict__ A, int nx, int ny, long long n,
                                                        unsigned long long pitch, int bx0, int bx1,
@@ -535,19 +537,31 @@ __global__ __launch_bounds__(256) void k3_diag_partial(const T* __restrict__ A, 
         const int k = threadIdx.x;
         double v = red[0][k];
         for (int q = 1; q < 4; ++q) v = k == 6 ? fmax(v, red[q][k]) : v + red[q][k];
-        partial[blockIdx.x * 8 + k] = v;
+        partial[(size_t)k * gridDim.x + blockIdx.x] = v;
     }
 }
 
-// second pass: one work-group per quantity, fixed-order tree (deterministic)
-__global__ __launch_bounds__(256) void k3_diag_final(const double* __restrict__ partial, int nblk, double* __restrict__ out) {
+// second pass: one 1024-thread work-group per quantity (k = 6 is a maximum, the others sums),
+// each thread folding partials t, t + 1024, ... in order with eight loads in flight, then a fixed
+// tree (deterministic)
+__global__ __launch_bounds__(1024) void k3_diag_final(const double* __restrict__ partial, int nblk, double* __restrict__ out) {
     const int k = blockIdx.x;
-    __shared__ double red[256];
-    double v = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += 256) v = k == 6 ? fmax(v, partial[b * 8 + k]) : v + partial[b * 8 + k];
+    __shared__ double red[1024];
+    const double* pk = partial + (size_t)k * nblk;
+    double v = 0.0;   // identity of both (the maximum is over |u| >= 0)
+    for (int b0 = threadIdx.x; b0 < nblk; b0 += 8 * 1024) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int b = b0 + u * 1024;
+            t[u] = b < nblk ? pk[b] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v = k == 6 ? fmax(v, t[u]) : v + t[u];
+    }
     red[threadIdx.x] = v;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
+    for (int w = 512; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w)
             red[threadIdx.x] = k == 6 ? fmax(red[threadIdx.x], red[threadIdx.x + w]) : red[threadIdx.x] + red[threadIdx.x + w];
         __syncthreads();

@@ -80,7 +80,6 @@ void make_layout(const lbm_config* c, Layout& L) {
     L.M = stencil_M(c->stencil);
     L.MS = L.M == 1 ? 2 : 1;
     L.esz = c->precision == LBM_FP64 ? 8 : 4;
-    const unsigned long long n = (unsigned long long)c->nx * c->ny;
     L.pitch = ((unsigned long long)c->nx + 63) / 64 * 64;
     L.f_bytes = align_up((size_t)L.Q * L.pitch * c->ny * L.esz);
     const bool xp = c->bc[0] == BC_PERIODIC, yp = c->bc[2] == BC_PERIODIC;
@@ -151,7 +150,7 @@ void make_layout(const lbm_config* c, Layout& L) {
         L.off_inlet[s] = off;
         if (L.s[s].kind == KIND_DIRICHLET) off += align_up((size_t)L.s[s].len * 4 * 8);
     }
-    L.diag_blocks = (int)std::min<unsigned long long>(1024, (n + 255) / 256);
+    L.diag_blocks = (int)(((unsigned long long)c->nx + 255) / 256 * c->ny);   // one per 256-node row tile
     L.off_diag = off;
     off += align_up((size_t)(L.diag_blocks + 1) * 8 * 8);
     L.total = off;
@@ -738,9 +737,9 @@ int lbm_diagnostics(lbm_ctx* c, double* h_out) {
     const int nb = c->L.diag_blocks;
     const int rc = dispatch(c, [&]<int Q, typename T>() -> int {
         hipLaunchKernelGGL((k_diag_partial<Q, T>), dim3(nb), dim3(256), 0, c->stream, (const T*)c->f[c->cur], c->cfg.nx,
-                           c->cfg.ny, c->L.pitch, g.x0, g.x1, g.y0, g.y1, c->diag);
+                           (c->cfg.nx + 255) / 256, c->L.pitch, g.x0, g.x1, g.y0, g.y1, c->diag);
         HIPCHK(c, hipGetLastError());
-        hipLaunchKernelGGL(k_diag_final, dim3(8), dim3(256), 0, c->stream, c->diag, nb, c->diag + (size_t)nb * 8);
+        hipLaunchKernelGGL(k_diag_final, dim3(8), dim3(1024), 0, c->stream, c->diag, nb, c->diag + (size_t)nb * 8);
         HIPCHK(c, hipGetLastError());
         return LBM_OK;
     });

@@ -346,7 +346,7 @@ int lbm3d_diagnostics(lbm3d_ctx* c, double* h_out) {
         hipLaunchKernelGGL((k3_diag_partial<T>), dim3(nb), dim3(256), 0, c->stream, (const T*)c->f[c->cur], c->cfg.nx,
                            c->cfg.ny, n, c->L.pitch, g.x0, g.x1, c->diag);
         HIPCHK3(c, hipGetLastError());
-        hipLaunchKernelGGL(k3_diag_final, dim3(8), dim3(256), 0, c->stream, c->diag, nb, c->diag + (size_t)nb * 8);
+        hipLaunchKernelGGL(k3_diag_final, dim3(8), dim3(1024), 0, c->stream, c->diag, nb, c->diag + (size_t)nb * 8);
         HIPCHK3(c, hipGetLastError());
         return LBM_OK;
     });
