@@ -56,13 +56,14 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def run_gpu(precision, steps, warmup):
+def run_gpu(precision, steps, warmup, q=Q, tau=None):
     import torch
     from paper_2307_16766_amd import lbm
-    cs2 = lbm.lattice_info(Q)[0]
-    tau = 0.5 + 0.1 / cs2
+    cs2 = lbm.lattice_info(q)[0]
+    if tau is None:
+        tau = 0.5 + 0.1 / cs2
     fields, prof = workload(NX, NY)
-    g = lbm.LBM(Q, NX, NY, tau, ["dirichlet", "lodi_relax", "periodic", "periodic"], fields, precision=precision)
+    g = lbm.LBM(q, NX, NY, tau, ["dirichlet", "lodi_relax", "periodic", "periodic"], fields, precision=precision)
     g.set_relax(1, **relax_params(cs2))
     g.set_inlet(0, prof)
     del fields
@@ -85,7 +86,7 @@ def run_gpu(precision, steps, warmup):
     g.close()
     del g
     torch.cuda.empty_cache()
-    bytes_per_launch = algorithmic_bytes(4 if precision == "fp32dev" else 8)
+    bytes_per_launch = algorithmic_bytes(4 if precision == "fp32dev" else 8, q)
     kernel_ms = kms / max(launches, 1)
     gbps = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
     return {
@@ -193,7 +194,7 @@ def run_3d(precision, steps, warmup, n=(512, 256, 256)):
             "finite": bool(d[7] == 0)}
 
 
-def algorithmic_bytes(esz):
+def algorithmic_bytes(esz, q=Q):
     """Bytes one step kernel must move: bulk nodes read and write q populations; the outflow
     side's M layers are written (equilibrium reconstruction) and its x_f column re-pulled (q
     reads); the Dirichlet inlet layers are static and cost nothing per step."""
@@ -201,7 +202,7 @@ def algorithmic_bytes(esz):
     bulk_nodes = (NX - 2 * M) * NY
     layer_nodes = M * NY
     strip_nodes = NY
-    return (2 * bulk_nodes + layer_nodes + strip_nodes) * Q * esz
+    return (2 * bulk_nodes + layer_nodes + strip_nodes) * q * esz
 
 
 def cpu_baseline(steps=None):
@@ -282,6 +283,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--no-d2q17", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=None)
     ap.add_argument("--copy-probe", type=float, default=None, metavar="GIB",
                     help="only run a plain copy of GIB gibibytes (counter calibration)")
@@ -314,6 +316,17 @@ def main():
         adj = run_adjoint_c4()
         eprint(f"[bench] adjoint: forward {adj['forward_ms']:.1f} ms, adjoint {adj['adjoint_ms']:.1f} ms, "
                f"ratio {adj['adjoint_over_forward']:.2f}")
+    d17 = None
+    if not args.no_d2q17:
+        # the same workload on D2Q17 (3rd-order equilibrium, M = 3), tau = 0.9
+        eprint(f"[bench] D2Q17 {NX}x{NY} (fp32dev, fp64)")
+        d17 = {}
+        for p in ("fp32dev", "fp64"):
+            r = run_gpu(p, 300 if p == "fp32dev" else 150, 20, q=17, tau=0.9)
+            d17[p] = {"workload": f"D2Q17 shear-layer run {NX}x{NY}, tau 0.9, Dirichlet inlet + LODI-RELAX outflow, periodic y",
+                      "mlups": r["mlups"], "ms_per_step": r["ms_per_step"], "bulk_kernel_ms": r["bulk_kernel_ms"],
+                      "bulk_GBps": r["bulk_GBps"], "bulk_frac": r["bulk_frac"], "finite": r["finite"]}
+        eprint(f"[bench] d2q17: fp32 {d17['fp32dev']['ms_per_step']:.3f} ms/step, fp64 {d17['fp64']['ms_per_step']:.3f}")
     d3 = None
     if not args.no_3d:
         eprint("[bench] D3Q39 512x256x256 (fp32dev, fp64)")
@@ -359,6 +372,7 @@ def main():
             "bulk_frac": r64["bulk_frac"], "fp32dev_over_fp64": r32["mlups"] / r64["mlups"],
         },
         "adjoint": adj,
+        "d2q17": d17,
         "d3q39": d3,
         "cpu_baseline": cpu,
         "finite": r32["finite"] and (r64 is None or r64["finite"]),
