@@ -506,3 +506,30 @@ def test_fd_variant_uniform_flow(stencil):
     o.step(100)
     r, ux, uy, T = o.macro()
     assert max(np.abs(r - 1).max(), np.abs(ux - u0).max(), np.abs(uy).max(), np.abs(T - 1).max()) < 1e-13
+
+
+@pytest.mark.parametrize("stencil", [37, 17])
+def test_corner_blocks_hold_one_state(stencil):
+    # Sec. 3.3, corner treatment: the one corner state of the diagonal analysis fills the whole
+    # M x M block (M = 3 for both stencils) with its equilibrium, so after any number of steps
+    # every node of a block carries the same populations and macroscopic values, bit for bit,
+    # while its neighbours outside differ
+    nx, ny, M = 30, 28, 3
+    o = O.Oracle(stencil, nx, ny, TAUS[stencil], ["lodi_relax", "lodi", "cbc_relax", "cbc"])
+    o.set_relax(-1, sigma=0.25, alpha=0.1, mach=0.05)
+    rho, ux, uy, T = W.random_temperature(nx, ny, std=1e-3, seed=5)
+    rng = np.random.default_rng(6)
+    o.init(rho + 1e-3 * rng.standard_normal((ny, nx)), ux + 0.01 + 1e-3 * rng.standard_normal((ny, nx)),
+           uy - 0.02 + 1e-3 * rng.standard_normal((ny, nx)), T)
+    o.step(20)
+    fields = o.macro()
+    pops = o.pops()
+    for xs in (slice(0, M), slice(nx - M, nx)):
+        for ys in (slice(0, M), slice(ny - M, ny)):
+            for f in list(fields) + list(pops):
+                blk = f[ys, xs]
+                assert np.ptp(blk) == 0.0
+            r = fields[0]
+            xin = M if xs.start == 0 else nx - M - 1          # the column next to the block
+            yin = ys.start
+            assert r[yin, xin] != r[yin, xs.start]
