@@ -50,6 +50,11 @@
  *    diagonal bulk nodes; the result is copied to the M x M corner block; corners are
  *    advanced before the straight sides, which see corner values interpolated in time.
  *  - Equilibrium Dirichlet reconstruction replaces all q populations on all M layers.
+ *
+ * Parity unpinned: the corners' coupling to the straight sides (the corner values that the
+ * sides' end rows see, interpolated in time) has no closed form or printed value to check
+ * against; the tests check it through the square's D4 symmetry and uniform-flow invariants only.
+ * The diagonal corner analysis and the M x M block copy are pinned directly.
  */
 #include <algorithm>
 #include <cmath>
