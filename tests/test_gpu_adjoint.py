@@ -90,6 +90,9 @@ CASES = {
     "d2q17_dirichlet_default_periodic_x": dict(stencil=17, nx=40, ny=46, tau=0.9,
                                                bc=["periodic", "periodic", "lodi_relax", "dirichlet"],
                                                steps=30, every=30, relax=dict(sigma=0.3, alpha=0.2, mach=0.05)),
+    "d2q9_dirichlet_default_periodic_y": dict(stencil=9, nx=40, ny=36, tau=0.6,
+                                              bc=["lodi_relax", "dirichlet", "periodic", "periodic"],
+                                              steps=30, every=8, relax=dict(sigma=0.3, alpha=0.2, mach=0.05)),
     # zero-gradient sides (eq. zg-bc): the layers copy the post-collision populations of x_f, the
     # corner blocks those of the inward diagonal node
     "d2q37_zg_corners": dict(stencil=37, nx=46, ny=52, tau=TAU_37, bc=["zg"] * 4, steps=30, every=11,
@@ -169,7 +172,8 @@ def test_adjoint_matches_oracle_tangents(name, loss):
     g.close()
 
 
-@pytest.mark.parametrize("name", ["d2q37_dirichlet_default_periodic_y", "d2q17_dirichlet_default_periodic_x"])
+@pytest.mark.parametrize("name", ["d2q37_dirichlet_default_periodic_y", "d2q17_dirichlet_default_periodic_x",
+                                  "d2q9_dirichlet_default_periodic_y"])
 def test_dirichlet_default_profile_gradient_on_layers(name):
     """With the default profile the first layer's initial fields carry the gradient of every layer
     of their row over every step, and the other layers' initial fields have none: directions
