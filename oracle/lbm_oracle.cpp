@@ -51,10 +51,12 @@
  *    advanced before the straight sides, which see corner values interpolated in time.
  *  - Equilibrium Dirichlet reconstruction replaces all q populations on all M layers.
  *
- * Parity unpinned: the corners' coupling to the straight sides (the corner values that the
- * sides' end rows see, interpolated in time) has no closed form or printed value to check
- * against; the tests check it through the square's D4 symmetry and uniform-flow invariants only.
- * The diagonal corner analysis and the M x M block copy are pinned directly.
+ * Pins of the boundary solve (tests/test_oracle_boundary_solve.py, test_oracle_characteristic.py):
+ * the RK4 step of a side and of a corner equals the degree-4 Taylor polynomial of the exact
+ * solution of the linearised layer system with linearly interpolated bulk values; the transverse
+ * terms equal the tangential flux Jacobian times the tangential derivatives; the end rows of a
+ * side see the corner block's value as their neighbour beyond the end (at t and t + dt
+ * interpolated like bulk values); the diagonal corner analysis and the M x M block copy directly.
  */
 #include <algorithm>
 #include <cmath>
@@ -720,6 +722,26 @@ struct Sim {
         visc_fd(c, j, r, V4);
     }
 
+    // transverse terms T of eq. NSF-CHAR (local components) at layer j, row r: the tangential
+    // flux derivatives, by central differences along the side (eq. FD-dx-center); at the end rows
+    // of a side with non-periodic rows the neighbour beyond the end is the corner block's value
+    void transverse(const SideCtx& c, int j, int r, S* Tv) const {
+        const SideGeo& g = *c.g;
+        auto lv = [&](int k, int rr, S* l) { S u4[4]; side_value(c, k, rr, u4); to_local(g.nax, g.sn, u4, l); };
+        S l0[4], up[4], dw[4];
+        lv(j, r, l0); lv(j, r + 1, up); lv(j, r - 1, dw);
+        auto dt = [&](S vu, S vd) { return 0.5 * (vu - vd); };
+        Tv[0] = -dt(up[0] * up[2], dw[0] * dw[2]);
+        Tv[1] = -l0[2] * dt(up[1], dw[1]);
+        if (L.thermal) {
+            Tv[2] = -(L.cs2 / l0[0]) * dt(up[0] * up[3], dw[0] * dw[3]) - l0[2] * dt(up[2], dw[2]);
+            Tv[3] = -dt(up[3] * up[2], dw[3] * dw[2]);
+        } else {
+            Tv[2] = -(L.cs2 / l0[0]) * dt(up[0], dw[0]) - l0[2] * dt(up[2], dw[2]);
+            Tv[3] = 0.0;
+        }
+    }
+
     void side_rhs(const SideCtx& c, int j, int r, S* dU) const {
         const SideGeo& g = *c.g;
         const int n = L.thermal ? 4 : 3;
@@ -734,19 +756,8 @@ struct Sim {
             S a[4], cc[4]; lv(j + 1, r, a); lv(j - 1, r, cc);
             for (int m = 0; m < 4; ++m) dn[m] = 0.5 * (a[m] - cc[m]);
         }
-        // transverse derivatives (central, along the side)
-        S up[4], dw[4]; lv(j, r + 1, up); lv(j, r - 1, dw);
-        auto dt = [&](S vu, S vd) { return 0.5 * (vu - vd); };
         S Tv[4];
-        Tv[0] = -dt(up[0] * up[2], dw[0] * dw[2]);
-        Tv[1] = -l0[2] * dt(up[1], dw[1]);
-        if (L.thermal) {
-            Tv[2] = -(L.cs2 / l0[0]) * dt(up[0] * up[3], dw[0] * dw[3]) - l0[2] * dt(up[2], dw[2]);
-            Tv[3] = -dt(up[3] * up[2], dw[3] * dw[2]);
-        } else {
-            Tv[2] = -(L.cs2 / l0[0]) * dt(up[0], dw[0]) - l0[2] * dt(up[2], dw[2]);
-            Tv[3] = 0.0;
-        }
+        transverse(c, j, r, Tv);
         S Vv[4];
         if (is_full_cbc(b) && vfd[c.s]) {
             visc_fd(c, j, r, Vv);
@@ -788,6 +799,12 @@ struct Sim {
         from_local_rate(g.nax, g.sn, rl, dU);
     }
 
+    // corner ids at the low-row and high-row ends of side s
+    void side_corners(int s, int& clo, int& chi) const {
+        if (geo[s].nax == 0) { clo = (s & 1) | 0; chi = (s & 1) | 2; }
+        else { clo = ((s - 2) << 1) | 0; chi = ((s - 2) << 1) | 1; }
+    }
+
     void side_solve(int s, std::vector<S>& Un, const S corner_vals[4][2][4]) {
         const SideGeo& g = geo[s];
         const size_t nY = (size_t)M * g.len * 4;
@@ -800,10 +817,8 @@ struct Sim {
         if (is_full_cbc(bc[s]) && !vfd[s]) visc_terms(g, V); else V.assign((size_t)g.len * 4, S(0.0));
         SideCtx c;
         c.g = &g; c.s = s; c.Y0 = &Y0; c.Un = &Un; c.V = &V;
-        // corner ids at the two ends of this side
         int clo, chi;
-        if (g.nax == 0) { clo = (s & 1) | 0; chi = (s & 1) | 2; }
-        else { clo = ((s - 2) << 1) | 0; chi = ((s - 2) << 1) | 1; }
+        side_corners(s, clo, chi);
         c.corner_lo[0] = corner_vals[clo][0]; c.corner_lo[1] = corner_vals[clo][1];
         c.corner_hi[0] = corner_vals[chi][0]; c.corner_hi[1] = corner_vals[chi][1];
         const double a_st[4] = {0.0, 0.5, 0.5, 1.0};   // classic RK4 stage offsets
@@ -823,6 +838,109 @@ struct Sim {
                 int x, y; node(g, j, r, x, y);
                 setU(Un, x, y, &acc[((size_t)(j - 1) * g.len + r) * 4]);
             }
+    }
+
+    // One RK4 step of the corner's LODI analysis (Sec. 3.3, corner treatment and "Time
+    // integration"): Ut holds the time-t field, Un the bulk values at t + dt; returns the corner
+    // node's value at t (U0) and at t + dt (acc).  The two inward diagonal bulk nodes are
+    // interpolated linearly in time at the stages; wave directions are those at t.
+    void corner_step(const Corner& c, const std::vector<S>& Ut, const std::vector<S>& Un, S* U0, S* acc) const {
+        int x, y; corner_node(c, x, y);
+        const int vx = -geo[c.sx].sn, vy = -geo[c.sy].sn;
+        getU(Ut, x, y, U0);
+        S b1n[4], b1p[4], b2n[4], b2p[4];
+        getU(Ut, x + vx, y + vy, b1n); getU(Un, x + vx, y + vy, b1p);
+        getU(Ut, x + 2 * vx, y + 2 * vy, b2n); getU(Un, x + 2 * vx, y + 2 * vy, b2p);
+        const double a_st[4] = {0.0, 0.5, 0.5, 1.0}, b_st[4] = {1.0, 2.0, 2.0, 1.0};
+        S Kc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int m = 0; m < 4; ++m) acc[m] = U0[m];
+        for (int st = 0; st < 4; ++st) {
+            const double th = a_st[st];
+            S Ys[4], B1[4], B2[4];
+            for (int m = 0; m < 4; ++m) {
+                Ys[m] = U0[m] + a_st[st] * Kc[m];
+                B1[m] = (1.0 - th) * b1n[m] + th * b1p[m];
+                B2[m] = (1.0 - th) * b2n[m] + th * b2p[m];
+            }
+            corner_rhs(c, Ys, U0, B1, B2, Kc);
+            for (int m = 0; m < 4; ++m) acc[m] = acc[m] + (b_st[st] / 6.0) * Kc[m];
+        }
+    }
+
+    // -------------------------------------------------- probes of the boundary solve
+    // (exposed through the C API so that the tests can pin the time integration, the transverse
+    // terms and the corner coupling against closed forms)
+    void layers_of(int s, const std::vector<S>& F, std::vector<S>& Y) const {
+        const SideGeo& g = geo[s];
+        Y.assign((size_t)M * g.len * 4, S(0.0));
+        for (int j = 1; j <= M; ++j)
+            for (int r = 0; r < g.len; ++r) {
+                int x, y; node(g, j, r, x, y);
+                getU(F, x, y, &Y[((size_t)(j - 1) * g.len + r) * 4]);
+            }
+    }
+    void corner_values_of(const std::vector<S>& F, S cv[4][4]) const {
+        for (int ci = 0; ci < 4; ++ci) {
+            for (int m = 0; m < 4; ++m) cv[ci][m] = 0.0;
+            Corner c = corner(ci);
+            if (!c.active) continue;
+            int x, y; corner_node(c, x, y);
+            getU(F, x, y, cv[ci]);
+        }
+    }
+    // right-hand side of side s at stage values Y [M][len][4] with the wave directions of the
+    // layer values in Uv; the bulk and corner values are read from Uv as they are (no time
+    // interpolation); V (CBC, mesoscopic) from the current pre-collision populations
+    void side_rhs_probe(int s, const std::vector<S>& Uv, const std::vector<S>& Y, std::vector<S>& K) {
+        const SideGeo& g = geo[s];
+        std::vector<S> Y0, V;
+        layers_of(s, Uv, Y0);
+        if (is_full_cbc(bc[s]) && !vfd[s]) visc_terms(g, V); else V.assign((size_t)g.len * 4, S(0.0));
+        S cv[4][4];
+        corner_values_of(Uv, cv);
+        int clo, chi;
+        side_corners(s, clo, chi);
+        SideCtx c;
+        c.g = &g; c.s = s; c.Y = &Y; c.Y0 = &Y0; c.Un = &Uv; c.V = &V; c.theta = 0.0;
+        c.corner_lo[0] = c.corner_lo[1] = cv[clo];
+        c.corner_hi[0] = c.corner_hi[1] = cv[chi];
+        std::vector<S> keep;
+        keep.swap(U);
+        U = Uv;
+        K.assign(Y.size(), S(0.0));
+        for (int j = 1; j <= M; ++j)
+            for (int r = 0; r < g.len; ++r) side_rhs(c, j, r, &K[((size_t)(j - 1) * g.len + r) * 4]);
+        U.swap(keep);
+    }
+    // one boundary step of side s from the time-t field Ut to t + dt, bulk and corner values at
+    // t + dt taken from Unp1; returns the layers' new values Y1 [M][len][4]
+    void side_step_probe(int s, const std::vector<S>& Ut, const std::vector<S>& Unp1, std::vector<S>& Y1) {
+        S c0[4][4], c1[4][4], cv[4][2][4];
+        corner_values_of(Ut, c0);
+        corner_values_of(Unp1, c1);
+        for (int ci = 0; ci < 4; ++ci)
+            for (int m = 0; m < 4; ++m) { cv[ci][0][m] = c0[ci][m]; cv[ci][1][m] = c1[ci][m]; }
+        std::vector<S> keep, Un = Unp1;
+        keep.swap(U);
+        U = Ut;
+        side_solve(s, Un, cv);
+        U.swap(keep);
+        layers_of(s, Un, Y1);
+    }
+    // transverse terms at layer j, row r of side s from the current macroscopic field
+    void transverse_probe(int s, int j, int r, S* Tv) const {
+        const SideGeo& g = geo[s];
+        std::vector<S> Y0;
+        layers_of(s, U, Y0);
+        S cv[4][4];
+        corner_values_of(U, cv);
+        int clo, chi;
+        side_corners(s, clo, chi);
+        SideCtx c;
+        c.g = &g; c.s = s; c.Y = &Y0; c.Y0 = &Y0; c.Un = &U; c.V = nullptr; c.theta = 0.0;
+        c.corner_lo[0] = c.corner_lo[1] = cv[clo];
+        c.corner_hi[0] = c.corner_hi[1] = cv[chi];
+        transverse(c, j, r, Tv);
     }
 
     // -------------------------------------------------- one time step
@@ -862,31 +980,11 @@ struct Sim {
         for (int ci = 0; ci < 4; ++ci) {
             Corner c = corner(ci);
             if (!c.active || c.zg) continue;
-            int x, y; corner_node(c, x, y);
-            const int vx = -geo[c.sx].sn, vy = -geo[c.sy].sn;
-            S U0[4]; getU(U, x, y, U0);
-            S b1n[4], b1p[4], b2n[4], b2p[4];
-            getU(U, x + vx, y + vy, b1n); getU(Un, x + vx, y + vy, b1p);
-            getU(U, x + 2 * vx, y + 2 * vy, b2n); getU(Un, x + 2 * vx, y + 2 * vy, b2p);
-            const double a_st[4] = {0.0, 0.5, 0.5, 1.0}, b_st[4] = {1.0, 2.0, 2.0, 1.0};
-            S Kc[4] = {0.0, 0.0, 0.0, 0.0}, acc[4];
-            for (int m = 0; m < 4; ++m) acc[m] = U0[m];
-            for (int st = 0; st < 4; ++st) {
-                const double th = a_st[st];
-                S Ys[4], B1[4], B2[4];
-                for (int m = 0; m < 4; ++m) {
-                    Ys[m] = U0[m] + a_st[st] * Kc[m];
-                    B1[m] = (1.0 - th) * b1n[m] + th * b1p[m];
-                    B2[m] = (1.0 - th) * b2n[m] + th * b2p[m];
-                }
-                corner_rhs(c, Ys, U0, B1, B2, Kc);
-                for (int m = 0; m < 4; ++m) acc[m] = acc[m] + (b_st[st] / 6.0) * Kc[m];
-            }
-            for (int m = 0; m < 4; ++m) { cv[ci][0][m] = U0[m]; cv[ci][1][m] = acc[m]; }
+            corner_step(c, U, Un, cv[ci][0], cv[ci][1]);
             for (int jx = 1; jx <= M; ++jx)
                 for (int jy = 1; jy <= M; ++jy) {
                     int xx = geo[c.sx].xf + geo[c.sx].sn * jx, yy = geo[c.sy].xf + geo[c.sy].sn * jy;
-                    setU(Un, xx, yy, acc);
+                    setU(Un, xx, yy, cv[ci][1]);
                 }
         }
         for (int s = 0; s < 4; ++s)
@@ -1272,6 +1370,60 @@ int oracle_visc_probe(void* h, int nax, int sn, int x, int y, double* out) {
     const int r = nax == 0 ? y : x;
     if (g.xf - 2 * sn < 0 || g.xf - 2 * sn >= g.Nn) return -1;
     s->visc_row(g, r, out);
+    return 0;
+}
+
+// Probes of the boundary solve.  Fields are [4][ny][nx] (rho, ux, uy, T), layer values
+// [M][len][4] (global components) with layer j at index j - 1 and rows as in oracle_side_len.
+static bool probe_side_ok(Sim<double>* s, int side) {
+    return side >= 0 && side <= 3 && is_char(s->bc[side]);
+}
+
+// Right-hand side of the layers' evolution (eq. thermal_LODI_macro_evo / thermal_CBC_macro_evo)
+// of a characteristic side at stage values Y, everything else (bulk nodes, corner blocks, the
+// wave directions from the layers) read from the field Uv without time interpolation.
+int oracle_side_rhs_probe(void* h, int side, const double* Uv, const double* Y, double* K) {
+    auto* s = static_cast<Sim<double>*>(h);
+    if (!probe_side_ok(s, side)) return -1;
+    const size_t nF = 4 * s->plane(), nY = (size_t)s->M * s->geo[side].len * 4;
+    std::vector<double> F(Uv, Uv + nF), Yv(Y, Y + nY), Kv;
+    s->side_rhs_probe(side, F, Yv, Kv);
+    std::memcpy(K, Kv.data(), nY * sizeof(double));
+    return 0;
+}
+
+// One RK4 step (Sec. 3.3, "Time integration") of a characteristic side from the field Ut at time
+// t, with the bulk and corner values at t + dt from Unp1; writes the layers' values at t + dt.
+int oracle_side_step_probe(void* h, int side, const double* Ut, const double* Unp1, double* Y1) {
+    auto* s = static_cast<Sim<double>*>(h);
+    if (!probe_side_ok(s, side)) return -1;
+    const size_t nF = 4 * s->plane(), nY = (size_t)s->M * s->geo[side].len * 4;
+    std::vector<double> A(Ut, Ut + nF), B(Unp1, Unp1 + nF), Yv;
+    s->side_step_probe(side, A, B, Yv);
+    std::memcpy(Y1, Yv.data(), nY * sizeof(double));
+    return 0;
+}
+
+// One RK4 step of corner cidx's diagonal LODI analysis from the field Ut at time t, with the two
+// inward diagonal bulk nodes at t + dt from Unp1; writes the corner value at t + dt.
+int oracle_corner_step_probe(void* h, int cidx, const double* Ut, const double* Unp1, double* out4) {
+    auto* s = static_cast<Sim<double>*>(h);
+    if (cidx < 0 || cidx > 3) return -1;
+    const auto c = s->corner(cidx);
+    if (!c.active || c.zg) return -1;
+    const size_t nF = 4 * s->plane();
+    std::vector<double> A(Ut, Ut + nF), B(Unp1, Unp1 + nF);
+    double U0[4];
+    s->corner_step(c, A, B, U0, out4);
+    return 0;
+}
+
+// Transverse terms T (eq. NSF-CHAR, local components (rho, u_n, u_t, T)) at layer j (1..M), row r
+// of a characteristic side, from the current macroscopic field.
+int oracle_transverse_probe(void* h, int side, int j, int r, double* out4) {
+    auto* s = static_cast<Sim<double>*>(h);
+    if (!probe_side_ok(s, side) || j < 1 || j > s->M || r < 0 || r >= s->geo[side].len) return -1;
+    s->transverse_probe(side, j, r, out4);
     return 0;
 }
 

@@ -53,6 +53,10 @@ def lib():
         L.oracle_diag.argtypes = [ctypes.c_void_p, _dp]
         L.oracle_visc_probe.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp]
         L.oracle_corner_rhs_probe.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp, _dp, _dp, _dp]
+        L.oracle_side_rhs_probe.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp, _dp]
+        L.oracle_side_step_probe.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp, _dp]
+        L.oracle_corner_step_probe.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp, _dp]
+        L.oracle_transverse_probe.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp]
         L.oracle_loss.restype = ctypes.c_double
         L.oracle_loss.argtypes = [ctypes.c_void_p]
         L.oracle_tangent_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, _ip,
@@ -161,6 +165,44 @@ class Oracle:
         out = np.zeros(4)
         if lib().oracle_corner_rhs_probe(self.h, cidx, *[_ptr(a) for a in arrs], _ptr(out)) != 0:
             raise ValueError("no characteristic corner there")
+        return out
+
+    def _field(self, F):
+        return np.ascontiguousarray(np.broadcast_to(np.asarray(F, dtype=np.float64), (4, self.ny, self.nx)))
+
+    def side_rhs_probe(self, side, Uv, Y):
+        """Right-hand side of a characteristic side's layers at stage values Y [M][len][4]; bulk
+        nodes, corner blocks and the wave directions are read from the field Uv [4][ny][nx]."""
+        Uv = self._field(Uv)
+        Y = np.ascontiguousarray(Y, dtype=np.float64)
+        K = np.zeros_like(Y)
+        if lib().oracle_side_rhs_probe(self.h, side, _ptr(Uv), _ptr(Y), _ptr(K)) != 0:
+            raise ValueError("not a characteristic side")
+        return K
+
+    def side_step_probe(self, side, Ut, Unp1):
+        """One RK4 boundary step of a side from field Ut to t + dt (bulk/corners at t + dt from
+        Unp1); returns the layers' new values [M][len][4]."""
+        Ut, Unp1 = self._field(Ut), self._field(Unp1)
+        M = lattice(self.stencil)[4]
+        Y1 = np.zeros((M, self.side_len(side), 4))
+        if lib().oracle_side_step_probe(self.h, side, _ptr(Ut), _ptr(Unp1), _ptr(Y1)) != 0:
+            raise ValueError("not a characteristic side")
+        return Y1
+
+    def corner_step_probe(self, cidx, Ut, Unp1):
+        """One RK4 step of a corner's diagonal LODI analysis; returns the corner value at t + dt."""
+        Ut, Unp1 = self._field(Ut), self._field(Unp1)
+        out = np.zeros(4)
+        if lib().oracle_corner_step_probe(self.h, cidx, _ptr(Ut), _ptr(Unp1), _ptr(out)) != 0:
+            raise ValueError("no characteristic corner there")
+        return out
+
+    def transverse_probe(self, side, j, r):
+        """Transverse terms (local components rho, u_n, u_t, T) at layer j, row r of a side."""
+        out = np.zeros(4)
+        if lib().oracle_transverse_probe(self.h, side, j, r, _ptr(out)) != 0:
+            raise ValueError("bad probe position")
         return out
 
     def set_recon(self, side, mode):
