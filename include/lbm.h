@@ -23,7 +23,8 @@
  *     stream; the library borrows them until lbm_destroy.  The library owns only its host-side
  *     context (and, while kernel timing is enabled, the timing events).
  *   - Asynchrony: every call that takes a context enqueues work on the caller's stream and
- *     returns without synchronising, except lbm_diagnostics, which synchronises.
+ *     returns without synchronising, except lbm_diagnostics, lbm_save, lbm_restore,
+ *     lbm_adjoint and lbm_step's non-finite checks (lbm_diag_every), which synchronise.
  *   - Errors: functions return LBM_OK (0) or a negative code; nothing throws across the ABI.
  *     lbm_last_error(ctx) gives a message for the last failure on that context
  *     (lbm_last_error(NULL) for failures before a context exists).
@@ -123,7 +124,8 @@ int lbm_init(const lbm_config* cfg, void* d_workspace, size_t workspace_bytes, v
              lbm_ctx** out);
 
 /* Set the relaxation parameters of side 0..3, or of every side with side = -1.  Takes effect
- * from the next lbm_step. */
+ * from the next lbm_step.  Discards a run recorded with lbm_record (lbm_adjoint then returns
+ * LBM_E_STATE), as do lbm_reconstruction and lbm_viscous. */
 int lbm_cbc_params(lbm_ctx* ctx, int side, const lbm_relax* p);
 
 /* Reconstruction mode (lbm_recon) of side 0..3, or of every characteristic side with side = -1;
@@ -141,8 +143,17 @@ int lbm_viscous(lbm_ctx* ctx, int side, int mode);
 int lbm_dirichlet_profile(lbm_ctx* ctx, int side, const double* d_U);
 
 /* Advance nsteps time steps: fused stream + collide on the bulk, characteristic boundary solve
- * and reconstruction on the boundary layers (Sec. 3.3, Fig. flowchart-cbc-lbm). */
+ * and reconstruction on the boundary layers (Sec. 3.3, Fig. flowchart-cbc-lbm).  With a check
+ * interval n > 0 set by lbm_diag_every, every step that brings the step count to a multiple of
+ * n is followed by the diagnostics' non-finite count (one read of the populations, and the
+ * call synchronises the stream there); when it is positive lbm_step stops and returns
+ * LBM_E_NONFINITE, with the state of that step kept and lbm_steps_done telling which step. */
 int lbm_step(lbm_ctx* ctx, int nsteps);
+
+/* Interval of lbm_step's non-finite check: n > 0 checks after every n-th step (counted since
+ * lbm_init, or the restored checkpoint's count), 0 (the default) turns it off; negative n
+ * returns LBM_E_ARG. */
+int lbm_diag_every(lbm_ctx* ctx, int n);
 
 /* Macroscopic fields (eq. macro) of the current state at every node, FP64 [ny][nx] device
  * arrays; d_T may be NULL. */
@@ -155,11 +166,15 @@ int lbm_boundary_state(lbm_ctx* ctx, int side, double* d_out);
 /* Diagnostics of the current state (synchronises the stream).  h_out (host) receives
  * [0] total mass, [1] x momentum, [2] y momentum, [3] energy 1/2 sum f |c|^2,
  * [4] loss = sum over bulk nodes of (P - cs^2)^2, [5] max |u|, [6] number of non-finite
- * populations, [7] steps done.  Returns LBM_E_NONFINITE when [6] > 0. */
+ * populations, [7] steps done.  Returns LBM_E_NONFINITE when [6] > 0.  The sums are
+ * deterministic: one FP64 partial per 256-node row tile (wavefront reductions), folded in a
+ * fixed order. */
 int lbm_diagnostics(lbm_ctx* ctx, double* h_out);
 
-/* Checkpoint of the complete state (populations and boundary solver state): device buffer of
- * lbm_state_bytes(ctx) bytes.  Save then restore reproduces the run bit for bit. */
+/* Checkpoint of the complete state (populations, boundary solver state and the Dirichlet
+ * profiles): device buffer of lbm_state_bytes(ctx) bytes.  Save then restore reproduces the run
+ * bit for bit, also when a Dirichlet profile was changed in between.  lbm_restore discards a
+ * run recorded with lbm_record. */
 size_t lbm_state_bytes(const lbm_ctx* ctx);
 int lbm_save(lbm_ctx* ctx, void* d_buf);
 int lbm_restore(lbm_ctx* ctx, const void* d_buf);
@@ -188,9 +203,9 @@ int lbm_bulk_kernel_time(lbm_ctx* ctx, double* total_ms, long* launches);
  * constants and the gradient with respect to the initial fields is 0 on them; with the default
  * profile every layer of a row holds, at every step, the equilibrium of the initial fields on the
  * first layer, which then carry the whole row's gradient (the other layers 0).  D2Q9
- * additionally needs one periodic axis (else LBM_E_UNSUPPORTED).  The boundary settings
- * (relaxation, reconstruction, viscous terms) must stay those of the recording: lbm_adjoint
- * recomputes the recorded steps with the settings current at its call.
+ * additionally needs one periodic axis (else LBM_E_UNSUPPORTED).  lbm_adjoint recomputes the
+ * recorded steps, so the boundary settings must stay those of the recording: lbm_cbc_params,
+ * lbm_reconstruction, lbm_viscous, lbm_dirichlet_profile and lbm_restore discard it.
  *
  * lbm_tape_bytes: device bytes of the tape for nsteps steps with a checkpoint every `every`
  * steps (0 for invalid arguments).  The tape holds ceil(nsteps / every) checkpoints of the

@@ -264,38 +264,54 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// partial[8][nblk] (component-major, nblk = gridDim.x): mass, jx, jy, energy, loss, max|u|,
-// non-finite count, 0.  One work-group per
-// 256-node x tile of one row (bpr tiles per row), one node per thread: a grid-stride loop over
-// fewer work-groups keeps fewer loads in flight and read 60 % of the HBM rate in FP32 against
-// ~85 % for this mapping (measured on 4096 x 2048).
+// Diagnostics of one node, accumulated into acc: mass, jx, jy, energy, loss (bulk nodes only),
+// max |u|, non-finite count.
 template <int Q, typename T>
+__device__ __forceinline__ void diag_node(const T* __restrict__ A, int x, int y, unsigned long long pitch, int bx0,
+                                          int bx1, int by0, int by1, double* acc) {
+    double d[Q];
+    double bad = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        d[i] = (double)A[pix<Q>(pitch, i, x, y)];
+        bad += (isfinite(d[i]) ? 0.0 : 1.0);
+    }
+    double rm1, u, v, th;
+    moments_dev<Q, double>(d, rm1, u, v, th);
+    const double r = 1.0 + rm1;
+    double e = Lat<Q>::cs2;   // 1/2 sum w |c|^2
+#pragma unroll
+    for (int i = 0; i < Q; ++i) e += 0.5 * (double)c2<Q>(i) * d[i];
+    acc[0] += r; acc[1] += r * u; acc[2] += r * v; acc[3] += e;
+    if (x >= bx0 && x <= bx1 && y >= by0 && y <= by1) {
+        const double p = Lat<Q>::cs2 * (rm1 + th + rm1 * th);   // P - cs^2
+        acc[4] += p * p;
+    }
+    const double um = sqrt(u * u + v * v);
+    acc[5] = (um == um) ? fmax(acc[5], um) : acc[5];
+    acc[6] += bad;
+}
+
+// partial[8][nblk] (component-major, nblk = gridDim.x): mass, jx, jy, energy, loss, max|u|,
+// non-finite count, 0.  One work-group per 256-node x tile of one row (bpr tiles per row), one
+// node per thread: a grid-stride loop over fewer work-groups keeps fewer loads in flight and read
+// 60 % of the HBM rate in FP32 against ~85 % for this mapping (measured on 4096 x 2048).  With
+// TPW, work-group b takes the tpw consecutive tiles b tpw .. b tpw + tpw - 1 (< ntiles), so that
+// the partials fit a fixed-size buffer.
+template <int Q, typename T, bool TPW>
 __global__ __launch_bounds__(256) void k_diag_partial(const T* __restrict__ A, int nx, int bpr, unsigned long long pitch,
-                                                      int bx0, int bx1, int by0, int by1, double* __restrict__ partial) {
+                                                      int bx0, int bx1, int by0, int by1, double* __restrict__ partial,
+                                                      int ntiles, int tpw) {
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-    const int x = (blockIdx.x % bpr) * 256 + threadIdx.x, y = blockIdx.x / bpr;
-    if (x < nx) {
-        double d[Q];
-        double bad = 0.0;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            d[i] = (double)A[pix<Q>(pitch, i, x, y)];
-            bad += (isfinite(d[i]) ? 0.0 : 1.0);
+    if (!TPW) {
+        const int x = (blockIdx.x % bpr) * 256 + threadIdx.x, y = blockIdx.x / bpr;
+        if (x < nx) diag_node<Q, T>(A, x, y, pitch, bx0, bx1, by0, by1, acc);
+    } else {
+        const int t0 = blockIdx.x * tpw, t1 = min(ntiles, t0 + tpw);
+        for (int t = t0; t < t1; ++t) {
+            const int x = (t % bpr) * 256 + threadIdx.x, y = t / bpr;
+            if (x < nx) diag_node<Q, T>(A, x, y, pitch, bx0, bx1, by0, by1, acc);
         }
-        double rm1, u, v, th;
-        moments_dev<Q, double>(d, rm1, u, v, th);
-        const double r = 1.0 + rm1;
-        double e = Lat<Q>::cs2;   // 1/2 sum w |c|^2
-#pragma unroll
-        for (int i = 0; i < Q; ++i) e += 0.5 * (double)c2<Q>(i) * d[i];
-        acc[0] += r; acc[1] += r * u; acc[2] += r * v; acc[3] += e;
-        if (x >= bx0 && x <= bx1 && y >= by0 && y <= by1) {
-            const double p = Lat<Q>::cs2 * (rm1 + th + rm1 * th);   // P - cs^2
-            acc[4] += p * p;
-        }
-        const double um = sqrt(u * u + v * v);
-        acc[5] = (um == um) ? fmax(acc[5], um) : acc[5];
-        acc[6] += bad;
     }
     __shared__ double red[4][8];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -315,8 +331,10 @@ __global__ __launch_bounds__(256) void k_diag_partial(const T* __restrict__ A, i
 
 // second pass: one 1024-thread work-group per quantity (k = 5 is a maximum, the others sums).
 // Thread t folds partials t, t + 1024, ... in that order, eight loads in flight at a time, then a
-// fixed tree over the threads: the result does not depend on timing (deterministic).
-__global__ __launch_bounds__(1024) void k_diag_final(const double* __restrict__ partial, int nblk, double* __restrict__ out) {
+// fixed tree over the threads: the result does not depend on timing (deterministic).  out[7]
+// receives v7 (the step count).
+__global__ __launch_bounds__(1024) void k_diag_final(const double* __restrict__ partial, int nblk, double* __restrict__ out,
+                                                     double v7) {
     const int k = blockIdx.x;   // 0..7
     __shared__ double red[1024];
     const double* pk = partial + (size_t)k * nblk;
@@ -338,7 +356,7 @@ __global__ __launch_bounds__(1024) void k_diag_final(const double* __restrict__ 
             red[threadIdx.x] = (k == 5) ? fmax(red[threadIdx.x], red[threadIdx.x + w]) : red[threadIdx.x] + red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[k] = red[0];
+    if (threadIdx.x == 0) out[k] = k == 7 ? v7 : red[0];
 }
 
 // ================================================================== characteristic boundary

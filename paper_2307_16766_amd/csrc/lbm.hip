@@ -185,7 +185,8 @@ struct lbm_ctx {
     double* diag = nullptr;
     int cur = 0;
     long steps = 0;
-    long save_steps = 0;
+    int diag_every = 0;            // lbm_step checks for non-finite populations every n steps (0: off)
+    long save_hdr[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // checkpoint header staging: steps, Dirichlet profile flags
     hipStream_t stream = nullptr;
     int nbnd = 0;
     lbm_relax relax[4];
@@ -580,6 +581,38 @@ int dispatch(const lbm_ctx* c, F&& f) {
     return c->cfg.precision == LBM_FP64 ? f.template operator()<37, double>() : f.template operator()<37, float>();
 }
 
+// Diagnostics of the current state into d_out[8] (device), on the context's stream: the first
+// pass writes nparts partials per quantity into `partials` (component-major, [8][nparts]), each
+// work-group covering tpw consecutive 256-node row tiles (tpw = 1: one tile each, nparts = the
+// tile count), the second pass folds them in a fixed order.
+int enqueue_diag(lbm_ctx* c, double* partials, int nparts, int tpw, double* d_out) {
+    const BulkArgs& g = c->bulk;
+    const int bpr = (c->cfg.nx + 255) / 256;
+    const int ntiles = c->L.diag_blocks;
+    return dispatch(c, [&]<int Q, typename T>() -> int {
+        if (tpw == 1)
+            hipLaunchKernelGGL((k_diag_partial<Q, T, false>), dim3(nparts), dim3(256), 0, c->stream, (const T*)c->f[c->cur],
+                               c->cfg.nx, bpr, c->L.pitch, g.x0, g.x1, g.y0, g.y1, partials, ntiles, 1);
+        else
+            hipLaunchKernelGGL((k_diag_partial<Q, T, true>), dim3(nparts), dim3(256), 0, c->stream, (const T*)c->f[c->cur],
+                               c->cfg.nx, bpr, c->L.pitch, g.x0, g.x1, g.y0, g.y1, partials, ntiles, tpw);
+        HIPCHK(c, hipGetLastError());
+        hipLaunchKernelGGL(k_diag_final, dim3(8), dim3(1024), 0, c->stream, partials, nparts, d_out, (double)c->steps);
+        HIPCHK(c, hipGetLastError());
+        return LBM_OK;
+    });
+}
+
+// Diagnostics into h_out[8] (host) from the workspace's scratch; synchronises the stream.
+int host_diag(lbm_ctx* c, double* h_out) {
+    const int nb = c->L.diag_blocks;
+    const int rc = enqueue_diag(c, c->diag, nb, 1, c->diag + (size_t)nb * 8);
+    if (rc != LBM_OK) return rc;
+    HIPCHK(c, hipMemcpyAsync(h_out, c->diag + (size_t)nb * 8, 8 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
 }  // namespace
 
 // =========================================================================== C ABI
@@ -648,6 +681,7 @@ int lbm_cbc_params(lbm_ctx* c, int side, const lbm_relax* p) {
     if (!(p->rho_inf > 0) || !(p->T_inf > 0)) return fail(c, LBM_E_ARG, "rho_inf and T_inf must be positive");
     for (int s = 0; s < 4; ++s)
         if (side < 0 || s == side) c->relax[s] = *p;
+    c->tape = Tape{};   // a recorded run no longer matches the boundary settings
     return LBM_OK;
 }
 
@@ -663,6 +697,7 @@ int lbm_reconstruction(lbm_ctx* c, int side, int mode) {
         }
         c->meso[s] = mode;
     }
+    c->tape = Tape{};   // a recorded run no longer matches the boundary settings
     return LBM_OK;
 }
 
@@ -678,6 +713,7 @@ int lbm_viscous(lbm_ctx* c, int side, int mode) {
         }
         c->vfd[s] = mode;
     }
+    c->tape = Tape{};   // a recorded run no longer matches the boundary settings
     return LBM_OK;
 }
 
@@ -705,6 +741,13 @@ int lbm_step(lbm_ctx* c, int nsteps) {
     for (int k = 0; k < nsteps; ++k) {
         const int rc = dispatch(c, [&]<int Q, typename T>() -> int { return launch_step<Q, T>(c); });
         if (rc != LBM_OK) return rc;
+        if (c->diag_every > 0 && c->steps % c->diag_every == 0) {
+            double out[8];
+            const int rd = host_diag(c, out);
+            if (rd != LBM_OK) return rd;
+            if (out[6] > 0)
+                return fail(c, LBM_E_NONFINITE, "non-finite populations after step " + std::to_string(c->steps));
+        }
     }
     return LBM_OK;
 }
@@ -733,39 +776,41 @@ int lbm_boundary_state(lbm_ctx* c, int side, double* d_out) {
 int lbm_diagnostics(lbm_ctx* c, double* h_out) {
     if (!c) return fail(nullptr, LBM_E_ARG, "null context");
     if (!h_out) return fail(c, LBM_E_ARG, "output pointer is NULL");
-    const BulkArgs& g = c->bulk;
-    const int nb = c->L.diag_blocks;
-    const int rc = dispatch(c, [&]<int Q, typename T>() -> int {
-        hipLaunchKernelGGL((k_diag_partial<Q, T>), dim3(nb), dim3(256), 0, c->stream, (const T*)c->f[c->cur], c->cfg.nx,
-                           (c->cfg.nx + 255) / 256, c->L.pitch, g.x0, g.x1, g.y0, g.y1, c->diag);
-        HIPCHK(c, hipGetLastError());
-        hipLaunchKernelGGL(k_diag_final, dim3(8), dim3(1024), 0, c->stream, c->diag, nb, c->diag + (size_t)nb * 8);
-        HIPCHK(c, hipGetLastError());
-        return LBM_OK;
-    });
-    if (rc != LBM_OK) return rc;
     double out[8];
-    HIPCHK(c, hipMemcpyAsync(out, c->diag + (size_t)nb * 8, sizeof(out), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    out[7] = (double)c->steps;
+    const int rc = host_diag(c, out);
+    if (rc != LBM_OK) return rc;
     std::memcpy(h_out, out, sizeof(out));
     if (out[6] > 0) return fail(c, LBM_E_NONFINITE, "non-finite populations");
     return LBM_OK;
 }
 
+int lbm_diag_every(lbm_ctx* c, int n) {
+    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+    if (n < 0) return fail(c, LBM_E_ARG, "n must be 0 (off) or a positive step count");
+    c->diag_every = n;
+    return LBM_OK;
+}
+
+// Checkpoint layout: a 256-byte header (steps done, the four Dirichlet-profile flags), the
+// current population buffer, the current boundary state region, the Dirichlet profiles.
 size_t lbm_state_bytes(const lbm_ctx* c) {
     if (!c) return 0;
-    return ALIGN + c->L.f_bytes + c->L.region_bytes;
+    return ALIGN + c->L.f_bytes + c->L.region_bytes + (c->L.off_diag - c->L.off_inlet[0]);
 }
 
 int lbm_save(lbm_ctx* c, void* d_buf) {
     if (!c) return fail(nullptr, LBM_E_ARG, "null context");
     if (!d_buf) return fail(c, LBM_E_ARG, "buffer is NULL");
     char* b = (char*)d_buf;
-    c->save_steps = c->steps;
-    HIPCHK(c, hipMemcpyAsync(b, &c->save_steps, sizeof(long), hipMemcpyHostToDevice, c->stream));
+    c->save_hdr[0] = c->steps;
+    for (int s = 0; s < 4; ++s) c->save_hdr[1 + s] = c->inlet_set[s];
+    HIPCHK(c, hipMemcpyAsync(b, c->save_hdr, sizeof(c->save_hdr), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(b + ALIGN, c->f[c->cur], c->L.f_bytes, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(b + ALIGN + c->L.f_bytes, c->region[c->cur], c->L.region_bytes, hipMemcpyDeviceToDevice, c->stream));
+    const size_t pbytes = c->L.off_diag - c->L.off_inlet[0];
+    if (pbytes > 0)
+        HIPCHK(c, hipMemcpyAsync(b + ALIGN + c->L.f_bytes + c->L.region_bytes, c->ws + c->L.off_inlet[0], pbytes,
+                                 hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return LBM_OK;
 }
@@ -774,15 +819,32 @@ int lbm_restore(lbm_ctx* c, const void* d_buf) {
     if (!c) return fail(nullptr, LBM_E_ARG, "null context");
     if (!d_buf) return fail(c, LBM_E_ARG, "buffer is NULL");
     const char* b = (const char*)d_buf;
-    long steps = 0;
-    HIPCHK(c, hipMemcpyAsync(&steps, b, sizeof(long), hipMemcpyDeviceToHost, c->stream));
+    long hdr[8];
+    HIPCHK(c, hipMemcpyAsync(hdr, b, sizeof(hdr), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->f[0], b + ALIGN, c->L.f_bytes, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->region[0], b + ALIGN + c->L.f_bytes, c->L.region_bytes, hipMemcpyDeviceToDevice, c->stream));
+    const size_t pbytes = c->L.off_diag - c->L.off_inlet[0];
+    if (pbytes > 0)
+        HIPCHK(c, hipMemcpyAsync(c->ws + c->L.off_inlet[0], b + ALIGN + c->L.f_bytes + c->L.region_bytes, pbytes,
+                                 hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->cur = 0;
-    c->steps = steps;
+    c->steps = hdr[0];
+    for (int s = 0; s < 4; ++s) c->inlet_set[s] = (int)hdr[1 + s];
     c->tape = Tape();
-    return LBM_OK;
+    // the step kernel never writes the layers of a Dirichlet side: both population buffers get
+    // the equilibrium of the restored profile
+    return dispatch(c, [&]<int Q, typename T>() -> int {
+        const BndArgs a = make_bnd(c);
+        for (int s = 0; s < 4; ++s) {
+            if (c->L.s[s].kind != KIND_DIRICHLET) continue;
+            const int tot = c->L.s[s].len * c->L.M;
+            hipLaunchKernelGGL((k_dirichlet<Q, T>), dim3((tot + 255) / 256), dim3(256), 0, c->stream, a, s, c->inlet[s],
+                               (T*)c->f[0], (T*)c->f[1]);
+            HIPCHK(c, hipGetLastError());
+        }
+        return LBM_OK;
+    });
 }
 
 size_t lbm_tape_bytes(const lbm_ctx* c, int nsteps, int every) {

@@ -23,7 +23,7 @@ VISC = {"meso": 0, "fd": 1}
 
 # exported symbols, as declared in include/lbm.h
 SYMBOLS = ["lbm_workspace_bytes", "lbm_init", "lbm_cbc_params", "lbm_reconstruction", "lbm_viscous", "lbm_dirichlet_profile", "lbm_step",
-           "lbm_macroscopic", "lbm_boundary_state", "lbm_diagnostics", "lbm_state_bytes", "lbm_save",
+           "lbm_macroscopic", "lbm_boundary_state", "lbm_diagnostics", "lbm_diag_every", "lbm_state_bytes", "lbm_save",
            "lbm_restore", "lbm_steps_done", "lbm_set_kernel_timing", "lbm_bulk_kernel_time",
            "lbm_tape_bytes", "lbm_record", "lbm_adjoint", "lbm_lattice_info", "lbm_last_error", "lbm_destroy"]
 
@@ -69,6 +69,7 @@ def load():
     L.lbm_macroscopic.argtypes = [_vp, _vp, _vp, _vp, _vp]
     L.lbm_boundary_state.argtypes = [_vp, ctypes.c_int, _vp]
     L.lbm_diagnostics.argtypes = [_vp, ctypes.POINTER(ctypes.c_double)]
+    L.lbm_diag_every.argtypes = [_vp, ctypes.c_int]
     L.lbm_state_bytes.restype = ctypes.c_size_t
     L.lbm_state_bytes.argtypes = [_vp]
     L.lbm_save.argtypes = [_vp, _vp]
@@ -209,6 +210,11 @@ class LBM:
             return np.array(out[:])
         self._check(rc)
         return np.array(out[:])
+
+    def set_diag_every(self, n):
+        """Check for non-finite populations every n steps inside step() (0: off); step() then
+        raises LBMError with code LBM_E_NONFINITE at the first check that finds one."""
+        self._check(load().lbm_diag_every(self.ctx, int(n)))
 
     def state_bytes(self):
         return load().lbm_state_bytes(self.ctx)

@@ -129,3 +129,84 @@ def test_kernel_timing():
     with pytest.raises(lbm.LBMError):
         g.set_kernel_timing(True, every=-1)
     g.close()
+
+
+def test_diag_every_stops_at_the_first_nonfinite_check():
+    # the blow-up case above: with a check every 5 steps, step() stops at the first multiple of
+    # 5 whose state holds a non-finite population, the same step at which the diagnostics of a
+    # run checked by hand first report one
+    log("[gpu-case] lbm_step non-finite check")
+    nx, ny = 32, 16
+    ux = np.where(np.arange(nx)[None, :] < nx // 2, 2.5, -2.5) * np.ones((ny, 1))
+    fields = (np.ones((ny, nx)), ux, 0, 1)
+    g = lbm.LBM(9, nx, ny, 0.5001, ["periodic"] * 4, fields, precision="fp64")
+    first = None
+    for k in range(200):
+        g.step(5)
+        if g.diagnostics(allow_nonfinite=True)[6] > 0:
+            first = g.steps_done()
+            break
+    g.close()
+    assert first is not None
+    g = lbm.LBM(9, nx, ny, 0.5001, ["periodic"] * 4, fields, precision="fp64")
+    g.set_diag_every(5)
+    with pytest.raises(lbm.LBMError) as e:
+        g.step(1000)
+    assert e.value.code == lbm.LBM_E_NONFINITE
+    assert g.steps_done() == first
+    # a finite run passes every check
+    h = lbm.LBM(37, 40, 40, TAU_37, BC, W.temperature_pulse(40, 40))
+    h.set_relax(-1, **RELAX)
+    h.set_diag_every(7)
+    h.step(50)
+    assert h.steps_done() == 50
+    with pytest.raises(lbm.LBMError):
+        h.set_diag_every(-1)
+    h.close()
+    g.close()
+
+
+def test_boundary_setters_discard_a_recording():
+    # lbm_adjoint recomputes the recorded steps with the settings current at its call: changing
+    # relaxation, reconstruction or viscous terms after lbm_record must refuse the adjoint
+    f = W.temperature_pulse(40, 40)
+    for change in (lambda g: g.set_relax(-1, sigma=0.3, alpha=0.1, mach=0.05),
+                   lambda g: g.set_reconstruction(-1, "neep"),
+                   lambda g: g.set_viscous(-1, "fd")):
+        g = lbm.LBM(37, 40, 40, TAU_37, ["lodi_relax", "cbc_relax", "periodic", "periodic"], f)
+        g.set_relax(-1, **RELAX)
+        g.record(6, 3)
+        change(g)
+        with pytest.raises(lbm.LBMError) as e:
+            g.adjoint()
+        assert e.value.code == lbm.LBM_E_STATE
+        g.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+def test_save_restore_keeps_the_dirichlet_profile(precision):
+    # a Dirichlet profile changed after the save is undone by the restore, on both population
+    # buffers: the restored run equals the straight one bit for bit
+    log(f"[gpu-case] save/restore with a Dirichlet profile {precision}")
+    nx, ny = 60, 40
+    f = W.temperature_pulse(nx, ny, amp=1e-3, width=5.0)
+    bc = ["dirichlet", "lodi_relax", "periodic", "periodic"]
+    p1 = np.tile([1.0, 0.02, 0.0, 1.0], (ny, 1))
+    p2 = np.tile([1.001, 0.05, 0.01, 1.002], (ny, 1))
+    g = lbm.LBM(37, nx, ny, TAU_37, bc, f, precision=precision)
+    g.set_relax(-1, **RELAX)
+    g.set_inlet(0, p1)
+    g.step(13)
+    buf = g.save()
+    g.step(20)
+    ref = g.macro_numpy()
+    g.set_inlet(0, p2)
+    g.step(3)
+    g.restore(buf)
+    assert g.steps_done() == 13
+    g.step(20)
+    got = g.macro_numpy()
+    for x, y in zip(ref, got):
+        assert np.array_equal(x, y)
+    assert np.allclose(got[1][:, :3], 0.02, atol=0, rtol=1e-5)
+    g.close()
