@@ -150,6 +150,21 @@ int lbm_dirichlet_profile(lbm_ctx* ctx, int side, const double* d_U);
  * LBM_E_NONFINITE, with the state of that step kept and lbm_steps_done telling which step. */
 int lbm_step(lbm_ctx* ctx, int nsteps);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): the diagnostics of lbm_diagnostics, enqueued on the
+ * context's stream without synchronising, allocating nothing and touching no workspace scratch.
+ * d_out: device FP64 [8], the same quantities as lbm_diagnostics' h_out ([7] = the step count
+ * when the call is made); the caller reads [6] for non-finite populations (this call does not
+ * return LBM_E_NONFINITE).  The partial sums live in a fixed device array of the library
+ * (16384 partials per quantity, 1 MiB per device, kept until the process ends); grids of more
+ * than 16384 row tiles of 256 nodes let each work-group fold several tiles, so every grid that
+ * lbm_init accepts fits, and up to that size the result equals lbm_diagnostics' bit for bit
+ * (beyond it the sums differ by rounding only).  All calls on one device share that array:
+ * calls in flight at the same time on one device (other streams, other threads) race; calls on
+ * one stream are ordered.  The device current at the call must be the context's (else
+ * LBM_E_STATE). */
+int lbm_diagnostics_noalloc(lbm_ctx* ctx, double* d_out);
+
 /* Interval of lbm_step's non-finite check: n > 0 checks after every n-th step (counted since
  * lbm_init, or the restored checkpoint's count), 0 (the default) turns it off; negative n
  * returns LBM_E_ARG. */

@@ -10,6 +10,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -20,9 +21,33 @@
 
 using namespace lbm;
 
+// Scratch of lbm_diagnostics_noalloc: the first pass's partials ([8][NOALLOC_PARTIALS],
+// component-major) and nothing else; every device the library runs on holds its own copy until
+// the process ends.  Host code never passes `scratch` itself to a kernel (on the host it names a
+// stand-in, not device memory): lbm_init looks up each device's address once.
+constexpr int NOALLOC_PARTIALS = 16384;
+static __device__ __align__(256) double scratch[8 * NOALLOC_PARTIALS];
+
 namespace {
 
 std::string g_err;
+
+// per-device address of `scratch` (hipGetSymbolAddress with that device current)
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[MAX_DEVICES] = {};
+
+hipError_t scratch_address(int dev, double** out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch[dev] = (double*)p;
+    }
+    *out = g_scratch[dev];
+    return hipSuccess;
+}
 
 constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
@@ -186,6 +211,8 @@ struct lbm_ctx {
     int cur = 0;
     long steps = 0;
     int diag_every = 0;            // lbm_step checks for non-finite populations every n steps (0: off)
+    int device = 0;                // HIP device current at lbm_init
+    double* scratch = nullptr;     // that device's copy of the file-scope `scratch` (device address)
     long save_hdr[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // checkpoint header staging: steps, Dirichlet profile flags
     hipStream_t stream = nullptr;
     int nbnd = 0;
@@ -651,6 +678,15 @@ int lbm_init(const lbm_config* cfg, void* d_workspace, size_t workspace_bytes, v
     for (int s = 0; s < 4; ++s) c->inlet[s] = (double*)(c->ws + c->L.off_inlet[s]);
     c->diag = (double*)(c->ws + c->L.off_diag);
     c->stream = (hipStream_t)hip_stream;
+    {
+        hipError_t e = hipGetDevice(&c->device);
+        if (e == hipSuccess && (c->device < 0 || c->device >= MAX_DEVICES)) e = hipErrorInvalidDevice;
+        if (e == hipSuccess) e = scratch_address(c->device, &c->scratch);
+        if (e != hipSuccess) {
+            delete c;
+            return fail(nullptr, LBM_E_HIP, std::string("device scratch lookup: ") + hipGetErrorString(e));
+        }
+    }
     for (int s = 0; s < 4; ++s) c->relax[s] = lbm_relax{0.0, 0.0, 1.0, 1.0, 0.0, 0.0};
     c->nbnd = 0;
     for (int s = 0; s < 4; ++s) c->nbnd += c->L.s[s].nblk;
@@ -782,6 +818,19 @@ int lbm_diagnostics(lbm_ctx* c, double* h_out) {
     std::memcpy(h_out, out, sizeof(out));
     if (out[6] > 0) return fail(c, LBM_E_NONFINITE, "non-finite populations");
     return LBM_OK;
+}
+
+int lbm_diagnostics_noalloc(lbm_ctx* c, double* d_out) {
+    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+    if (!d_out) return fail(c, LBM_E_ARG, "output pointer is NULL");
+    int dev = -1;
+    HIPCHK(c, hipGetDevice(&dev));
+    if (dev != c->device || !c->scratch) return fail(c, LBM_E_STATE, "the context's device is not the current device");
+    const int ntiles = c->L.diag_blocks;
+    const int tpw = (ntiles + NOALLOC_PARTIALS - 1) / NOALLOC_PARTIALS;   // row tiles per work-group
+    const int nparts = (ntiles + tpw - 1) / tpw;
+    if (tpw < 1 || nparts > NOALLOC_PARTIALS) return fail(c, LBM_E_ARG, "grid too large for the fixed diagnostics scratch");
+    return enqueue_diag(c, c->scratch, nparts, tpw, d_out);
 }
 
 int lbm_diag_every(lbm_ctx* c, int n) {

@@ -23,7 +23,7 @@ VISC = {"meso": 0, "fd": 1}
 
 # exported symbols, as declared in include/lbm.h
 SYMBOLS = ["lbm_workspace_bytes", "lbm_init", "lbm_cbc_params", "lbm_reconstruction", "lbm_viscous", "lbm_dirichlet_profile", "lbm_step",
-           "lbm_macroscopic", "lbm_boundary_state", "lbm_diagnostics", "lbm_diag_every", "lbm_state_bytes", "lbm_save",
+           "lbm_macroscopic", "lbm_boundary_state", "lbm_diagnostics", "lbm_diagnostics_noalloc", "lbm_diag_every", "lbm_state_bytes", "lbm_save",
            "lbm_restore", "lbm_steps_done", "lbm_set_kernel_timing", "lbm_bulk_kernel_time",
            "lbm_tape_bytes", "lbm_record", "lbm_adjoint", "lbm_lattice_info", "lbm_last_error", "lbm_destroy"]
 
@@ -70,6 +70,7 @@ def load():
     L.lbm_boundary_state.argtypes = [_vp, ctypes.c_int, _vp]
     L.lbm_diagnostics.argtypes = [_vp, ctypes.POINTER(ctypes.c_double)]
     L.lbm_diag_every.argtypes = [_vp, ctypes.c_int]
+    L.lbm_diagnostics_noalloc.argtypes = [_vp, _vp]
     L.lbm_state_bytes.restype = ctypes.c_size_t
     L.lbm_state_bytes.argtypes = [_vp]
     L.lbm_save.argtypes = [_vp, _vp]
@@ -210,6 +211,13 @@ class LBM:
             return np.array(out[:])
         self._check(rc)
         return np.array(out[:])
+
+    def diagnostics_noalloc(self, out):
+        """Enqueue the diagnostics into the float64 device tensor out[8] without allocating or
+        synchronising (lbm_diagnostics_noalloc)."""
+        if out.dtype != self.torch.float64 or out.numel() < 8 or not out.is_cuda or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 device tensor of 8 elements")
+        self._check(load().lbm_diagnostics_noalloc(self.ctx, _vp(out.data_ptr())))
 
     def set_diag_every(self, n):
         """Check for non-finite populations every n steps inside step() (0: off); step() then
