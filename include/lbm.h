@@ -100,9 +100,10 @@ typedef struct lbm_relax {
 enum lbm_recon { LBM_RECON_EQUILIBRIUM = 0, LBM_RECON_NEEP = 1 };
 
 /* Viscous terms V of a CBC side (eq. NSF-CHAR).  MESO (default): from the non-equilibrium
- * moments of the populations at x_f, x_f-1, x_f-2 (Sec. 3.3 "Evaluation of viscous terms", eq.
- * LaplaceU and eq. LaplaceT), frozen at time t during the RK4 stages and shared by the M layers
- * of a row.  FD: the -FD variant of Sec. 4.2 ("Treatment of viscous terms"): nu lap(u) and
+ * moments of the populations (Sec. 3.3 "Evaluation of viscous terms", eq. LaplaceU and eq.
+ * LaplaceT) at x_f - M, x_f - M - 1, x_f - M - 2, the first bulk nodes of the row none of whose
+ * populations streamed from the layers, one-sided along the normal and central along the side;
+ * frozen at time t during the RK4 stages and shared by the M layers of a row.  FD: the -FD variant of Sec. 4.2 ("Treatment of viscous terms"): nu lap(u) and
  * 2 nu lap(T) by second differences of the macroscopic values of each layer (the backward
  * four-point formula on the outermost layer, central differences on inner layers and along the
  * side) plus the viscous heating from first differences, evaluated at every RK4 stage. */

@@ -33,6 +33,13 @@
  *  - Non-equilibrium part f^neq = f - f^eq (eq. NEEP); viscous stress
  *    Pi' = -(1 - 1/(2 tau)) sum c c f^neq (eq. LaplaceU); physical heat flux
  *    q = (1 - 1/(2 tau)) 1/2 sum f |c-u|^2 (c-u) (eq. LaplaceT with the same factor).
+ *  - Where the mesoscopic viscous terms are evaluated (Sec. 3.3, "Evaluation of viscous terms"):
+ *    at x_f - M, the first bulk node whose pre-collision populations all streamed from bulk
+ *    nodes, with the one-sided difference over x_f - M, x_f - M - 1, x_f - M - 2 and central
+ *    differences along the side; the result serves every layer of the row.  At x_f itself (the
+ *    paper's wording) the populations streamed in from the equilibrium layers carry no
+ *    non-equilibrium part, and the one-sided difference across that deficit feeds back on the
+ *    layers' state: CBC-RELAX with the equilibrium BC then grows without bound.
  *  - Relaxation (eq. LODI-Relax / CBC-Relax, Z = P, transverse target 0) acts on the incoming
  *    acoustic amplitude only: -alpha T_x,i + K (P - P_inf) / (4 rho cs^2) (thermal) or
  *    -alpha T_x,i + K (P - P_inf) (isothermal), K = sigma (1 - Ma^2) c_inf / L.  Incoming
@@ -528,16 +535,19 @@ struct Sim {
     }
 
     // V (local components, eq. NSF-CHAR) at row r of a side, frozen at the old time level: the
-    // divergence of Pi' and q at x_f, one-sided along the normal (eq. FD-dx-bw) and central
-    // along the side (eq. FD-dx-center), plus the viscous heating Pi':grad u = Pi':Pi' / mu.
-    void visc_row(const SideGeo& g, int r, S* V4) const {
+    // divergence of Pi' and q at the bulk node kof nodes inward of x_f, one-sided along the normal
+    // (eq. FD-dx-bw over that node and the next two inward) and central along the side
+    // (eq. FD-dx-center), plus the viscous heating Pi':grad u = Pi':Pi' / mu.  The side solve
+    // takes kof = M: x_f - M is the first node none of whose populations streamed from the
+    // layers (with the equilibrium BC those carry no non-equilibrium part).
+    void visc_row(const SideGeo& g, int r, S* V4, int kof) const {
         const double nu = (tau - 0.5) * L.cs2;
         S d[3][6], up[6], dn[6];
-        for (int k = 0; k < 3; ++k) { int x, y; node(g, -k, r, x, y); visc_node(g, x, y, d[k]); }
+        for (int k = 0; k < 3; ++k) { int x, y; node(g, -kof - k, r, x, y); visc_node(g, x, y, d[k]); }
         int x, y;
-        if (g.tper || r + 1 < g.len) { node(g, 0, r + 1, x, y); visc_node(g, x, y, up); }
+        if (g.tper || r + 1 < g.len) { node(g, -kof, r + 1, x, y); visc_node(g, x, y, up); }
         else { for (auto& v : up) v = 0.0; }
-        if (g.tper || r - 1 >= 0) { node(g, 0, r - 1, x, y); visc_node(g, x, y, dn); }
+        if (g.tper || r - 1 >= 0) { node(g, -kof, r - 1, x, y); visc_node(g, x, y, dn); }
         else { for (auto& v : dn) v = 0.0; }
         auto dn_ = [&](int c) { return 0.5 * (3.0 * d[0][c] - 4.0 * d[1][c] + d[2][c]); };
         auto dt_ = [&](int c) { return 0.5 * (up[c] - dn[c]); };
@@ -554,7 +564,7 @@ struct Sim {
 
     void visc_terms(const SideGeo& g, std::vector<S>& V) const {
         V.assign((size_t)g.len * 4, S(0.0));
-        for (int r = 0; r < g.len; ++r) visc_row(g, r, &V[(size_t)r * 4]);
+        for (int r = 0; r < g.len; ++r) visc_row(g, r, &V[(size_t)r * 4], M);
     }
 
     // -------------------------------------------------- frames
@@ -1369,7 +1379,7 @@ int oracle_visc_probe(void* h, int nax, int sn, int x, int y, double* out) {
     g.xf = nax == 0 ? x : y;
     const int r = nax == 0 ? y : x;
     if (g.xf - 2 * sn < 0 || g.xf - 2 * sn >= g.Nn) return -1;
-    s->visc_row(g, r, out);
+    s->visc_row(g, r, out, 0);
     return 0;
 }
 

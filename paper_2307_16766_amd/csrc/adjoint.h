@@ -30,7 +30,7 @@
 //                  G = (dm/dM)^T (df^eq/dm)^T lambda, M the linear moments (sum f, sum f c,
 //                  sum f |c|^2); at n = 0 it gives dL/d(rho0, ux0, uy0, T0) = (df^eq/dm)^T lambda^0.
 // Supported boundaries: all of them.  CBC sides with the mesoscopic viscous terms add their VJP
-// at the nodes x_f .. x_f - 2, NEEP and zero-gradient sides add terms of nu^{n+1}(x_f); the layers
+// at the nodes x_f - M .. x_f - M - 2, NEEP and zero-gradient sides add terms of nu^{n+1}(x_f); the layers
 // of a Dirichlet side are constants of the given profile, or, with the default profile (the
 // initial state of the first layer), collect the adjoint of that profile (k_adj_dir_collect).
 #pragma once
@@ -717,7 +717,7 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
         for (int m = 0; m < 4; ++m) mub0[((size_t)jj * len + rp) * 4 + m] = ybn[m];
     }
     if (meso_v) {
-        // adjoint of the viscous moments of time n at x_f, x_f - 1, x_f - 2 of the owned rows, from
+        // adjoint of the viscous moments of time n at x_f - M .. x_f - M - 2 of the owned rows, from
         // the adjoints of V of rows r - 1, r, r + 1 (complete on rows within one of the owned
         // range); k_adj_bulk adds it to nu^n through the moments' derivatives
         if (t < NN)
@@ -1201,7 +1201,7 @@ __global__ __launch_bounds__(256) void k_adj_bulk(AdjArgs g, BulkArgs k, int bpr
 #pragma unroll
     for (int i = 0; i < Q; ++i) out[(unsigned long long)i * pitch] = (1.0 - om) * lam[i] + om * phi_dot<Q>(i, GM);
     if (Lat<Q>::thermal && g.vism) {
-        // nodes x_f, x_f - 1, x_f - 2 of a CBC side with the mesoscopic viscous terms: the moments
+        // nodes x_f - M, x_f - M - 1, x_f - M - 2 of a CBC side with the mesoscopic viscous terms: the moments
         // Pi' and q of eq. LaplaceU / LaplaceT taken from g^n there (time-n inputs of the next
         // step's V); with d = c_i - u, f = 1 - 1/(2 tau):
         //   d Pi'_ab / d g_i = -f (d_a d_b - |d|^2 delta_ab / 2),
@@ -1212,7 +1212,7 @@ __global__ __launch_bounds__(256) void k_adj_bulk(AdjArgs g, BulkArgs k, int bpr
             if (S.kind != KIND_CHAR || !(S.scheme == BC_CBC || S.scheme == BC_CBC_RELAX) || S.vfd) continue;
             const bool xn = S.nax == 0;
             const int nc = xn ? x : y, tc = xn ? y : x;
-            const int kk = (S.xf - nc) * S.sn, rr = tc - S.r0;
+            const int kk = (S.xf - nc) * S.sn - M, rr = tc - S.r0;   // nodes x_f - M - kk
             if (kk < 0 || kk > 2 || rr < 0 || rr >= S.len) continue;
             const size_t o6 = ((size_t)kk * S.len + rr) * 6;
             const double* vb = (const double*)(g.adj_cur + S.off_vis) + o6;

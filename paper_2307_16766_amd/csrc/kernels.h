@@ -8,7 +8,7 @@
 //            the write stream of a row of work-groups in one contiguous region.
 //   region : two parity copies of the boundary solver state (FP64): per characteristic side
 //            U_b[M][len][4], the bulk strip U[MS][len][4] at x_f (and x_f - 1 for M = 1), the
-//            viscous moments [3][len][6] at x_f, x_f-1, x_f-2; per corner U_c[4] and the two
+//            viscous moments [3][len][6] at x_f-M .. x_f-M-2; per corner U_c[4] and the two
 //            inward diagonal bulk nodes [2][4].  Parity p holds time level n with n % 2 = p.
 // One time step n -> n+1 is one launch of k_step: its first work-groups each take a chunk of
 // rows of a boundary side (re-pull of the strip from A, RK4 of the characteristic system in
@@ -497,8 +497,8 @@ __device__ __forceinline__ void visc_moments(const SideDev& s, const double* d, 
 }
 
 // Mesoscopic viscous terms V (side-local: 0, V_n, V_t, V_T of eq. NSF-CHAR with eq. LaplaceU /
-// LaplaceT) of one side row rp from the viscous moments vis[k][len][6] of x_f, x_f - 1, x_f - 2:
-// divergence of Pi' and q one-sided along the normal at x_f (eq. FD-dx-bw) and central along the
+// LaplaceT) of one side row rp from the viscous moments vis[k][len][6] of x_f - M - k, k = 0..2:
+// divergence of Pi' and q one-sided along the normal at x_f - M (eq. FD-dx-bw) and central along the
 // side between rows rup and rdw (-1: no row there, its moments taken as 0), plus the viscous
 // heating Pi':Pi' / mu.
 template <int Q>
@@ -630,30 +630,37 @@ __device__ void char_chunk(const T* __restrict__ A, T* __restrict__ B, const Bnd
         const double* src = &st[((size_t)k * len + phys(r)) * 4];
         for (int m = 0; m < 4; ++m) sBn[(lr * MS + k) * 4 + m] = src[m];
     }
-    constexpr int KPmax = 3;
-    const int KP = full ? KPmax : MS;
+    // per row: the strip nodes x_f (.. x_f - MS + 1), then for CBC sides the three nodes of the
+    // viscous moments, x_f - M - kv (kv = 0, 1, 2): the first nodes inward of x_f none of whose
+    // populations streamed from the layers (a node there that is no bulk node holds an
+    // equilibrium, whose non-equilibrium moments are 0)
+    const int KP = full ? MS + 3 : MS;
     for (int t = tid; t < NR * KP; t += blockDim.x) {
         const int lr = t / KP, k = t % KP, r = r0 - 4 + lr;
         if (!valid(r)) continue;
         const int rp = phys(r);
         const bool owned = r >= r0 && r < r1;
-        const bool need_strip = k < MS;
-        const bool need_vis = full && owned;
-        if (!need_strip && !need_vis) continue;
-        int x, y; side_node(sd, -k, rp, x, y);
-        double d[Q];
-        pull_node<Q, T>(A, a, x, y, d);
-        if (need_strip) {
+        if (k < MS) {
+            int x, y; side_node(sd, -k, rp, x, y);
+            double d[Q];
+            pull_node<Q, T>(A, a, x, y, d);
             double u4[4];
             moments_u4<Q>(d, u4);
             for (int m = 0; m < 4; ++m) sBp[(lr * MS + k) * 4 + m] = u4[m];
             if (owned) for (int m = 0; m < 4; ++m) stn[((size_t)k * len + rp) * 4 + m] = u4[m];
+            continue;
         }
-        if (need_vis) {
-            double o6[6];
+        if (!owned) continue;
+        const int kv = k - MS;
+        int x, y; side_node(sd, -(M + kv), rp, x, y);
+        const bool bulk = (a.xper || (x >= M && x <= a.nx - 1 - M)) && (a.yper || (y >= M && y <= a.ny - 1 - M));
+        double o6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (bulk) {
+            double d[Q];
+            pull_node<Q, T>(A, a, x, y, d);
             visc_moments<Q>(sd, d, a.tau, o6);
-            for (int m = 0; m < 6; ++m) visn[((size_t)k * len + rp) * 6 + m] = o6[m];
         }
+        for (int m = 0; m < 6; ++m) visn[((size_t)kv * len + rp) * 6 + m] = o6[m];
     }
     // viscous terms of time level n (frozen during the RK stages)
     if (full && !sd.vfd) {

@@ -1,6 +1,8 @@
 """Shared helpers of the GPU parity tests: run the HIP library and the oracle on the same seeded
 inputs and compare macroscopic fields node by node."""
+import json
 import math
+import os
 import sys
 
 import numpy as np
@@ -15,12 +17,16 @@ CS2_17 = O.lattice(17)[0]
 CS_17 = math.sqrt(CS2_17)
 TAU_17 = 0.9   # the D2Q17 runs of Sec. 4.1
 
-# Tolerances: relative L2 error bound on rho and T, and on u the same relative bound plus an
-# absolute rounding floor per step.  The floor is needed because u is compared where it is small
-# (1e-6..1e-4 in the pulse cases) while it is a moment of O(w_i) populations: the oracle stores
-# f itself, whose rounding is about one ulp of an O(1) number per step (2.2e-16 in FP64); FP32
-# deviation storage rounds deviations of size ~1e-3 w_i at 6e-8 relative (~1e-10 per step).
-TOL = {"fp64": (1e-12, 2.2e-16), "fp32dev": (2e-5, 1e-10)}
+# Tolerances: relative L2 error bound on rho, u and T.  In FP64, where the fluid is at rest apart
+# from a pulse (rms |u| of the reference below U_FLOOR_BELOW, i.e. u ~ 1e-6..1e-4), u alone also
+# gets an absolute rounding floor of one ulp of 1 per step: u is then a moment of O(w_i)
+# populations that the oracle stores as f itself, rounded to ~2.2e-16 per step, so a relative
+# bound of 1e-12 on u ~ 1e-5 would measure the oracle's own rounding (measured: 5e-11 .. 8e-10
+# relative on the at-rest cases).  Flows with a background velocity, and FP32 deviation storage
+# everywhere, take the plain relative bound.  Every comparison's achieved errors are appended as
+# a JSON line to the file named by the environment variable PARITY_LOG, when set.
+TOL = {"fp64": (1e-12, 2.2e-16), "fp32dev": (2e-5, 0.0)}
+U_FLOOR_BELOW = 1e-3
 
 
 def log(msg):
@@ -67,15 +73,28 @@ def make_pair(stencil, nx, ny, tau, bc, fields, precision, relax=None, inlet=Non
     return g, o
 
 
+def record(entry):
+    path = os.environ.get("PARITY_LOG")
+    if path:
+        with open(path, "a") as fh:
+            fh.write(json.dumps(entry) + "\n")
+
+
 def check_fields(name, precision, n, gpu, ref, tol=None):
     """Assert parity of (rho, u, T) after n steps; returns the relative errors."""
     rel, floor = TOL[precision] if tol is None else tol
     errs = rel_errors(gpu, ref)
-    assert all(np.isfinite(errs)), (name, n, errs)
-    assert errs[0] <= rel and errs[2] <= rel, f"{name} {precision} step {n}: rel errors rho/u/T = {errs}"
     du = math.sqrt(np.mean((gpu[1] - ref[1]) ** 2 + (gpu[2] - ref[2]) ** 2))
     uref = math.sqrt(np.mean(ref[1] ** 2 + ref[2] ** 2))
-    assert du <= rel * uref + floor * (n + 1), f"{name} {precision} step {n}: rms du {du:.3e}, rms u {uref:.3e}"
+    at_rest = uref < U_FLOOR_BELOW and floor > 0
+    record({"case": name, "precision": precision, "step": n, "rel_rho": errs[0], "rel_u": errs[1], "rel_T": errs[2],
+            "rms_u": uref, "u_floor": at_rest})
+    assert all(np.isfinite(errs)), (name, n, errs)
+    assert errs[0] <= rel and errs[2] <= rel, f"{name} {precision} step {n}: rel errors rho/u/T = {errs}"
+    if at_rest:
+        assert du <= rel * uref + floor * (n + 1), f"{name} {precision} step {n}: rms du {du:.3e}, rms u {uref:.3e}"
+    else:
+        assert errs[1] <= rel, f"{name} {precision} step {n}: relative u error {errs[1]:.3e} (rms u {uref:.3e})"
     return errs
 
 

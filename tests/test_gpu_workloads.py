@@ -108,12 +108,10 @@ def test_c3_first_steps_against_oracle():
     g.close()
 
 
-@pytest.mark.parametrize("alpha,steps", [(0.0, 6000), (0.2, 1500)])
+@pytest.mark.parametrize("alpha,steps", [(0.2, 6000), (0.0, 6000)])
 def test_c3_full_run_fp32_vs_fp64(alpha, steps):
     # The vortex (x0 = 256, convected at u0 = 0.2 cs) crosses the CBC-RELAX outflow around step
-    # 4600.  With transverse relaxation alpha = Ma = 0.2 the outflow develops a slowly growing
-    # mode after ~3000 steps (e-folding ~330 steps; it is absent with alpha = 0), so the
-    # 6000-step precision check relaxes pressure only and alpha = 0.2 is checked over 1500 steps.
+    # 4600; transverse relaxation alpha = Ma = 0.2 as specified, and alpha = 0 for comparison.
     log(f"[gpu-case] C3 alpha={alpha} {steps} steps fp32dev vs fp64")
     res = {}
     for prec in ("fp64", "fp32dev"):
@@ -129,6 +127,13 @@ def test_c3_full_run_fp32_vs_fp64(alpha, steps):
     assert abs(res["fp64"][1].mean() - u0) < 0.01 * u0
     P = res["fp64"][0] * res["fp64"][3]
     assert np.abs(P - 1).max() < 5e-3
+    # no grid-scale mode at the outflow: the second difference of u_x along y over the last
+    # columns stays at the level the passing vortex leaves (a growing boundary mode reached 5e-4
+    # here with the viscous terms taken across the layer-streamed nodes)
+    sl = res["fp64"][1][:, -8:]
+    d2 = np.abs(np.roll(sl, 1, 0) - 2 * sl + np.roll(sl, -1, 0)).max()
+    log(f"C3 alpha={alpha}: grid-scale u_x at the outflow {d2:.2e}")
+    assert d2 < 1e-5
 
 
 # --- D2Q37 random temperature field, 256 x 256, LODI-RELAX on four sides (adjoint workload)
