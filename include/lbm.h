@@ -71,7 +71,8 @@ enum lbm_bc {
 typedef struct lbm_config {
     int stencil;     /* LBM_D2Q9, LBM_D2Q17 or LBM_D2Q37 */
     int precision;   /* lbm_precision */
-    int nx, ny;      /* nodes; non-periodic axes need >= 2M+3 nodes, periodic ones >= M+1 */
+    int nx, ny;      /* nodes; non-periodic axes need >= 2M+3 nodes (3M+3 normal to a CBC side),
+                        periodic ones >= M+1 */
     double tau;      /* BGK relaxation time, > 1/2; nu = (tau - 1/2) cs^2 (Sec. 2) */
     int bc[4];       /* lbm_bc for sides x0, x1, y0, y1 */
 } lbm_config;

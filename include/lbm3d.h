@@ -11,7 +11,8 @@
  *     (d = 3 in its polynomials); T = sum f |c - u|^2 / (3 rho cs^2);
  *   - faces: the characteristic system of Appendix A (A, S, S^-1, Lambda in the local frame
  *     (rho, u_n, u_t1, u_t2, T), c_v = 3/2, gamma = 5/3), its transverse terms in y and z and
- *     viscous terms from the mesoscopic moments at x_f, x_f - 1, x_f - 2; incoming amplitudes by
+ *     viscous terms from the mesoscopic moments at x_f - M, x_f - M - 1, x_f - M - 2 (the first
+ *     bulk nodes none of whose populations streamed from the layers); incoming amplitudes by
  *     the four schemes of Tab. CBCs; RK4 as in two dimensions; equilibrium or NEEP
  *     reconstruction of all populations on the M = 3 layers.
  *   The paper gives no edge or corner treatment in 3D: y and z are always periodic.
@@ -38,7 +39,8 @@ enum lbm3d_stencil { LBM_D3Q39 = 39 };
 typedef struct lbm3d_config {
     int stencil;     /* LBM_D3Q39 */
     int precision;   /* lbm_precision: LBM_FP64 or LBM_FP32DEV (deviations f - w_i in float) */
-    int nx, ny, nz;  /* nodes; nx >= 2M+3 = 9 with boundary faces (>= 4 if periodic), ny, nz >= 4 */
+    int nx, ny, nz;  /* nodes; nx >= 2M+3 = 9 with boundary faces, 3M+3 = 12 with a CBC face (>= 4 if
+                        periodic); ny, nz >= 4 */
     double tau;      /* BGK relaxation time, > 1/2; nu = (tau - 1/2) cs^2 */
     int bc[2];       /* lbm_bc of the faces x = 0 and x = nx - 1 */
 } lbm3d_config;

@@ -341,7 +341,8 @@ struct Sim3 {
     // V (local frame of outward normal g x) at bulk node (x0, y, z), frozen at time t:
     // div Pi' / rho and the temperature term, normal derivatives one-sided over x0, x0 - g,
     // x0 - 2 g (eq. FD-dx-bw), tangential derivatives central along y and z (eq. FD-dx-center).
-    // On a face, x0 = x_f and g = sn.
+    // On a face, x0 = x_f - sn M (the first node none of whose populations streamed from the
+    // layers) and g = sn.
     void visc_row(int g, int x0, int y, int z, double* V5) const {
         const double nu = (tau - 0.5) * L.cs2;
         double d[3][10], yp[10], ym[10], zp[10], zm[10];
@@ -466,7 +467,7 @@ struct Sim3 {
                 for (int y = 0; y < ny; ++y) getU(U, xk(s, j), y, z, &Y0[((size_t)(j - 1) * R + (size_t)z * ny + y) * 5]);
         if (full3(bc[s]))
             for (int z = 0; z < nz; ++z)
-                for (int y = 0; y < ny; ++y) visc_row(sn(s), xf(s), y, z, &V[((size_t)z * ny + y) * 5]);
+                for (int y = 0; y < ny; ++y) visc_row(sn(s), xf(s) - sn(s) * M, y, z, &V[((size_t)z * ny + y) * 5]);
         FaceCtx c;
         c.s = s; c.Y0 = &Y0; c.Un = &Un; c.V = &V;
         const double a_st[4] = {0.0, 0.5, 0.5, 1.0}, b_st[4] = {1.0, 2.0, 2.0, 1.0};
@@ -630,6 +631,8 @@ void* oracle3d_create(int stencil, int nx, int ny, int nz, double tau, const int
     if ((bc[0] == B3_PERIODIC) != (bc[1] == B3_PERIODIC)) { g_err3 = "periodic x-faces come in pairs"; return nullptr; }
     const bool xp = bc[0] == B3_PERIODIC;
     if (nx < (xp ? L.M + 1 : 2 * L.M + 3) || ny < L.M + 1 || nz < L.M + 1) { g_err3 = "grid too small"; return nullptr; }
+    // the viscous terms of a CBC face are evaluated at x_f - M .. x_f - M - 2 (bulk nodes)
+    if ((full3(bc[0]) || full3(bc[1])) && nx < 3 * L.M + 3) { g_err3 = "CBC faces need nx >= 3M + 3"; return nullptr; }
     return new Sim3(L, nx, ny, nz, tau, bc);
 }
 

@@ -1105,6 +1105,11 @@ int validate(int stencil, int nx, int ny, double tau, const int* bc) {
     }
     const bool xp = bc[0] == BC_PERIODIC, yp = bc[2] == BC_PERIODIC;
     if (nx < (xp ? M + 1 : 2 * M + 3) || ny < (yp ? M + 1 : 2 * M + 3)) { g_err = "grid too small"; return -1; }
+    // the viscous terms of a CBC side are evaluated at x_f - M .. x_f - M - 2 (bulk nodes)
+    if (((is_full_cbc(bc[0]) || is_full_cbc(bc[1])) && nx < 3 * M + 3) ||
+        ((is_full_cbc(bc[2]) || is_full_cbc(bc[3])) && ny < 3 * M + 3)) {
+        g_err = "CBC sides need at least 3M + 3 nodes along their normal"; return -1;
+    }
     if (!xp && !yp) {
         for (int cx = 0; cx < 2; ++cx)
             for (int cy = 2; cy < 4; ++cy) {

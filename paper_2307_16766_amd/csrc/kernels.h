@@ -192,7 +192,7 @@ __global__ __launch_bounds__(256) void k_init_boundary(BndArgs a, const double* 
                 double* v0 = (double*)(a.reg_cur + sd.off_vis);
                 double* v1 = (double*)(a.reg_next + sd.off_vis);
                 for (int k = 0; k < 3; ++k) {
-                    int x, y; side_node(sd, -k, r, x, y);
+                    int x, y; side_node(sd, -(M + k), r, x, y);
                     const double rk = rho[y * a.nx + x];
                     for (int c = 0; c < 6; ++c) {
                         v0[((size_t)k * sd.len + r) * 6 + c] = c == 0 ? rk : 0.0;

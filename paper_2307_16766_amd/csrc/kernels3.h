@@ -4,7 +4,7 @@
 // Data layout in HBM: populations as deviations f - w_i, row-interleaved SoA f[z][y][i][x] (a
 // "row" is one (y, z) pair; its q planes are contiguous, the x pitch is padded to 64 elements).
 // Face state (FP64, two parity copies): U_b[M][rows][5], the bulk value of x_f [rows][5] and the
-// viscous moments of x_f, x_f - 1, x_f - 2 [3][rows][10] (CBC schemes); RK4 stage inputs and the
+// viscous moments of x_f - M, x_f - M - 1, x_f - M - 2 [3][rows][10] (CBC schemes); RK4 stage inputs and the
 // viscous terms are single buffers.
 //
 // One time step = face kernels, which need only the old level A: k3_prep (strip and viscous
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(256) void k3_init_faces(Args3 a, const double* __re
         if (is_full3(fc.scheme)) {
             double* vis = (double*)(reg + fc.off_vis);
             for (int k = 0; k < 3; ++k) {
-                field(fc.xf - fc.sn * k, u5);
+                field(fc.xf - fc.sn * (L3::M + k), u5);
                 for (int c = 0; c < 10; ++c) vis[ivis(a.rows, k, c, r)] = c == 0 ? u5[0] : 0.0;
             }
         }
@@ -224,41 +224,42 @@ __device__ __forceinline__ void visc_moments3(int sn, const double* d, double ta
     o[7] = sn * 0.5 * fac * qx; o[8] = 0.5 * fac * qy; o[9] = 0.5 * fac * qz;
 }
 
-// Three threads per face row, one per node x_f - sn k (k = 0, 1, 2): consecutive threads pull
-// neighbouring x of the same row, so each load instruction touches a third of the cache lines
-// that one thread per row would.  New level: moments of x_f (the strip) and, for the CBC
-// schemes, the viscous moments of the three nodes, from the pulls of A.  Old level (CBC
+// Four threads per face row, one per node: x_f (k = 0) and x_f - sn (M + k - 1) (k = 1, 2, 3):
+// consecutive threads pull nearby x of the same row, so each load instruction touches fewer
+// cache lines than one thread per row would.  New level: moments of x_f (the strip) and, for the
+// CBC schemes, the viscous moments of the other three nodes, from the pulls of A.  Old level (CBC
 // schemes, thread k = 0): the viscous terms V (eq. NSF-CHAR, Appendix A), frozen during the RK4
 // stages -- div Pi' / rho and (-div q + Pi':Pi' / (2 rho nu)) / (rho c_v cs^2), normal derivatives
-// one-sided over x_f, x_f - 1, x_f - 2 (eq. FD-dx-bw), tangential ones central in y and z
+// one-sided over x_f - M .. x_f - M - 2 (eq. FD-dx-bw), tangential ones central in y and z
 // (eq. FD-dx-center).
 template <typename T>
 __global__ __launch_bounds__(256) void k3_prep(const T* __restrict__ A, Args3 a) {
     const int s = blockIdx.y;
     const Face3& fc = a.f[s];
     const int t = blockIdx.x * 256 + threadIdx.x;
-    if (!is_char3(fc.scheme) || t >= 3 * a.rows) return;
-    const int r = t / 3, k = t - 3 * r;
+    if (!is_char3(fc.scheme) || t >= 4 * a.rows) return;
+    // four threads per row: k = 0 the strip node x_f, k = 1..3 the viscous-moment nodes
+    // x_f - M - (k - 1), the first nodes inward of x_f none of whose populations streamed from
+    // the layers (bulk nodes: the configuration keeps nx >= 3M + 3 for CBC faces)
+    const int r = t / 4, k = t - 4 * r;
     const int y = r % a.ny, z = r / a.ny;
     const bool full = is_full3(fc.scheme);
     if (!full && k > 0) return;
     double d[L3::Q];
-    pull3<T>(A, a, fc.xf - fc.sn * k, y, z, d);
+    pull3<T>(A, a, k == 0 ? fc.xf : fc.xf - fc.sn * (L3::M + k - 1), y, z, d);
     if (k == 0) {
         double rm1, u, v, w, th;
         moments3_dev<double>(d, rm1, u, v, w, th);
         double* stn = (double*)(a.reg_next + fc.off_strip);
         const double o[5] = {1.0 + rm1, u, v, w, 1.0 + th};
         for (int m = 0; m < 5; ++m) stn[(size_t)m * a.rows + r] = o[m];
-    }
-    if (!full) return;
-    {
+    } else {
         double o[10];
         visc_moments3(fc.sn, d, a.tau, o);
         double* visn = (double*)(a.reg_next + fc.off_vis);
-        for (int c = 0; c < 10; ++c) visn[ivis(a.rows, k, c, r)] = o[c];
+        for (int c = 0; c < 10; ++c) visn[ivis(a.rows, k - 1, c, r)] = o[c];
     }
-    if (k != 0) return;
+    if (!full || k != 0) return;
     const double* vis = (const double*)(a.reg_cur + fc.off_vis);
     auto at = [&](int kk, int yy, int zz, int c) {
         return vis[ivis(a.rows, kk, c, wrap3(zz, a.nz) * a.ny + wrap3(yy, a.ny))];

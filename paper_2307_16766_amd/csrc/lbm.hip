@@ -83,6 +83,11 @@ int validate(const lbm_config* c, std::string& err) {
     const int M = stencil_M(c->stencil);
     const bool xp = c->bc[0] == BC_PERIODIC, yp = c->bc[2] == BC_PERIODIC;
     if (c->nx < (xp ? M + 1 : 2 * M + 3) || c->ny < (yp ? M + 1 : 2 * M + 3)) { err = "grid too small"; return LBM_E_ARG; }
+    // the viscous terms of a CBC side are evaluated at x_f - M .. x_f - M - 2, which must be bulk nodes
+    if (((is_full(c->bc[0]) || is_full(c->bc[1])) && c->nx < 3 * M + 3) ||
+        ((is_full(c->bc[2]) || is_full(c->bc[3])) && c->ny < 3 * M + 3)) {
+        err = "CBC sides need at least 3M + 3 nodes along their normal"; return LBM_E_ARG;
+    }
     if ((double)c->nx * (double)c->ny > 2.0e9) { err = "grid too large"; return LBM_E_ARG; }
     {   // the step kernel's row of bulk tile t is umulhi(t, floor(2^32 / bpr) + 1): exact while t * bpr < 2^32
         const unsigned long long bpr = ((unsigned long long)c->nx + 255) / 256;

@@ -46,6 +46,9 @@ int validate3(const lbm3d_config* c, std::string& err) {
     if ((c->bc[0] == LBM_BC_PERIODIC) != (c->bc[1] == LBM_BC_PERIODIC)) { err = "periodic faces must come in pairs"; return LBM_E_ARG; }
     const bool xp = c->bc[0] == LBM_BC_PERIODIC;
     if (c->nx < (xp ? L3::M + 1 : 2 * L3::M + 3) || c->ny < L3::M + 1 || c->nz < L3::M + 1) { err = "grid too small"; return LBM_E_ARG; }
+    // the viscous terms of a CBC face are evaluated at x_f - M .. x_f - M - 2, which must be bulk nodes
+    if ((c->bc[0] == LBM_BC_CBC || c->bc[0] == LBM_BC_CBC_RELAX || c->bc[1] == LBM_BC_CBC || c->bc[1] == LBM_BC_CBC_RELAX) &&
+        c->nx < 3 * L3::M + 3) { err = "CBC faces need nx >= 3M + 3"; return LBM_E_ARG; }
     const double n = (double)c->nx * (double)c->ny * (double)c->nz;
     if (n > 2.0e9) { err = "grid too large"; return LBM_E_ARG; }
     const unsigned long long bpr = ((unsigned long long)c->nx + 255) / 256;
@@ -179,7 +182,7 @@ int launch_step3(lbm3d_ctx* c) {
     // staged for the bulk kernel's boundary-layer lanes
     if (!a.xper) {
         if (c->cfg.bc[0] != LBM_BC_ZG || c->cfg.bc[1] != LBM_BC_ZG) {
-            hipLaunchKernelGGL((k3_prep<T>), dim3((3 * rows + 255) / 256, 2), dim3(256), 0, c->stream, A, a);
+            hipLaunchKernelGGL((k3_prep<T>), dim3((4 * rows + 255) / 256, 2), dim3(256), 0, c->stream, A, a);
             HIPCHK3(c, hipGetLastError());
             for (int st = 0; st < 4; ++st) {
                 hipLaunchKernelGGL(k3_stage, dim3((L3::M * rows + 255) / 256, 2), dim3(256), 0, c->stream, a, st);

@@ -85,10 +85,19 @@ def test_config_validation():
         lbm.make_config(9, 64, 48, 0.6, ["cbc", "cbc", "periodic", "periodic"]),  # CBC needs D2Q37
         lbm.make_config(37, 64, 48, 0.6, ["lodi", "lodi", "zg", "zg"]),           # mixed corner
         lbm.make_config(11, 64, 48, 0.6, ["periodic"] * 4),                       # unknown stencil
+        lbm.make_config(37, 11, 48, 0.6, ["lodi", "cbc", "periodic", "periodic"]),  # CBC: nx < 3M + 3
+        lbm.make_config(17, 64, 11, 0.9, ["lodi", "lodi", "cbc_relax", "lodi"]),     # CBC: ny < 3M + 3
     ]
     for c in bad:
         assert L.lbm_workspace_bytes(ctypes.byref(c)) == 0
         assert L.lbm_last_error(None)
+    # the smallest grids: 2M + 3 nodes across LODI sides, 3M + 3 across a CBC side
+    for c in (lbm.make_config(37, 9, 9, 0.6, ["lodi"] * 4), lbm.make_config(37, 12, 9, 0.6, ["lodi", "cbc", "lodi", "lodi"])):
+        assert L.lbm_workspace_bytes(ctypes.byref(c)) > 0
+    # the oracle applies the same rule
+    with pytest.raises(ValueError):
+        O.Oracle(37, 11, 48, 0.6, ["lodi", "cbc", "periodic", "periodic"])
+    O.Oracle(37, 12, 48, 0.6, ["lodi", "cbc", "periodic", "periodic"]).close()
 
 
 def test_fp32dev_halves_population_bytes():

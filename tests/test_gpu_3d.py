@@ -125,12 +125,19 @@ def test_3d_multi_tile():
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
-def test_3d_minimum_grid(precision):
-    # the smallest accepted box: nx = 2M + 3 = 9 with two faces (the strips of both faces share
-    # the three bulk columns), ny = nz = M + 1 = 4 (every periodic wrap of a 3-step pull)
-    nx, ny, nz = 9, 4, 4
-    compare3("minimum", nx, ny, nz, ["cbc_relax", "lodi_relax"], drifting_pulse(nx, ny, nz, (4, 1.5, 2.0), width=1.5),
+@pytest.mark.parametrize("nx,bc", [(9, ["lodi", "lodi_relax"]), (12, ["cbc_relax", "lodi_relax"])])
+def test_3d_minimum_grid(precision, nx, bc):
+    # the smallest accepted boxes: nx = 2M + 3 = 9 with two faces (the strips of both faces share
+    # the three bulk columns), 3M + 3 = 12 with a CBC face (its viscous moments come from x_f - M ..
+    # x_f - M - 2, here the other face's strip column among them); ny = nz = M + 1 = 4 (every
+    # periodic wrap of a 3-step pull)
+    from paper_2307_16766_amd import lbm3d
+    ny, nz = 4, 4
+    compare3("minimum", nx, ny, nz, bc, drifting_pulse(nx, ny, nz, (nx // 2, 1.5, 2.0), width=1.5),
              precision, [1, 2, 5, 20], relax=RELAX)
+    if bc[0] == "cbc_relax":
+        with pytest.raises(lbm3d._lbm.LBMError):
+            lbm3d.LBM3D(nx - 1, ny, nz, TAU, bc, drifting_pulse(nx - 1, ny, nz, (5, 1.5, 2.0)))
 
 
 def test_3d_zero_steps_and_errors():
