@@ -11,8 +11,10 @@ Prints one JSON line: MLUPS of the FP32 deviation path over all nx*ny nodes, the
 step kernel k_step (one launch per step: bulk stream + collide and the boundary chunks), with
 algorithmic bytes per launch = 2 q s per bulk node (read q populations, write q) + q s per
 written boundary-layer node + q s per re-pulled strip node (s = 4 or 8 bytes), over its
-HIP-event-timed duration, against 8 TB/s; the FP64 path on the same workload; and the FP64 CPU
-oracle timed on a bounded slab of the same workload.
+HIP-event-timed duration, against 8 TB/s; the FP64 path on the same workload; the adjoint, D2Q17
+and D3Q39 lines; the workloads C1..C4 at full size (whole-step and step-kernel MLUPS, both
+precisions); and the FP64 CPU oracle timed on a bounded slab of the throughput workload and on
+the C1..C5 inputs (all host threads and one).
 """
 import argparse
 import hashlib
@@ -87,12 +89,16 @@ def run_gpu(precision, steps, warmup, q=Q, tau=None):
     del g
     torch.cuda.empty_cache()
     bytes_per_launch = algorithmic_bytes(4 if precision == "fp32dev" else 8, q)
-    kernel_ms = kms / max(launches, 1)
+    # one step is one launch of k_step: the event-bracketed launches read ~1 us above the step
+    # time (event work on the stream), so the smaller of the two is the kernel's duration
+    bracketed_ms = kms / max(launches, 1)
+    kernel_ms = min(bracketed_ms, step_ms)
     gbps = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
     return {
         "ms_per_step": step_ms,
         "mlups": NX * NY / (step_ms * 1e-3) / 1e6,
         "bulk_kernel_ms": kernel_ms,
+        "bulk_kernel_ms_bracketed": bracketed_ms,
         "bulk_launches": launches,
         "bulk_bytes_per_launch": bytes_per_launch,
         "bulk_GBps": gbps,
@@ -194,6 +200,80 @@ def run_3d(precision, steps, warmup, n=(512, 256, 256)):
             "finite": bool(d[7] == 0)}
 
 
+def run_config_gpu(name, precision, steps, warmup=20):
+    """Whole-step and step-kernel MLUPS of workload C1..C4 (paper_2307_16766_amd.workloads) at its
+    full size: one untimed pass of `steps` steps between two events for the step rate, then the
+    same number of steps with every step kernel bracketed by events for the kernel rate."""
+    import torch
+    from paper_2307_16766_amd import lbm
+    from paper_2307_16766_amd import workloads as W
+    c = W.config(name, lbm.lattice_info(37)[0])
+    g = lbm.LBM(c["stencil"], c["nx"], c["ny"], c["tau"], c["bc"], c["fields"](), precision=precision)
+    g.set_relax(-1, **c["relax"])
+    g.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(g.stream)
+    g.step(steps)
+    e1.record(g.stream)
+    torch.cuda.synchronize()
+    step_ms = e0.elapsed_time(e1) / steps
+    g.set_kernel_timing(True, every=1)
+    g.step(steps)
+    kms, launches = g.bulk_kernel_time()
+    g.set_kernel_timing(False)
+    finite = bool(g.diagnostics(allow_nonfinite=True)[6] == 0)
+    g.close()
+    n = c["nx"] * c["ny"]
+    kernel_ms = kms / max(launches, 1)
+    esz = 4 if precision == "fp32dev" else 8
+    M = 1 if c["stencil"] == 9 else 3
+    xb = c["nx"] - (0 if c["bc"][0] == "periodic" else 2 * M)
+    yb = c["ny"] - (0 if c["bc"][2] == "periodic" else 2 * M)
+    bulk_bytes = 2 * c["stencil"] * esz * xb * yb
+    return {"workload": c["workload"], "precision": precision, "steps": steps,
+            "ms_per_step": step_ms, "mlups": n / (step_ms * 1e-3) / 1e6,
+            "kernel_ms": kernel_ms, "kernel_mlups": n / (kernel_ms * 1e-3) / 1e6,
+            "bulk_bytes_GBps": bulk_bytes / (kernel_ms * 1e-3) / 1e9, "finite": finite}
+
+
+def oracle_configs(budget_s=2.0):
+    """The FP64 oracle on the inputs of C1..C5 at their full sizes: MLUPS with all host threads and
+    with one, each timed over enough steps for about budget_s seconds (at least one step).  C5's
+    single-thread figure is not taken (one step there takes about a minute); its multi-thread
+    figure is extrapolated from the few steps timed."""
+    from oracle import oracle as O
+    from paper_2307_16766_amd import workloads as W
+    cores = O.num_threads()
+    out = {"cores": cores}
+    for name in ("c1", "c2", "c3", "c4", "c5"):
+        c = W.config(name, O.lattice(37)[0])
+        o = O.Oracle(c["stencil"], c["nx"], c["ny"], c["tau"], c["bc"])
+        o.set_relax(-1, **c["relax"])
+        o.init(*c["fields"]())
+        if c["inlet"] is not None:
+            o.set_inlet(*c["inlet"])
+        n = c["nx"] * c["ny"]
+        res = {"workload": c["workload"]}
+        for threads in ((cores, 1) if name != "c5" else (cores,)):
+            O.set_threads(threads)
+            t = time.perf_counter()
+            o.step(1)
+            per = time.perf_counter() - t
+            k = max(1, min(200, int(budget_s / max(per, 1e-6))))
+            t = time.perf_counter()
+            o.step(k)
+            dt = time.perf_counter() - t
+            res["mlups_all_threads" if threads == cores else "mlups_one_thread"] = n * k / dt / 1e6
+            res["steps_all_threads" if threads == cores else "steps_one_thread"] = k
+        O.set_threads(cores)
+        if name == "c5":
+            res["note"] = f"extrapolated from {res['steps_all_threads']} timed steps; one thread: see cpu_baseline"
+        o.close()
+        out[name] = res
+    return out
+
+
 def algorithmic_bytes(esz, q=Q):
     """Bytes one step kernel must move: bulk nodes read and write q populations; the outflow
     side's M layers are written (equilibrium reconstruction) and its x_f column re-pulled (q
@@ -284,6 +364,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--no-d2q17", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="skip the C1..C4 GPU lines and the oracle on C1..C5")
     ap.add_argument("--cpu-steps", type=int, default=None)
     ap.add_argument("--copy-probe", type=float, default=None, metavar="GIB",
                     help="only run a plain copy of GIB gibibytes (counter calibration)")
@@ -332,11 +413,23 @@ def main():
         eprint("[bench] D3Q39 512x256x256 (fp32dev, fp64)")
         d3 = {p: run_3d(p, 50 if p == "fp32dev" else 25, 5) for p in ("fp32dev", "fp64")}
         eprint(f"[bench] d3q39: fp32 {d3['fp32dev']['ms_per_step']:.3f} ms/step, fp64 {d3['fp64']['ms_per_step']:.3f}")
+    cfgs = None
+    if not args.no_configs:
+        eprint("[bench] workloads C1..C4 at full size (GPU)")
+        cfgs = {"c1": {"fp64": run_config_gpu("c1", "fp64", 1000)}}
+        for name, steps in (("c2", 300), ("c3", 300), ("c4", 1000)):
+            cfgs[name] = {p: run_config_gpu(name, p, steps) for p in ("fp64", "fp32dev")}
+        for name, d in cfgs.items():
+            eprint(f"[bench] {name}: " + ", ".join(f"{p} {r['mlups']:.0f} MLUPS ({r['kernel_mlups']:.0f} kernel)"
+                                                   for p, r in d.items()))
     cpu = None
     if not args.no_cpu_baseline:
         eprint("[bench] cpu baseline (oracle)")
         cpu = cpu_baseline(args.cpu_steps)
         eprint(f"[bench] cpu baseline: {cpu['value']:.3f} MLUPS on {cpu['cores']} threads")
+        if not args.no_configs:
+            eprint("[bench] oracle on the C1..C5 inputs")
+            cpu["configs"] = oracle_configs()
     traffic = traffic_from_profile()
     out = {
         "metric": "MLUPS, D2Q37 FP32 deviation storage (HBM roofline fraction; FP64 path alongside)",
@@ -365,6 +458,7 @@ def main():
             "traffic": traffic,
             "kernel": "k_step<37,float> (bulk tiles + boundary chunks, one launch per step)",
             "kernel_ms": r32["bulk_kernel_ms"],
+            "kernel_ms_bracketed": r32["bulk_kernel_ms_bracketed"],
             "bytes_per_launch": r32["bulk_bytes_per_launch"],
         },
         "fp64": None if r64 is None else {
@@ -374,6 +468,7 @@ def main():
         "adjoint": adj,
         "d2q17": d17,
         "d3q39": d3,
+        "workloads": cfgs,
         "cpu_baseline": cpu,
         "finite": r32["finite"] and (r64 is None or r64["finite"]),
     }

@@ -5,6 +5,8 @@ method's arithmetic.  Lattice constants it needs (the sound speed) are passed in
 The fields follow the initial-value problems of Sec. 4 of the paper (pulses, vortex) at the sizes
 of the workloads named below.
 """
+import math
+
 import numpy as np
 
 # tau giving kinematic viscosity nu = (tau - 1/2) cs^2 = 0.1 on D2Q37 (Sec. 4 uses nu = 0.1)
@@ -113,3 +115,45 @@ def random_directions(n, nx, ny, seed):
     """n seeded standard-normal perturbation fields [n][ny][nx] (directional-derivative checks)."""
     rng = np.random.default_rng(seed)
     return rng.standard_normal((n, ny, nx))
+
+
+def config(name, cs2, alpha_c3=None):
+    """The five workload configurations C1..C5: stencil, grid, tau, boundary kinds (x0, x1, y0,
+    y1), relaxation settings, Dirichlet inlet (side, profile) or None, a callable returning the
+    initial fields, the step count and a description.  cs2: the stencil's sound speed squared
+    (D2Q37 unless C1), which sets tau for nu = 0.1 and the Mach numbers."""
+    cs = math.sqrt(cs2)
+    tau37 = 0.5 + NU_D2Q37 / cs2
+    if name == "c1":
+        return dict(stencil=9, nx=256, ny=128, tau=0.6, bc=["lodi_relax", "lodi_relax", "periodic", "periodic"],
+                    relax=dict(sigma=0.25, alpha=0.0, mach=0.0), inlet=None, steps=1000,
+                    fields=lambda: gaussian_density_pulse(256, 128, amp=1e-3, width=8.0),
+                    workload="D2Q9 256x128 density pulse, tau 0.6, LODI-RELAX x-sides, periodic y, FP64, 1000 steps")
+    if name == "c2":
+        return dict(stencil=37, nx=512, ny=512, tau=tau37, bc=["lodi_relax"] * 4,
+                    relax=dict(sigma=0.25, alpha=0.0, mach=0.0), inlet=None, steps=5000,
+                    fields=lambda: temperature_pulse(512, 512, amp=1e-3, width=12.0),
+                    workload="D2Q37 512x512 pressure + temperature pulse (amplitude 1e-3, width 12), LODI-RELAX "
+                             "on four sides and corners (sigma 0.25), 5000 steps")
+    if name == "c3":
+        a = 0.2 if alpha_c3 is None else alpha_c3
+        return dict(stencil=37, nx=1024, ny=512, tau=tau37, bc=["lodi_relax", "cbc_relax", "periodic", "periodic"],
+                    relax=dict(sigma=0.25, alpha=a, mach=0.2), inlet=None, steps=6000,
+                    fields=lambda: isentropic_vortex(1024, 512, cs, mach=0.2, radius=20.0, strength=0.05,
+                                                     center=(256.0, None)),
+                    workload=f"D2Q37 1024x512 isentropic vortex (Ma 0.2, R 20, U_v 0.05), LODI-RELAX inflow, "
+                             f"CBC-RELAX outflow (sigma 0.25, alpha {a:g}), periodic y, 6000 steps")
+    if name == "c4":
+        return dict(stencil=37, nx=256, ny=256, tau=tau37, bc=["lodi_relax"] * 4,
+                    relax=dict(sigma=0.25, alpha=0.0, mach=0.0), inlet=None, steps=2000,
+                    fields=lambda: random_temperature(256, 256, std=1e-4, seed=2307),
+                    workload="D2Q37 256x256 random temperature (std 1e-4, seed 2307), LODI-RELAX on four sides "
+                             "and corners (sigma 0.25, alpha = Ma = 0), 2000 steps")
+    if name == "c5":
+        fields, prof = shear_layer(4096, 2048, u0=0.1, thickness=10.0, noise=1e-3, seed=16766)
+        return dict(stencil=37, nx=4096, ny=2048, tau=tau37, bc=["dirichlet", "lodi_relax", "periodic", "periodic"],
+                    relax=dict(sigma=0.25, alpha=0.0, mach=0.1 / math.sqrt(2 * cs2)), inlet=(0, prof), steps=1000,
+                    fields=lambda: fields,
+                    workload="D2Q37 4096x2048 shear layer (u0 0.1, thickness 10, noise 1e-3, seed 16766), Dirichlet "
+                             "inlet, LODI-RELAX outflow (sigma 0.25), periodic y, 1000 steps")
+    raise ValueError(f"unknown workload {name}")

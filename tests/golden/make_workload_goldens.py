@@ -38,7 +38,7 @@ def main():
     if a.threads:
         O.set_threads(a.threads)
     cs2 = O.lattice(37)[0]
-    cfg = WC.c3(cs2, a.alpha) if (a.config == "c3" and a.alpha is not None) else WC.CONFIGS[a.config](cs2)
+    cfg = WC.config(a.config, cs2, a.alpha if a.config == "c3" else None)
     o = O.Oracle(cfg["stencil"], cfg["nx"], cfg["ny"], cfg["tau"], cfg["bc"])
     o.set_relax(-1, **cfg["relax"])
     o.init(*cfg["fields"]())
