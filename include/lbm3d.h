@@ -1,7 +1,8 @@
 /*
  * lbm3d.h -- C ABI of the three-dimensional path of liblbm_hip.so: thermal lattice Boltzmann
- * on the D3Q39 stencil with characteristic (LODI / CBC) boundaries on the two x-faces of a box
- * that is periodic in y and z, on one AMD Instinct MI355X (gfx950).
+ * on the D3Q39 stencil with characteristic (LODI / CBC) boundaries on the two faces normal to one
+ * axis (x, y or z) of a box that is periodic along the other two, on one AMD Instinct MI355X
+ * (gfx950).
  *
  * Method: Klass, Gabbana & Bartel, "Characteristic Boundary Condition for Thermal Lattice
  * Boltzmann Methods" (arXiv 2307.16766), Appendix A (CBC and LODI for the Navier-Stokes-Fourier
@@ -10,17 +11,19 @@
  *     Gauss-Hermite rule with cs^2 = 2/3, with the 3rd-order Hermite equilibrium of eq. feq-3
  *     (d = 3 in its polynomials); T = sum f |c - u|^2 / (3 rho cs^2);
  *   - faces: the characteristic system of Appendix A (A, S, S^-1, Lambda in the local frame
- *     (rho, u_n, u_t1, u_t2, T), c_v = 3/2, gamma = 5/3), its transverse terms in y and z and
+ *     (rho, u_n, u_t1, u_t2, T), c_v = 3/2, gamma = 5/3), its transverse terms along the two
+ *     tangential axes and
  *     viscous terms from the mesoscopic moments at x_f - M, x_f - M - 1, x_f - M - 2 (the first
  *     bulk nodes none of whose populations streamed from the layers); incoming amplitudes by
  *     the four schemes of Tab. CBCs; RK4 as in two dimensions; equilibrium or NEEP
  *     reconstruction of all populations on the M = 3 layers.
- *   The paper gives no edge or corner treatment in 3D: y and z are always periodic.
+ *   The paper gives no edge or corner treatment in 3D: the two axes along the faces are always
+ *   periodic.
  *
  * Conventions as in lbm.h: lattice units, T dimensionless with reference 1, caller-owned device
  * memory (d_* pointers) and stream, asynchronous calls except lbm3d_diagnostics, negative error
  * codes from enum lbm_status, messages from lbm3d_last_error.  Macroscopic arrays are FP64
- * [nz][ny][nx] with x fastest.  Face order: x = 0, x = nx - 1.
+ * [nz][ny][nx] with x fastest.  Face order: low end, high end of the face axis.
  */
 #ifndef LBM3D_H
 #define LBM3D_H
@@ -39,10 +42,16 @@ enum lbm3d_stencil { LBM_D3Q39 = 39 };
 typedef struct lbm3d_config {
     int stencil;     /* LBM_D3Q39 */
     int precision;   /* lbm_precision: LBM_FP64 or LBM_FP32DEV (deviations f - w_i in float) */
-    int nx, ny, nz;  /* nodes; nx >= 2M+3 = 9 with boundary faces, 3M+3 = 12 with a CBC face (>= 4 if
-                        periodic); ny, nz >= 4 */
+    int nx, ny, nz;  /* nodes; along the face axis >= 2M+3 = 9 with boundary faces, 3M+3 = 12 with a
+                        CBC face (>= 4 if periodic); along the other axes >= 4 */
     double tau;      /* BGK relaxation time, > 1/2; nu = (tau - 1/2) cs^2 */
-    int bc[2];       /* lbm_bc of the faces x = 0 and x = nx - 1 */
+    int bc[2];       /* lbm_bc of the faces at the low and the high end of the face axis */
+    int axis;        /* face axis: 0 = x (faces x = 0, nx - 1), 1 = y, 2 = z; the other two axes
+                        are periodic.  Appendix A's system is written for the normal along x; a
+                        face normal to y or z uses it rotated, with the local frame (u_n, u_t1,
+                        u_t2) = (u_y, u_z, u_x) or (u_z, u_x, u_y).  Internally the library
+                        stores the grid with the face axis as its fastest axis; input and output
+                        arrays keep the caller's [nz][ny][nx] layout. */
 } lbm3d_config;
 
 typedef struct lbm3d_ctx lbm3d_ctx;

@@ -1,8 +1,8 @@
 /*
  * lbm3d_oracle.cpp -- plain FP64 CPU reference of the three-dimensional extension of the
  * characteristic boundary conditions of Klass, Gabbana & Bartel (arXiv 2307.16766, Appendix A):
- * thermal BGK lattice Boltzmann on the D3Q39 stencil with LODI / CBC boundaries on the two
- * x-faces of a box that is periodic in y and z.
+ * thermal BGK lattice Boltzmann on the D3Q39 stencil with LODI / CBC boundaries on the two faces
+ * normal to one axis (x, y or z) of a box that is periodic along the other two.
  *
  * TEST INFRASTRUCTURE.  Like the two-dimensional oracle, this file is what the GPU library is
  * checked against; only the test-suite, the package smoke check and the CPU-baseline leg of the
@@ -11,7 +11,7 @@
  * definition, the characteristic matrices from the formulas of Appendix A.
  *
  * Steps (one time step, unfused, in the order of the paper's flowcharts):
- *     stream -> macroscopic fields -> collide -> characteristic solve on each x-face (RK4)
+ *     stream -> macroscopic fields -> collide -> characteristic solve on each face (RK4)
  *     -> mesoscopic Dirichlet reconstruction (equilibrium or eq. NEEP) / zero gradient.
  *
  * Readings (each also listed in the design notes):
@@ -22,15 +22,17 @@
  *  - d = 3: c_v = 3/2, c_p = 5/2, gamma = 5/3 (Appendix A); T = sum f |c-u|^2 / (3 rho cs^2).
  *  - Characteristic system: A, S, S^-1 and Lambda of Appendix A in the local frame
  *    U = (rho, u_n, u_t1, u_t2, T), waves ordered entropy, shear t1, shear t2, acoustic -/+.
- *    The transverse terms are those of Appendix A, with central differences along y and z.
- *  - Viscous terms of the CBC schemes from the mesoscopic moments at x_f, x_f-1, x_f-2 (as in
- *    2D): V_u = div(Pi') / rho, V_T = (-div q + Pi':Pi' / (2 rho nu)) / (rho c_v cs^2), with
+ *    The transverse terms are those of Appendix A, with central differences along the two
+ *    tangential axes (t1, t2) = the axes that follow the normal cyclically (y, z for x-faces;
+ *    z, x for y-faces; x, y for z-faces): Appendix A written for a face normal to x, rotated.
+ *  - Viscous terms of the CBC schemes from the mesoscopic moments at x_f - M .. x_f - M - 2 (as
+ *    in 2D): V_u = div(Pi') / rho, V_T = (-div q + Pi':Pi' / (2 rho nu)) / (rho c_v cs^2), with
  *    Pi' = -(1 - 1/(2 tau)) sum c c (f - f^eq) and q = (1 - 1/(2 tau)) 1/2 sum f |c-u|^2 (c-u).
  *  - Relaxation: the incoming acoustic amplitude gets -alpha T_x,i + K (P - P_inf) / (5 rho cs^2),
  *    the pressure coefficient of the acoustic rows of S (1/5 in 3D, 1/4 in 2D), with
  *    K = sigma (1 - Ma^2) c_inf / L and c_inf = sqrt(gamma cs^2 T_inf).
- *  - Faces: only the x-faces carry boundaries; y and z are periodic (the paper gives no edge or
- *    corner treatment in 3D).
+ *  - Faces: the two faces normal to one axis carry boundaries; the other two axes are periodic
+ *    (the paper gives no edge or corner treatment in 3D).
  */
 #include <algorithm>
 #include <array>
@@ -247,50 +249,70 @@ struct Relax3 {
 struct Sim3 {
     const Lattice3& L;
     int nx, ny, nz, q, M;
+    int ax;              // axis normal to the two faces: 0 = x, 1 = y, 2 = z
+    int dim[3];          // nx, ny, nz
     double tau;
-    int bc[2];           // x = 0 and x = nx - 1; y and z are periodic
-    bool xper;
+    int bc[2];           // faces at the low and the high end of axis ax; the other axes are periodic
+    bool fper;           // faces periodic (no boundaries)
     Relax3 rp[2];
     int meso[2] = {0, 0};
     std::vector<double> f, fpre, U;   // f, fpre: [q][nz][ny][nx]; U: [5][nz][ny][nx]
     long steps = 0;
 
-    Sim3(const Lattice3& lat, int nx_, int ny_, int nz_, double tau_, const int* bc_)
-        : L(lat), nx(nx_), ny(ny_), nz(nz_), q(lat.q), M(lat.M), tau(tau_) {
+    Sim3(const Lattice3& lat, int nx_, int ny_, int nz_, double tau_, const int* bc_, int ax_)
+        : L(lat), nx(nx_), ny(ny_), nz(nz_), q(lat.q), M(lat.M), ax(ax_), tau(tau_) {
+        dim[0] = nx; dim[1] = ny; dim[2] = nz;
         bc[0] = bc_[0]; bc[1] = bc_[1];
-        xper = bc[0] == B3_PERIODIC;
+        fper = bc[0] == B3_PERIODIC;
         f.assign((size_t)q * plane(), 0.0);
         fpre = f;
         U.assign((size_t)5 * plane(), 0.0);
     }
 
+    // face frame: the normal axis ax and the tangential axes a1 = ax + 1, a2 = ax + 2 (mod 3); a
+    // node of a face's row is (kn, t1, t2) with kn along the normal; rows r = t2 * n1 + t1
+    int a1() const { return (ax + 1) % 3; }
+    int a2() const { return (ax + 2) % 3; }
+    int nn() const { return dim[ax]; }
+    int n1() const { return dim[a1()]; }
+    int n2() const { return dim[a2()]; }
     size_t plane() const { return (size_t)nx * ny * nz; }
     size_t id(int x, int y, int z) const { return ((size_t)z * ny + y) * nx + x; }
-    bool is_bulk(int x) const { return xper || (x >= M && x <= nx - 1 - M); }
+    size_t fid(int kn, int t1, int t2) const {
+        int c[3];
+        c[ax] = kn; c[a1()] = t1; c[a2()] = t2;
+        return id(c[0], c[1], c[2]);
+    }
+    bool is_bulk_n(int kn) const { return fper || (kn >= M && kn <= nn() - 1 - M); }
+    bool is_bulk(int x, int y, int z) const { const int c[3] = {x, y, z}; return is_bulk_n(c[ax]); }
     int sn(int s) const { return s == 0 ? -1 : 1; }
-    int xf(int s) const { return s == 0 ? M : nx - 1 - M; }
+    int xf(int s) const { return s == 0 ? M : nn() - 1 - M; }
     int xk(int s, int k) const { return xf(s) + sn(s) * k; }   // k = 0: x_f; k = j: layer j
-    int wy(int y) const { return ((y % ny) + ny) % ny; }
-    int wz(int z) const { return ((z % nz) + nz) % nz; }
-    void getU(const std::vector<double>& F, int x, int y, int z, double* u5) const {
-        for (int c = 0; c < 5; ++c) u5[c] = F[c * plane() + id(x, y, z)];
+    int w1(int t) const { return ((t % n1()) + n1()) % n1(); }
+    int w2(int t) const { return ((t % n2()) + n2()) % n2(); }
+    void getU(const std::vector<double>& F, size_t k, double* u5) const {
+        for (int c = 0; c < 5; ++c) u5[c] = F[c * plane() + k];
     }
-    void setU(std::vector<double>& F, int x, int y, int z, const double* u5) const {
-        for (int c = 0; c < 5; ++c) F[c * plane() + id(x, y, z)] = u5[c];
+    void setU(std::vector<double>& F, size_t k, const double* u5) const {
+        for (int c = 0; c < 5; ++c) F[c * plane() + k] = u5[c];
     }
-    void node_feq(std::vector<double>& F, int x, int y, int z, const double* u5) const {
+    void node_feq(std::vector<double>& F, size_t k, const double* u5) const {
         std::vector<double> fe(q);
         equilibrium3(L, u5[0], u5[1], u5[2], u5[3], u5[4], fe.data());
-        for (int i = 0; i < q; ++i) F[i * plane() + id(x, y, z)] = fe[i];
+        for (int i = 0; i < q; ++i) F[i * plane() + k] = fe[i];
     }
-    void node_moments(const std::vector<double>& F, int x, int y, int z, double* u5) const {
+    void node_moments(const std::vector<double>& F, size_t k, double* u5) const {
         std::vector<double> fl(q);
-        for (int i = 0; i < q; ++i) fl[i] = F[i * plane() + id(x, y, z)];
+        for (int i = 0; i < q; ++i) fl[i] = F[i * plane() + k];
         moments3(L, fl.data(), u5);
     }
-    // local frame of face s: (rho, u_n, u_y, u_z, T), u_n = sn u_x
-    void to_local(int s, const double* g, double* l) const { l[0] = g[0]; l[1] = sn(s) * g[1]; l[2] = g[2]; l[3] = g[3]; l[4] = g[4]; }
-    void rate_to_global(int s, const double* l, double* g) const { g[0] = l[0]; g[1] = sn(s) * l[1]; g[2] = l[2]; g[3] = l[3]; g[4] = l[4]; }
+    // local frame of face s: (rho, u_n, u_t1, u_t2, T), u_n = sn u_ax
+    void to_local(int s, const double* g, double* l) const {
+        l[0] = g[0]; l[1] = sn(s) * g[1 + ax]; l[2] = g[1 + a1()]; l[3] = g[1 + a2()]; l[4] = g[4];
+    }
+    void rate_to_global(int s, const double* l, double* g) const {
+        g[0] = l[0]; g[1 + ax] = sn(s) * l[1]; g[1 + a1()] = l[2]; g[1 + a2()] = l[3]; g[4] = l[4];
+    }
 
     void init(const double* rho, const double* ux, const double* uy, const double* uz, const double* T) {
         for (int z = 0; z < nz; ++z)
@@ -298,8 +320,8 @@ struct Sim3 {
                 for (int x = 0; x < nx; ++x) {
                     const size_t k = id(x, y, z);
                     const double u5[5] = {rho[k], ux[k], uy[k], uz[k], T[k]};
-                    setU(U, x, y, z, u5);
-                    node_feq(f, x, y, z, u5);
+                    setU(U, k, u5);
+                    node_feq(f, k, u5);
                 }
         fpre = f;
         steps = 0;
@@ -308,17 +330,19 @@ struct Sim3 {
     double relax_K(int s) const {
         const Relax3& p = rp[s];
         const double cinf = std::sqrt(GAMMA3 * L.cs2 * p.T_inf);
-        const double Lg = p.length > 0 ? p.length : (double)nx;
+        const double Lg = p.length > 0 ? p.length : (double)nn();
         return p.sigma * (1.0 - p.mach * p.mach) * cinf / Lg;
     }
 
-    // Pi' (nn, n1, n2, 11, 12, 22), q (n, 1, 2) in the local frame and rho at a node, from the
-    // pre-collision populations of the current time level; zero on boundary layers (equilibria)
-    void visc_node(int g, int x, int y, int z, double* o10) const {
+    // Pi' (nn, n1, n2, 11, 12, 22), q (n, 1, 2) in the local frame of outward normal g e_ax and
+    // rho at node (kn, t1, t2), from the pre-collision populations of the current time level; zero
+    // on boundary layers (equilibria)
+    void visc_node(int g, int kn, int t1, int t2, double* o10) const {
         for (int c = 0; c < 10; ++c) o10[c] = 0.0;
-        if (!is_bulk(x)) return;
+        if (!is_bulk_n(kn)) return;
+        const size_t k = fid(kn, t1, t2);
         std::vector<double> fl(q), fe(q);
-        for (int i = 0; i < q; ++i) fl[i] = fpre[i * plane() + id(x, y, z)];
+        for (int i = 0; i < q; ++i) fl[i] = fpre[i * plane() + k];
         double u5[5];
         moments3(L, fl.data(), u5);
         equilibrium3(L, u5[0], u5[1], u5[2], u5[3], u5[4], fe.data());
@@ -332,23 +356,24 @@ struct Sim3 {
             const double e = fl[i] * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) * 0.5 * fac;
             for (int a = 0; a < 3; ++a) Qv[a] += e * d[a];
         }
+        const int n = ax, b1 = a1(), b2 = a2();
         o10[0] = u5[0];
-        o10[1] = P[0][0]; o10[2] = g * P[0][1]; o10[3] = g * P[0][2];
-        o10[4] = P[1][1]; o10[5] = P[1][2]; o10[6] = P[2][2];
-        o10[7] = g * Qv[0]; o10[8] = Qv[1]; o10[9] = Qv[2];
+        o10[1] = P[n][n]; o10[2] = g * P[n][b1]; o10[3] = g * P[n][b2];
+        o10[4] = P[b1][b1]; o10[5] = P[b1][b2]; o10[6] = P[b2][b2];
+        o10[7] = g * Qv[n]; o10[8] = Qv[b1]; o10[9] = Qv[b2];
     }
 
-    // V (local frame of outward normal g x) at bulk node (x0, y, z), frozen at time t:
-    // div Pi' / rho and the temperature term, normal derivatives one-sided over x0, x0 - g,
-    // x0 - 2 g (eq. FD-dx-bw), tangential derivatives central along y and z (eq. FD-dx-center).
-    // On a face, x0 = x_f - sn M (the first node none of whose populations streamed from the
-    // layers) and g = sn.
-    void visc_row(int g, int x0, int y, int z, double* V5) const {
+    // V (local frame of outward normal g e_ax) at bulk node (kn0, t1, t2), frozen at time t:
+    // div Pi' / rho and the temperature term, normal derivatives one-sided over kn0, kn0 - g,
+    // kn0 - 2 g (eq. FD-dx-bw), tangential derivatives central along t1 and t2 (eq.
+    // FD-dx-center).  On a face, kn0 = x_f - sn M (the first node none of whose populations
+    // streamed from the layers) and g = sn.
+    void visc_row(int g, int kn0, int t1, int t2, double* V5) const {
         const double nu = (tau - 0.5) * L.cs2;
         double d[3][10], yp[10], ym[10], zp[10], zm[10];
-        for (int k = 0; k < 3; ++k) visc_node(g, x0 - g * k, y, z, d[k]);
-        visc_node(g, x0, wy(y + 1), z, yp); visc_node(g, x0, wy(y - 1), z, ym);
-        visc_node(g, x0, y, wz(z + 1), zp); visc_node(g, x0, y, wz(z - 1), zm);
+        for (int k = 0; k < 3; ++k) visc_node(g, kn0 - g * k, t1, t2, d[k]);
+        visc_node(g, kn0, w1(t1 + 1), t2, yp); visc_node(g, kn0, w1(t1 - 1), t2, ym);
+        visc_node(g, kn0, t1, w2(t2 + 1), zp); visc_node(g, kn0, t1, w2(t2 - 1), zm);
         auto dn = [&](int c) { return 0.5 * (3.0 * d[0][c] - 4.0 * d[1][c] + d[2][c]); };
         auto d1 = [&](int c) { return 0.5 * (yp[c] - ym[c]); };
         auto d2 = [&](int c) { return 0.5 * (zp[c] - zm[c]); };
@@ -364,35 +389,35 @@ struct Sim3 {
 
     struct FaceCtx {
         int s;
-        const std::vector<double>* Y;    // stage values [M][ny*nz][5]
+        const std::vector<double>* Y;    // stage values [M][n1*n2][5]
         const std::vector<double>* Y0;   // values at time t
         const std::vector<double>* Un;   // macroscopic field at t + dt (bulk filled)
-        const std::vector<double>* V;    // viscous terms [ny*nz][5]
+        const std::vector<double>* V;    // viscous terms [n1*n2][5]
         double theta;
     };
 
-    // value (global components) at outward index k of row (y, z): layers from the stage
+    // value (global components) at outward index k of row (t1, t2): layers from the stage
     // values, bulk nodes interpolated in time
-    void face_value(const FaceCtx& c, int k, int y, int z, double* u5) const {
-        y = wy(y); z = wz(z);
-        const int r = z * ny + y;
+    void face_value(const FaceCtx& c, int k, int t1, int t2, double* u5) const {
+        t1 = w1(t1); t2 = w2(t2);
+        const size_t r = (size_t)t2 * n1() + t1;
         if (k >= 1) {
-            for (int m = 0; m < 5; ++m) u5[m] = (*c.Y)[((size_t)(k - 1) * ny * nz + r) * 5 + m];
+            for (int m = 0; m < 5; ++m) u5[m] = (*c.Y)[((size_t)(k - 1) * n1() * n2() + r) * 5 + m];
             return;
         }
-        const int x = xk(c.s, k);
+        const size_t node = fid(xk(c.s, k), t1, t2);
         double a[5], b[5];
-        getU(U, x, y, z, a); getU(*c.Un, x, y, z, b);
+        getU(U, node, a); getU(*c.Un, node, b);
         for (int m = 0; m < 5; ++m) u5[m] = (1.0 - c.theta) * a[m] + c.theta * b[m];
     }
 
-    // transverse terms of Appendix A (local frame, t1 = y, t2 = z) at layer j of row (y, z),
-    // central differences of the stage values along y and z
-    void transverse(const FaceCtx& c, int j, int y, int z, double* Tv) const {
-        auto lv = [&](int k, int yy, int zz, double* l) { double g[5]; face_value(c, k, yy, zz, g); to_local(c.s, g, l); };
+    // transverse terms of Appendix A (local frame) at layer j of row (t1, t2), central
+    // differences of the stage values along t1 and t2
+    void transverse(const FaceCtx& c, int j, int t1, int t2, double* Tv) const {
+        auto lv = [&](int k, int u1, int u2, double* l) { double g[5]; face_value(c, k, u1, u2, g); to_local(c.s, g, l); };
         double l0[5], yp[5], ym[5], zp[5], zm[5];
-        lv(j, y, z, l0);
-        lv(j, y + 1, z, yp); lv(j, y - 1, z, ym); lv(j, y, z + 1, zp); lv(j, y, z - 1, zm);
+        lv(j, t1, t2, l0);
+        lv(j, t1 + 1, t2, yp); lv(j, t1 - 1, t2, ym); lv(j, t1, t2 + 1, zp); lv(j, t1, t2 - 1, zm);
         auto dy = [&](double u, double d) { return 0.5 * (u - d); };
         const double cs2 = L.cs2;
         const double rho = l0[0], v = l0[2], w = l0[3], T = l0[4];
@@ -403,39 +428,46 @@ struct Sim3 {
         Tv[4] = -(T / CV3) * (dy(yp[2], ym[2]) + dy(zp[3], zm[3])) - (v * dy(yp[4], ym[4]) + w * dy(zp[4], zm[4]));
     }
 
-    // the transverse terms at layer j of row (y, z) of face s from the current state
-    void transverse_probe(int s, int j, int y, int z, double* Tv) const {
-        const size_t R = (size_t)ny * nz;
-        std::vector<double> Y0((size_t)M * R * 5);
-        for (int jj = 1; jj <= M; ++jj)
-            for (int zz = 0; zz < nz; ++zz)
-                for (int yy = 0; yy < ny; ++yy) getU(U, xk(s, jj), yy, zz, &Y0[((size_t)(jj - 1) * R + (size_t)zz * ny + yy) * 5]);
-        FaceCtx c;
-        c.s = s; c.Y = &Y0; c.Y0 = &Y0; c.Un = &U; c.V = nullptr; c.theta = 0.0;
-        transverse(c, j, y, z, Tv);
+    void layers_of(int s, const std::vector<double>& F, std::vector<double>& Y) const {
+        const size_t R = (size_t)n1() * n2();
+        Y.assign((size_t)M * R * 5, 0.0);
+        for (int j = 1; j <= M; ++j)
+            for (int t2 = 0; t2 < n2(); ++t2)
+                for (int t1 = 0; t1 < n1(); ++t1)
+                    getU(F, fid(xk(s, j), t1, t2), &Y[((size_t)(j - 1) * R + (size_t)t2 * n1() + t1) * 5]);
     }
 
-    void face_rhs(const FaceCtx& c, int j, int y, int z, double* dU) const {
+    // the transverse terms at layer j of row (t1, t2) of face s from the current state
+    void transverse_probe(int s, int j, int t1, int t2, double* Tv) const {
+        std::vector<double> Y0;
+        layers_of(s, U, Y0);
+        FaceCtx c;
+        c.s = s; c.Y = &Y0; c.Y0 = &Y0; c.Un = &U; c.V = nullptr; c.theta = 0.0;
+        transverse(c, j, t1, t2, Tv);
+    }
+
+    void face_rhs(const FaceCtx& c, int j, int t1, int t2, double* dU) const {
         const int s = c.s, b = bc[s];
-        auto lv = [&](int k, int yy, int zz, double* l) { double g[5]; face_value(c, k, yy, zz, g); to_local(s, g, l); };
+        auto lv = [&](int k, int u1, int u2, double* l) { double g[5]; face_value(c, k, u1, u2, g); to_local(s, g, l); };
         double l0[5], dn[5];
-        lv(j, y, z, l0);
+        lv(j, t1, t2, l0);
         if (j == M) {
-            double a[5], bb[5], cc[5]; lv(M, y, z, a); lv(M - 1, y, z, bb); lv(M - 2, y, z, cc);
+            double a[5], bb[5], cc[5]; lv(M, t1, t2, a); lv(M - 1, t1, t2, bb); lv(M - 2, t1, t2, cc);
             for (int m = 0; m < 5; ++m) dn[m] = 0.5 * (3.0 * a[m] - 4.0 * bb[m] + cc[m]);
         } else {
-            double a[5], cc[5]; lv(j + 1, y, z, a); lv(j - 1, y, z, cc);
+            double a[5], cc[5]; lv(j + 1, t1, t2, a); lv(j - 1, t1, t2, cc);
             for (int m = 0; m < 5; ++m) dn[m] = 0.5 * (a[m] - cc[m]);
         }
         const double cs2 = L.cs2;
         const double rho = l0[0], T = l0[4];
         double Tv[5];
-        transverse(c, j, y, z, Tv);
+        transverse(c, j, t1, t2, Tv);
+        const size_t r = (size_t)w2(t2) * n1() + w1(t1);
         double Vv[5] = {0, 0, 0, 0, 0};
-        if (full3(b)) for (int m = 0; m < 5; ++m) Vv[m] = (*c.V)[((size_t)wz(z) * ny + wy(y)) * 5 + m];
+        if (full3(b)) for (int m = 0; m < 5; ++m) Vv[m] = (*c.V)[r * 5 + m];
         Char5 cs = char_system3(cs2, l0);
         double u0g[5], l00[5];
-        for (int m = 0; m < 5; ++m) u0g[m] = (*c.Y0)[((size_t)(j - 1) * ny * nz + (size_t)wz(z) * ny + wy(y)) * 5 + m];
+        for (int m = 0; m < 5; ++m) u0g[m] = (*c.Y0)[((size_t)(j - 1) * n1() * n2() + r) * 5 + m];
         to_local(s, u0g, l00);
         Char5 cs0 = char_system3(cs2, l00);
         double Sd[5], ST[5], SV[5];
@@ -460,14 +492,12 @@ struct Sim3 {
     }
 
     void face_solve(int s, std::vector<double>& Un) {
-        const size_t R = (size_t)ny * nz, nY = (size_t)M * R * 5;
-        std::vector<double> Y0(nY), Ys(nY), Kk(nY, 0.0), acc(nY), V((size_t)R * 5, 0.0);
-        for (int j = 1; j <= M; ++j)
-            for (int z = 0; z < nz; ++z)
-                for (int y = 0; y < ny; ++y) getU(U, xk(s, j), y, z, &Y0[((size_t)(j - 1) * R + (size_t)z * ny + y) * 5]);
+        const size_t R = (size_t)n1() * n2(), nY = (size_t)M * R * 5;
+        std::vector<double> Y0, Ys(nY), Kk(nY, 0.0), acc(nY), V((size_t)R * 5, 0.0);
+        layers_of(s, U, Y0);
         if (full3(bc[s]))
-            for (int z = 0; z < nz; ++z)
-                for (int y = 0; y < ny; ++y) visc_row(sn(s), xf(s) - sn(s) * M, y, z, &V[((size_t)z * ny + y) * 5]);
+            for (int t2 = 0; t2 < n2(); ++t2)
+                for (int t1 = 0; t1 < n1(); ++t1) visc_row(sn(s), xf(s) - sn(s) * M, t1, t2, &V[((size_t)t2 * n1() + t1) * 5]);
         FaceCtx c;
         c.s = s; c.Y0 = &Y0; c.Un = &Un; c.V = &V;
         const double a_st[4] = {0.0, 0.5, 0.5, 1.0}, b_st[4] = {1.0, 2.0, 2.0, 1.0};
@@ -477,29 +507,35 @@ struct Sim3 {
             c.Y = &Ys; c.theta = a_st[st];
             std::vector<double> Kn(nY);
             for (int j = 1; j <= M; ++j)
-                for (int z = 0; z < nz; ++z)
-                    for (int y = 0; y < ny; ++y) face_rhs(c, j, y, z, &Kn[((size_t)(j - 1) * R + (size_t)z * ny + y) * 5]);
+                for (int t2 = 0; t2 < n2(); ++t2)
+                    for (int t1 = 0; t1 < n1(); ++t1)
+                        face_rhs(c, j, t1, t2, &Kn[((size_t)(j - 1) * R + (size_t)t2 * n1() + t1) * 5]);
             Kk = Kn;
             for (size_t k = 0; k < nY; ++k) acc[k] += (b_st[st] / 6.0) * Kk[k];
         }
         for (int j = 1; j <= M; ++j)
-            for (int z = 0; z < nz; ++z)
-                for (int y = 0; y < ny; ++y) setU(Un, xk(s, j), y, z, &acc[((size_t)(j - 1) * R + (size_t)z * ny + y) * 5]);
+            for (int t2 = 0; t2 < n2(); ++t2)
+                for (int t1 = 0; t1 < n1(); ++t1)
+                    setU(Un, fid(xk(s, j), t1, t2), &acc[((size_t)(j - 1) * R + (size_t)t2 * n1() + t1) * 5]);
     }
 
     void step() {
         const size_t P = plane();
         std::vector<double> fs(f.size(), 0.0), fc(f.size(), 0.0), Un(U.size(), 0.0);
-        // 1. streaming on bulk nodes (periodic in y, z and, if so configured, x)
+        bool per[3] = {true, true, true};
+        per[ax] = fper;
+        // 1. streaming on bulk nodes (periodic along the tangential axes and, without faces, along
+        // the normal one)
 #pragma omp parallel for schedule(static)
         for (int z = 0; z < nz; ++z)
             for (int y = 0; y < ny; ++y)
                 for (int x = 0; x < nx; ++x) {
-                    if (!is_bulk(x)) continue;
+                    if (!is_bulk(x, y, z)) continue;
                     for (int i = 0; i < q; ++i) {
-                        int xs = x - L.cx[i];
-                        if (xper) xs = ((xs % nx) + nx) % nx;
-                        fs[i * P + id(x, y, z)] = f[i * P + id(xs, wy(y - L.cy[i]), wz(z - L.cz[i]))];
+                        int src[3] = {x - L.cx[i], y - L.cy[i], z - L.cz[i]};
+                        for (int d = 0; d < 3; ++d)
+                            if (per[d]) src[d] = ((src[d] % dim[d]) + dim[d]) % dim[d];
+                        fs[i * P + id(x, y, z)] = f[i * P + id(src[0], src[1], src[2])];
                     }
                 }
         // 2./3. moments and BGK collision on bulk nodes
@@ -510,43 +546,45 @@ struct Sim3 {
             for (int z = 0; z < nz; ++z)
                 for (int y = 0; y < ny; ++y)
                     for (int x = 0; x < nx; ++x) {
-                        if (!is_bulk(x)) continue;
-                        for (int i = 0; i < q; ++i) fl[i] = fs[i * P + id(x, y, z)];
+                        if (!is_bulk(x, y, z)) continue;
+                        const size_t k = id(x, y, z);
+                        for (int i = 0; i < q; ++i) fl[i] = fs[i * P + k];
                         double u5[5];
                         moments3(L, fl.data(), u5);
-                        setU(Un, x, y, z, u5);
+                        setU(Un, k, u5);
                         equilibrium3(L, u5[0], u5[1], u5[2], u5[3], u5[4], fe.data());
-                        for (int i = 0; i < q; ++i) fc[i * P + id(x, y, z)] = fl[i] - (fl[i] - fe[i]) / tau;
+                        for (int i = 0; i < q; ++i) fc[i * P + k] = fl[i] - (fl[i] - fe[i]) / tau;
                     }
         }
-        // 4. characteristic solve on each x-face
+        // 4. characteristic solve on each face
         for (int s = 0; s < 2; ++s)
             if (char3(bc[s])) face_solve(s, Un);
         // 5. reconstruction of the layers
         for (int s = 0; s < 2; ++s) {
             if (bc[s] == B3_PERIODIC) continue;
-            for (int z = 0; z < nz; ++z)
-                for (int y = 0; y < ny; ++y)
+            for (int t2 = 0; t2 < n2(); ++t2)
+                for (int t1 = 0; t1 < n1(); ++t1)
                     for (int j = 1; j <= M; ++j) {
-                        const int x = xk(s, j), xff = xf(s);
+                        const size_t k = fid(xk(s, j), t1, t2), kf = fid(xf(s), t1, t2);
                         if (bc[s] == B3_ZG) {
-                            for (int i = 0; i < q; ++i) fc[i * P + id(x, y, z)] = fc[i * P + id(xff, y, z)];
-                            double u5[5]; node_moments(fc, x, y, z, u5); setU(Un, x, y, z, u5);
+                            for (int i = 0; i < q; ++i) fc[i * P + k] = fc[i * P + kf];
+                            double u5[5]; node_moments(fc, k, u5); setU(Un, k, u5);
                             continue;
                         }
-                        double u5[5]; getU(Un, x, y, z, u5); node_feq(fc, x, y, z, u5);
+                        double u5[5]; getU(Un, k, u5); node_feq(fc, k, u5);
                         if (meso[s] == 1) {   // eq. NEEP, post-collision non-equilibrium part of x_f
-                            double uf[5]; getU(Un, xff, y, z, uf);
+                            double uf[5]; getU(Un, kf, uf);
                             std::vector<double> fe(q);
                             equilibrium3(L, uf[0], uf[1], uf[2], uf[3], uf[4], fe.data());
-                            for (int i = 0; i < q; ++i) fc[i * P + id(x, y, z)] += fc[i * P + id(xff, y, z)] - fe[i];
+                            for (int i = 0; i < q; ++i) fc[i * P + k] += fc[i * P + kf] - fe[i];
                         }
                     }
         }
         // pre-collision populations of the new time level (viscous terms of the next step)
         for (size_t k = 0; k < fs.size(); ++k) {
-            const int x = (int)((k % P) % nx);
-            fpre[k] = is_bulk(x) ? fs[k] : fc[k];
+            const size_t nd = k % P;
+            const int x = (int)(nd % nx), y = (int)((nd / nx) % ny), z = (int)(nd / ((size_t)nx * ny));
+            fpre[k] = is_bulk(x, y, z) ? fs[k] : fc[k];
         }
         f.swap(fc);
         U.swap(Un);
@@ -560,16 +598,16 @@ struct Sim3 {
         for (int z = 0; z < nz; ++z)
             for (int y = 0; y < ny; ++y)
                 for (int x = 0; x < nx; ++x) {
-                    double r = 0, ax = 0, ay = 0, az = 0, en = 0;
+                    double r = 0, ax_ = 0, ay = 0, az = 0, en = 0;
                     for (int i = 0; i < q; ++i) {
                         const double fi = f[i * plane() + id(x, y, z)];
                         if (!std::isfinite(fi)) bad += 1;
-                        r += fi; ax += fi * L.cx[i]; ay += fi * L.cy[i]; az += fi * L.cz[i];
+                        r += fi; ax_ += fi * L.cx[i]; ay += fi * L.cy[i]; az += fi * L.cz[i];
                         en += 0.5 * fi * (L.cx[i] * L.cx[i] + L.cy[i] * L.cy[i] + L.cz[i] * L.cz[i]);
                     }
-                    m += r; jx += ax; jy += ay; jz += az; e += en;
-                    umax = std::max(umax, std::sqrt(ax * ax + ay * ay + az * az) / r);
-                    if (is_bulk(x)) {
+                    m += r; jx += ax_; jy += ay; jz += az; e += en;
+                    umax = std::max(umax, std::sqrt(ax_ * ax_ + ay * ay + az * az) / r);
+                    if (is_bulk(x, y, z)) {
                         const double p = L.cs2 * U[id(x, y, z)] * U[4 * plane() + id(x, y, z)] - L.cs2;
                         loss += p * p;
                     }
@@ -622,18 +660,28 @@ int oracle3d_char_matrices(int stencil, const double* U, double* A, double* S, d
     return 0;
 }
 
-void* oracle3d_create(int stencil, int nx, int ny, int nz, double tau, const int* bc) {
+// Faces normal to axis `axis` (0 = x, 1 = y, 2 = z) at its two ends; the other two axes periodic.
+void* oracle3d_create_axis(int stencil, int nx, int ny, int nz, double tau, const int* bc, int axis) {
     const Lattice3& L = lattice3(stencil);
     if (L.q == 0) { g_err3 = "stencil must be 39"; return nullptr; }
     if (!(tau > 0.5)) { g_err3 = "tau must exceed 1/2"; return nullptr; }
+    if (axis < 0 || axis > 2) { g_err3 = "axis must be 0, 1 or 2"; return nullptr; }
     for (int s = 0; s < 2; ++s)
         if (bc[s] < B3_PERIODIC || bc[s] > B3_ZG) { g_err3 = "unknown boundary type"; return nullptr; }
-    if ((bc[0] == B3_PERIODIC) != (bc[1] == B3_PERIODIC)) { g_err3 = "periodic x-faces come in pairs"; return nullptr; }
-    const bool xp = bc[0] == B3_PERIODIC;
-    if (nx < (xp ? L.M + 1 : 2 * L.M + 3) || ny < L.M + 1 || nz < L.M + 1) { g_err3 = "grid too small"; return nullptr; }
+    if ((bc[0] == B3_PERIODIC) != (bc[1] == B3_PERIODIC)) { g_err3 = "periodic faces come in pairs"; return nullptr; }
+    const bool fp = bc[0] == B3_PERIODIC;
+    const int d[3] = {nx, ny, nz};
+    for (int a = 0; a < 3; ++a) {
+        const int need = (a == axis && !fp) ? 2 * L.M + 3 : L.M + 1;
+        if (d[a] < need) { g_err3 = "grid too small"; return nullptr; }
+    }
     // the viscous terms of a CBC face are evaluated at x_f - M .. x_f - M - 2 (bulk nodes)
-    if ((full3(bc[0]) || full3(bc[1])) && nx < 3 * L.M + 3) { g_err3 = "CBC faces need nx >= 3M + 3"; return nullptr; }
-    return new Sim3(L, nx, ny, nz, tau, bc);
+    if ((full3(bc[0]) || full3(bc[1])) && d[axis] < 3 * L.M + 3) { g_err3 = "CBC faces need 3M + 3 nodes across"; return nullptr; }
+    return new Sim3(L, nx, ny, nz, tau, bc, axis);
+}
+
+void* oracle3d_create(int stencil, int nx, int ny, int nz, double tau, const int* bc) {
+    return oracle3d_create_axis(stencil, nx, ny, nz, tau, bc, 0);
 }
 
 void oracle3d_destroy(void* h) { delete static_cast<Sim3*>(h); }
@@ -686,25 +734,26 @@ int oracle3d_diag(void* h, double* out8) {
     return 0;
 }
 
-// V (local frame of outward normal g x, g = +-1) at bulk node (x, y, z) at the current time,
-// as the CBC faces evaluate it at x_f; x, x - g, x - 2 g must be bulk nodes
-// transverse terms (local components) at layer j (1..M) of row (y, z) of x-face `side`
-int oracle3d_transverse_probe(void* h, int side, int j, int y, int z, double* out5) {
+// transverse terms (local components) at layer j (1..M) of row (t1, t2) of face `side` (t1, t2:
+// coordinates along the axes following the normal, e.g. y and z for x-faces)
+int oracle3d_transverse_probe(void* h, int side, int j, int t1, int t2, double* out5) {
     auto* s = static_cast<Sim3*>(h);
     if (side < 0 || side > 1 || s->bc[side] == B3_PERIODIC || j < 1 || j > s->M) return -1;
-    if (y < 0 || y >= s->ny || z < 0 || z >= s->nz) return -1;
-    s->transverse_probe(side, j, y, z, out5);
+    if (t1 < 0 || t1 >= s->n1() || t2 < 0 || t2 >= s->n2()) return -1;
+    s->transverse_probe(side, j, t1, t2, out5);
     return 0;
 }
 
-int oracle3d_visc_probe(void* h, int g, int x, int y, int z, double* out5) {
+// V (local frame of outward normal g e_axis, g = +-1) at bulk node (kn, t1, t2) at the current
+// time, as a face evaluates it at x_f - sn M; kn, kn - g, kn - 2 g must be bulk nodes
+int oracle3d_visc_probe(void* h, int g, int kn, int t1, int t2, double* out5) {
     auto* s = static_cast<Sim3*>(h);
-    if ((g != 1 && g != -1) || y < 0 || y >= s->ny || z < 0 || z >= s->nz) return -1;
+    if ((g != 1 && g != -1) || t1 < 0 || t1 >= s->n1() || t2 < 0 || t2 >= s->n2()) return -1;
     for (int k = 0; k < 3; ++k) {
-        const int xx = x - g * k;
-        if (xx < 0 || xx >= s->nx || !s->is_bulk(xx)) return -1;
+        const int kk = kn - g * k;
+        if (kk < 0 || kk >= s->nn() || !s->is_bulk_n(kk)) return -1;
     }
-    s->visc_row(g, x, y, z, out5);
+    s->visc_row(g, kn, t1, t2, out5);
     return 0;
 }
 

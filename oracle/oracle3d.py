@@ -32,6 +32,9 @@ def lib():
         L.oracle3d_char_matrices.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, _dp]
         L.oracle3d_create.restype = ctypes.c_void_p
         L.oracle3d_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, _ip]
+        L.oracle3d_create_axis.restype = ctypes.c_void_p
+        L.oracle3d_create_axis.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, _ip,
+                                           ctypes.c_int]
         L.oracle3d_destroy.argtypes = [ctypes.c_void_p]
         L.oracle3d_set_relax.argtypes = [ctypes.c_void_p, ctypes.c_int] + [ctypes.c_double] * 6
         L.oracle3d_set_recon.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
@@ -79,12 +82,13 @@ def char_matrices(U, stencil=39):
 
 
 class Oracle3D:
-    """One 3D simulation: D3Q39, periodic in y and z, bc = [x0 face, x1 face]."""
+    """One 3D simulation: D3Q39, bc = [low face, high face] of the axis `axis` (0 = x, 1 = y,
+    2 = z), periodic along the other two axes."""
 
-    def __init__(self, nx, ny, nz, tau, bc, stencil=39):
-        self.nx, self.ny, self.nz, self.tau = nx, ny, nz, tau
+    def __init__(self, nx, ny, nz, tau, bc, stencil=39, axis=0):
+        self.nx, self.ny, self.nz, self.tau, self.axis = nx, ny, nz, tau, axis
         codes = (ctypes.c_int * 2)(*[BC[b] for b in bc])
-        h = lib().oracle3d_create(stencil, nx, ny, nz, tau, codes)
+        h = lib().oracle3d_create_axis(stencil, nx, ny, nz, tau, codes, axis)
         if not h:
             raise ValueError(lib().oracle3d_last_error().decode())
         self.h = h
@@ -126,14 +130,16 @@ class Oracle3D:
         return out
 
     def transverse_probe(self, side, j, y, z):
-        """Transverse terms (local components) at layer j of row (y, z) of an x-face, current state."""
+        """Transverse terms (local components) at layer j of row (t1, t2) = (y, z) of a face (for
+        faces normal to y: (z, x); to z: (x, y)), current state."""
         out = np.zeros(5)
         if lib().oracle3d_transverse_probe(self.h, side, j, y, z, _ptr(out)) != 0:
             raise ValueError("bad probe")
         return out
 
     def visc_probe(self, g, x, y, z):
-        """V (local frame of the outward normal g e_x) at bulk node (x, y, z), as a face at x_f = x."""
+        """V (local frame of the outward normal g e_axis) at bulk node (x, y, z) = (normal, t1, t2)
+        coordinates, as a face evaluates it there."""
         out = np.zeros(5)
         if lib().oracle3d_visc_probe(self.h, g, x, y, z, _ptr(out)) != 0:
             raise ValueError("bad probe")

@@ -43,6 +43,18 @@ struct Args3 {
     Face3 f[2];
 };
 
+// Caller arrays [nz][ny][nx] (x fastest) indexed from the library's internal grid, whose x axis is
+// the axis normal to the faces: the caller's linear index of internal node (x, y, z) is
+// x s[0] + y s[1] + z s[2]; with faces normal to x, s = (1, nx, nx ny).
+struct UStride3 {
+    long long s[3];
+};
+
+// library velocity index of each velocity of the caller's frame (populations output)
+struct VMap3 {
+    int i[39];
+};
+
 __device__ __forceinline__ int wrap3(int v, int n) {
     v = v < 0 ? v + n : v;
     return v >= n ? v - n : v;
@@ -141,14 +153,15 @@ template <typename T>
 __global__ __launch_bounds__(256) void k3_init(const double* __restrict__ rho, const double* __restrict__ ux,
                                                const double* __restrict__ uy, const double* __restrict__ uz,
                                                const double* __restrict__ Tf, T* __restrict__ A, T* __restrict__ B,
-                                               int nx, int ny, long long n, unsigned long long pitch) {
+                                               int nx, int ny, long long n, unsigned long long pitch, UStride3 us) {
     const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
     if (id >= n) return;
     const int x = (int)(id % nx);
     const long long r = id / nx;
     const int y = (int)(r % ny), z = (int)(r / ny);
+    const long long u = x * us.s[0] + y * us.s[1] + z * us.s[2];
     double fe[L3::Q];
-    feq3_dev<double>(rho[id] - 1.0, ux[id], uy[id], uz[id], Tf[id] - 1.0, fe);
+    feq3_dev<double>(rho[u] - 1.0, ux[u], uy[u], uz[u], Tf[u] - 1.0, fe);
 #pragma unroll
     for (int i = 0; i < L3::Q; ++i) {
         A[pix3(pitch, ny, i, x, y, z)] = (T)fe[i];
@@ -166,14 +179,14 @@ __device__ __forceinline__ size_t ivis(int rows, int k, int c, int r) { return (
 // viscous stress and no heat flux
 __global__ __launch_bounds__(256) void k3_init_faces(Args3 a, const double* __restrict__ rho, const double* __restrict__ ux,
                                                      const double* __restrict__ uy, const double* __restrict__ uz,
-                                                     const double* __restrict__ Tf) {
+                                                     const double* __restrict__ Tf, UStride3 us) {
     const int s = blockIdx.y;
     const Face3& fc = a.f[s];
     const int r = blockIdx.x * 256 + threadIdx.x;
     if (!is_char3(fc.scheme) || r >= a.rows) return;
     const int y = r % a.ny, z = r / a.ny;
     auto field = [&](int x, double* u5) {
-        const size_t id = ((size_t)z * a.ny + y) * a.nx + x;
+        const long long id = x * us.s[0] + y * us.s[1] + z * us.s[2];
         u5[0] = rho[id]; u5[1] = ux[id]; u5[2] = uy[id]; u5[3] = uz[id]; u5[4] = Tf[id];
     };
     for (int p = 0; p < 2; ++p) {
@@ -455,7 +468,7 @@ __global__ __launch_bounds__(256) void k3_final(const T* __restrict__ A, T* __re
 template <typename T>
 __global__ __launch_bounds__(256) void k3_macro(const T* __restrict__ A, int nx, int ny, long long n, unsigned long long pitch,
                                                 double* __restrict__ rho, double* __restrict__ ux, double* __restrict__ uy,
-                                                double* __restrict__ uz, double* __restrict__ Tf) {
+                                                double* __restrict__ uz, double* __restrict__ Tf, UStride3 us) {
     const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
     if (id >= n) return;
     const int x = (int)(id % nx);
@@ -466,20 +479,26 @@ __global__ __launch_bounds__(256) void k3_macro(const T* __restrict__ A, int nx,
     for (int i = 0; i < L3::Q; ++i) d[i] = (double)A[pix3(pitch, ny, i, x, y, z)];
     double rm1, u, v, w, th;
     moments3_dev<double>(d, rm1, u, v, w, th);
-    rho[id] = 1.0 + rm1; ux[id] = u; uy[id] = v; uz[id] = w; Tf[id] = 1.0 + th;
+    const long long o = x * us.s[0] + y * us.s[1] + z * us.s[2];
+    rho[o] = 1.0 + rm1; ux[o] = u; uy[o] = v; uz[o] = w; Tf[o] = 1.0 + th;
 }
 
-// full populations f = w_i + d_i in library order, FP64 [q][nz][ny][nx]
+// full populations f = w_i + d_i, FP64 [q][nz][ny][nx] in the caller's frame: plane j holds the
+// library velocity vm.i[j] of the internal grid (the same velocity as j, axes permuted)
 template <typename T>
 __global__ __launch_bounds__(256) void k3_pops(const T* __restrict__ A, int nx, int ny, long long n, unsigned long long pitch,
-                                               double* __restrict__ out) {
+                                               double* __restrict__ out, UStride3 us, VMap3 vm) {
     const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
     if (id >= n) return;
     const int x = (int)(id % nx);
     const long long rr = id / nx;
     const int y = (int)(rr % ny), z = (int)(rr / ny);
+    const long long o = x * us.s[0] + y * us.s[1] + z * us.s[2];
 #pragma unroll
-    for (int i = 0; i < L3::Q; ++i) out[(long long)i * n + id] = wt3(i) + (double)A[pix3(pitch, ny, i, x, y, z)];
+    for (int j = 0; j < L3::Q; ++j) {
+        const int i = vm.i[j];
+        out[(long long)j * n + o] = wt3(i) + (double)A[pix3(pitch, ny, i, x, y, z)];
+    }
 }
 
 __device__ __forceinline__ double wsum3(double v) {

@@ -33,8 +33,21 @@ struct Layout3 {
     Face3 f[2];
 };
 
-int validate3(const lbm3d_config* c, std::string& err) {
-    if (!c) { err = "null config"; return LBM_E_ARG; }
+// the configuration on the library's internal grid: the face axis becomes x, the two axes that
+// follow it cyclically become y and z
+lbm3d_config internal3(const lbm3d_config* u) {
+    lbm3d_config c = *u;
+    const int d[3] = {u->nx, u->ny, u->nz}, a = u->axis;
+    c.nx = d[a]; c.ny = d[(a + 1) % 3]; c.nz = d[(a + 2) % 3];
+    c.axis = 0;
+    return c;
+}
+
+int validate3(const lbm3d_config* u, std::string& err) {
+    if (!u) { err = "null config"; return LBM_E_ARG; }
+    if (u->axis < 0 || u->axis > 2) { err = "axis must be 0 (x), 1 (y) or 2 (z)"; return LBM_E_ARG; }
+    const lbm3d_config ic = internal3(u);
+    const lbm3d_config* c = &ic;
     if (c->stencil != LBM_D3Q39) { err = "stencil must be LBM_D3Q39"; return LBM_E_ARG; }
     if (c->precision != LBM_FP64 && c->precision != LBM_FP32DEV) { err = "unknown precision"; return LBM_E_ARG; }
     if (!(c->tau > 0.5) || !std::isfinite(c->tau)) { err = "tau must be a finite value above 1/2"; return LBM_E_ARG; }
@@ -48,7 +61,7 @@ int validate3(const lbm3d_config* c, std::string& err) {
     if (c->nx < (xp ? L3::M + 1 : 2 * L3::M + 3) || c->ny < L3::M + 1 || c->nz < L3::M + 1) { err = "grid too small"; return LBM_E_ARG; }
     // the viscous terms of a CBC face are evaluated at x_f - M .. x_f - M - 2, which must be bulk nodes
     if ((c->bc[0] == LBM_BC_CBC || c->bc[0] == LBM_BC_CBC_RELAX || c->bc[1] == LBM_BC_CBC || c->bc[1] == LBM_BC_CBC_RELAX) &&
-        c->nx < 3 * L3::M + 3) { err = "CBC faces need nx >= 3M + 3"; return LBM_E_ARG; }
+        c->nx < 3 * L3::M + 3) { err = "CBC faces need 3M + 3 nodes across"; return LBM_E_ARG; }
     const double n = (double)c->nx * (double)c->ny * (double)c->nz;
     if (n > 2.0e9) { err = "grid too large"; return LBM_E_ARG; }
     const unsigned long long bpr = ((unsigned long long)c->nx + 255) / 256;
@@ -91,7 +104,10 @@ void make_layout3(const lbm3d_config* c, Layout3& L) {
 }  // namespace
 
 struct lbm3d_ctx {
-    lbm3d_config cfg;
+    lbm3d_config cfg;              // on the internal grid (faces normal to its x axis)
+    int axis = 0;                  // the caller's face axis
+    UStride3 us;                   // caller index of internal nodes
+    VMap3 vm;                      // library velocity of each caller-frame velocity
     Layout3 L;
     char* ws = nullptr;
     void* f[2] = {nullptr, nullptr};
@@ -226,8 +242,9 @@ extern "C" {
 size_t lbm3d_workspace_bytes(const lbm3d_config* cfg) {
     std::string err;
     if (validate3(cfg, err) != LBM_OK) { g_err3 = err; return 0; }
+    const lbm3d_config ic = internal3(cfg);
     Layout3 L;
-    make_layout3(cfg, L);
+    make_layout3(&ic, L);
     return L.total;
 }
 
@@ -243,8 +260,26 @@ int lbm3d_init(const lbm3d_config* cfg, void* d_workspace, size_t workspace_byte
     if (!d_rho0 || !d_ux0 || !d_uy0 || !d_uz0 || !d_T0) return fail3(nullptr, LBM_E_ARG, "initial field pointer is NULL");
     lbm3d_ctx* c = new (std::nothrow) lbm3d_ctx();
     if (!c) return fail3(nullptr, LBM_E_ARG, "out of host memory");
-    c->cfg = *cfg;
-    make_layout3(cfg, c->L);
+    c->cfg = internal3(cfg);
+    c->axis = cfg->axis;
+    {
+        const long long ustr[3] = {1, cfg->nx, (long long)cfg->nx * cfg->ny};
+        for (int k = 0; k < 3; ++k) c->us.s[k] = ustr[(c->axis + k) % 3];
+        // caller-frame velocity j = (c_x, c_y, c_z) is the internal velocity with components
+        // (c[axis], c[axis + 1], c[axis + 2])
+        for (int j = 0; j < L3::Q; ++j) {
+            const int cu[3] = {cx3(j), cy3(j), cz3(j)};
+            const int ci[3] = {cu[c->axis], cu[(c->axis + 1) % 3], cu[(c->axis + 2) % 3]};
+            c->vm.i[j] = -1;
+            for (int i = 0; i < L3::Q; ++i)
+                if (cx3(i) == ci[0] && cy3(i) == ci[1] && cz3(i) == ci[2]) c->vm.i[j] = i;
+            if (c->vm.i[j] < 0) {   // the velocity set is closed under axis permutations
+                delete c;
+                return fail3(nullptr, LBM_E_UNSUPPORTED, "velocity set not closed under the axis permutation");
+            }
+        }
+    }
+    make_layout3(&c->cfg, c->L);
     if (workspace_bytes < c->L.total) {
         delete c;
         return fail3(nullptr, LBM_E_ARG, "workspace smaller than lbm3d_workspace_bytes(cfg)");
@@ -258,13 +293,18 @@ int lbm3d_init(const lbm3d_config* cfg, void* d_workspace, size_t workspace_byte
     c->stream = (hipStream_t)hip_stream;
     for (int s = 0; s < 2; ++s) c->relax[s] = lbm_relax{0.0, 0.0, 1.0, 1.0, 0.0, 0.0};
     const long long n = (long long)cfg->nx * cfg->ny * cfg->nz;
+    // velocity components on the internal axes
+    const double* uin[3] = {d_ux0, d_uy0, d_uz0};
+    const double* u0 = uin[c->axis];
+    const double* u1 = uin[(c->axis + 1) % 3];
+    const double* u2 = uin[(c->axis + 2) % 3];
     const int rc = dispatch3(c, [&]<typename T>() -> int {
-        hipLaunchKernelGGL((k3_init<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, d_rho0, d_ux0, d_uy0,
-                           d_uz0, d_T0, (T*)c->f[0], (T*)c->f[1], cfg->nx, cfg->ny, n, c->L.pitch);
+        hipLaunchKernelGGL((k3_init<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, d_rho0, u0, u1, u2,
+                           d_T0, (T*)c->f[0], (T*)c->f[1], c->cfg.nx, c->cfg.ny, n, c->L.pitch, c->us);
         HIPCHK3(c, hipGetLastError());
         const Args3 a = make_args3(c);
-        hipLaunchKernelGGL(k3_init_faces, dim3((c->L.rows + 255) / 256, 2), dim3(256), 0, c->stream, a, d_rho0, d_ux0,
-                           d_uy0, d_uz0, d_T0);
+        hipLaunchKernelGGL(k3_init_faces, dim3((c->L.rows + 255) / 256, 2), dim3(256), 0, c->stream, a, d_rho0, u0, u1, u2,
+                           d_T0, c->us);
         HIPCHK3(c, hipGetLastError());
         return LBM_OK;
     });
@@ -319,9 +359,11 @@ int lbm3d_macroscopic(lbm3d_ctx* c, double* rho, double* ux, double* uy, double*
     if (!c) return fail3(nullptr, LBM_E_ARG, "null context");
     if (!rho || !ux || !uy || !uz || !Tf) return fail3(c, LBM_E_ARG, "output pointer is NULL");
     const long long n = (long long)c->cfg.nx * c->cfg.ny * c->cfg.nz;
+    double* uo[3] = {ux, uy, uz};
     return dispatch3(c, [&]<typename T>() -> int {
         hipLaunchKernelGGL((k3_macro<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, (const T*)c->f[c->cur],
-                           c->cfg.nx, c->cfg.ny, n, c->L.pitch, rho, ux, uy, uz, Tf);
+                           c->cfg.nx, c->cfg.ny, n, c->L.pitch, rho, uo[c->axis], uo[(c->axis + 1) % 3],
+                           uo[(c->axis + 2) % 3], Tf, c->us);
         HIPCHK3(c, hipGetLastError());
         return LBM_OK;
     });
@@ -333,7 +375,7 @@ int lbm3d_populations(lbm3d_ctx* c, double* d_out) {
     const long long n = (long long)c->cfg.nx * c->cfg.ny * c->cfg.nz;
     return dispatch3(c, [&]<typename T>() -> int {
         hipLaunchKernelGGL((k3_pops<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, (const T*)c->f[c->cur],
-                           c->cfg.nx, c->cfg.ny, n, c->L.pitch, d_out);
+                           c->cfg.nx, c->cfg.ny, n, c->L.pitch, d_out, c->us, c->vm);
         HIPCHK3(c, hipGetLastError());
         return LBM_OK;
     });
@@ -357,6 +399,9 @@ int lbm3d_diagnostics(lbm3d_ctx* c, double* h_out) {
     double out[8];
     HIPCHK3(c, hipMemcpyAsync(out, c->diag + (size_t)nb * 8, sizeof(out), hipMemcpyDeviceToHost, c->stream));
     HIPCHK3(c, hipStreamSynchronize(c->stream));
+    // momentum components of the internal axes to the caller's
+    const double j[3] = {out[1], out[2], out[3]};
+    for (int k = 0; k < 3; ++k) out[1 + (c->axis + k) % 3] = j[k];
     std::memcpy(h_out, out, sizeof(out));
     if (out[7] > 0) return fail3(c, LBM_E_NONFINITE, "non-finite populations");
     return LBM_OK;

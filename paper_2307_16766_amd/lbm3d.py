@@ -22,7 +22,7 @@ _ready = False
 
 class Config3(ctypes.Structure):
     _fields_ = [("stencil", ctypes.c_int), ("precision", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
-                ("nz", ctypes.c_int), ("tau", ctypes.c_double), ("bc", ctypes.c_int * 2)]
+                ("nz", ctypes.c_int), ("tau", ctypes.c_double), ("bc", ctypes.c_int * 2), ("axis", ctypes.c_int)]
 
 
 def load():
@@ -63,20 +63,21 @@ def lattice_info(stencil=D3Q39):
     return cs2.value, np.array(w[:q]), np.array(c[0][:q]), np.array(c[1][:q]), np.array(c[2][:q]), M.value
 
 
-def make_config(nx, ny, nz, tau, bc, precision="fp64", stencil=D3Q39):
+def make_config(nx, ny, nz, tau, bc, precision="fp64", stencil=D3Q39, axis=0):
     codes = [BC3[b] if isinstance(b, str) else int(b) for b in bc]
     prec = _lbm.PRECISION[precision] if isinstance(precision, str) else int(precision)
-    return Config3(stencil, prec, nx, ny, nz, tau, (ctypes.c_int * 2)(*codes))
+    return Config3(stencil, prec, nx, ny, nz, tau, (ctypes.c_int * 2)(*codes), axis)
 
 
 class LBM3D:
-    """One 3D simulation on the current HIP device: bc = [face x = 0, face x = nx - 1]."""
+    """One 3D simulation on the current HIP device: bc = [low face, high face] of the face axis
+    `axis` (0 = x, 1 = y, 2 = z); the other two axes are periodic."""
 
-    def __init__(self, nx, ny, nz, tau, bc, fields, precision="fp64", stream=None):
+    def __init__(self, nx, ny, nz, tau, bc, fields, precision="fp64", stream=None, axis=0):
         import torch
         L = load()
         self.torch = torch
-        self.cfg = make_config(nx, ny, nz, tau, bc, precision)
+        self.cfg = make_config(nx, ny, nz, tau, bc, precision, axis=axis)
         self.nx, self.ny, self.nz = nx, ny, nz
         nbytes = L.lbm3d_workspace_bytes(ctypes.byref(self.cfg))
         if nbytes == 0:

@@ -52,8 +52,16 @@ def test_3d_lattice_and_validation():
                 lbm3d.make_config(32, 8, 8, 0.9, ["periodic", "lodi"]),      # unpaired
                 lbm3d.make_config(8, 8, 8, 0.9, ["lodi", "lodi"]),           # too short in x
                 lbm3d.make_config(32, 3, 8, 0.9, ["lodi", "lodi"]),          # too thin in y
-                lbm3d.make_config(32, 8, 8, 0.9, ["lodi", 6])):              # Dirichlet not offered in 3D
+                lbm3d.make_config(32, 8, 8, 0.9, ["lodi", 6]),               # Dirichlet not offered in 3D
+                lbm3d.make_config(32, 8, 8, 0.9, ["lodi", "lodi"], axis=3),  # no such axis
+                lbm3d.make_config(32, 8, 8, 0.9, ["lodi", "lodi"], axis=1),  # 8 < 2M + 3 nodes along y
+                lbm3d.make_config(8, 32, 11, 0.9, ["cbc", "lodi"], axis=2)):  # 11 < 3M + 3 along z (CBC)
         assert L.lbm3d_workspace_bytes(ctypes.byref(bad)) == 0
+    # faces normal to y and z: the workspace of the rotated problem
+    a = L.lbm3d_workspace_bytes(ctypes.byref(lbm3d.make_config(32, 8, 6, 0.9, ["cbc", "lodi"])))
+    b = L.lbm3d_workspace_bytes(ctypes.byref(lbm3d.make_config(6, 32, 8, 0.9, ["cbc", "lodi"], axis=1)))
+    c = L.lbm3d_workspace_bytes(ctypes.byref(lbm3d.make_config(8, 6, 32, 0.9, ["cbc", "lodi"], axis=2)))
+    assert a == b == c > 0
 
 
 @pytest.mark.parametrize("stencil", [9, 17, 37])
