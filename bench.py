@@ -200,6 +200,36 @@ def run_3d(precision, steps, warmup, n=(512, 256, 256)):
             "finite": bool(d[7] == 0)}
 
 
+def run_diag_every_cost(steps=500, every=100):
+    """Cost of lbm_step's non-finite check on the throughput workload (FP32 deviation storage):
+    the same `steps` steps with and without a check every `every` steps, event-timed."""
+    import torch
+    from paper_2307_16766_amd import lbm
+    cs2 = lbm.lattice_info(Q)[0]
+    fields, prof = workload(NX, NY)
+    g = lbm.LBM(Q, NX, NY, 0.5 + 0.1 / cs2, ["dirichlet", "lodi_relax", "periodic", "periodic"], fields,
+                precision="fp32dev")
+    del fields
+    g.set_relax(1, **relax_params(cs2))
+    g.set_inlet(0, prof)
+    g.step(20)
+    out = {}
+    for n in (0, every, 0, every):
+        g.set_diag_every(n)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(g.stream)
+        g.step(steps)
+        e1.record(g.stream)
+        torch.cuda.synchronize()
+        out.setdefault(n, []).append(e0.elapsed_time(e1) / steps)
+    g.close()
+    torch.cuda.empty_cache()
+    base, chk = min(out[0]), min(out[every])
+    return {"workload": f"D2Q37 {NX}x{NY} FP32 deviation throughput run, {steps} steps",
+            "every": every, "ms_per_step_off": base, "ms_per_step_on": chk, "overhead": chk / base - 1.0}
+
+
 def run_config_gpu(name, precision, steps, warmup=20):
     """Whole-step and step-kernel MLUPS of workload C1..C4 (paper_2307_16766_amd.workloads) at its
     full size: one untimed pass of `steps` steps between two events for the step rate, then the
@@ -413,6 +443,12 @@ def main():
         eprint("[bench] D3Q39 512x256x256 (fp32dev, fp64)")
         d3 = {p: run_3d(p, 50 if p == "fp32dev" else 25, 5) for p in ("fp32dev", "fp64")}
         eprint(f"[bench] d3q39: fp32 {d3['fp32dev']['ms_per_step']:.3f} ms/step, fp64 {d3['fp64']['ms_per_step']:.3f}")
+    dchk = None
+    if not args.no_configs:
+        eprint("[bench] non-finite check every 100 steps (throughput run)")
+        dchk = run_diag_every_cost()
+        eprint(f"[bench] check every 100: {dchk['ms_per_step_on']:.4f} vs {dchk['ms_per_step_off']:.4f} ms/step "
+               f"({100 * dchk['overhead']:.2f} %)")
     cfgs = None
     if not args.no_configs:
         eprint("[bench] workloads C1..C4 at full size (GPU)")
@@ -469,6 +505,7 @@ def main():
         "d2q17": d17,
         "d3q39": d3,
         "workloads": cfgs,
+        "nonfinite_check": dchk,
         "cpu_baseline": cpu,
         "finite": r32["finite"] and (r64 is None or r64["finite"]),
     }
