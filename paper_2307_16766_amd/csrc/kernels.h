@@ -363,12 +363,12 @@ __global__ __launch_bounds__(1024) void k_diag_final(const double* __restrict__ 
 // Rate dU/dt (side-local (rho, u_n, u_t, T)) of one boundary node: wave amplitudes of
 // eq. thermal_WAV written out with T~ = cs^2 T, incoming amplitudes by scheme (Tab. CBCs), the
 // relaxation acting on the incoming acoustic wave, then -S^-1 Lbar (+ T + V for CBC variants).
-// up / dw: node values at the neighbouring rows (transverse central differences); U0: the
-// node's value at time t, which fixes the wave directions.
+// up / dw: node values at the neighbouring rows (transverse central differences); u0, s0: normal
+// velocity and sound speed of the node at time t, which fix the wave directions.
 template <int Q>
-__device__ __forceinline__ void char_rate(const double* U, const double* dn, const double* up, const double* dw,
-                                          const double* V, const double* U0, int scheme, double K, double alpha,
-                                          double Pinf, double* rate) {
+__device__ __forceinline__ void char_rate_dir(const double* U, const double* dn, const double* up, const double* dw,
+                                              const double* V, double u0, double s0, int scheme, double K,
+                                              double alpha, double Pinf, double* rate) {
     constexpr bool THERMAL = Lat<Q>::thermal;
     constexpr double cs2 = Lat<Q>::cs2;
     constexpr double cs = Lat<Q>::cs;
@@ -387,10 +387,8 @@ __device__ __forceinline__ void char_rate(const double* U, const double* dn, con
         T3 = -cs2 * ir * 0.5 * (up[0] - dw[0]) - v * 0.5 * (up[2] - dw[2]);
         T4 = 0.0;
     }
-    const double u0 = U0[1];
     if (THERMAL) {
         const double s = sqrt(2.0 * cs2 * T);
-        const double s0 = sqrt(2.0 * cs2 * U0[3]);
         const double a = 0.25 * T * ir, b = s * (0.25 / cs2);
         const double L1 = u * (-2.0 * a * dn[0] + 0.5 * dn[3]);
         const double L2 = u * dn[2];
@@ -437,13 +435,27 @@ __device__ __forceinline__ void char_rate(const double* U, const double* dn, con
             inp = pr - alpha * (cs2 * T1 + rho * c * T2);
         }
         const double B0 = u0 >= 0.0 ? L0 : 0.0;
-        const double Bm = u0 - c >= 0.0 ? Lm : inm;
-        const double Bp = u0 + c >= 0.0 ? Lp : inp;
+        const double Bm = u0 - s0 >= 0.0 ? Lm : inm;
+        const double Bp = u0 + s0 >= 0.0 ? Lp : inp;
         rate[0] = -(Bm + Bp) * (0.5 / cs2);
         rate[1] = (Bm - Bp) * (0.5 / c) * ir;
         rate[2] = -B0;
         rate[3] = 0.0;
     }
+}
+
+// sound speed that sets the wave directions at a node of side-local value U0 (time t)
+template <int Q>
+__device__ __forceinline__ double char_speed(const double* U0) {
+    return Lat<Q>::thermal ? sqrt(2.0 * Lat<Q>::cs2 * U0[3]) : Lat<Q>::cs;
+}
+
+// U0: the node's side-local value at time t
+template <int Q>
+__device__ __forceinline__ void char_rate(const double* U, const double* dn, const double* up, const double* dw,
+                                          const double* V, const double* U0, int scheme, double K, double alpha,
+                                          double Pinf, double* rate) {
+    char_rate_dir<Q>(U, dn, up, dw, V, U0[1], char_speed<Q>(U0), scheme, K, alpha, Pinf, rate);
 }
 
 __device__ __forceinline__ void to_local(const SideDev& s, const double* g, double* l) {
@@ -556,15 +568,14 @@ __device__ __forceinline__ void write_feq(T* __restrict__ B, unsigned long long 
 }
 
 // one corner: RK4 of the diagonal LODI system from the pulled populations of the two inward
-// diagonal nodes (d1, d2: time n+1) and the stored time-n values; U_c^{n+1} goes to cp_out and,
-// for the owning (x-side) work-group, to the next parity region
+// diagonal nodes (d1, d2: time n+1) and their time-n moments cdn[8]; Un: U_c at time n.  U_c^{n+1}
+// goes to cp_out and, for the owning (x-side) work-group, to the next parity region
 template <int Q, bool HIST>
-__device__ void corner_rk4(const BndArgs& a, int ci, bool owner, const double* d1, const double* d2, const double* Un,
-                           double* cp_out) {
+__device__ void corner_rk4(const BndArgs& a, int ci, bool owner, const double* d1, const double* d2, const double* cdn,
+                           const double* Un, double* cp_out) {
     const CornerDev& c = a.c[ci];
-    const double* cd = (const double*)(a.reg_cur + c.off_cd);
     double D1n[4], D2n[4], D1p[4], D2p[4];
-    for (int k = 0; k < 4; ++k) { D1n[k] = cd[k]; D2n[k] = cd[4 + k]; }
+    for (int k = 0; k < 4; ++k) { D1n[k] = cdn[k]; D2n[k] = cdn[4 + k]; }
     moments_u4<Q>(d1, D1p);
     moments_u4<Q>(d2, D2p);
     const double ast[4] = {0.0, 0.5, 0.5, 1.0}, bst[4] = {1.0, 2.0, 2.0, 1.0};
@@ -586,27 +597,49 @@ __device__ void corner_rk4(const BndArgs& a, int ci, bool owner, const double* d
     for (int m = 0; m < 4; ++m) cp_out[m] = acc[m];
     if (owner) {
         double* cun = (double*)(a.reg_next + c.off_cu);
-        double* cdn = (double*)(a.reg_next + c.off_cd);
-        for (int m = 0; m < 4; ++m) { cun[m] = acc[m]; cdn[m] = D1p[m]; cdn[4 + m] = D2p[m]; }
+        double* cdn_next = (double*)(a.reg_next + c.off_cd);
+        for (int m = 0; m < 4; ++m) { cun[m] = acc[m]; cdn_next[m] = D1p[m]; cdn_next[4 + m] = D2p[m]; }
     }
 }
 
 // ---------------------------------------------------------------- chunk of a characteristic side
-// LDS row lr <-> side row r = r0 - 4 + lr (4 halo rows: one per RK stage).  Thread t handles
-// node (lr = t / M, layer j = t % M + 1) in the RK stages.
+// LDS row lr <-> side row r = r0 - 4 + lr: CR rows, of which CR - 8 are owned, plus 4 halo rows on
+// each side (one per RK stage, so chunks need no grid-wide synchronisation).  Node threads
+// t < NN = CR M (three wavefronts) each own node (lr = t / M, layer j = t % M + 1) for the whole
+// step and keep its time-n value, stage value and RK4 sum in registers; the fourth wavefront pulls
+// the strip, runs the corner RK4 and fills the strip and corner slots of the stage buffers.  The
+// stage buffers hold every node in side-local components (rho, u_n, u_t, T), slots
+// k = -(MS - 1) .. M along the normal (strip nodes, then layers) at slot index k + MS - 1, and are
+// double-buffered, so an RK stage needs one barrier.
+template <int Q> struct ChunkShape {
+    static constexpr int M = Lat<Q>::M, MS = (M == 1) ? 2 : 1;
+    static constexpr int CR = 192 / M;      // LDS rows per work-group
+    static constexpr int NN = CR * M;       // node threads (192: three wavefronts)
+    static constexpr int S = M + MS;        // normal slots per row
+};
+
 template <int Q, typename T, bool HIST>
 __device__ void char_chunk(const T* __restrict__ A, T* __restrict__ B, const BndArgs& a, const SideDev& sd, int chunk) {
-    constexpr int M = Lat<Q>::M, NR = 256 / M, MS = (M == 1) ? 2 : 1;
+    using CS = ChunkShape<Q>;
+    constexpr int M = CS::M, MS = CS::MS, CR = CS::CR, NN = CS::NN, S = CS::S;
     constexpr bool TH = Lat<Q>::thermal;
-    __shared__ double sY0[NR * M * 4], sYs[NR * M * 4], sK[NR * M * 4], sAcc[NR * M * 4];
-    __shared__ double sBn[NR * MS * 4], sBp[NR * MS * 4], sV[NR * 4];
-    __shared__ double sC[2][2][4];      // corner values at the ends [lo, hi][time n, n+1]
-    __shared__ double sCd[2][2][Q];     // pulled populations of the corners' inward diagonal nodes
+    static_assert(NN == 192 && 4 * Q + 24 <= NN, "chunk layout");
+    __shared__ double sY[2][CR * S * 4];                  // stage values (side-local)
+    __shared__ double sBn[CR * MS * 4], sBp[CR * MS * 4];  // strip at time n, n+1 (side-local)
+    __shared__ double sV[CR * 4];                         // mesoscopic viscous terms of time n
+    __shared__ double sC[2][2][4];                        // corners [lo, hi][time n, n+1] (global)
+    __shared__ double sCn[2][8];                          // time-n moments of their inward diagonal nodes
+    __shared__ double sCd[2][2][Q];                       // pulled populations of those nodes (n+1)
     const int tid = threadIdx.x;
     const int len = sd.len, tper = sd.tper;
     const int r0 = chunk * sd.rows;
     const int r1 = min(r0 + sd.rows, len);
-    const bool need_c[2] = {!tper && r0 == 0, !tper && r1 == len};
+    // corners beyond the ends of a side with non-periodic rows (row -1, row len): needed by every
+    // chunk whose rows computed in stage 0 (within 3 of its own) reach row 0 / row len - 1, i.e.
+    // also by the last-but-one chunk when the last one has fewer than 4 rows; their state and
+    // blocks are written by the chunk that owns the end row
+    const bool need_c[2] = {!tper && r0 <= 3, !tper && r1 >= len - 3};
+    const bool own_c[2] = {!tper && r0 == 0, !tper && r1 == len};
     const bool full = sd.scheme == BC_CBC || sd.scheme == BC_CBC_RELAX;
     const double* ub = (const double*)(a.reg_cur + sd.off_ub);
     double* ubn = (double*)(a.reg_next + sd.off_ub);
@@ -616,38 +649,79 @@ __device__ void char_chunk(const T* __restrict__ A, T* __restrict__ B, const Bnd
     double* visn = (double*)(a.reg_next + sd.off_vis);
     auto valid = [&](int r) { return tper || (r >= 0 && r < len); };
     auto phys = [&](int r) { return tper ? ((r % len) + len) % len : r; };
+    auto Yat = [&](int buf, int lr, int slot) { return &sY[buf][(lr * S + slot) * 4]; };
+    // LDS rows of the corner rows (row -1, row len) where need_c holds: 3 - r0 >= 0, and
+    // len - r0 + 4 <= CR - 1 since r1 >= len - 3 and r1 - r0 <= CR - 8
+    const int lr_c[2] = {3 - r0, len - r0 + 4};
+
+    const bool node = tid < NN;
+    const int lr = tid / M, jj = tid % M, sj = jj + MS;   // node threads: LDS row, layer j - 1, slot
+    const int r = r0 - 4 + lr;
+    const bool vr = node && valid(r);
+    const int pr = vr ? phys(r) : 0;
 
     // ---- phase A: load time level n, re-pull time level n+1 ------------------------------
-    for (int t = tid; t < NR * M; t += blockDim.x) {
-        const int lr = t / M, j = t % M, r = r0 - 4 + lr;
-        if (!valid(r)) continue;
-        const double* src = &ub[((size_t)j * len + phys(r)) * 4];
-        for (int m = 0; m < 4; ++m) sY0[(lr * M + j) * 4 + m] = src[m];
+    // loads first (node value, strip values, corner inputs), uses after the pulls, so that their
+    // latencies overlap
+    double g_u[4];
+    {
+        const double* src = &ub[((size_t)jj * len + pr) * 4];
+        for (int m = 0; m < 4; ++m) g_u[m] = src[m];
     }
-    for (int t = tid; t < NR * MS; t += blockDim.x) {
-        const int lr = t / MS, k = t % MS, r = r0 - 4 + lr;
-        if (!valid(r)) continue;
-        const double* src = &st[((size_t)k * len + phys(r)) * 4];
-        for (int m = 0; m < 4; ++m) sBn[(lr * MS + k) * 4 + m] = src[m];
+    constexpr int KB = (MS + M - 1) / M;   // strip slots loaded per node thread (2 for M = 1)
+    double g_b[KB][4];
+    for (int kb = 0; kb < KB; ++kb) {
+        const int k = jj + kb * M;
+        const double* src = &st[((size_t)(k < MS ? k : 0) * len + pr) * 4];
+        for (int m = 0; m < 4; ++m) g_b[kb][m] = src[m];
     }
-    // per row: the strip nodes x_f (.. x_f - MS + 1), then for CBC sides the three nodes of the
-    // viscous moments, x_f - M - kv (kv = 0, 1, 2): the first nodes inward of x_f none of whose
-    // populations streamed from the layers (a node there that is no bulk node holds an
-    // equilibrium, whose non-equilibrium moments are 0)
+    // corner inputs: 4 Q pulled populations, then 2 x 4 time-n values and 2 x 8 diagonal moments
+    double g_c = 0.0;
+    int ce = -1;
+    if (tid < 4 * Q) {
+        const int e = tid / (2 * Q), k = (tid / Q) % 2, i = tid % Q;
+        if (need_c[e]) {
+            const CornerDev& c = a.c[e == 0 ? sd.corner_lo : sd.corner_hi];
+            const int x = c.xc + (k + 1) * c.vx - cx<Q>(i), y = c.yc + (k + 1) * c.vy - cy<Q>(i);
+            g_c = (double)A[pix<Q>(a.pitch, i, x, y)];
+            ce = e;
+        }
+    } else if (tid < 4 * Q + 24) {
+        const int u = tid - 4 * Q, e = u / 12, m = u % 12;
+        if (need_c[e]) {
+            const CornerDev& c = a.c[e == 0 ? sd.corner_lo : sd.corner_hi];
+            g_c = m < 4 ? ((const double*)(a.reg_cur + c.off_cu))[m] : ((const double*)(a.reg_cur + c.off_cd))[m - 4];
+            ce = e;
+        }
+    }
+    // viscous terms of time level n (frozen during the RK stages)
+    if (full && !sd.vfd) {
+        const double nu = (a.tau - 0.5) * Lat<Q>::cs2;
+        for (int l2 = tid; l2 < CR; l2 += blockDim.x) {
+            const int rr = r0 - 4 + l2;
+            if (!valid(rr)) continue;
+            visc_terms_row<Q>(vis, len, phys(rr), valid(rr + 1) ? phys(rr + 1) : -1, valid(rr - 1) ? phys(rr - 1) : -1,
+                              nu, &sV[l2 * 4]);
+        }
+    }
+    // pulls, the fourth wavefront first: per row the strip nodes x_f (.. x_f - MS + 1), then for
+    // CBC sides the three nodes of the viscous moments, x_f - M - kv (kv = 0, 1, 2): the first nodes
+    // inward of x_f none of whose populations streamed from the layers (a node there that is no
+    // bulk node holds an equilibrium, whose non-equilibrium moments are 0)
     const int KP = full ? MS + 3 : MS;
-    for (int t = tid; t < NR * KP; t += blockDim.x) {
-        const int lr = t / KP, k = t % KP, r = r0 - 4 + lr;
-        if (!valid(r)) continue;
-        const int rp = phys(r);
-        const bool owned = r >= r0 && r < r1;
+    for (int p = (tid + 256 - NN) & 255; p < CR * KP; p += 256) {
+        const int lp = p / KP, k = p % KP, rq = r0 - 4 + lp;
+        if (!valid(rq)) continue;
+        const int rp = phys(rq);
+        const bool owned = rq >= r0 && rq < r1;
         if (k < MS) {
             int x, y; side_node(sd, -k, rp, x, y);
             double d[Q];
             pull_node<Q, T>(A, a, x, y, d);
             double u4[4];
             moments_u4<Q>(d, u4);
-            for (int m = 0; m < 4; ++m) sBp[(lr * MS + k) * 4 + m] = u4[m];
             if (owned) for (int m = 0; m < 4; ++m) stn[((size_t)k * len + rp) * 4 + m] = u4[m];
+            to_local(sd, u4, &sBp[(lp * MS + k) * 4]);
             continue;
         }
         if (!owned) continue;
@@ -662,152 +736,137 @@ __device__ void char_chunk(const T* __restrict__ A, T* __restrict__ B, const Bnd
         }
         for (int m = 0; m < 6; ++m) visn[((size_t)kv * len + rp) * 6 + m] = o6[m];
     }
-    // viscous terms of time level n (frozen during the RK stages)
-    if (full && !sd.vfd) {
-        const double nu = (a.tau - 0.5) * Lat<Q>::cs2;
-        for (int lr = tid; lr < NR; lr += blockDim.x) {
-            const int r = r0 - 4 + lr;
-            if (!valid(r)) continue;
-            visc_terms_row<Q>(vis, len, phys(r), valid(r + 1) ? phys(r + 1) : -1, valid(r - 1) ? phys(r - 1) : -1, nu,
-                              &sV[lr * 4]);
+    // stage-0 inputs: node values, strip at time n, corner values at time n in the corner rows
+    double Y0[4] = {0.0, 0.0, 0.0, 0.0};
+    if (vr) {
+        to_local(sd, g_u, Y0);
+        for (int m = 0; m < 4; ++m) Yat(0, lr, sj)[m] = Y0[m];
+        for (int kb = 0; kb < KB; ++kb) {
+            const int k = jj + kb * M;
+            if (k >= MS) continue;
+            double l[4];
+            to_local(sd, g_b[kb], l);
+            for (int m = 0; m < 4; ++m) { sBn[(lr * MS + k) * 4 + m] = l[m]; Yat(0, lr, MS - 1 - k)[m] = l[m]; }
         }
     }
-    // corners at the ends of a side with non-periodic rows: time-n value, and the pull of the two
-    // inward diagonal nodes spread over the work-group (the RK4 follows the first barrier)
-    for (int t = tid; t < 4 * Q; t += blockDim.x) {
-        const int e = t / (2 * Q), k = (t / Q) % 2, i = t % Q;
-        if (!need_c[e]) continue;
-        const CornerDev& c = a.c[e == 0 ? sd.corner_lo : sd.corner_hi];
-        const int x = c.xc + (k + 1) * c.vx - cx<Q>(i), y = c.yc + (k + 1) * c.vy - cy<Q>(i);
-        sCd[e][k][i] = (double)A[pix<Q>(a.pitch, i, x, y)];
+    if (ce >= 0) {
+        if (tid < 4 * Q) {
+            sCd[ce][(tid / Q) % 2][tid % Q] = g_c;
+        } else {
+            const int m = (tid - 4 * Q) % 12;
+            if (m < 4) { sC[ce][0][m] = g_c; sC[ce][1][m] = g_c; }
+            else sCn[ce][m - 4] = g_c;
+        }
     }
-    if (tid < 8) {   // time n (the time n+1 slot is set by the corner RK4)
-        const int e = tid / 4, m = tid % 4;
+    if (!node && tid - NN < 2) {   // corner rows of the stage-0 buffer (the time-n values again)
+        const int e = tid - NN;
         if (need_c[e]) {
-            const double v = ((const double*)(a.reg_cur + a.c[e == 0 ? sd.corner_lo : sd.corner_hi].off_cu))[m];
-            sC[e][0][m] = v;
-            sC[e][1][m] = v;
+            const double* cu = (const double*)(a.reg_cur + a.c[e == 0 ? sd.corner_lo : sd.corner_hi].off_cu);
+            double g[4], l[4];
+            for (int m = 0; m < 4; ++m) g[m] = cu[m];
+            to_local(sd, g, l);
+            for (int k = MS; k < S; ++k)
+                for (int m = 0; m < 4; ++m) Yat(0, lr_c[e], k)[m] = l[m];
         }
-    }
-    for (int t = tid; t < NR * M; t += blockDim.x) {
-        const int lr = t / M, r = r0 - 4 + lr;
-        if (r >= r0 && r < r1)
-            for (int m = 0; m < 4; ++m) sAcc[t * 4 + m] = sY0[t * 4 + m];
     }
     __syncthreads();
 
-    // corner RK4 on two threads (as a branch inside the stage loop, overlapping stage 0, it raises
-    // the register pressure of the whole kernel enough to spill in the bulk path)
-    if (need_c[0] && tid == 0)
-        corner_rk4<Q, HIST>(a, sd.corner_lo, sd.owns_corners, sCd[0][0], sCd[0][1], sC[0][0], sC[0][1]);
-    if (need_c[1] && tid == NR * M - 1)
-        corner_rk4<Q, HIST>(a, sd.corner_hi, sd.owns_corners, sCd[1][0], sCd[1][1], sC[1][0], sC[1][1]);
-    __syncthreads();
-    // ---- phase B: RK4, stage st valid on rows within 3 - st of the owned range -------------
+    // ---- phase B: RK4; stage st computes rates on rows within 3 - st of the owned range --------
     const double ast[4] = {0.0, 0.5, 0.5, 1.0}, bst[4] = {1.0, 2.0, 2.0, 1.0};
+    // normal differences at layer j: eq. FD-dx-bw at j = M (and the backward second difference of
+    // the -FD variant, Sec. 4.2, for M = 3), eq. FD-dx-center below; offsets -3 .. +1 from slot sj
+    const bool one = jj == M - 1;
+    const int sm1 = sj - 1, sm2 = max(sj - 2, 0), sm3 = max(sj - 3, 0), sp1 = min(sj + 1, S - 1);
+    const double u0 = Y0[1], s0 = char_speed<Q>(Y0);
+    double Ys[4], acc[4], Vl[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int m = 0; m < 4; ++m) { Ys[m] = Y0[m]; acc[m] = Y0[m]; }
+    if (node && full && !sd.vfd)
+        for (int m = 0; m < 4; ++m) Vl[m] = sV[lr * 4 + m];
+    const bool owned = vr && r >= r0 && r < r1;
     for (int stg = 0; stg < 4; ++stg) {
-        const int hy = 4 - stg, he = 3 - stg;
-        for (int t = tid; t < NR * M; t += blockDim.x) {
-            const int lr = t / M, r = r0 - 4 + lr;
-            if (r < r0 - hy || r >= r1 + hy || !valid(r)) continue;
-            for (int m = 0; m < 4; ++m) sYs[t * 4 + m] = stg == 0 ? sY0[t * 4 + m] : sY0[t * 4 + m] + ast[stg] * sK[t * 4 + m];
-            if (HIST && stg > 0 && r >= r0 && r < r1) {
-                double* ys = (double*)(a.reg_next + sd.off_stage);
-                const int jj = t % M;
-                for (int m = 0; m < 4; ++m) ys[(((size_t)(stg - 1) * M + jj) * len + r) * 4 + m] = sYs[t * 4 + m];
-            }
-        }
-        __syncthreads();
-        const double th = ast[stg];
-        for (int t = tid; t < NR * M; t += blockDim.x) {
-            const int lr = t / M, jj = t % M, j = jj + 1, r = r0 - 4 + lr;
-            if (r < r0 - he || r >= r1 + he || !valid(r)) continue;
-            // side-local values along the normal (k) at this row
-            auto val_n = [&](int k, double* l) {
-                double g[4];
-                if (k >= 1) {
-                    for (int m = 0; m < 4; ++m) g[m] = sYs[(lr * M + k - 1) * 4 + m];
-                } else {
-                    const double* bn = &sBn[(lr * MS - k) * 4];
-                    const double* bp = &sBp[(lr * MS - k) * 4];
-                    for (int m = 0; m < 4; ++m) g[m] = (1.0 - th) * bn[m] + th * bp[m];
+        const int cur = stg & 1, nxt = cur ^ 1;
+        const int he = 3 - stg;
+        if (node) {
+            if (vr && r >= r0 - he && r < r1 + he) {
+                const double* vm1 = Yat(cur, lr, sm1);
+                const double* vm2 = Yat(cur, lr, sm2);
+                const double* vp1 = Yat(cur, lr, sp1);
+                const double* up = Yat(cur, lr + 1, sj);
+                const double* dw = Yat(cur, lr - 1, sj);
+                double dn[4];
+                for (int m = 0; m < 4; ++m)
+                    dn[m] = one ? 0.5 * (3.0 * Ys[m] - 4.0 * vm1[m] + vm2[m]) : 0.5 * (vp1[m] - vm1[m]);
+                if (full && sd.vfd) {
+                    // the -FD variant (Sec. 4.2, treatment of viscous terms): Laplacians of eq.
+                    // NSF-CHAR by second differences of the stage values, heating from the first
+                    // differences; c_p / Pr = 2
+                    const double* vm3 = Yat(cur, lr, sm3);
+                    const double nu = (a.tau - 0.5) * Lat<Q>::cs2;
+                    double lap[4];
+                    for (int m = 1; m < 4; ++m) {
+                        const double d2n = one ? (M == 3 ? 2.0 * Ys[m] - 5.0 * vm1[m] + 4.0 * vm2[m] - vm3[m] : 0.0)
+                                               : vp1[m] - 2.0 * Ys[m] + vm1[m];
+                        lap[m] = d2n + up[m] - 2.0 * Ys[m] + dw[m];
+                    }
+                    Vl[1] = nu * lap[1];
+                    Vl[2] = nu * lap[2];
+                    if (TH) {
+                        const double sa = dn[1] - 0.5 * (up[2] - dw[2]), sb = 0.5 * (up[1] - dw[1]) + dn[2];
+                        Vl[3] = 2.0 * nu * lap[3] + nu * (1.0 / Lat<Q>::cs2) * (sa * sa + sb * sb);
+                    }
                 }
+                double rl[4];
+                char_rate_dir<Q>(Ys, dn, up, dw, Vl, u0, s0, sd.scheme, sd.K, sd.alpha, sd.Pinf, rl);
+                for (int m = 0; m < 4; ++m) acc[m] += bst[stg] * (1.0 / 6.0) * rl[m];
+                if (stg < 3) {
+                    for (int m = 0; m < 4; ++m) Ys[m] = Y0[m] + ast[stg + 1] * rl[m];
+                    for (int m = 0; m < 4; ++m) Yat(nxt, lr, sj)[m] = Ys[m];
+                    if (HIST && owned) {
+                        double g[4];
+                        rate_to_global(sd, Ys, g);
+                        double* ys = (double*)(a.reg_next + sd.off_stage);
+                        for (int m = 0; m < 4; ++m) ys[(((size_t)stg * M + jj) * len + r) * 4 + m] = g[m];
+                    }
+                }
+            }
+        } else if (stg < 3) {
+            const int u = tid - NN;
+            // corner RK4 while stage 0 runs (it needs the corners' time-n values only): lane 0 the
+            // low corner, lane 1 the high corner
+            if (stg == 0 && u < 2 && need_c[u])
+                corner_rk4<Q, HIST>(a, u == 0 ? sd.corner_lo : sd.corner_hi, sd.owns_corners && own_c[u], sCd[u][0],
+                                    sCd[u][1], sCn[u], sC[u][0], sC[u][1]);
+            const double th = ast[stg + 1];
+            if (u < 2 && need_c[u]) {   // corner rows of the next stage input
+                double g[4], l[4];
+                for (int m = 0; m < 4; ++m) g[m] = (1.0 - th) * sC[u][0][m] + th * sC[u][1][m];
                 to_local(sd, g, l);
-            };
-            auto val_t = [&](int rr, double* l) {   // same layer, row rr (LDS row lr + rr - r)
-                double g[4];
-                if (!tper && rr < 0) {
-                    for (int m = 0; m < 4; ++m) g[m] = (1.0 - th) * sC[0][0][m] + th * sC[0][1][m];
-                } else if (!tper && rr >= len) {
-                    for (int m = 0; m < 4; ++m) g[m] = (1.0 - th) * sC[1][0][m] + th * sC[1][1][m];
-                } else {
-                    const int l2 = lr + (rr - r);
-                    for (int m = 0; m < 4; ++m) g[m] = sYs[(l2 * M + jj) * 4 + m];
-                }
-                to_local(sd, g, l);
-            };
-            double U[4], dn[4], up[4], dw[4], U0[4], Vl[4] = {0, 0, 0, 0}, d2n[4] = {0, 0, 0, 0};
-            val_n(j, U);
-            if (j == M) {   // eq. FD-dx-bw
-                double b1[4], b2[4], b3[4];
-                val_n(M - 1, b1); val_n(M - 2, b2);
-                for (int m = 0; m < 4; ++m) dn[m] = 0.5 * (3.0 * U[m] - 4.0 * b1[m] + b2[m]);
-                if (M == 3 && full && sd.vfd) {   // backward second difference (Sec. 4.2)
-                    val_n(M - 3, b3);
-                    for (int m = 0; m < 4; ++m) d2n[m] = 2.0 * U[m] - 5.0 * b1[m] + 4.0 * b2[m] - b3[m];
-                }
-            } else {        // eq. FD-dx-center
-                double p1[4], m1[4];
-                val_n(j + 1, p1); val_n(j - 1, m1);
-                for (int m = 0; m < 4; ++m) { dn[m] = 0.5 * (p1[m] - m1[m]); d2n[m] = p1[m] - 2.0 * U[m] + m1[m]; }
+                for (int k = MS; k < S; ++k)
+                    for (int m = 0; m < 4; ++m) Yat(nxt, lr_c[u], k)[m] = l[m];
             }
-            val_t(r + 1, up);
-            val_t(r - 1, dw);
-            to_local(sd, &sY0[t * 4], U0);
-            if (full && !sd.vfd) {
-                for (int m = 0; m < 4; ++m) Vl[m] = sV[lr * 4 + m];
-            } else if (full) {
-                // the -FD variant (Sec. 4.2, treatment of viscous terms): Laplacians of eq.
-                // NSF-CHAR by second differences of the stage values, heating from the first
-                // differences; c_p / Pr = 2
-                const double nu = (a.tau - 0.5) * Lat<Q>::cs2;
-                double lap[4];
-                for (int m = 1; m < 4; ++m) lap[m] = d2n[m] + up[m] - 2.0 * U[m] + dw[m];
-                Vl[1] = nu * lap[1];
-                Vl[2] = nu * lap[2];
-                if (TH) {
-                    const double sa = dn[1] - 0.5 * (up[2] - dw[2]), sb = 0.5 * (up[1] - dw[1]) + dn[2];
-                    Vl[3] = 2.0 * nu * lap[3] + nu * (1.0 / Lat<Q>::cs2) * (sa * sa + sb * sb);
-                }
-            }
-            double rl[4], rg[4];
-            char_rate<Q>(U, dn, up, dw, Vl, U0, sd.scheme, sd.K, sd.alpha, sd.Pinf, rl);
-            rate_to_global(sd, rl, rg);
-            for (int m = 0; m < 4; ++m) sK[t * 4 + m] = rg[m];
-            if (r >= r0 && r < r1)
-                for (int m = 0; m < 4; ++m) sAcc[t * 4 + m] += bst[stg] * (1.0 / 6.0) * rg[m];
+            for (int l2 = u; l2 < CR; l2 += 256 - NN)   // strip slots of the next stage input
+                for (int k = 0; k < MS; ++k)
+                    for (int m = 0; m < 4; ++m)
+                        Yat(nxt, l2, MS - 1 - k)[m] = (1.0 - th) * sBn[(l2 * MS + k) * 4 + m] + th * sBp[(l2 * MS + k) * 4 + m];
         }
-        // corner RK4 while stage 0 runs (its rates use the corners' time-n values only), on
-        // threads whose LDS row lies beyond the side's end: the first for the low corner, the
-        // last for the high corner
-        __syncthreads();
+        if (stg < 3) __syncthreads();
     }
 
     // ---- phase C: new boundary state and reconstruction of the layers ------------------------
-    for (int t = tid; t < (r1 - r0) * M; t += blockDim.x) {
-        const int lr = 4 + t / M, j = t % M, r = r0 + t / M;
-        const double* u4 = &sAcc[(lr * M + j) * 4];
-        for (int m = 0; m < 4; ++m) ubn[((size_t)j * len + r) * 4 + m] = u4[m];
-        int x, y; side_node(sd, j + 1, r, x, y);
+    if (owned) {
+        double u4[4];
+        rate_to_global(sd, acc, u4);
+        for (int m = 0; m < 4; ++m) ubn[((size_t)jj * len + r) * 4 + m] = u4[m];
+        int x, y; side_node(sd, jj + 1, r, x, y);
         if (sd.meso == 0) {   // equilibrium BC: all populations at equilibrium
             write_feq<Q, T>(B, a.pitch, x, y, u4);
         } else {              // eq. NEEP: plus the post-collision non-equilibrium part of x_f
             int xf, yf; side_node(sd, 0, r, xf, yf);
             double d[Q], fe[Q];
             pull_node<Q, T>(A, a, xf, yf, d);
-            double rm1, ux, uy, th;
-            moments_dev<Q, double>(d, rm1, ux, uy, th);
-            feq_dev<Q, double>(rm1, ux, uy, th, fe);
+            double rm1, ux, uy, thv;
+            moments_dev<Q, double>(d, rm1, ux, uy, thv);
+            feq_dev<Q, double>(rm1, ux, uy, thv, fe);
             const double c = 1.0 - a.omega;
 #pragma unroll
             for (int i = 0; i < Q; ++i) d[i] = c * (d[i] - fe[i]);
@@ -816,13 +875,13 @@ __device__ void char_chunk(const T* __restrict__ A, T* __restrict__ B, const Bnd
             for (int i = 0; i < Q; ++i) B[pix<Q>(a.pitch, i, x, y)] = (T)(fe[i] + d[i]);
         }
     }
-    // the x-side's work-groups write the M x M corner blocks (threads from the top of the
-    // work-group, which have no layer node here: a chunk has at most 256 - 8 M rows x M layers)
-    if (sd.owns_corners) {
-        const int u = (int)blockDim.x - 1 - tid;
+    // the x-side's work-groups write the M x M corner blocks (fourth wavefront; the corner values
+    // at n+1 were set in stage 0)
+    if (sd.owns_corners && !node) {
+        const int u = tid - NN;
         if (u < 2 * M * M) {
             const int e = u / (M * M), jx = (u / M) % M, jy = u % M;
-            if (need_c[e]) {
+            if (own_c[e]) {
                 const CornerDev& c = a.c[e == 0 ? sd.corner_lo : sd.corner_hi];
                 write_feq<Q, T>(B, a.pitch, c.x0 + c.sxn * jx, c.y0 + c.syn * jy, sC[e][1]);
             }

@@ -58,7 +58,7 @@ bool is_full(int b) { return b == BC_CBC || b == BC_CBC_RELAX; }
 
 int stencil_M(int st) { return st == 9 ? 1 : 3; }
 double stencil_cs2(int st) { return st == 9 ? Lat<9>::cs2 : st == 17 ? Lat<17>::cs2 : Lat<37>::cs2; }
-int chunk_rows(int M) { return 256 / M - 8; }   // must match NR - 8 in char_chunk
+int chunk_rows(int M) { return 192 / M - 8; }   // must match ChunkShape::CR - 8 in char_chunk
 
 struct Layout {
     int Q = 0, M = 0, MS = 0;

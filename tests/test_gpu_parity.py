@@ -93,6 +93,20 @@ def test_d2q37_multi_tile(precision):
                 (rho, ux + 0.02, uy, T), precision, [1, 5, 20], relax=RELAX)
 
 
+@pytest.mark.parametrize("precision", PRECISIONS)
+@pytest.mark.parametrize("stencil,nx,ny", [(37, 63, 65), (17, 93, 94), (9, 187, 188)])
+def test_short_last_chunk(stencil, nx, ny, precision):
+    # side lengths (between the corner blocks) one to three rows past a multiple of the chunk
+    # height (56 / 88 / 184 rows for M = 3 / 2 / 1): the last chunk owns 1-3 rows, so the RK
+    # halo of the one before it reaches the corner beyond the side's end; pulse next to that corner
+    f = W.temperature_pulse(nx, ny, amp=1e-3, width=4.0, center=(nx - 8.0, ny - 8.0))
+    rho, ux, uy, T = f
+    tau = {37: TAU_37, 17: 0.9, 9: 0.6}[stencil]
+    bc = ["lodi_relax", "cbc_relax", "lodi_relax", "lodi_relax"] if stencil != 9 else ["lodi_relax"] * 4
+    compare_run(f"short-last-chunk-d2q{stencil}", stencil, nx, ny, tau, bc, (rho, ux + 0.01, uy - 0.005, T), precision,
+                [1, 5, 20, 60], relax=RELAX)
+
+
 def test_d2q9_multi_tile():
     nx, ny = 600, 300
     f = W.gaussian_density_pulse(nx, ny, amp=1e-3, width=12.0, center=(40.0, 280.0))
