@@ -7,9 +7,9 @@ Stored per snapshot step n: rows_n [4][len(rows)][nx] and cols_n [4][ny][len(col
 (rho, ux, uy, T), and the whole-field sums and sums of squares sum_n, sumsq_n [4].
 
 Run from the repository root, one configuration per call:
-    python tests/golden/make_workload_goldens.py c5     (about 2.5 hours on 8 cores)
-    python tests/golden/make_workload_goldens.py c2     (about 25 minutes)
-    python tests/golden/make_workload_goldens.py c3     (about 1 hour)
+    python tests/golden/make_workload_goldens.py c5 --threads 6   (about 2.1 hours)
+    python tests/golden/make_workload_goldens.py c2 --threads 2   (about 25 minutes)
+    python tests/golden/make_workload_goldens.py c3 --threads 2   (about 1 hour)
 Optional: --alpha A (C3's transverse relaxation), --threads N.
 """
 import argparse
