@@ -536,23 +536,24 @@ __device__ __forceinline__ void visc_terms_row(const double* vis, int len, int r
     V[3] = vt;
 }
 
-// corner LODI along the outward diagonal, rate in global components
+// corner LODI along the outward diagonal, rate in global components; ln, s0: the corner's time-n
+// value in diagonal-local components and its sound speed (fix the wave directions)
 template <int Q>
 __device__ __forceinline__ void corner_rate(const CornerDev& c, const double* Uc, const double* U1, const double* U2,
-                                            const double* Un, double* rate) {
+                                            const double* ln, double s0, double* rate) {
     const double tdx = -c.ndy, tdy = c.ndx;
-    double l0[4], l1[4], l2[4], ln[4];
+    double l0[4], l1[4], l2[4];
     auto loc = [&](const double* g, double* l) {
         l[0] = g[0]; l[1] = g[1] * c.ndx + g[2] * c.ndy; l[2] = g[1] * tdx + g[2] * tdy; l[3] = g[3];
     };
-    loc(Uc, l0); loc(U1, l1); loc(U2, l2); loc(Un, ln);
+    loc(Uc, l0); loc(U1, l1); loc(U2, l2);
     constexpr double inv = 0.35355339059327376220;   // 1 / (2 sqrt 2): diagonal spacing sqrt 2
     double dn[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) dn[k] = (3.0 * l0[k] - 4.0 * l1[k] + l2[k]) * inv;
     const double zero[4] = {0, 0, 0, 0};
     double rl[4];
-    char_rate<Q>(l0, dn, l0, l0, zero, ln, c.relax ? BC_LODI_RELAX : BC_LODI, c.K, 0.0, c.Pinf, rl);
+    char_rate_dir<Q>(l0, dn, l0, l0, zero, ln[1], s0, c.relax ? BC_LODI_RELAX : BC_LODI, c.K, 0.0, c.Pinf, rl);
     rate[0] = rl[0];
     rate[1] = rl[1] * c.ndx + rl[2] * tdx;
     rate[2] = rl[1] * c.ndy + rl[2] * tdy;
@@ -567,20 +568,19 @@ __device__ __forceinline__ void write_feq(T* __restrict__ B, unsigned long long 
     for (int i = 0; i < Q; ++i) B[pix<Q>(pitch, i, x, y)] = (T)fe[i];
 }
 
-// one corner: RK4 of the diagonal LODI system from the pulled populations of the two inward
-// diagonal nodes (d1, d2: time n+1) and their time-n moments cdn[8]; Un: U_c at time n.  U_c^{n+1}
-// goes to cp_out and, for the owning (x-side) work-group, to the next parity region
+// one corner: RK4 of the diagonal LODI system from the moments of the two inward diagonal nodes
+// at time n (cdn[8]) and n+1 (D1p, D2p: of their pulled populations); Un: U_c at time n.
+// U_c^{n+1} goes to cp_out and, for the owning (x-side) work-group, to the next parity region
 template <int Q, bool HIST>
-__device__ void corner_rk4(const BndArgs& a, int ci, bool owner, const double* d1, const double* d2, const double* cdn,
-                           const double* Un, double* cp_out) {
-    const CornerDev& c = a.c[ci];
-    double D1n[4], D2n[4], D1p[4], D2p[4];
+__device__ void corner_rk4(const BndArgs& a, const CornerDev& c, bool owner, const double* D1p, const double* D2p,
+                           const double* cdn, const double* Un, double* cp_out) {
+    double D1n[4], D2n[4];
     for (int k = 0; k < 4; ++k) { D1n[k] = cdn[k]; D2n[k] = cdn[4 + k]; }
-    moments_u4<Q>(d1, D1p);
-    moments_u4<Q>(d2, D2p);
     const double ast[4] = {0.0, 0.5, 0.5, 1.0}, bst[4] = {1.0, 2.0, 2.0, 1.0};
     double k4[4] = {0, 0, 0, 0}, acc[4];
     for (int m = 0; m < 4; ++m) acc[m] = Un[m];
+    const double ln[4] = {Un[0], Un[1] * c.ndx + Un[2] * c.ndy, -Un[1] * c.ndy + Un[2] * c.ndx, Un[3]};
+    const double s0 = char_speed<Q>(ln);
     for (int st = 0; st < 4; ++st) {
         const double th = ast[st];
         double Y[4], B1[4], B2[4];
@@ -591,7 +591,7 @@ __device__ void corner_rk4(const BndArgs& a, int ci, bool owner, const double* d
         }
         if (HIST && owner && st > 0)
             for (int m = 0; m < 4; ++m) ((double*)(a.reg_next + c.off_cs))[(st - 1) * 4 + m] = Y[m];
-        corner_rate<Q>(c, Y, B1, B2, Un, k4);
+        corner_rate<Q>(c, Y, B1, B2, ln, s0, k4);
         for (int m = 0; m < 4; ++m) acc[m] += bst[st] * (1.0 / 6.0) * k4[m];
     }
     for (int m = 0; m < 4; ++m) cp_out[m] = acc[m];
@@ -607,10 +607,58 @@ __device__ void corner_rk4(const BndArgs& a, int ci, bool owner, const double* d
 // each side (one per RK stage, so chunks need no grid-wide synchronisation).  Node threads
 // t < NN = CR M (three wavefronts) each own node (lr = t / M, layer j = t % M + 1) for the whole
 // step and keep its time-n value, stage value and RK4 sum in registers; the fourth wavefront pulls
-// the strip, runs the corner RK4 and fills the strip and corner slots of the stage buffers.  The
+// the strip and fills the strip and corner slots of the stage buffers; lanes of the first pull the
+// corners' inward diagonal nodes and run the corner RK4 while the strip pull is in flight.  The
 // stage buffers hold every node in side-local components (rho, u_n, u_t, T), slots
 // k = -(MS - 1) .. M along the normal (strip nodes, then layers) at slot index k + MS - 1, and are
 // double-buffered, so an RK stage needs one barrier.
+// A descriptor in the kernel arguments read with a uniform index, its fields passed through
+// readfirstlane: selecting between two such copies per lane then selects values.  (A per-lane
+// choice between two descriptors is otherwise turned into a load through a per-lane address: a
+// vector load from the kernel arguments, each waited for before the next, and the wait also holds
+// every load issued before it.)
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ unsigned long long uni(unsigned long long v) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ double uni(double v) {
+    return __longlong_as_double((long long)uni((unsigned long long)__double_as_longlong(v)));
+}
+__device__ __forceinline__ CornerDev uniform_corner(const CornerDev& c) {
+    CornerDev u;
+    u.active = uni(c.active); u.zg = uni(c.zg); u.relax = uni(c.relax);
+    u.xc = uni(c.xc); u.yc = uni(c.yc); u.vx = uni(c.vx); u.vy = uni(c.vy);
+    u.x0 = uni(c.x0); u.y0 = uni(c.y0); u.sxn = uni(c.sxn); u.syn = uni(c.syn);
+    u.K = uni(c.K); u.Pinf = uni(c.Pinf); u.ndx = uni(c.ndx); u.ndy = uni(c.ndy);
+    u.off_cu = uni(c.off_cu); u.off_cd = uni(c.off_cd); u.off_cs = uni(c.off_cs);
+    return u;
+}
+// corner descriptor of the low (h = false) or high end, per lane, from uniform copies
+__device__ __forceinline__ CornerDev pick_corner(const CornerDev& lo, const CornerDev& hi, bool h) {
+    CornerDev c;
+    c.active = h ? hi.active : lo.active;
+    c.zg = h ? hi.zg : lo.zg;
+    c.relax = h ? hi.relax : lo.relax;
+    c.xc = h ? hi.xc : lo.xc;
+    c.yc = h ? hi.yc : lo.yc;
+    c.vx = h ? hi.vx : lo.vx;
+    c.vy = h ? hi.vy : lo.vy;
+    c.x0 = h ? hi.x0 : lo.x0;
+    c.y0 = h ? hi.y0 : lo.y0;
+    c.sxn = h ? hi.sxn : lo.sxn;
+    c.syn = h ? hi.syn : lo.syn;
+    c.K = h ? hi.K : lo.K;
+    c.Pinf = h ? hi.Pinf : lo.Pinf;
+    c.ndx = h ? hi.ndx : lo.ndx;
+    c.ndy = h ? hi.ndy : lo.ndy;
+    c.off_cu = h ? hi.off_cu : lo.off_cu;
+    c.off_cd = h ? hi.off_cd : lo.off_cd;
+    c.off_cs = h ? hi.off_cs : lo.off_cs;
+    return c;
+}
+
 template <int Q> struct ChunkShape {
     static constexpr int M = Lat<Q>::M, MS = (M == 1) ? 2 : 1;
     static constexpr int CR = 192 / M;      // LDS rows per work-group
@@ -623,13 +671,13 @@ __device__ void char_chunk(const T* __restrict__ A, T* __restrict__ B, const Bnd
     using CS = ChunkShape<Q>;
     constexpr int M = CS::M, MS = CS::MS, CR = CS::CR, NN = CS::NN, S = CS::S;
     constexpr bool TH = Lat<Q>::thermal;
-    static_assert(NN == 192 && 4 * Q + 24 <= NN, "chunk layout");
+    static_assert(NN == 192, "chunk layout");
     __shared__ double sY[2][CR * S * 4];                  // stage values (side-local)
     __shared__ double sBn[CR * MS * 4], sBp[CR * MS * 4];  // strip at time n, n+1 (side-local)
     __shared__ double sV[CR * 4];                         // mesoscopic viscous terms of time n
     __shared__ double sC[2][2][4];                        // corners [lo, hi][time n, n+1] (global)
     __shared__ double sCn[2][8];                          // time-n moments of their inward diagonal nodes
-    __shared__ double sCd[2][2][Q];                       // pulled populations of those nodes (n+1)
+    __shared__ double sCp[2][2][4];                       // their moments at n+1
     const int tid = threadIdx.x;
     const int len = sd.len, tper = sd.tper;
     const int r0 = chunk * sd.rows;
@@ -653,11 +701,14 @@ __device__ void char_chunk(const T* __restrict__ A, T* __restrict__ B, const Bnd
     // LDS rows of the corner rows (row -1, row len) where need_c holds: 3 - r0 >= 0, and
     // len - r0 + 4 <= CR - 1 since r1 >= len - 3 and r1 - r0 <= CR - 8
     const int lr_c[2] = {3 - r0, len - r0 + 4};
+    const CornerDev cLo = uniform_corner(a.c[sd.corner_lo < 0 ? 0 : sd.corner_lo]);
+    const CornerDev cHi = uniform_corner(a.c[sd.corner_hi < 0 ? 0 : sd.corner_hi]);
 
+    const int nlr = min(CR, r1 - r0 + 8);                 // LDS rows in use
     const bool node = tid < NN;
     const int lr = tid / M, jj = tid % M, sj = jj + MS;   // node threads: LDS row, layer j - 1, slot
     const int r = r0 - 4 + lr;
-    const bool vr = node && valid(r);
+    const bool vr = node && lr < nlr && valid(r);
     const int pr = vr ? phys(r) : 0;
 
     // ---- phase A: load time level n, re-pull time level n+1 ------------------------------
@@ -675,29 +726,21 @@ __device__ void char_chunk(const T* __restrict__ A, T* __restrict__ B, const Bnd
         const double* src = &st[((size_t)(k < MS ? k : 0) * len + pr) * 4];
         for (int m = 0; m < 4; ++m) g_b[kb][m] = src[m];
     }
-    // corner inputs: 4 Q pulled populations, then 2 x 4 time-n values and 2 x 8 diagonal moments
+    // corner inputs: threads 0..3 pull the corners' inward diagonal nodes (corner tid / 2, node
+    // tid % 2 + 1 steps in; one whole pull per thread, so the lattice offsets are constants), threads
+    // 4..27 load the 2 x 4 time-n values and the 2 x 8 time-n moments of those nodes
     double g_c = 0.0;
-    int ce = -1;
-    if (tid < 4 * Q) {
-        const int e = tid / (2 * Q), k = (tid / Q) % 2, i = tid % Q;
-        if (need_c[e]) {
-            const CornerDev& c = a.c[e == 0 ? sd.corner_lo : sd.corner_hi];
-            const int x = c.xc + (k + 1) * c.vx - cx<Q>(i), y = c.yc + (k + 1) * c.vy - cy<Q>(i);
-            g_c = (double)A[pix<Q>(a.pitch, i, x, y)];
-            ce = e;
-        }
-    } else if (tid < 4 * Q + 24) {
-        const int u = tid - 4 * Q, e = u / 12, m = u % 12;
-        if (need_c[e]) {
-            const CornerDev& c = a.c[e == 0 ? sd.corner_lo : sd.corner_hi];
-            g_c = m < 4 ? ((const double*)(a.reg_cur + c.off_cu))[m] : ((const double*)(a.reg_cur + c.off_cd))[m - 4];
-            ce = e;
-        }
+    const bool cpull = tid < 4 && need_c[tid >> 1];
+    const int cv = tid - 4, cve = cv / 12, cvm = cv % 12;
+    const bool cval = cv >= 0 && cv < 24 && need_c[cve];
+    if (cval) {
+        const CornerDev c = pick_corner(cLo, cHi, cve == 1);
+        g_c = cvm < 4 ? ((const double*)(a.reg_cur + c.off_cu))[cvm] : ((const double*)(a.reg_cur + c.off_cd))[cvm - 4];
     }
     // viscous terms of time level n (frozen during the RK stages)
     if (full && !sd.vfd) {
         const double nu = (a.tau - 0.5) * Lat<Q>::cs2;
-        for (int l2 = tid; l2 < CR; l2 += blockDim.x) {
+        for (int l2 = tid; l2 < nlr; l2 += blockDim.x) {
             const int rr = r0 - 4 + l2;
             if (!valid(rr)) continue;
             visc_terms_row<Q>(vis, len, phys(rr), valid(rr + 1) ? phys(rr + 1) : -1, valid(rr - 1) ? phys(rr - 1) : -1,
@@ -709,7 +752,7 @@ __device__ void char_chunk(const T* __restrict__ A, T* __restrict__ B, const Bnd
     // inward of x_f none of whose populations streamed from the layers (a node there that is no
     // bulk node holds an equilibrium, whose non-equilibrium moments are 0)
     const int KP = full ? MS + 3 : MS;
-    for (int p = (tid + 256 - NN) & 255; p < CR * KP; p += 256) {
+    for (int p = (tid + 256 - NN) & 255; p < nlr * KP; p += 256) {
         const int lp = p / KP, k = p % KP, rq = r0 - 4 + lp;
         if (!valid(rq)) continue;
         const int rp = phys(rq);
@@ -736,6 +779,14 @@ __device__ void char_chunk(const T* __restrict__ A, T* __restrict__ B, const Bnd
         }
         for (int m = 0; m < 6; ++m) visn[((size_t)kv * len + rp) * 6 + m] = o6[m];
     }
+    if (cpull) {   // (after the pulls: no node thread of a LODI side pulls, so these loads overlap the rest)
+        const CornerDev c = pick_corner(cLo, cHi, (tid >> 1) == 1);
+        const int x = c.xc + ((tid & 1) + 1) * c.vx, y = c.yc + ((tid & 1) + 1) * c.vy;
+        double d[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) d[i] = (double)A[pix<Q>(a.pitch, i, x - cx<Q>(i), y - cy<Q>(i))];
+        moments_u4<Q>(d, sCp[tid >> 1][tid & 1]);
+    }
     // stage-0 inputs: node values, strip at time n, corner values at time n in the corner rows
     double Y0[4] = {0.0, 0.0, 0.0, 0.0};
     if (vr) {
@@ -749,25 +800,27 @@ __device__ void char_chunk(const T* __restrict__ A, T* __restrict__ B, const Bnd
             for (int m = 0; m < 4; ++m) { sBn[(lr * MS + k) * 4 + m] = l[m]; Yat(0, lr, MS - 1 - k)[m] = l[m]; }
         }
     }
-    if (ce >= 0) {
-        if (tid < 4 * Q) {
-            sCd[ce][(tid / Q) % 2][tid % Q] = g_c;
+    if (cval) {
+        if (cvm < 4) {
+            sC[cve][0][cvm] = g_c;
+            sC[cve][1][cvm] = g_c;
+            // the corner row of the stage-0 input: this component, side-local, on every layer
+            const int lm = cvm == 0 || cvm == 3 ? cvm : (cvm == 1 + sd.nax ? 1 : 2);
+            const double v = cvm == 1 + sd.nax ? sd.sn * g_c : g_c;
+            for (int k = MS; k < S; ++k) Yat(0, lr_c[cve], k)[lm] = v;
         } else {
-            const int m = (tid - 4 * Q) % 12;
-            if (m < 4) { sC[ce][0][m] = g_c; sC[ce][1][m] = g_c; }
-            else sCn[ce][m - 4] = g_c;
+            sCn[cve][cvm - 4] = g_c;
         }
     }
-    if (!node && tid - NN < 2) {   // corner rows of the stage-0 buffer (the time-n values again)
-        const int e = tid - NN;
-        if (need_c[e]) {
-            const double* cu = (const double*)(a.reg_cur + a.c[e == 0 ? sd.corner_lo : sd.corner_hi].off_cu);
-            double g[4], l[4];
-            for (int m = 0; m < 4; ++m) g[m] = cu[m];
-            to_local(sd, g, l);
-            for (int k = MS; k < S; ++k)
-                for (int m = 0; m < 4; ++m) Yat(0, lr_c[e], k)[m] = l[m];
-        }
+    // corner RK4 (time-n values and n+1 moments written above by lanes of this same wavefront, in
+    // program order): lane 0 the low corner, lane 2 the high corner, while the fourth wavefront
+    // is still pulling the strip
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (tid < 4 && (tid & 1) == 0 && need_c[tid >> 1]) {
+        const int e = tid >> 1;
+        corner_rk4<Q, HIST>(a, pick_corner(cLo, cHi, e == 1), sd.owns_corners && own_c[e], sCp[e][0], sCp[e][1], sCn[e],
+                            sC[e][0], sC[e][1]);
     }
     __syncthreads();
 
@@ -831,11 +884,6 @@ __device__ void char_chunk(const T* __restrict__ A, T* __restrict__ B, const Bnd
             }
         } else if (stg < 3) {
             const int u = tid - NN;
-            // corner RK4 while stage 0 runs (it needs the corners' time-n values only): lane 0 the
-            // low corner, lane 1 the high corner
-            if (stg == 0 && u < 2 && need_c[u])
-                corner_rk4<Q, HIST>(a, u == 0 ? sd.corner_lo : sd.corner_hi, sd.owns_corners && own_c[u], sCd[u][0],
-                                    sCd[u][1], sCn[u], sC[u][0], sC[u][1]);
             const double th = ast[stg + 1];
             if (u < 2 && need_c[u]) {   // corner rows of the next stage input
                 double g[4], l[4];
@@ -844,7 +892,7 @@ __device__ void char_chunk(const T* __restrict__ A, T* __restrict__ B, const Bnd
                 for (int k = MS; k < S; ++k)
                     for (int m = 0; m < 4; ++m) Yat(nxt, lr_c[u], k)[m] = l[m];
             }
-            for (int l2 = u; l2 < CR; l2 += 256 - NN)   // strip slots of the next stage input
+            for (int l2 = u; l2 < nlr; l2 += 256 - NN)   // strip slots of the next stage input
                 for (int k = 0; k < MS; ++k)
                     for (int m = 0; m < 4; ++m)
                         Yat(nxt, l2, MS - 1 - k)[m] = (1.0 - th) * sBn[(l2 * MS + k) * 4 + m] + th * sBp[(l2 * MS + k) * 4 + m];
@@ -882,7 +930,7 @@ __device__ void char_chunk(const T* __restrict__ A, T* __restrict__ B, const Bnd
         if (u < 2 * M * M) {
             const int e = u / (M * M), jx = (u / M) % M, jy = u % M;
             if (own_c[e]) {
-                const CornerDev& c = a.c[e == 0 ? sd.corner_lo : sd.corner_hi];
+                const CornerDev c = pick_corner(cLo, cHi, e == 1);
                 write_feq<Q, T>(B, a.pitch, c.x0 + c.sxn * jx, c.y0 + c.syn * jy, sC[e][1]);
             }
         }
