@@ -425,7 +425,7 @@ struct AdjArgs {
     const double* mom1;      // moments of time n + 1 (bulk nodes), same layout
     double* grad;            // n = 0: dL/d(rho0, ux0, uy0, T0), [4][ny][nx]
     int ablk0[4], anblk[4];  // side blocks of k_adj_side
-    int arows;               // owned rows per side block
+    int arows[4];            // owned rows per side block, per side
     int nadj;                // total side blocks
     int cside[4][2];         // per corner: adjacent side of each axis (-1 if none)
     int crow[4][2];          // per corner: that side's row next to the corner
@@ -450,10 +450,10 @@ template <int Q, bool CBC>
 __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk, int chunk) {
     constexpr int M = Lat<Q>::M, NR = 256 / M, MS = (M == 1) ? 2 : 1, H = 8, NN = NR * M;
     __shared__ double sY[4][NN * 4];            // stage inputs Y_0 = U_b^n, Y_1, Y_2, Y_3 (global components)
-    __shared__ double sYb1[NN * 4];             // adjoint of U_b^{n+1}
-    __shared__ double sG[NN * 4];               // adjoint of the stage input of the later stage
-    __shared__ double sGn[NN * 4], sGu[NN * 4], sGd[NN * 4];   // per node: adjoints of dn, up, dw
-    __shared__ double sG2[(M == 3 ? NN : 1) * 4];              // per node: adjoint of d2n (-FD viscous terms)
+    // per node and stage (double-buffered: one barrier per reverse stage): adjoints of dn, up, dw
+    // and of d2n (-FD viscous terms)
+    __shared__ double sGn[2][NN * 4], sGu[2][NN * 4], sGd[2][NN * 4];
+    __shared__ double sG2[2][(M == 3 ? NN : 1) * 4];
     __shared__ double sVr[NR * 4];                             // per row: mesoscopic viscous terms of time n
     __shared__ double sXn[NR * MS * 4], sXp[NR * MS * 4];       // strip values at n, n+1
     __shared__ double sXbn[NR * MS * 4], sXbp[NR * MS * 4];     // strip adjoints (owned rows)
@@ -463,8 +463,9 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
     const BndArgs& a = g.b;
     const int tid = threadIdx.x;
     const int len = sd.len, tper = sd.tper;
-    const int r0 = chunk * g.arows;
-    const int r1 = min(r0 + g.arows, len);
+    const int r0 = chunk * g.arows[side];
+    const int r1 = min(r0 + g.arows[side], len);
+    const int nlr = min(NR, r1 - r0 + 2 * H);   // LDS rows in use
     const double* ubn = (const double*)(a.reg_cur + sd.off_ub);
     const double* ubp = (const double*)(a.reg_next + sd.off_ub);
     const double* stn = (const double*)(a.reg_cur + sd.off_strip);
@@ -480,37 +481,57 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
     // ---- phase A: time-n and time-(n+1) values, fold of lambda^{n+1} on the layers ----------
     const int t = tid;
     const int lr = t / M, jj = t % M, j = jj + 1, r = r0 - H + lr;
-    const bool node = t < NN && valid(r);
-    if (t < NN) {
-        for (int m = 0; m < 4; ++m) { sYb1[t * 4 + m] = 0.0; sG[t * 4 + m] = 0.0; }
-        if (node) {
-            const int rp = phys(r);
-            for (int m = 0; m < 4; ++m) sY[0][t * 4 + m] = ubn[((size_t)jj * len + rp) * 4 + m];
-            if (within(r, 4)) {
-                double u4[4], lam[Q], G[4];
-                for (int m = 0; m < 4; ++m) u4[m] = ubp[((size_t)jj * len + rp) * 4 + m];
-                int x, y; side_node(sd, j, rp, x, y);
-#pragma unroll
-                for (int i = 0; i < Q; ++i) lam[i] = g.V1[pix<Q>(a.pitch, i, x, y)];
-                feq_vjp<Q>(u4, lam, G);
-                for (int m = 0; m < 4; ++m) sYb1[t * 4 + m] = mub1[((size_t)jj * len + rp) * 4 + m] + G[m];
-            }
-        }
+    const bool node = t < NN && lr < nlr && valid(r);
+    double yb1[4] = {0.0, 0.0, 0.0, 0.0};   // adjoint of this node's U_b^{n+1}
+    // every load of this phase is issued before the first use of any, so that their latencies
+    // overlap (a store to LDS waits for its value, and waits on loads go in issue order)
+    const bool fold = node && within(r, 4);
+    const int rp = node ? phys(r) : 0;
+    double y0v[4], yv[3][4], u4[4], mb[4], lam[Q];
+    if (node) {
+        // stage inputs Y_0 = U_b^n and Y_1..Y_3 (stored by the recomputation of this step)
+        const double* ys = (const double*)(a.reg_next + sd.off_stage);
+        for (int m = 0; m < 4; ++m) y0v[m] = ubn[((size_t)jj * len + rp) * 4 + m];
+        for (int st = 1; st <= 3; ++st)
+            for (int m = 0; m < 4; ++m) yv[st - 1][m] = ys[(((size_t)(st - 1) * M + jj) * len + rp) * 4 + m];
     }
-    for (int e = tid; e < NR * MS; e += blockDim.x) {
+    if (fold) {   // lambda^{n+1} of this layer node, folded into the adjoint of U_b^{n+1} below
+        for (int m = 0; m < 4; ++m) u4[m] = ubp[((size_t)jj * len + rp) * 4 + m];
+        for (int m = 0; m < 4; ++m) mb[m] = mub1[((size_t)jj * len + rp) * 4 + m];
+        int x, y; side_node(sd, j, rp, x, y);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) lam[i] = g.V1[pix<Q>(a.pitch, i, x, y)];
+    }
+    double cval = 0.0;
+    if (!tper && tid < 16) {
+        // the two corners' offsets read with uniform indices (see uniform_corner)
+        const unsigned long long oLo = uni(a.c[sd.corner_lo < 0 ? 0 : sd.corner_lo].off_cu);
+        const unsigned long long oHi = uni(a.c[sd.corner_hi < 0 ? 0 : sd.corner_hi].off_cu);
+        const int e = tid / 8, w = (tid / 4) % 2, m = tid % 4;
+        const char* reg = w == 0 ? a.reg_cur : a.reg_next;
+        cval = ((const double*)(reg + (e == 0 ? oLo : oHi)))[m];
+    }
+    for (int e = tid; e < nlr * MS; e += blockDim.x) {
         const int l2 = e / MS, k = e % MS, rr = r0 - H + l2;
         for (int m = 0; m < 4; ++m) { sXbn[e * 4 + m] = 0.0; sXbp[e * 4 + m] = 0.0; }
         if (!valid(rr)) continue;
+        double xn[4], xp[4];
         for (int m = 0; m < 4; ++m) {
-            sXn[e * 4 + m] = stn[((size_t)k * len + phys(rr)) * 4 + m];
-            sXp[e * 4 + m] = stp[((size_t)k * len + phys(rr)) * 4 + m];
+            xn[m] = stn[((size_t)k * len + phys(rr)) * 4 + m];
+            xp[m] = stp[((size_t)k * len + phys(rr)) * 4 + m];
         }
+        for (int m = 0; m < 4; ++m) { sXn[e * 4 + m] = xn[m]; sXp[e * 4 + m] = xp[m]; }
     }
-    if (!tper && tid < 16) {
-        const int e = tid / 8, w = (tid / 4) % 2, m = tid % 4;
-        const int ci = e == 0 ? sd.corner_lo : sd.corner_hi;
-        const char* reg = w == 0 ? a.reg_cur : a.reg_next;
-        sC[e][w][m] = ((const double*)(reg + a.c[ci].off_cu))[m];
+    if (!tper && tid < 16) (&sC[0][0][0])[tid] = cval;   // [e][w][m] = tid / 8, (tid / 4) % 2, tid % 4
+    if (node) {
+        for (int m = 0; m < 4; ++m) sY[0][t * 4 + m] = y0v[m];
+        for (int st = 1; st <= 3; ++st)
+            for (int m = 0; m < 4; ++m) sY[st][t * 4 + m] = yv[st - 1][m];
+    }
+    if (fold) {
+        double G[4];
+        feq_vjp<Q>(u4, lam, G);
+        for (int m = 0; m < 4; ++m) yb1[m] = mb[m] + G[m];
     }
     if (tid < 2 * 2 * M * 4) (&sCb[0][0][0][0])[tid] = 0.0;
     // mesoscopic viscous terms of time n (CBC sides without -FD), as in the forward step
@@ -518,7 +539,7 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
     const bool fd_v = CBC && (sd.scheme == BC_CBC || sd.scheme == BC_CBC_RELAX) && sd.vfd;   // second differences enter
     const double nu = (a.tau - 0.5) * Lat<Q>::cs2;
     const double* visn = meso_v ? (const double*)(a.reg_cur + sd.off_vis) : nullptr;
-    for (int l2 = tid; l2 < NR; l2 += blockDim.x) {
+    for (int l2 = tid; l2 < nlr; l2 += blockDim.x) {
         const int rr = r0 - H + l2;
         for (int m = 0; m < 4; ++m) sVr[l2 * 4 + m] = 0.0;
         if (meso_v && valid(rr))
@@ -604,29 +625,24 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
         to_local(sd, &sY[0][t * 4], U0);
     };
 
-    // ---- phase B: stage inputs Y_1..Y_3, stored by the recomputation of this step --------------
-    {
-        const double* ys = (const double*)(a.reg_next + sd.off_stage);
-        if (node)
-            for (int st = 1; st <= 3; ++st)
-                for (int m = 0; m < 4; ++m)
-                    sY[st][t * 4 + m] = ys[(((size_t)(st - 1) * M + jj) * len + phys(r)) * 4 + m];
-    }
-    __syncthreads();
-
-    // ---- phase C: reverse stages 3..0 ---------------------------------------------------------
+    // ---- phase C: reverse stages 3..0 (stage inputs loaded in phase A) ------------------------
     const bool owned = node && r >= r0 && r < r1;
     double ybn[4];   // adjoint of U_b^n (owned rows)
-    for (int m = 0; m < 4; ++m) ybn[m] = owned ? sYb1[t * 4 + m] : 0.0;
+    for (int m = 0; m < 4; ++m) ybn[m] = owned ? yb1[m] : 0.0;
     double aK = 0.0, aA = 0.0;
     double vacc[4] = {0.0, 0.0, 0.0, 0.0};   // adjoint of this node's mesoscopic V, summed over the stages
+    double gnext[4] = {0.0, 0.0, 0.0, 0.0};  // adjoint of this node's input of the later stage
     for (int st = 3; st >= 0; --st) {
         const double th = ast[st];
+        double* bGn = sGn[st & 1];
+        double* bGu = sGu[st & 1];
+        double* bGd = sGd[st & 1];
+        double* bG2 = sG2[st & 1];
         double gself[4] = {0, 0, 0, 0};
         if (node && within(r, st + 1)) {
             double kb[4], rb[4];
             for (int m = 0; m < 4; ++m)
-                kb[m] = bst[st] * (1.0 / 6.0) * sYb1[t * 4 + m] + (st < 3 ? ast[st + 1] * sG[t * 4 + m] : 0.0);
+                kb[m] = bst[st] * (1.0 / 6.0) * yb1[m] + (st < 3 ? ast[st + 1] * gnext[m] : 0.0);
             to_local(sd, kb, rb);
             double U[4], dn[4], d2n[4], up[4], dw[4], U0[4];
             inputs(st, U, dn, d2n, up, dw, U0);
@@ -643,15 +659,15 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
             rate_to_global(sd, dwbl, dwbg);
             for (int m = 0; m < 4; ++m) {
                 gself[m] = Ubg[m] + (j == M ? 1.5 * dnbg[m] : 0.0);
-                sGn[t * 4 + m] = dnbg[m];
-                sGu[t * 4 + m] = upbg[m];
-                sGd[t * 4 + m] = dwbg[m];
+                bGn[t * 4 + m] = dnbg[m];
+                bGu[t * 4 + m] = upbg[m];
+                bGd[t * 4 + m] = dwbg[m];
             }
             if constexpr (M == 3)
                 if (fd_v)
                     for (int m = 0; m < 4; ++m) {
                         gself[m] += (j == M ? 2.0 : -2.0) * d2nbg[m];
-                        sG2[t * 4 + m] = d2nbg[m];
+                        bG2[t * 4 + m] = d2nbg[m];
                     }
             if (owned) {
                 aK += Kb;
@@ -685,12 +701,12 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
                 if (q == M) cf = (j == M - 1) ? -2.0 : (j == M - 2 ? 0.5 : 0.0);
                 else cf = (j == q + 1) ? 0.5 : (j == q - 1 ? -0.5 : 0.0);
                 if (cf != 0.0)
-                    for (int m = 0; m < 4; ++m) yb[m] += cf * sGn[((lr * M) + q - 1) * 4 + m];
+                    for (int m = 0; m < 4; ++m) yb[m] += cf * bGn[((lr * M) + q - 1) * 4 + m];
                 if constexpr (M == 3) if (fd_v) {   // second differences: backward (2, -5, 4, -1) at q = M, central below
                     const double c2 = q == M ? (j == M - 1 ? -5.0 : (j == M - 2 ? 4.0 : 0.0))
                                              : ((j == q + 1 || j == q - 1) ? 1.0 : 0.0);
                     if (c2 != 0.0)
-                        for (int m = 0; m < 4; ++m) yb[m] += c2 * sG2[((lr * M) + q - 1) * 4 + m];
+                        for (int m = 0; m < 4; ++m) yb[m] += c2 * bG2[((lr * M) + q - 1) * 4 + m];
                 }
             }
             if constexpr (M == 3) if (fd_v) {
@@ -698,18 +714,20 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
                 // -1 in layer M's backward one (owned rows, as the first differences' strip terms)
                 if (owned && jj == 0)
                     for (int m = 0; m < 4; ++m) {
-                        const double xb = sG2[(lr * M) * 4 + m] - sG2[(lr * M + M - 1) * 4 + m];
+                        const double xb = bG2[(lr * M) * 4 + m] - bG2[(lr * M + M - 1) * 4 + m];
                         sXbn[(lr * MS) * 4 + m] += (1.0 - th) * xb;
                         sXbp[(lr * MS) * 4 + m] += th * xb;
                     }
             }
-            if (valid(r - 1)) for (int m = 0; m < 4; ++m) yb[m] += sGu[((lr - 1) * M + jj) * 4 + m];
-            if (valid(r + 1)) for (int m = 0; m < 4; ++m) yb[m] += sGd[((lr + 1) * M + jj) * 4 + m];
-            for (int m = 0; m < 4; ++m) sG[t * 4 + m] = yb[m];
+            if (valid(r - 1)) for (int m = 0; m < 4; ++m) yb[m] += bGu[((lr - 1) * M + jj) * 4 + m];
+            if (valid(r + 1)) for (int m = 0; m < 4; ++m) yb[m] += bGd[((lr + 1) * M + jj) * 4 + m];
+            for (int m = 0; m < 4; ++m) gnext[m] = yb[m];
             if (owned) for (int m = 0; m < 4; ++m) ybn[m] += yb[m];
         }
-        __syncthreads();
+        // (no second barrier: the next stage writes the other buffers; a thread reaches its
+        // writes to these only after the next stage's barrier, which every gather here precedes)
     }
+    __syncthreads();   // the strip adjoints and buffers of the last stage, read below
 
     // ---- phase D: outputs ----------------------------------------------------------------------
     if (owned) {
@@ -721,7 +739,7 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
         // the adjoints of V of rows r - 1, r, r + 1 (complete on rows within one of the owned
         // range); k_adj_bulk adds it to nu^n through the moments' derivatives
         if (t < NN)
-            for (int m = 0; m < 4; ++m) sGn[t * 4 + m] = node ? vacc[m] : 0.0;
+            for (int m = 0; m < 4; ++m) sGn[1][t * 4 + m] = node ? vacc[m] : 0.0;
         __syncthreads();
         constexpr double cs2 = Lat<Q>::cs2;
         double* visb = (double*)(g.adj_cur + sd.off_vis);
@@ -730,7 +748,7 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
             auto vsum = [&](int l, double* o) {
                 for (int m = 0; m < 4; ++m) {
                     o[m] = 0.0;
-                    for (int q = 0; q < M; ++q) o[m] += sGn[(l * M + q) * 4 + m];
+                    for (int q = 0; q < M; ++q) o[m] += sGn[1][(l * M + q) * 4 + m];
                 }
             };
             const bool hm = valid(rr - 1), hp = valid(rr + 1);
@@ -1002,8 +1020,7 @@ __device__ void zg_adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int 
 // blocks after the side chunks).  CBC: compiled with the CBC variants' terms (some side is CBC
 // or CBC-RELAX); without them the LODI schemes run a leaner kernel.
 template <int Q, bool CBC>
-__global__ __launch_bounds__(256) void k_adj_side(AdjArgs g) {
-    const int b = blockIdx.x;
+__device__ __forceinline__ void adj_side_block(const AdjArgs& g, int b) {
     if (b >= g.nadj) {
         corner_adj<Q>(g, b - g.nadj);
         return;
@@ -1013,6 +1030,11 @@ __global__ __launch_bounds__(256) void k_adj_side(AdjArgs g) {
     if (s == 4) return;
     if (g.b.s[s].kind == KIND_ZG) zg_adj_chunk<Q>(g, g.b.s[s], s, b - g.ablk0[s]);
     else adj_chunk<Q, CBC>(g, g.b.s[s], s, b, b - g.ablk0[s]);
+}
+
+template <int Q, bool CBC>
+__global__ __launch_bounds__(256) void k_adj_side(AdjArgs g) {
+    adj_side_block<Q, CBC>(g, (int)blockIdx.x);
 }
 
 // corners after the side chunks (coupled case)
@@ -1078,6 +1100,9 @@ __global__ __launch_bounds__(256) void k_adj_bulk(AdjArgs g, BulkArgs k, int bpr
     const int x = (blockIdx.x % bpr) * 256 + threadIdx.x, y = blockIdx.x / bpr;
     if (x >= k.nx) return;
     const unsigned long long pitch = k.pitch;
+    // this node's moments of time n, loaded with the pull (every node has them)
+    const unsigned long long plane = (unsigned long long)k.ny * pitch, o = (unsigned long long)y * pitch + x;
+    const double m[4] = {g.mom[o], g.mom[plane + o], g.mom[2 * plane + o], Lat<Q>::thermal ? g.mom[3 * plane + o] : 1.0};
     double lam[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -1127,28 +1152,31 @@ __global__ __launch_bounds__(256) void k_adj_bulk(AdjArgs g, BulkArgs k, int bpr
     // adjacent strips' end rows) and c + 2v, for the nodes that pull from them
     constexpr int M = Lat<Q>::M;
     const bool corner_rows = y <= 3 * M + 1 || y >= k.ny - 2 - 3 * M;   // uniform per work-group
-    for (int ci = 0; corner_rows && ci < 4; ++ci) {
-        const CornerDev& c = g.b.c[ci];
-        if (!c.active || c.zg) continue;
-        for (int e = 0; e < 2; ++e) {
-            const int dx = c.xc + (e + 1) * c.vx - x, dy = c.yc + (e + 1) * c.vy - y;
-            if (dx < -M || dx > M || dy < -M || dy > M) continue;
-            double GM[4];
-            for (int m = 0; m < 4; ++m) {
-                GM[m] = g.gm[(8 + ci * 2 + e) * 4 + m];
-                if (e == 0)
-                    for (int ax = 0; ax < 2; ++ax)
-                        GM[m] += g.gm[(g.cside[ci][ax] * 2 + (g.crow[ci][ax] == 0 ? 0 : 1)) * 4 + m];
-            }
+    if (corner_rows) {
+        // the four corners' descriptors through uniform copies (scalar loads, see uniform_corner),
+        // the corrections loaded only by the threads next to a diagonal node
+        for (int ci = 0; ci < 4; ++ci) {
+            const CornerDev c = uniform_corner(g.b.c[ci]);
+            if (!c.active || c.zg) continue;
+            int gi[2];
+            for (int ax = 0; ax < 2; ++ax) gi[ax] = uni(g.cside[ci][ax] * 2 + (g.crow[ci][ax] == 0 ? 0 : 1));
+            for (int e = 0; e < 2; ++e) {
+                const int dx = c.xc + (e + 1) * c.vx - x, dy = c.yc + (e + 1) * c.vy - y;
+                if (dx < -M || dx > M || dy < -M || dy > M) continue;
+                double GM[4];
+                for (int m = 0; m < 4; ++m) {
+                    GM[m] = g.gm[(8 + ci * 2 + e) * 4 + m];
+                    if (e == 0)
+                        for (int ax = 0; ax < 2; ++ax) GM[m] += g.gm[gi[ax] * 4 + m];
+                }
 #pragma unroll
-            for (int i = 0; i < Q; ++i)
-                if (cx<Q>(i) == dx && cy<Q>(i) == dy) lam[i] += phi_dot<Q>(i, GM);
+                for (int i = 0; i < Q; ++i)
+                    if (cx<Q>(i) == dx && cy<Q>(i) == dy) lam[i] += phi_dot<Q>(i, GM);
+            }
         }
     }
     if (INIT) {
         const int id = y * k.nx + x;
-        const unsigned long long plane = (unsigned long long)k.ny * pitch, o = (unsigned long long)y * pitch + x;
-        const double m[4] = {g.mom[o], g.mom[plane + o], g.mom[2 * plane + o], Lat<Q>::thermal ? g.mom[3 * plane + o] : 1.0};
         if (g.dir_any) {
             // lambda^1 and lambda^0 of a default-profile layer node go to its row's profile
             const double* prof;
@@ -1192,8 +1220,6 @@ __global__ __launch_bounds__(256) void k_adj_bulk(AdjArgs g, BulkArgs k, int bpr
         }
         return;
     }
-    const unsigned long long plane = (unsigned long long)k.ny * pitch, o = (unsigned long long)y * pitch + x;
-    const double m[4] = {g.mom[o], g.mom[plane + o], g.mom[2 * plane + o], g.mom[3 * plane + o]};
     double G[4], GM[4];
     feq_vjp<Q>(m, lam, G);
     mom_vjp<Q>(m, G, GM);

@@ -66,9 +66,15 @@ int chunk_rows(int M) { return 192 / M - 8; }   // must match ChunkShape::CR - 8
 // 39 -> 34 us in FP32).  Where the bulk runs far longer than a chunk (from 8192 bulk work-groups
 // on), the boundary is hidden behind it and the extra work-groups only take CU slots (4096 x 2048:
 // 398.5 -> 404 us), so the chunks stay full height.
+bool short_x_chunks(int nx, int ny) { return (long long)((nx + 255) / 256) * ny < 8192; }
 int chunk_rows_x(int M, int nx, int ny) {
-    const long long tiles = (long long)((nx + 255) / 256) * ny;
-    if (tiles >= 8192) return chunk_rows(M);
+    if (!short_x_chunks(nx, ny)) return chunk_rows(M);
+    return M == 3 ? 16 : M == 2 ? 24 : 48;
+}
+// the same for the reverse chunks of the adjoint (its halo is 8 rows on each side)
+int adj_rows(int M) { return 256 / M - 16; }   // must match NR - 2 H in adj_chunk
+int adj_rows_x(int M, int nx, int ny) {
+    if (!short_x_chunks(nx, ny)) return adj_rows(M);
     return M == 3 ? 16 : M == 2 ? 24 : 48;
 }
 
@@ -213,7 +219,7 @@ struct Tape {
     size_t off_neep[4] = {0, 0, 0, 0};   // per characteristic / ZG side: [len][Q + 4] terms of nu^{n+1}(x_f)
     size_t off_zgc = 0;                  // per zero-gradient corner: [Q + 4] terms of nu^{n+1}(c + v)
     size_t off_dacc[4] = {0, 0, 0, 0};   // per Dirichlet side: [M][len][4] adjoint of a default profile
-    int ablk0[4] = {0, 0, 0, 0}, anblk[4] = {0, 0, 0, 0}, arows = 0, nadj = 0;
+    int ablk0[4] = {0, 0, 0, 0}, anblk[4] = {0, 0, 0, 0}, arows[4] = {0, 0, 0, 0}, nadj = 0;
 };
 
 struct lbm_ctx {
@@ -389,7 +395,7 @@ int adjoint_supported(const lbm_ctx* c, std::string& err) {
     return LBM_OK;
 }
 
-void tape_layout(const Layout& L, int ny, int N, int K, Tape& t) {
+void tape_layout(const Layout& L, int nx, int ny, int N, int K, Tape& t) {
     t.N = N;
     t.K = K;
     t.nchk = (N + K - 1) / K;
@@ -405,11 +411,11 @@ void tape_layout(const Layout& L, int ny, int N, int K, Tape& t) {
     for (int k = 0; k < 2; ++k) { t.off_adj[k] = off; off += L.region_bytes; }
     t.off_ccon = off; off += align_up(4 * 2 * 2 * 4 * 8);
     t.off_gm = off; off += align_up(16 * 4 * 8);
-    t.arows = 256 / L.M - 16;   // must match NR - 2 H in adj_chunk
     t.nadj = 0;
     for (int s = 0; s < 4; ++s) {
+        t.arows[s] = L.s[s].nax == 0 ? adj_rows_x(L.M, nx, ny) : adj_rows(L.M);
         t.ablk0[s] = t.nadj;
-        t.anblk[s] = L.s[s].kind == KIND_CHAR ? (L.s[s].len + t.arows - 1) / t.arows
+        t.anblk[s] = L.s[s].kind == KIND_CHAR ? (L.s[s].len + t.arows[s] - 1) / t.arows[s]
                    : L.s[s].kind == KIND_ZG ? (L.s[s].len + 255) / 256 : 0;
         t.nadj += t.anblk[s];
     }
@@ -463,7 +469,7 @@ int run_adjoint(lbm_ctx* c, const double* seed, double* grad, double* h_relax) {
     g.acc = (double*)(base + t.off_acc);
     g.grad = grad;
     for (int s = 0; s < 4; ++s) { g.ablk0[s] = t.ablk0[s]; g.anblk[s] = t.anblk[s]; }
-    g.arows = t.arows;
+    for (int s = 0; s < 4; ++s) g.arows[s] = t.arows[s];
     g.nadj = t.nadj;
     for (int ci = 0; ci < 4; ++ci)
         for (int ax = 0; ax < 2; ++ax) {
@@ -916,7 +922,7 @@ int lbm_restore(lbm_ctx* c, const void* d_buf) {
 size_t lbm_tape_bytes(const lbm_ctx* c, int nsteps, int every) {
     if (!c || nsteps < 1 || every < 1) return 0;
     Tape t;
-    tape_layout(c->L, c->cfg.ny, nsteps, std::min(every, nsteps), t);
+    tape_layout(c->L, c->cfg.nx, c->cfg.ny, nsteps, std::min(every, nsteps), t);
     return t.total;
 }
 
@@ -929,7 +935,7 @@ int lbm_record(lbm_ctx* c, int nsteps, int every, void* d_tape, size_t tape_byte
     if (!d_tape || ((uintptr_t)d_tape % ALIGN) != 0) return fail(c, LBM_E_ARG, "tape must be non-NULL and 256-byte aligned");
     if (c->steps != 0) return fail(c, LBM_E_STATE, "recording starts from the initial state (no steps taken)");
     Tape t;
-    tape_layout(c->L, c->cfg.ny, nsteps, std::min(every, nsteps), t);
+    tape_layout(c->L, c->cfg.nx, c->cfg.ny, nsteps, std::min(every, nsteps), t);
     if (tape_bytes < t.total) return fail(c, LBM_E_ARG, "tape smaller than lbm_tape_bytes");
     t.base = (char*)d_tape;
     for (int n = 0; n < nsteps; ++n) {
