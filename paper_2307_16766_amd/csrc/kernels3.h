@@ -8,7 +8,8 @@
 // viscous terms are single buffers.
 //
 // One time step = face kernels, which need only the old level A: k3_prep (strip and viscous
-// moments of the new level from pulls of A, viscous terms of the old level), four k3_stage
+// moments of the new level from pulls of A -- read from the compact face strips that the
+// previous bulk launch wrote, see StripMap3 --, viscous terms of the old level), four k3_stage
 // launches (one per RK4 stage of the coupled face system) and k3_final (new layer populations:
 // equilibrium, eq. NEEP or zero gradient, staged in a small buffer); then the bulk kernel (fused
 // pull-stream + moments + BGK, HBM-bound), whose boundary-layer lanes store the staged layer
@@ -85,7 +86,43 @@ struct Bulk3 {
     float omega_f;
     double omega_d;
     const void* lay;   // layer populations of the new level staged by k3_final, [face][rows][M][Q] of T
+    void* strip;       // face strips of the new level (see StripMap3), NULL without characteristic faces
 };
+
+// Face strips: per characteristic face and row (y, z), the populations that the next step's face
+// pulls read from this row, entry i nk + k of the row's block = f(X_k - c_ix, y, z, i), X_0 = x_f
+// (the strip node) and X_k = x_f - sn (M + k - 1), k = 1..3 (the viscous-moment nodes of the CBC
+// schemes; nk = 4 there, 1 for the LODI schemes).  A row's block is padded to whole 128-byte lines
+// and written whole (padding included) by the bulk kernel's work-group holding the row's window of
+// x (12 nodes with the viscous-moment nodes, else 7): partly written lines would cost a
+// read-modify-write each.  k3_prep then reads 160-640 bytes per row and face instead of one
+// 128-byte line per population.
+struct StripMap3 {
+    int nk[2];     // k slots per face: 4 (CBC schemes), 1 (LODI schemes), 0 (no strip)
+    int lo[2];     // first x of the face's window
+    int w[2];      // window width
+    int xf[2], sn[2];
+    int blk[2];    // elements per row block (Q nk, padded to 128 bytes)
+};
+// first element of face s's blocks
+__device__ __forceinline__ size_t strip_base(const StripMap3& m, int s, int rows) {
+    return s == 0 ? 0 : (size_t)rows * m.blk[0];
+}
+// c_x of population i for a per-lane i, from two packed constants (3 bits per velocity): a lookup
+// in the constant table would be a global load
+__host__ __device__ constexpr unsigned long long pack_cx3(int from) {
+    unsigned long long v = 0;
+    for (int j = 0; j < 21 && from + j < L3::Q; ++j) v |= (unsigned long long)(cx3(from + j) + 3) << (3 * j);
+    return v;
+}
+__device__ __forceinline__ int cx3_dyn(int i) {
+    constexpr unsigned long long lo = pack_cx3(0), hi = pack_cx3(21);
+    const unsigned long long v = i < 21 ? (lo >> (3 * i)) : (hi >> (3 * (i - 21)));
+    return (int)(v & 7ull) - 3;
+}
+__device__ __forceinline__ int strip_x(const StripMap3& m, int s, int k) {
+    return k == 0 ? m.xf[s] : m.xf[s] - m.sn[s] * (L3::M + k - 1);
+}
 
 // One thread per node of a 256-node x-tile of one row (the tiles cover x = 0 .. nx - 1).  Loads
 // are issued source row by source row (49 (dy, dz) combinations, unrolled; only those holding
@@ -107,16 +144,22 @@ struct Bulk3 {
 // reconstruction) and was slower.
 template <typename T, bool PX>
 __global__ __launch_bounds__(256, (sizeof(T) == 4 ? 3 : 2)) void k3_bulk(const T* __restrict__ A, T* __restrict__ B, Bulk3 g,
-                                                                          int bpr, unsigned magic) {
+                                                                          StripMap3 sm, int bpr, unsigned magic) {
     const unsigned t0 = blockIdx.x;
     const unsigned per = gridDim.x >> 3;
     const unsigned t = (gridDim.x & 7u) ? t0 : (t0 & 7u) * per + (t0 >> 3);
     const unsigned row = bpr == 1 ? t : __umulhi(t, magic);
-    const int x = (int)(t - row * (unsigned)bpr) * 256 + (int)threadIdx.x;
+    const int xt0 = (int)(t - row * (unsigned)bpr) * 256;
+    const int x = xt0 + (int)threadIdx.x;
     const int z = (int)(row / (unsigned)g.ny), y = (int)(row - (unsigned)z * (unsigned)g.ny);
-    if (x >= g.nx) return;
+    // the face strips: whether this tile holds part of a face's window (uniform per work-group)
+    bool win[2] = {false, false};
+    if (!PX && g.strip)
+        for (int s = 0; s < 2; ++s) win[s] = sm.nk[s] > 0 && sm.lo[s] <= xt0 + 255 && sm.lo[s] + sm.w[s] - 1 >= xt0;
+    if (x >= g.nx && !win[0] && !win[1]) return;
     const bool act = PX || (x >= g.x0 && x <= g.x1);
     T d[L3::Q];
+    if (x < g.nx) {
 #pragma unroll
     for (int dz = -L3::M; dz <= L3::M; ++dz) {
 #pragma unroll
@@ -146,6 +189,63 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 ? 3 : 2)) void k3_bulk(const T
     T* Bo = B + pix3(g.pitch, g.ny, 0, x, y, z);
 #pragma unroll
     for (int i = 0; i < L3::Q; ++i) __builtin_nontemporal_store(d[i], Bo + (unsigned long long)i * g.pitch);
+    }
+    if (PX || !(win[0] || win[1])) return;
+    // the window's values through LDS, then the row's strip blocks with contiguous stores.  When
+    // the window lies in one wavefront (the usual case) that wavefront does it alone, with no
+    // work-group barrier (a barrier made every bulk work-group wait for its slowest wavefront:
+    // -6 % of the FP32 bulk rate on 512 x 256 x 256); a window across wavefronts or tiles takes
+    // the barrier.
+    __shared__ T sW[2][12][L3::Q];
+    const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+    bool solo[2] = {false, false}, shared = false;
+    for (int s = 0; s < 2; ++s) {
+        if (!win[s]) continue;
+        const int l0 = sm.lo[s] - xt0, l1 = l0 + sm.w[s] - 1;
+        solo[s] = l0 >= 0 && l1 <= 255 && (l0 >> 6) == (l1 >> 6);
+        shared = shared || !solo[s];
+    }
+    for (int s = 0; s < 2; ++s)
+        if (win[s] && x < g.nx && x >= sm.lo[s] && x < sm.lo[s] + sm.w[s]) {
+#pragma unroll
+            for (int i = 0; i < L3::Q; ++i) sW[s][x - sm.lo[s]][i] = d[i];
+        }
+    if (shared) __syncthreads();
+    for (int s = 0; s < 2; ++s) {
+        if (!win[s]) continue;
+        int e0 = (int)threadIdx.x, de = 256;
+        if (solo[s]) {   // only the window's wavefront, after its own LDS writes
+            if (wave != ((sm.lo[s] - xt0) >> 6)) continue;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            e0 = lane;
+            de = 64;
+        }
+        T* blk = (T*)g.strip + strip_base(sm, s, g.rows) + (size_t)row * sm.blk[s];
+        const int nk = sm.nk[s];
+        for (int e = e0; e < sm.blk[s]; e += de) {
+            if (e >= L3::Q * nk) {   // padding, written so that the block's lines are whole
+                blk[e] = (T)0;
+                continue;
+            }
+            const int i = e / nk, k = e - i * nk;
+            const int xs = strip_x(sm, s, k) - cx3_dyn(i);
+            if (xs >= xt0 && xs <= xt0 + 255) blk[e] = sW[s][xs - sm.lo[s]][i];
+        }
+    }
+}
+
+// the face strips of the initial state (f^0), in the layout the bulk kernel writes them
+template <typename T>
+__global__ __launch_bounds__(256) void k3_fill_strip(const T* __restrict__ A, Bulk3 g, StripMap3 sm) {
+    const int s = blockIdx.y;
+    const int nk = sm.nk[s];
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (nk == 0 || e >= (long long)g.rows * L3::Q * nk) return;
+    const int row = (int)(e / (L3::Q * nk)), q = (int)(e - (long long)row * L3::Q * nk), i = q / nk, k = q % nk;
+    const int z = row / g.ny, y = row - z * g.ny;
+    ((T*)g.strip)[strip_base(sm, s, g.rows) + (size_t)row * sm.blk[s] + q] =
+        A[pix3(g.pitch, g.ny, i, strip_x(sm, s, k) - cx3(i), y, z)];
 }
 
 // ================================================================== initialisation
@@ -237,16 +337,16 @@ __device__ __forceinline__ void visc_moments3(int sn, const double* d, double ta
     o[7] = sn * 0.5 * fac * qx; o[8] = 0.5 * fac * qy; o[9] = 0.5 * fac * qz;
 }
 
-// Four threads per face row, one per node: x_f (k = 0) and x_f - sn (M + k - 1) (k = 1, 2, 3):
-// consecutive threads pull nearby x of the same row, so each load instruction touches fewer
-// cache lines than one thread per row would.  New level: moments of x_f (the strip) and, for the
-// CBC schemes, the viscous moments of the other three nodes, from the pulls of A.  Old level (CBC
+// Four threads per face row, one per node: x_f (k = 0) and x_f - sn (M + k - 1) (k = 1, 2, 3),
+// pulling from the face strips the previous bulk launch (or k3_fill_strip) wrote (consecutive
+// threads read neighbouring entries of the same row blocks).  New level: moments of x_f (the
+// strip) and, for the CBC schemes, the viscous moments of the other three nodes.  Old level (CBC
 // schemes, thread k = 0): the viscous terms V (eq. NSF-CHAR, Appendix A), frozen during the RK4
 // stages -- div Pi' / rho and (-div q + Pi':Pi' / (2 rho nu)) / (rho c_v cs^2), normal derivatives
 // one-sided over x_f - M .. x_f - M - 2 (eq. FD-dx-bw), tangential ones central in y and z
 // (eq. FD-dx-center).
 template <typename T>
-__global__ __launch_bounds__(256) void k3_prep(const T* __restrict__ A, Args3 a) {
+__global__ __launch_bounds__(256) void k3_prep(const T* __restrict__ strip, StripMap3 sm, Args3 a) {
     const int s = blockIdx.y;
     const Face3& fc = a.f[s];
     const int t = blockIdx.x * 256 + threadIdx.x;
@@ -258,8 +358,14 @@ __global__ __launch_bounds__(256) void k3_prep(const T* __restrict__ A, Args3 a)
     const int y = r % a.ny, z = r / a.ny;
     const bool full = is_full3(fc.scheme);
     if (!full && k > 0) return;
+    // the pull of node X_k from the face strips: population i of it is strip entry (i, k) of the
+    // row (y - c_iy, z - c_iz)
     double d[L3::Q];
-    pull3<T>(A, a, k == 0 ? fc.xf : fc.xf - fc.sn * (L3::M + k - 1), y, z, d);
+    const T* sb = strip + strip_base(sm, s, a.rows);
+    const int nk = sm.nk[s], bl = sm.blk[s];
+#pragma unroll
+    for (int i = 0; i < L3::Q; ++i)
+        d[i] = (double)sb[(size_t)(wrap3(z - cz3(i), a.nz) * a.ny + wrap3(y - cy3(i), a.ny)) * bl + i * nk + k];
     if (k == 0) {
         double rm1, u, v, w, th;
         moments3_dev<double>(d, rm1, u, v, w, th);

@@ -1,7 +1,8 @@
 // lbm3d.hip -- host side of the three-dimensional C ABI (include/lbm3d.h) in liblbm_hip.so.
 //
 // The caller's workspace holds two population buffers, two parity copies of the face state, the
-// RK4 stage buffers, the viscous terms and the diagnostics scratch.  One step is the bulk kernel
+// RK4 stage buffers, the viscous terms, the diagnostics scratch, the staged layer populations and
+// the compact face strips.  One step is the bulk kernel
 // followed by the face kernels, all on the caller's stream.
 #include <hip/hip_runtime.h>
 
@@ -29,8 +30,10 @@ struct Layout3 {
     int rows = 0;
     size_t f_bytes = 0, region_bytes = 0, off_region = 0, off_Ya = 0, off_Yb = 0, off_V = 0, off_diag = 0, total = 0;
     size_t off_lay = 0;   // staged layer populations of the new level [face][rows][M][Q] (storage type)
+    size_t off_strip = 0; // face strips [face][rows][sm.blk] (storage type; see StripMap3)
     int diag_blocks = 0;
     Face3 f[2];
+    StripMap3 sm;
 };
 
 // the configuration on the library's internal grid: the face axis becomes x, the two axes that
@@ -98,7 +101,24 @@ void make_layout3(const lbm3d_config* c, Layout3& L) {
     L.off_diag = L.off_V + al3((size_t)2 * L.rows * 5 * 8);
     L.diag_blocks = 1024;
     L.off_lay = L.off_diag + al3((size_t)(L.diag_blocks + 1) * 8 * 8);
-    L.total = L.off_lay + al3((size_t)2 * L.rows * L3::M * L3::Q * L.esz);
+    std::memset(&L.sm, 0, sizeof(L.sm));
+    bool any = false;
+    for (int s = 0; s < 2; ++s) {
+        const int b = c->bc[s];
+        const bool ch = b >= LBM_BC_LODI && b <= LBM_BC_CBC_RELAX, full = b == LBM_BC_CBC || b == LBM_BC_CBC_RELAX;
+        L.sm.nk[s] = !ch ? 0 : full ? 4 : 1;
+        L.sm.xf[s] = L.f[s].xf;
+        L.sm.sn[s] = L.f[s].sn;
+        // x of the pulled nodes X_k - c_x, |c_x| <= M: x_f - 3 .. x_f + 3 with the strip node only,
+        // also the three viscous-moment nodes inward of it otherwise
+        L.sm.w[s] = L.sm.nk[s] == 4 ? 12 : 7;
+        L.sm.lo[s] = (s == 0 || L.sm.nk[s] != 4) ? L.f[s].xf - L3::M : L.f[s].xf - L3::M - (L3::M + 2);
+        any = any || ch;
+    }
+    for (int s = 0; s < 2; ++s)
+        L.sm.blk[s] = (int)((((size_t)L3::Q * L.sm.nk[s] * L.esz + 127) / 128 * 128) / L.esz);
+    L.off_strip = L.off_lay + al3((size_t)2 * L.rows * L3::M * L3::Q * L.esz);
+    L.total = L.off_strip + (any ? al3((size_t)L.rows * (L.sm.blk[0] + L.sm.blk[1]) * L.esz) : 0);
 }
 
 }  // namespace
@@ -176,6 +196,7 @@ Bulk3 make_bulk3(const lbm3d_ctx* c) {
     g.omega_f = (float)(1.0 / c->cfg.tau);
     g.rows = c->L.rows;
     g.lay = c->ws + c->L.off_lay;
+    g.strip = (c->L.sm.nk[0] || c->L.sm.nk[1]) ? (void*)(c->ws + c->L.off_strip) : nullptr;
     return g;
 }
 
@@ -198,7 +219,8 @@ int launch_step3(lbm3d_ctx* c) {
     // staged for the bulk kernel's boundary-layer lanes
     if (!a.xper) {
         if (c->cfg.bc[0] != LBM_BC_ZG || c->cfg.bc[1] != LBM_BC_ZG) {
-            hipLaunchKernelGGL((k3_prep<T>), dim3((4 * rows + 255) / 256, 2), dim3(256), 0, c->stream, A, a);
+            hipLaunchKernelGGL((k3_prep<T>), dim3((4 * rows + 255) / 256, 2), dim3(256), 0, c->stream,
+                               (const T*)(c->ws + c->L.off_strip), c->L.sm, a);
             HIPCHK3(c, hipGetLastError());
             for (int st = 0; st < 4; ++st) {
                 hipLaunchKernelGGL(k3_stage, dim3((L3::M * rows + 255) / 256, 2), dim3(256), 0, c->stream, a, st);
@@ -221,9 +243,10 @@ int launch_step3(lbm3d_ctx* c) {
     // FP32: an unused dynamic LDS reservation of 54000 bytes caps the bulk kernel at 3 work-groups
     // per CU (160 KiB of LDS), where the many-stream pull pattern streams best (73.6 % against
     // 71.2 % at the register-limited 5 per CU on 512 x 256 x 256); FP64 is at 2 per CU anyway.
-    const unsigned lds = sizeof(T) == 4 ? 54000u : 0u;
-    if (a.xper) hipLaunchKernelGGL((k3_bulk<T, true>), dim3(nblk), dim3(256), lds, c->stream, A, B, g, bpr, magic);
-    else hipLaunchKernelGGL((k3_bulk<T, false>), dim3(nblk), dim3(256), lds, c->stream, A, B, g, bpr, magic);
+    // (less the kernel's own static LDS for the face strips)
+    const unsigned lds = sizeof(T) == 4 ? 54000u - (unsigned)(sizeof(T) * (2 * 12 * L3::Q)) : 0u;
+    if (a.xper) hipLaunchKernelGGL((k3_bulk<T, true>), dim3(nblk), dim3(256), lds, c->stream, A, B, g, c->L.sm, bpr, magic);
+    else hipLaunchKernelGGL((k3_bulk<T, false>), dim3(nblk), dim3(256), lds, c->stream, A, B, g, c->L.sm, bpr, magic);
     HIPCHK3(c, hipGetLastError());
     if (rec) {
         HIPCHK3(c, hipEventRecord(c->tev[2 * c->tcount + 1], c->stream));
@@ -306,6 +329,13 @@ int lbm3d_init(const lbm3d_config* cfg, void* d_workspace, size_t workspace_byte
         hipLaunchKernelGGL(k3_init_faces, dim3((c->L.rows + 255) / 256, 2), dim3(256), 0, c->stream, a, d_rho0, u0, u1, u2,
                            d_T0, c->us);
         HIPCHK3(c, hipGetLastError());
+        const Bulk3 g = make_bulk3(c);
+        if (g.strip) {   // the face strips of f^0, which the first step's k3_prep reads
+            const long long ne = (long long)c->L.rows * L3::Q * 4;   // covers either face's entries
+            hipLaunchKernelGGL((k3_fill_strip<T>), dim3((unsigned)((ne + 255) / 256), 2), dim3(256), 0, c->stream,
+                               (const T*)c->f[0], g, c->L.sm);
+            HIPCHK3(c, hipGetLastError());
+        }
         return LBM_OK;
     });
     if (rc != LBM_OK) {
