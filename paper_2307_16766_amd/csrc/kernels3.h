@@ -8,7 +8,7 @@
 // viscous terms are single buffers.
 //
 // One time step = face kernels, which need only the old level A: k3_prep (strip and viscous
-// moments of the new level from pulls of A -- read from the compact face strips that the
+// moments of the new level from pulls of A -- in FP64, read from the compact face strips that the
 // previous bulk launch wrote, see StripMap3 --, viscous terms of the old level), four k3_stage
 // launches (one per RK4 stage of the coupled face system) and k3_final (new layer populations:
 // equilibrium, eq. NEEP or zero gradient, staged in a small buffer); then the bulk kernel (fused
@@ -96,7 +96,9 @@ struct Bulk3 {
 // and written whole (padding included) by the bulk kernel's work-group holding the row's window of
 // x (12 nodes with the viscous-moment nodes, else 7): partly written lines would cost a
 // read-modify-write each.  k3_prep then reads 160-640 bytes per row and face instead of one
-// 128-byte line per population.
+// 128-byte line per population.  Kept in FP64 storage only: there it shortens the 3D step by
+// 2.3 % on 512 x 256 x 256, while in FP32 the window wavefront's extra work lengthens every bulk
+// work-group of a launch held at 3 per CU, which costs more (1.4 %) than the pulls it saves.
 struct StripMap3 {
     int nk[2];     // k slots per face: 4 (CBC schemes), 1 (LODI schemes), 0 (no strip)
     int lo[2];     // first x of the face's window
@@ -338,15 +340,15 @@ __device__ __forceinline__ void visc_moments3(int sn, const double* d, double ta
 }
 
 // Four threads per face row, one per node: x_f (k = 0) and x_f - sn (M + k - 1) (k = 1, 2, 3),
-// pulling from the face strips the previous bulk launch (or k3_fill_strip) wrote (consecutive
-// threads read neighbouring entries of the same row blocks).  New level: moments of x_f (the
+// pulling from the face strips the previous bulk launch (or k3_fill_strip) wrote, or from A where
+// no strips are kept (consecutive threads then pull nearby x of the same row).  New level: moments of x_f (the
 // strip) and, for the CBC schemes, the viscous moments of the other three nodes.  Old level (CBC
 // schemes, thread k = 0): the viscous terms V (eq. NSF-CHAR, Appendix A), frozen during the RK4
 // stages -- div Pi' / rho and (-div q + Pi':Pi' / (2 rho nu)) / (rho c_v cs^2), normal derivatives
 // one-sided over x_f - M .. x_f - M - 2 (eq. FD-dx-bw), tangential ones central in y and z
 // (eq. FD-dx-center).
 template <typename T>
-__global__ __launch_bounds__(256) void k3_prep(const T* __restrict__ strip, StripMap3 sm, Args3 a) {
+__global__ __launch_bounds__(256) void k3_prep(const T* __restrict__ A, const T* __restrict__ strip, StripMap3 sm, Args3 a) {
     const int s = blockIdx.y;
     const Face3& fc = a.f[s];
     const int t = blockIdx.x * 256 + threadIdx.x;
@@ -358,14 +360,18 @@ __global__ __launch_bounds__(256) void k3_prep(const T* __restrict__ strip, Stri
     const int y = r % a.ny, z = r / a.ny;
     const bool full = is_full3(fc.scheme);
     if (!full && k > 0) return;
-    // the pull of node X_k from the face strips: population i of it is strip entry (i, k) of the
-    // row (y - c_iy, z - c_iz)
+    // the pull of node X_k: from the face strips when kept (population i of it is strip entry
+    // (i, k) of the row (y - c_iy, z - c_iz)), else from A
     double d[L3::Q];
-    const T* sb = strip + strip_base(sm, s, a.rows);
-    const int nk = sm.nk[s], bl = sm.blk[s];
+    if (strip) {
+        const T* sb = strip + strip_base(sm, s, a.rows);
+        const int nk = sm.nk[s], bl = sm.blk[s];
 #pragma unroll
-    for (int i = 0; i < L3::Q; ++i)
-        d[i] = (double)sb[(size_t)(wrap3(z - cz3(i), a.nz) * a.ny + wrap3(y - cy3(i), a.ny)) * bl + i * nk + k];
+        for (int i = 0; i < L3::Q; ++i)
+            d[i] = (double)sb[(size_t)(wrap3(z - cz3(i), a.nz) * a.ny + wrap3(y - cy3(i), a.ny)) * bl + i * nk + k];
+    } else {
+        pull3<T>(A, a, k == 0 ? fc.xf : fc.xf - fc.sn * (L3::M + k - 1), y, z, d);
+    }
     if (k == 0) {
         double rm1, u, v, w, th;
         moments3_dev<double>(d, rm1, u, v, w, th);

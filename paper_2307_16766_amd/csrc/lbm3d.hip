@@ -106,14 +106,14 @@ void make_layout3(const lbm3d_config* c, Layout3& L) {
     for (int s = 0; s < 2; ++s) {
         const int b = c->bc[s];
         const bool ch = b >= LBM_BC_LODI && b <= LBM_BC_CBC_RELAX, full = b == LBM_BC_CBC || b == LBM_BC_CBC_RELAX;
-        L.sm.nk[s] = !ch ? 0 : full ? 4 : 1;
+        L.sm.nk[s] = !ch || L.esz != 8 ? 0 : full ? 4 : 1;   // strips in FP64 storage only (see StripMap3)
         L.sm.xf[s] = L.f[s].xf;
         L.sm.sn[s] = L.f[s].sn;
         // x of the pulled nodes X_k - c_x, |c_x| <= M: x_f - 3 .. x_f + 3 with the strip node only,
         // also the three viscous-moment nodes inward of it otherwise
         L.sm.w[s] = L.sm.nk[s] == 4 ? 12 : 7;
         L.sm.lo[s] = (s == 0 || L.sm.nk[s] != 4) ? L.f[s].xf - L3::M : L.f[s].xf - L3::M - (L3::M + 2);
-        any = any || ch;
+        any = any || L.sm.nk[s] > 0;
     }
     for (int s = 0; s < 2; ++s)
         L.sm.blk[s] = (int)((((size_t)L3::Q * L.sm.nk[s] * L.esz + 127) / 128 * 128) / L.esz);
@@ -219,8 +219,8 @@ int launch_step3(lbm3d_ctx* c) {
     // staged for the bulk kernel's boundary-layer lanes
     if (!a.xper) {
         if (c->cfg.bc[0] != LBM_BC_ZG || c->cfg.bc[1] != LBM_BC_ZG) {
-            hipLaunchKernelGGL((k3_prep<T>), dim3((4 * rows + 255) / 256, 2), dim3(256), 0, c->stream,
-                               (const T*)(c->ws + c->L.off_strip), c->L.sm, a);
+            hipLaunchKernelGGL((k3_prep<T>), dim3((4 * rows + 255) / 256, 2), dim3(256), 0, c->stream, A,
+                               g.strip ? (const T*)g.strip : nullptr, c->L.sm, a);
             HIPCHK3(c, hipGetLastError());
             for (int st = 0; st < 4; ++st) {
                 hipLaunchKernelGGL(k3_stage, dim3((L3::M * rows + 255) / 256, 2), dim3(256), 0, c->stream, a, st);
