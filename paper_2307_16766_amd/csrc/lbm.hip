@@ -71,6 +71,9 @@ int chunk_rows_x(int M, int nx, int ny) {
     if (!short_x_chunks(nx, ny)) return chunk_rows(M);
     return M == 3 ? 16 : M == 2 ? 24 : 48;
 }
+// sides normal to y (coalesced pulls) take half-height chunks on the same small grids: their
+// reconstruction and corner chunks then end sooner
+int chunk_rows_y(int M, int nx, int ny) { return short_x_chunks(nx, ny) ? chunk_rows(M) / 2 : chunk_rows(M); }
 // the same for the reverse chunks of the adjoint (its halo is 8 rows on each side)
 int adj_rows(int M) { return 256 / M - 16; }   // must match NR - 2 H in adj_chunk
 int adj_rows_x(int M, int nx, int ny) {
@@ -155,7 +158,7 @@ void make_layout(const lbm_config* c, Layout& L) {
         d.owns_corners = d.nax == 0;
         d.Pinf = 0;
         if (d.kind == KIND_CHAR) {
-            d.rows = d.nax == 0 ? chunk_rows_x(L.M, c->nx, c->ny) : chunk_rows(L.M);
+            d.rows = d.nax == 0 ? chunk_rows_x(L.M, c->nx, c->ny) : chunk_rows_y(L.M, c->nx, c->ny);
             d.nblk = (d.len + d.rows - 1) / d.rows;
             d.off_ub = reg; reg += align_up((size_t)L.M * d.len * 4 * 8);
             d.off_strip = reg; reg += align_up((size_t)L.MS * d.len * 4 * 8);
