@@ -503,6 +503,8 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
         for (int i = 0; i < Q; ++i) lam[i] = g.V1[pix<Q>(a.pitch, i, x, y)];
     }
     double cval = 0.0;
+    // this work-group's running sums of the parameter adjoints, added to at the end
+    const double acc0 = tid < 2 ? g.acc[blk * 2 + tid] : 0.0;
     if (!tper && tid < 16) {
         // the two corners' offsets read with uniform indices (see uniform_corner)
         const unsigned long long oLo = uni(a.c[sd.corner_lo < 0 ? 0 : sd.corner_lo].off_cu);
@@ -808,21 +810,26 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
         if (rr < r0 || rr >= r1 || !valid(rr)) continue;
         const int rp = phys(rr);
         const size_t o = ((size_t)k * len + rp) * 4;
-        double Z[4], GM[4];
+        const bool end_row = !tper && k == 0 && (rp == 0 || rp == len - 1);   // len >= 3: the two ends differ
+        int x, y; side_node(sd, -k, rp, x, y);
+        double* v1 = g.V1 + pix<Q>(a.pitch, 0, x, y);
+        // every load before the first store (one round trip)
+        double Z[4], v[Q];
+        for (int m = 0; m < 4; ++m) Z[m] = xbp[o + m];
+        if (!end_row) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) v[i] = v1[(unsigned long long)i * a.pitch];
+        }
+        double GM[4];
         for (int m = 0; m < 4; ++m) {
             xbo[o + m] = sXbn[e * 4 + m];
-            Z[m] = sXbp[e * 4 + m] + xbp[o + m];
+            Z[m] += sXbp[e * 4 + m];
         }
         mom_vjp<Q>(&sXp[e * 4], Z, GM);
-        if (!tper && k == 0 && (rp == 0 || rp == len - 1)) {   // len >= 3: the two ends differ
+        if (end_row) {
             for (int m = 0; m < 4; ++m) g.gm[(side * 2 + (rp == 0 ? 0 : 1)) * 4 + m] = GM[m];
             continue;
         }
-        int x, y; side_node(sd, -k, rp, x, y);
-        double* v1 = g.V1 + pix<Q>(a.pitch, 0, x, y);
-        double v[Q];   // all loads before the stores
-#pragma unroll
-        for (int i = 0; i < Q; ++i) v[i] = v1[(unsigned long long)i * a.pitch];
 #pragma unroll
         for (int i = 0; i < Q; ++i) v1[(unsigned long long)i * a.pitch] = v[i] + phi_dot<Q>(i, GM);
     }
@@ -842,7 +849,7 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
     __syncthreads();
     if (tid < 2) {
         const double v = sRed[tid][0] + sRed[tid][1] + sRed[tid][2] + sRed[tid][3];
-        g.acc[blk * 2 + tid] += v;
+        g.acc[blk * 2 + tid] = acc0 + v;
     }
 }
 

@@ -74,9 +74,12 @@ int chunk_rows_x(int M, int nx, int ny) {
 // sides normal to y (coalesced pulls) take half-height chunks on the same small grids: their
 // reconstruction and corner chunks then end sooner
 int chunk_rows_y(int M, int nx, int ny) { return short_x_chunks(nx, ny) ? chunk_rows(M) / 2 : chunk_rows(M); }
-// the same for the reverse chunks of the adjoint (its halo is 8 rows on each side)
+// Reverse chunks of the adjoint (halo of 8 rows on each side): on the same small grids every
+// side takes the short height, since a reverse chunk's load phase grows with its rows whatever
+// the side's orientation and the sweep waits for the slowest chunk (256^2 D2Q37: sides normal to
+// y at 69 -> 17 rows took the reverse step from 39.7 to 37.7 us)
 int adj_rows(int M) { return 256 / M - 16; }   // must match NR - 2 H in adj_chunk
-int adj_rows_x(int M, int nx, int ny) {
+int adj_rows_short(int M, int nx, int ny) {
     if (!short_x_chunks(nx, ny)) return adj_rows(M);
     return M == 3 ? 16 : M == 2 ? 24 : 48;
 }
@@ -416,7 +419,7 @@ void tape_layout(const Layout& L, int nx, int ny, int N, int K, Tape& t) {
     t.off_gm = off; off += align_up(16 * 4 * 8);
     t.nadj = 0;
     for (int s = 0; s < 4; ++s) {
-        t.arows[s] = L.s[s].nax == 0 ? adj_rows_x(L.M, nx, ny) : adj_rows(L.M);
+        t.arows[s] = adj_rows_short(L.M, nx, ny);
         t.ablk0[s] = t.nadj;
         t.anblk[s] = L.s[s].kind == KIND_CHAR ? (L.s[s].len + t.arows[s] - 1) / t.arows[s]
                    : L.s[s].kind == KIND_ZG ? (L.s[s].len + 255) / 256 : 0;
