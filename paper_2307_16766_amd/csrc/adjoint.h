@@ -203,6 +203,8 @@ __device__ __forceinline__ void char_rate_vjp(const double* U, const double* dn,
         }
         const double s = sqrt(2.0 * cs2 * T);
         const double s0 = sqrt(2.0 * cs2 * U0[3]);
+        // reciprocals taken once (each division is a long dependent sequence on the stage's chain)
+        const double iT = 1.0 / T, is = 1.0 / s;
         const double a = 0.25 * T * ir, b = s * (0.25 / cs2);
         const double W3 = a * dn[0] - b * dn[1] + 0.25 * dn[3];
         const double W4 = a * dn[0] + b * dn[1] + 0.25 * dn[3];
@@ -223,15 +225,15 @@ __device__ __forceinline__ void char_rate_vjp(const double* U, const double* dn,
         }
         const bool o1 = u0 >= 0.0, o3 = u0 - s0 >= 0.0, o4 = u0 + s0 >= 0.0;
         const double B1 = o1 ? L1 : in1, B3 = o3 ? L3 : in3, B4 = o4 ? L4 : in4;
-        const double rhoT = rho / T, q = 2.0 * cs2 / s;
+        const double rhoT = rho * iT, q = 2.0 * cs2 * is;
         const double Bb1 = rb[0] * rhoT - rb[3];
         const double Bb2 = -rb[2];
         const double Bb3 = -rb[0] * rhoT + rb[1] * q - rb[3];
         const double Bb4 = -rb[0] * rhoT - rb[1] * q - rb[3];
         const double Bs = B1 - B3 - B4;
-        rhob += rb[0] * Bs / T;
-        Tb += -rb[0] * rho * Bs / (T * T);
-        double sb = -rb[1] * q * (B3 - B4) / s;
+        rhob += rb[0] * Bs * iT;
+        Tb += -rb[0] * rho * Bs * iT * iT;
+        double sb = -rb[1] * q * (B3 - B4) * is;
         const double L1b = o1 ? Bb1 : 0.0, L2b = o1 ? Bb2 : 0.0, L3b = o3 ? Bb3 : 0.0, L4b = o4 ? Bb4 : 0.0;
         const double in1b = o1 ? 0.0 : Bb1, in2b = o1 ? 0.0 : Bb2;
         const double in3b = o3 ? 0.0 : Bb3, in4b = o4 ? 0.0 : Bb4;
@@ -244,7 +246,7 @@ __device__ __forceinline__ void char_rate_vjp(const double* U, const double* dn,
             Kb = prb * (rho * cs2 * T - Pinf) * ir * (0.25 / cs2);
             // pr = K (T / 4 - Pinf / (4 cs^2 rho))
             Tb += prb * K * 0.25;
-            rhob += prb * K * 0.25 * Pinf * ir * ir / cs2;
+            rhob += prb * K * 0.25 * Pinf * ir * ir * (1.0 / cs2);
         }
         if (full) {
             // incoming amplitudes S (T + V) (in2 = T3 + V2) and the direct T + V of the rate
@@ -287,7 +289,7 @@ __device__ __forceinline__ void char_rate_vjp(const double* U, const double* dn,
         sb += bb * (0.25 / cs2);
         Tb += ab * 0.25 * ir;
         rhob += -ab * 0.25 * T * ir * ir;
-        Tb += sb * cs2 / s;
+        Tb += sb * cs2 * is;
         if (full && !vfd) {
             Vb[1] = V1b;
             Vb[2] = V2b;
