@@ -580,53 +580,67 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
 
     const double ast[4] = {0.0, 0.5, 0.5, 1.0}, bst[4] = {1.0, 2.0, 2.0, 1.0};
     // side-local stage-st inputs of this thread's node
+    // The stage inputs of this node, side-local.  Every LDS read is issued unconditionally (indices
+    // clamped into the arrays, the alternatives chosen by value afterwards), so that a stage waits
+    // for the LDS once instead of once per branch: dn = cU U + cA Y(kA) + cB Y(kB) with the
+    // one-sided (j = M, eq. FD-dx-bw) or central (eq. FD-dx-center) coefficients, Y(k) of layer
+    // k >= 1 from the stored stage input, of k <= 0 from the strip interpolated in time.
+    const int nax = sd.nax;
+    const double snv = sd.sn;
+    auto loc = [&](const double* gv, double* l) {   // to_local
+        l[0] = gv[0];
+        l[1] = snv * (nax == 0 ? gv[1] : gv[2]);
+        l[2] = nax == 0 ? gv[2] : gv[1];
+        l[3] = gv[3];
+    };
+    const bool one = j == M;
+    const int kA = one ? M - 1 : j + 1, kB = one ? M - 2 : j - 1, kC = M - 3;
+    const double cU = one ? 1.5 : 0.0, cA = one ? -2.0 : 0.5, cB = one ? 0.5 : -0.5;
+    const int lrc = min(max(lr, 1), NR - 2);   // clamped row (the reads of non-node threads stay in the arrays)
     auto inputs = [&](int st, double* U, double* dn, double* d2n, double* up, double* dw, double* U0) {
         const double th = ast[st];
         const double* Ys = sY[st];
-        auto val_n = [&](int k, double* l) {
-            double gv[4];
-            if (k >= 1) {
-                for (int m = 0; m < 4; ++m) gv[m] = Ys[(lr * M + k - 1) * 4 + m];
-            } else {
-                const double* bn = &sXn[(lr * MS - k) * 4];
-                const double* bp = &sXp[(lr * MS - k) * 4];
-                for (int m = 0; m < 4; ++m) gv[m] = (1.0 - th) * bn[m] + th * bp[m];
-            }
-            to_local(sd, gv, l);
+        auto rd = [&](int k, double* gv) {   // Y(k), global components
+            const double* y = &Ys[(lrc * M + max(k, 1) - 1) * 4];
+            const double* bn = &sXn[(lrc * MS + min(max(-k, 0), MS - 1)) * 4];
+            const double* bp = &sXp[(lrc * MS + min(max(-k, 0), MS - 1)) * 4];
+            double yv[4], sv[4];
+            for (int m = 0; m < 4; ++m) { yv[m] = y[m]; sv[m] = (1.0 - th) * bn[m] + th * bp[m]; }
+            for (int m = 0; m < 4; ++m) gv[m] = k >= 1 ? yv[m] : sv[m];
         };
-        auto val_t = [&](int rr, double* l) {
-            double gv[4];
-            if (!tper && rr < 0) {
-                for (int m = 0; m < 4; ++m) gv[m] = (1.0 - th) * sC[0][0][m] + th * sC[0][1][m];
-            } else if (!tper && rr >= len) {
-                for (int m = 0; m < 4; ++m) gv[m] = (1.0 - th) * sC[1][0][m] + th * sC[1][1][m];
-            } else {
-                const int l2 = lr + (rr - r);
-                for (int m = 0; m < 4; ++m) gv[m] = Ys[(l2 * M + jj) * 4 + m];
-            }
-            to_local(sd, gv, l);
-        };
-        val_n(j, U);
-        for (int m = 0; m < 4; ++m) d2n[m] = 0.0;
-        if (j == M) {
-            double b1[4], b2[4];
-            val_n(M - 1, b1); val_n(M - 2, b2);
-            for (int m = 0; m < 4; ++m) dn[m] = 0.5 * (3.0 * U[m] - 4.0 * b1[m] + b2[m]);
-            if (M == 3 && fd_v) {   // backward second difference of the -FD viscous terms (Sec. 4.2)
-                double b3[4];
-                val_n(M - 3, b3);
-                for (int m = 0; m < 4; ++m) d2n[m] = 2.0 * U[m] - 5.0 * b1[m] + 4.0 * b2[m] - b3[m];
-            }
-        } else {
-            double p1[4], m1[4];
-            val_n(j + 1, p1); val_n(j - 1, m1);
-            for (int m = 0; m < 4; ++m) dn[m] = 0.5 * (p1[m] - m1[m]);
-            if (fd_v)
-                for (int m = 0; m < 4; ++m) d2n[m] = p1[m] - 2.0 * U[m] + m1[m];
+        double gU[4], gA[4], gB[4], gC[4] = {0.0, 0.0, 0.0, 0.0}, gu[4], gd[4], cu[4], cd[4], g0[4];
+        rd(j, gU);
+        rd(kA, gA);
+        rd(kB, gB);
+        if (M == 3 && fd_v) rd(kC, gC);
+        const double* yu = &Ys[(min(lrc + 1, NR - 1) * M + jj) * 4];
+        const double* yd = &Ys[(max(lrc - 1, 0) * M + jj) * 4];
+        for (int m = 0; m < 4; ++m) {
+            gu[m] = yu[m];
+            gd[m] = yd[m];
+            cu[m] = (1.0 - th) * sC[1][0][m] + th * sC[1][1][m];   // row len: the high corner
+            cd[m] = (1.0 - th) * sC[0][0][m] + th * sC[0][1][m];   // row -1: the low corner
+            g0[m] = sY[0][t * 4 + m];
         }
-        val_t(r + 1, up);
-        val_t(r - 1, dw);
-        to_local(sd, &sY[0][t * 4], U0);
+        const bool cor_u = !tper && r + 1 >= len, cor_d = !tper && r - 1 < 0;
+        for (int m = 0; m < 4; ++m) {
+            gu[m] = cor_u ? cu[m] : gu[m];
+            gd[m] = cor_d ? cd[m] : gd[m];
+        }
+        double a[4], b[4], c[4];
+        loc(gU, U);
+        loc(gA, a);
+        loc(gB, b);
+        loc(gu, up);
+        loc(gd, dw);
+        loc(g0, U0);
+        for (int m = 0; m < 4; ++m) dn[m] = cU * U[m] + cA * a[m] + cB * b[m];
+        for (int m = 0; m < 4; ++m) d2n[m] = 0.0;
+        if (fd_v) {   // second differences of the -FD viscous terms (Sec. 4.2): backward at j = M
+            loc(gC, c);
+            for (int m = 0; m < 4; ++m)
+                d2n[m] = one ? (M == 3 ? 2.0 * U[m] - 5.0 * a[m] + 4.0 * b[m] - c[m] : 0.0) : a[m] - 2.0 * U[m] + b[m];
+        }
     };
 
     // ---- phase C: reverse stages 3..0 (stage inputs loaded in phase A) ------------------------
@@ -697,20 +711,30 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
         __syncthreads();
         // gather the adjoint of this stage's input on rows within st of the owned range
         if (node && within(r, st)) {
+            // every read first (clamped indices), the terms chosen by value: one LDS wait
+            double vq[M][4], vu[4], vd[4];
+            for (int q = 1; q <= M; ++q)
+                for (int m = 0; m < 4; ++m) vq[q - 1][m] = bGn[((lrc * M) + q - 1) * 4 + m];
+            for (int m = 0; m < 4; ++m) {
+                vu[m] = bGu[(max(lrc - 1, 0) * M + jj) * 4 + m];
+                vd[m] = bGd[(min(lrc + 1, NR - 1) * M + jj) * 4 + m];
+            }
             double yb[4];
             for (int m = 0; m < 4; ++m) yb[m] = gself[m];
-            for (int q = 1; q <= M; ++q) {   // normal differences of the other layers of this row
-                double cf = 0.0;
-                if (q == j) continue;
-                if (q == M) cf = (j == M - 1) ? -2.0 : (j == M - 2 ? 0.5 : 0.0);
-                else cf = (j == q + 1) ? 0.5 : (j == q - 1 ? -0.5 : 0.0);
-                if (cf != 0.0)
-                    for (int m = 0; m < 4; ++m) yb[m] += cf * bGn[((lr * M) + q - 1) * 4 + m];
-                if constexpr (M == 3) if (fd_v) {   // second differences: backward (2, -5, 4, -1) at q = M, central below
+            for (int q = 1; q <= M; ++q) {   // normal differences of the other layers of this row (cf = 0 at q = j)
+                const double cf = q == M ? ((j == M - 1) ? -2.0 : (j == M - 2 ? 0.5 : 0.0))
+                                         : ((j == q + 1) ? 0.5 : (j == q - 1 ? -0.5 : 0.0));
+                for (int m = 0; m < 4; ++m) yb[m] += cf != 0.0 ? cf * vq[q - 1][m] : 0.0;
+            }
+            if constexpr (M == 3) if (fd_v) {   // second differences: backward (2, -5, 4, -1) at q = M, central below
+                double v2[M][4];
+                for (int q = 1; q <= M; ++q)
+                    for (int m = 0; m < 4; ++m) v2[q - 1][m] = bG2[((lrc * M) + q - 1) * 4 + m];
+                for (int q = 1; q <= M; ++q) {
+                    if (q == j) continue;
                     const double c2 = q == M ? (j == M - 1 ? -5.0 : (j == M - 2 ? 4.0 : 0.0))
                                              : ((j == q + 1 || j == q - 1) ? 1.0 : 0.0);
-                    if (c2 != 0.0)
-                        for (int m = 0; m < 4; ++m) yb[m] += c2 * bG2[((lr * M) + q - 1) * 4 + m];
+                    for (int m = 0; m < 4; ++m) yb[m] += c2 != 0.0 ? c2 * v2[q - 1][m] : 0.0;
                 }
             }
             if constexpr (M == 3) if (fd_v) {
@@ -723,8 +747,9 @@ __device__ void adj_chunk(const AdjArgs& g, const SideDev& sd, int side, int blk
                         sXbp[(lr * MS) * 4 + m] += th * xb;
                     }
             }
-            if (valid(r - 1)) for (int m = 0; m < 4; ++m) yb[m] += bGu[((lr - 1) * M + jj) * 4 + m];
-            if (valid(r + 1)) for (int m = 0; m < 4; ++m) yb[m] += bGd[((lr + 1) * M + jj) * 4 + m];
+            const bool vm1 = valid(r - 1), vp1 = valid(r + 1);
+            for (int m = 0; m < 4; ++m) yb[m] += vm1 ? vu[m] : 0.0;
+            for (int m = 0; m < 4; ++m) yb[m] += vp1 ? vd[m] : 0.0;
             for (int m = 0; m < 4; ++m) gnext[m] = yb[m];
             if (owned) for (int m = 0; m < 4; ++m) ybn[m] += yb[m];
         }
