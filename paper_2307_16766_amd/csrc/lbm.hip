@@ -81,7 +81,7 @@ int chunk_rows_y(int M, int nx, int ny) { return short_x_chunks(nx, ny) ? chunk_
 int adj_rows(int M) { return 256 / M - 16; }   // must match NR - 2 H in adj_chunk
 int adj_rows_short(int M, int nx, int ny) {
     if (!short_x_chunks(nx, ny)) return adj_rows(M);
-    return M == 3 ? 16 : M == 2 ? 24 : 48;
+    return M == 3 ? 12 : M == 2 ? 24 : 48;   // D2Q37: 16 -> 12 rows, 36.34 -> 36.07 us per 256^2 reverse step
 }
 
 struct Layout {
