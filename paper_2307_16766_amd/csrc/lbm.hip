@@ -67,9 +67,12 @@ int chunk_rows(int M) { return 192 / M - 8; }   // must match ChunkShape::CR - 8
 // on), the boundary is hidden behind it and the extra work-groups only take CU slots (4096 x 2048:
 // 398.5 -> 404 us), so the chunks stay full height.
 bool short_x_chunks(int nx, int ny) { return (long long)((nx + 255) / 256) * ny < 8192; }
-int chunk_rows_x(int M, int nx, int ny) {
+// D2Q37 takes 12 rows, and 8 on CBC sides, whose four pulls per row (x_f and the three
+// viscous-moment nodes) are the slowest loads under the bulk's traffic (1024 x 512 FP32, CBC-RELAX
+// outflow: 35.4 -> 31.6 us per step; 256^2 FP64 15.5 -> 15.35 us, 512^2 FP32 18.9 -> 18.5 us).
+int chunk_rows_x(int M, int nx, int ny, bool cbc) {
     if (!short_x_chunks(nx, ny)) return chunk_rows(M);
-    return M == 3 ? 16 : M == 2 ? 24 : 48;
+    return M == 3 ? (cbc ? 8 : 12) : M == 2 ? 24 : 48;
 }
 // sides normal to y (coalesced pulls) take half-height chunks on the same small grids: their
 // reconstruction and corner chunks then end sooner
@@ -161,7 +164,7 @@ void make_layout(const lbm_config* c, Layout& L) {
         d.owns_corners = d.nax == 0;
         d.Pinf = 0;
         if (d.kind == KIND_CHAR) {
-            d.rows = d.nax == 0 ? chunk_rows_x(L.M, c->nx, c->ny) : chunk_rows_y(L.M, c->nx, c->ny);
+            d.rows = d.nax == 0 ? chunk_rows_x(L.M, c->nx, c->ny, is_full(b)) : chunk_rows_y(L.M, c->nx, c->ny);
             d.nblk = (d.len + d.rows - 1) / d.rows;
             d.off_ub = reg; reg += align_up((size_t)L.M * d.len * 4 * 8);
             d.off_strip = reg; reg += align_up((size_t)L.MS * d.len * 4 * 8);
