@@ -69,10 +69,11 @@ int chunk_rows(int M) { return 192 / M - 8; }   // must match ChunkShape::CR - 8
 bool short_x_chunks(int nx, int ny) { return (long long)((nx + 255) / 256) * ny < 8192; }
 // D2Q37 takes 12 rows, and 8 on CBC sides, whose four pulls per row (x_f and the three
 // viscous-moment nodes) are the slowest loads under the bulk's traffic (1024 x 512 FP32, CBC-RELAX
-// outflow: 35.4 -> 31.6 us per step; 256^2 FP64 15.5 -> 15.35 us, 512^2 FP32 18.9 -> 18.5 us).
+// outflow: 35.4 -> 31.3 us per step; 256^2 FP64 15.6 -> 15.4 us); D2Q9 takes 16 rows (256 x 128:
+// 7.7 -> 6.8 us per step).
 int chunk_rows_x(int M, int nx, int ny, bool cbc) {
     if (!short_x_chunks(nx, ny)) return chunk_rows(M);
-    return M == 3 ? (cbc ? 8 : 12) : M == 2 ? 24 : 48;
+    return M == 3 ? (cbc ? 8 : 12) : M == 2 ? 24 : 16;
 }
 // sides normal to y (coalesced pulls) take half-height chunks on the same small grids: their
 // reconstruction and corner chunks then end sooner

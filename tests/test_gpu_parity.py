@@ -98,7 +98,7 @@ def test_d2q37_multi_tile(precision):
 def test_short_last_chunk(stencil, nx, ny, precision):
     # side lengths (between the corner blocks) one to three rows past a multiple of the chunk
     # height on these small grids (sides normal to y: 28 / 44 / 92 rows for M = 3 / 2 / 1, sides
-    # normal to x: 12, or 8 on CBC sides / 24 / 48): the last chunk owns 1-3 rows, so the RK halo of the one before it
+    # normal to x: 12, or 8 on CBC sides / 24 / 16): the last chunk owns 1-3 rows, so the RK halo of the one before it
     # reaches the corner beyond the side's end; pulse next to that corner
     f = W.temperature_pulse(nx, ny, amp=1e-3, width=4.0, center=(nx - 8.0, ny - 8.0))
     rho, ux, uy, T = f
